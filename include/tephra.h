@@ -1,0 +1,209 @@
+/*
+ * tephra: matrix-free geometric-multigrid solver of the 2D incompressible
+ * variable-viscosity Stokes equations on the stress-conservative staggered
+ * grid, for AMD Instinct MI355X (gfx950).
+ *
+ * The problem (Ch. 3 "Conservation of Mass and Momentum", Ch. 4
+ * "Stress-Conservative Finite Differences", eq. stokes_saddle):
+ *
+ *     [ L  G ] [v]   [f]      L v = div_h(eta (grad_h v + grad_h v^T))
+ *     [ D  0 ] [p] = [0],     G p = -grad_h p,  D v = div_h v,
+ *
+ * with f = -rho g (gravity moved to the right-hand side) plus an optional
+ * extra body force.  The solver is flexible GMRES(m) in FP64 (Ch. 4
+ * "Accelerators", "Comparison with FGMRES") preconditioned by one Uzawa step
+ * (Sec. "Uzawa Iteration as a Fixed Point Method"): a geometric multigrid
+ * V-cycle on L (Sec. "Multigrid Cycles") followed by the viscosity-scaled
+ * pressure update.  The stopping test is the relative energy residual of
+ * Sec. "Residual Norms".
+ *
+ * ARRAY CONVENTION (all field arguments).  A problem of nx x ny cells uses
+ * dense row-major FP64 arrays of (ny + 2) x (nx + 2) entries, row index i
+ * along y, column index j along x (Ch. 4 "Staggered Grid Layout"):
+ *   basic node (i, j) at (j dx, i dy), i in [0, ny], j in [0, nx]: eta_b, rho_b
+ *   cell centre (i, j) at ((j - 1/2) dx, (i - 1/2) dy), i, j in [1, n]: eta_p, p
+ *   vx (i, j) at (j dx, (i - 1/2) dy): unknowns i in [1, ny], j in [1, nx - 1]
+ *   vy (i, j) at ((j - 1/2) dx, i dy): unknowns i in [1, ny - 1], j in [1, nx]
+ * Entries outside those ranges are ignored on input.  Velocity outputs hold
+ * zero on the walls and mirrored ghosts (+1 free slip, -1 no slip) outside
+ * them; pressure outputs have zero mean over the nx*ny cells; residual-type
+ * outputs (tph_apply) are zero outside the equation rows.
+ *
+ * POINTERS AND OWNERSHIP.  Every field pointer is a DEVICE pointer on the
+ * device current when the solver was created (for example a torch tensor's
+ * data_ptr()).  The caller owns it; the library never keeps it after the call
+ * returns.  tph_set_coefficients copies what it needs into library-owned
+ * device workspace.
+ *
+ * STREAMS.  All work is enqueued on the hipStream_t given to tph_create.
+ * Entry points that report scalars (solve, energy residual) synchronise that
+ * stream before returning.
+ *
+ * ERRORS.  Every entry point returns a tph_status; nothing is thrown across
+ * the ABI.  A human-readable message for the calling thread's last failure
+ * is available from tph_last_error().  Descriptor and size checks run on the
+ * host before any device work.  Viscosity that is not finite and positive,
+ * or a non-finite density / force, is detected by a device check inside
+ * tph_set_coefficients (TPH_ERR_INVALID / TPH_ERR_NONFINITE).  A solve that
+ * exhausts max_iters returns TPH_NOT_CONVERGED (a warning: the best iterate
+ * is written and the info block filled).
+ *
+ * THREADING.  A handle must not be used from two threads at once.
+ */
+#ifndef TEPHRA_H
+#define TEPHRA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TPH_OK = 0,
+    TPH_NOT_CONVERGED = 1,
+    TPH_ERR_INVALID = -1,
+    TPH_ERR_OOM = -2,
+    TPH_ERR_HIP = -3,
+    TPH_ERR_NONFINITE = -4,
+    TPH_ERR_UNSUPPORTED = -5
+} tph_status;
+
+/* Per-wall velocity condition (Ch. 3 "Boundary Conditions"). */
+enum { TPH_FREE_SLIP = 0, TPH_NO_SLIP = 1 };
+/* Wall order in tph_desc.bc: west (x = 0), east (x = lx), south (row 0), north (row ny). */
+enum { TPH_WEST = 0, TPH_EAST = 1, TPH_SOUTH = 2, TPH_NORTH = 3 };
+/* TPH_FP64: V-cycle in FP64.  TPH_MIXED: V-cycle smoothing and transfers in
+ * FP32; outer residual, Krylov orthogonalisation, coarsest solve and the
+ * pressure step stay FP64. */
+enum { TPH_FP64 = 0, TPH_MIXED = 1 };
+/* Smoother on L (Sec. "Smoothers"): damped Jacobi (eq. damped_jacobi) or
+ * damped Gauss-Seidel (eq. sor_update) in four colour half-sweeps
+ * (vx red, vx black, vy red, vy black; red = (i + j) even). */
+enum { TPH_SMOOTH_JACOBI = 0, TPH_SMOOTH_GS = 1 };
+/* Coarse-level viscosity: normalised bilinear restriction of eta
+ * (arithmetic) or of log(eta) (geometric). */
+enum { TPH_MEAN_ARITHMETIC = 0, TPH_MEAN_GEOMETRIC = 1 };
+
+typedef struct tph_desc {
+    int32_t nx, ny;        /* cells; each must be divisible by 2^(levels-1)  */
+    double lx, ly;         /* domain size, dx = lx / nx, dy = ly / ny        */
+    int32_t bc[4];         /* TPH_FREE_SLIP / TPH_NO_SLIP per wall           */
+    int32_t precision;     /* TPH_FP64 or TPH_MIXED                          */
+    int32_t levels;        /* multigrid levels; 0 = automatic (coarsest side in [8, 16)) */
+    int32_t smoother;      /* TPH_SMOOTH_*                                    */
+    int32_t nu_pre;        /* pre-smoothing sweeps on the finest level       */
+    int32_t nu_post;       /* post-smoothing sweeps on the finest level      */
+    double nu_growth;      /* sweeps on level l = ceil(nu * nu_growth^l)     */
+    double omega;          /* smoother damping                                */
+    double alpha;          /* Uzawa pressure relaxation                       */
+    int32_t eta_mean;      /* TPH_MEAN_*                                      */
+    double rtol;           /* relative energy residual target                 */
+    int32_t restart;       /* FGMRES restart length m (1..64)                 */
+    int32_t max_iters;     /* total FGMRES iterations                         */
+    int32_t reserved[8];   /* must be zero                                    */
+} tph_desc;
+
+typedef struct tph_info {
+    int32_t iters;         /* FGMRES iterations (= preconditioner applications) */
+    int32_t restarts;      /* restart cycles started                          */
+    double res_energy;     /* true relative energy residual of the result     */
+    double res_estimate;   /* FGMRES least-squares estimate at exit           */
+    double t_setup_ms;     /* last tph_set_coefficients, device time          */
+    double t_solve_ms;     /* this solve, host wall time                      */
+    double* history;       /* optional caller-owned HOST buffer: estimate per iteration */
+    int32_t history_len;   /* its capacity (entries)                          */
+} tph_info;
+
+typedef struct tph_solver tph_solver;
+
+/* Fill *d with the defaults for an nx x ny unit-square free-slip problem:
+ * mixed precision, automatic levels, coloured Gauss-Seidel (omega 1) with 2
+ * sweeps doubling per level, alpha 1, arithmetic coarse viscosity,
+ * rtol 1e-8, restart 20, max_iters 500. */
+void tph_desc_default(tph_desc* d, int32_t nx, int32_t ny);
+
+/* Create a solver for the grid in *desc; hip_stream is a hipStream_t (NULL:
+ * the null stream).  Allocates all device workspace (levels, Krylov basis).
+ * Errors: TPH_ERR_INVALID (sizes, levels, parameters), TPH_ERR_OOM,
+ * TPH_ERR_HIP.  *out is NULL on failure. */
+tph_status tph_create(const tph_desc* desc, void* hip_stream, tph_solver** out);
+
+/* Coefficient setup (hot-path step "coefficient setup"): copies eta_b,
+ * eta_p (basic nodes, cell centres) and builds f = -rho_b g averaged to the
+ * velocity nodes (x: mean of the basic nodes below/above; y: left/right) plus
+ * fx_extra / fy_extra sampled at vx / vy nodes (both nullable); restricts the
+ * viscosities down every level (normalised bilinear weights, Alg. "4-Color
+ * Parallel Restriction" in gather form) and factors the coarsest operator in
+ * FP64.  All arrays are device (ny+2) x (nx+2) FP64.  Must precede any solve
+ * or apply. */
+tph_status tph_set_coefficients(tph_solver* s, const double* eta_b, const double* eta_p,
+                                const double* rho_b, double gx, double gy,
+                                const double* fx_extra, const double* fy_extra);
+
+/* Solve A [v; p] = [f; 0] to desc.rtol in the relative energy residual.
+ * vx, vy, p: in = initial guess (unknown entries), out = solution.
+ * info may be NULL.  Returns TPH_OK or TPH_NOT_CONVERGED (or an error). */
+tph_status tph_solve(tph_solver* s, double* vx, double* vy, double* p, tph_info* info);
+
+/* Same with an explicit right-hand side (fx at vx rows, fy at vy rows, fp at
+ * continuity rows), replacing the one from tph_set_coefficients for this call
+ * only.  Used for the adjoint solve (A is symmetric, A = A^T). */
+tph_status tph_solve_rhs(tph_solver* s, const double* fx, const double* fy, const double* fp,
+                         double* vx, double* vy, double* p, tph_info* info);
+
+/* (ax, ay, ap) = A (vx, vy, p) in FP64, matrix-free (Ch. 6 point-wise
+ * operator and its mirror).  Outputs are zero outside the equation rows. */
+tph_status tph_apply(tph_solver* s, const double* vx, const double* vy, const double* p,
+                     double* ax, double* ay, double* ap);
+
+/* One application of the Uzawa preconditioner M^{-1} (Sec. "Uzawa Iteration
+ * as a Fixed Point Method", M = [[L, 0], [D, (alpha eta_p)^{-1}]]): z_v = one
+ * V-cycle on L r_v = z_v from zero, in the solver's precision; z_p =
+ * alpha eta_p (r_p - D z_v).  With levels = 1 the V-cycle is the exact FP64
+ * solve.  Inputs are residual-type arrays, outputs solution-type arrays. */
+tph_status tph_precondition(tph_solver* s, const double* rx, const double* ry, const double* rp,
+                            double* zx, double* zy, double* zp);
+
+/* Relative energy residual of (vx, vy, p) for the right-hand side of
+ * tph_set_coefficients (Sec. "Global Relative Energy Residual"). */
+tph_status tph_energy_residual(tph_solver* s, const double* vx, const double* vy,
+                               const double* p, double* out);
+
+/* Copy the viscosities of multigrid level l (0 = finest) into device arrays
+ * of that level's shape ((ny_l + 2) x (nx_l + 2), FP64). */
+tph_status tph_level_viscosity(tph_solver* s, int32_t level, double* eta_b, double* eta_p);
+
+/* Number of levels actually used, and level l's cell counts. */
+tph_status tph_level_shape(tph_solver* s, int32_t level, int32_t* nx, int32_t* ny);
+
+/* Adjoint solve A^T lam = g (A is symmetric, so this is the forward solver
+ * with right-hand side g = (gvx, gvy, gp)); lam is written zero-mean in
+ * pressure.  Any of gvx, gvy, gp may be NULL (zero). */
+tph_status tph_solve_adjoint(tph_solver* s, const double* gvx, const double* gvy, const double* gp,
+                             double* lvx, double* lvy, double* lp, tph_info* info);
+
+/* Gradient of a functional J(v, p) with respect to the coefficients, given
+ * the forward solution x = (vx, vy, p) and the adjoint lam = (lvx, lvy, lp):
+ * dJ/d eta_p(c) = 2 (exx(lam) exx(x) + eyy(lam) eyy(x)) at cell centres,
+ * dJ/d eta_b(b) = w_b gamma(lam) gamma(x) at basic nodes (gamma =
+ * d vx/dy + d vy/dx with mirrored ghosts; w_b = 1 inside, 1/2 on a no-slip
+ * wall), dJ/d rho_b = lam^T df/d rho_b.  Any output may be NULL. */
+tph_status tph_coeff_gradient(tph_solver* s, const double* vx, const double* vy, const double* p,
+                              const double* lvx, const double* lvy, const double* lp,
+                              double* g_eta_b, double* g_eta_p, double* g_rho_b);
+
+/* Release everything the solver owns.  NULL is allowed. */
+void tph_destroy(tph_solver* s);
+
+/* Message of the calling thread's last error ("" if none). */
+const char* tph_last_error(void);
+
+/* Library version string. */
+const char* tph_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TEPHRA_H */

@@ -1,0 +1,260 @@
+"""tephra: MI355X-native matrix-free multigrid Stokes solver (Python binding).
+
+Thin wrapper over the C ABI of ``include/tephra.h``: torch tensors provide
+device memory and the stream, every step of the solve runs in the HIP
+library.  Field arrays are float64 CUDA tensors of shape (ny + 2, nx + 2) in
+the staggered-grid convention documented in the header.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+from typing import Optional, Sequence, Tuple
+
+import torch
+
+from . import _lib
+from ._lib import (FP64, FREE_SLIP, MEAN_ARITHMETIC, MEAN_GEOMETRIC, MIXED, NO_SLIP,
+                   SMOOTH_GS, SMOOTH_JACOBI, TephraError)
+
+__all__ = ["Solver", "SolveInfo", "StokesFunction", "solve", "FP64", "MIXED", "FREE_SLIP",
+           "NO_SLIP", "SMOOTH_GS", "SMOOTH_JACOBI", "MEAN_ARITHMETIC", "MEAN_GEOMETRIC",
+           "TephraError", "library"]
+
+
+def library():
+    """The loaded libtephra.so (raises if it has not been built)."""
+    return _lib.load()
+
+
+@dataclass
+class SolveInfo:
+    status: str
+    iters: int
+    restarts: int
+    res_energy: float
+    res_estimate: float
+    t_setup_ms: float
+    t_solve_ms: float
+    history: list = field(default_factory=list)
+
+
+def _ptr(t: Optional[torch.Tensor], shape, name: str):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != shape:
+        raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of shape {shape}, got "
+                         f"{t.dtype} {tuple(t.shape)} on {t.device}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One problem size with its device workspace (tph_create)."""
+
+    def __init__(self, nx: int, ny: int, lx: float = 1.0, ly: float = 1.0,
+                 bc: Sequence[int] = (FREE_SLIP,) * 4, precision: int = MIXED,
+                 levels: int = 0, smoother: int = SMOOTH_GS, nu_pre: int = 2, nu_post: int = 2,
+                 nu_growth: float = 2.0, omega: float = 1.0, alpha: float = 1.0,
+                 eta_mean: int = MEAN_ARITHMETIC, rtol: float = 1e-8, restart: int = 20,
+                 max_iters: int = 500, device: Optional[torch.device] = None,
+                 stream: Optional[torch.cuda.Stream] = None):
+        lib = _lib.load()
+        d = _lib.Desc()
+        lib.tph_desc_default(ctypes.byref(d), nx, ny)
+        d.lx, d.ly = float(lx), float(ly)
+        for w in range(4):
+            d.bc[w] = int(bc[w])
+        d.precision = int(precision)
+        d.levels = int(levels)
+        d.smoother = int(smoother)
+        d.nu_pre, d.nu_post = int(nu_pre), int(nu_post)
+        d.nu_growth = float(nu_growth)
+        d.omega, d.alpha = float(omega), float(alpha)
+        d.eta_mean = int(eta_mean)
+        d.rtol = float(rtol)
+        d.restart, d.max_iters = int(restart), int(max_iters)
+        self.desc = d
+        self.nx, self.ny = nx, ny
+        self.shape = (ny + 2, nx + 2)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            h = ctypes.c_void_p()
+            _lib.check("tph_create", lib.tph_create(ctypes.byref(d), ctypes.c_void_p(self.stream.cuda_stream),
+                                                    ctypes.byref(h)))
+        self._h = h
+        self._lib = lib
+
+    # -- lifetime -----------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.tph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- helpers --------------------------------------------------------------
+    def zeros(self) -> torch.Tensor:
+        return torch.zeros(self.shape, dtype=torch.float64, device=self.device)
+
+    def _p(self, t, name):
+        return _ptr(t, self.shape, name)
+
+    def _sync_in(self):
+        # work queued by torch on another stream must be visible to the library
+        if self.stream != torch.cuda.current_stream(self.device):
+            self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def _info(self, info: _lib.Info, status: int, hist) -> SolveInfo:
+        n = min(info.iters, len(hist))
+        return SolveInfo(_lib.STATUS_NAMES.get(status, str(status)), info.iters, info.restarts,
+                         info.res_energy, info.res_estimate, info.t_setup_ms, info.t_solve_ms,
+                         [hist[k] for k in range(n)])
+
+    # -- entry points ---------------------------------------------------------
+    @property
+    def levels(self) -> int:
+        n = 0
+        while True:
+            nx = ctypes.c_int32()
+            st = self._lib.tph_level_shape(self._h, n, ctypes.byref(nx), None)
+            if st != 0:
+                return n
+            n += 1
+
+    def level_shape(self, level: int) -> Tuple[int, int]:
+        nx, ny = ctypes.c_int32(), ctypes.c_int32()
+        _lib.check("tph_level_shape", self._lib.tph_level_shape(self._h, level, ctypes.byref(nx), ctypes.byref(ny)))
+        return nx.value, ny.value
+
+    def set_coefficients(self, eta_b, eta_p, rho_b, gx: float = 0.0, gy: float = -1.0,
+                         fx_extra=None, fy_extra=None):
+        self._sync_in()
+        _lib.check("tph_set_coefficients", self._lib.tph_set_coefficients(
+            self._h, self._p(eta_b, "eta_b"), self._p(eta_p, "eta_p"), self._p(rho_b, "rho_b"),
+            float(gx), float(gy), self._p(fx_extra, "fx_extra"), self._p(fy_extra, "fy_extra")))
+
+    def solve(self, vx=None, vy=None, p=None, history: int = 0, raise_on_fail: bool = False):
+        vx = self.zeros() if vx is None else vx
+        vy = self.zeros() if vy is None else vy
+        p = self.zeros() if p is None else p
+        info = _lib.Info()
+        hist = (ctypes.c_double * max(history, 1))()
+        if history:
+            info.history = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
+            info.history_len = history
+        self._sync_in()
+        st = self._lib.tph_solve(self._h, self._p(vx, "vx"), self._p(vy, "vy"), self._p(p, "p"), ctypes.byref(info))
+        _lib.check("tph_solve", st, allow_not_converged=not raise_on_fail)
+        return vx, vy, p, self._info(info, st, hist if history else [])
+
+    def solve_rhs(self, fx, fy, fp=None, vx=None, vy=None, p=None):
+        vx = self.zeros() if vx is None else vx
+        vy = self.zeros() if vy is None else vy
+        p = self.zeros() if p is None else p
+        fp = self.zeros() if fp is None else fp
+        info = _lib.Info()
+        self._sync_in()
+        st = self._lib.tph_solve_rhs(self._h, self._p(fx, "fx"), self._p(fy, "fy"), self._p(fp, "fp"),
+                                     self._p(vx, "vx"), self._p(vy, "vy"), self._p(p, "p"), ctypes.byref(info))
+        _lib.check("tph_solve_rhs", st, allow_not_converged=True)
+        return vx, vy, p, self._info(info, st, [])
+
+    def apply(self, vx, vy, p):
+        ax, ay, ap = self.zeros(), self.zeros(), self.zeros()
+        self._sync_in()
+        _lib.check("tph_apply", self._lib.tph_apply(self._h, self._p(vx, "vx"), self._p(vy, "vy"), self._p(p, "p"),
+                                                    self._p(ax, "ax"), self._p(ay, "ay"), self._p(ap, "ap")))
+        return ax, ay, ap
+
+    def precondition(self, rx, ry, rp):
+        zx, zy, zp = self.zeros(), self.zeros(), self.zeros()
+        self._sync_in()
+        _lib.check("tph_precondition", self._lib.tph_precondition(
+            self._h, self._p(rx, "rx"), self._p(ry, "ry"), self._p(rp, "rp"),
+            self._p(zx, "zx"), self._p(zy, "zy"), self._p(zp, "zp")))
+        return zx, zy, zp
+
+    def energy_residual(self, vx, vy, p) -> float:
+        out = ctypes.c_double()
+        self._sync_in()
+        _lib.check("tph_energy_residual", self._lib.tph_energy_residual(
+            self._h, self._p(vx, "vx"), self._p(vy, "vy"), self._p(p, "p"), ctypes.byref(out)))
+        return out.value
+
+    def level_viscosity(self, level: int):
+        nx, ny = self.level_shape(level)
+        eb = torch.zeros((ny + 2, nx + 2), dtype=torch.float64, device=self.device)
+        ep = torch.zeros_like(eb)
+        self._sync_in()
+        _lib.check("tph_level_viscosity", self._lib.tph_level_viscosity(
+            self._h, level, ctypes.c_void_p(eb.data_ptr()), ctypes.c_void_p(ep.data_ptr())))
+        return eb, ep
+
+    def solve_adjoint(self, gvx=None, gvy=None, gp=None):
+        lx, ly, lp = self.zeros(), self.zeros(), self.zeros()
+        info = _lib.Info()
+        self._sync_in()
+        st = self._lib.tph_solve_adjoint(self._h, self._p(gvx, "gvx"), self._p(gvy, "gvy"), self._p(gp, "gp"),
+                                         self._p(lx, "lvx"), self._p(ly, "lvy"), self._p(lp, "lp"),
+                                         ctypes.byref(info))
+        _lib.check("tph_solve_adjoint", st, allow_not_converged=True)
+        return lx, ly, lp, self._info(info, st, [])
+
+    def coeff_gradient(self, vx, vy, p, lvx, lvy, lp):
+        gb, gp, gr = self.zeros(), self.zeros(), self.zeros()
+        self._sync_in()
+        _lib.check("tph_coeff_gradient", self._lib.tph_coeff_gradient(
+            self._h, self._p(vx, "vx"), self._p(vy, "vy"), self._p(p, "p"),
+            self._p(lvx, "lvx"), self._p(lvy, "lvy"), self._p(lp, "lp"),
+            self._p(gb, "g_eta_b"), self._p(gp, "g_eta_p"), self._p(gr, "g_rho_b")))
+        return gb, gp, gr
+
+
+def solve(eta_b, eta_p, rho_b, gx: float = 0.0, gy: float = -1.0, lx: float = 1.0, ly: float = 1.0,
+          **params):
+    """One-shot solve: returns (vx, vy, p, info)."""
+    ny, nx = eta_b.shape[0] - 2, eta_b.shape[1] - 2
+    with Solver(nx, ny, lx, ly, device=eta_b.device, **params) as s:
+        s.set_coefficients(eta_b, eta_p, rho_b, gx, gy)
+        return s.solve()
+
+
+class StokesFunction(torch.autograd.Function):
+    """(eta_b, eta_p, rho_b) -> (vx, vy, p) with a hand-written adjoint backward.
+
+    Forward: tph_set_coefficients + tph_solve on the given solver.  Backward:
+    the adjoint solve (A is symmetric) with right-hand side (dJ/dvx, dJ/dvy,
+    dJ/dp), then the coefficient-gradient kernel.
+    """
+
+    @staticmethod
+    def forward(ctx, eta_b, eta_p, rho_b, solver: Solver, gx: float = 0.0, gy: float = -1.0):
+        solver.set_coefficients(eta_b.detach().contiguous(), eta_p.detach().contiguous(),
+                                rho_b.detach().contiguous(), gx, gy)
+        vx, vy, p, info = solver.solve()
+        ctx.solver = solver
+        ctx.info = info
+        ctx.save_for_backward(vx, vy, p)
+        return vx, vy, p
+
+    @staticmethod
+    def backward(ctx, gvx, gvy, gp):
+        s: Solver = ctx.solver
+        vx, vy, p = ctx.saved_tensors
+        z = lambda g: s.zeros() if g is None else g.contiguous()
+        lx, ly, lp, _ = s.solve_adjoint(z(gvx), z(gvy), z(gp))
+        gb, gpp, gr = s.coeff_gradient(vx, vy, p, lx, ly, lp)
+        return gb, gpp, gr, None, None, None

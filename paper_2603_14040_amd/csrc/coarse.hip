@@ -1,0 +1,183 @@
+// Coarsest-level solve in FP64 (Ch. 4 "Multigrid Cycles": the coarsest
+// correction equation is solved directly).  The dense matrix M = -L of the
+// coarsest level (symmetric positive definite) is assembled on the device
+// from the rediscretised stencil, inverted once per coefficient set by an
+// in-place Gauss-Jordan sweep in a single workgroup, and applied as a dense
+// matrix-vector product (one wavefront per row).  Unknown order: vx(i, j)
+// row-major (i in [1, ny], j in [1, nx-1]), then vy(i, j) (i in [1, ny-1],
+// j in [1, nx]).
+#include "kernels.h"
+#include "reduce.h"
+
+namespace tph {
+
+int coarse_unknowns(const Geom& g) { return g.ny * (g.nx - 1) + (g.ny - 1) * g.nx; }
+
+namespace {
+
+__device__ __forceinline__ void unknown_to_node(const Geom& g, int m, int& comp, int& i, int& j) {
+    const int nvx = g.ny * (g.nx - 1);
+    if (m < nvx) {
+        comp = 0;
+        i = 1 + m / (g.nx - 1);
+        j = 1 + m % (g.nx - 1);
+    } else {
+        m -= nvx;
+        comp = 1;
+        i = 1 + m / g.nx;
+        j = 1 + m % g.nx;
+    }
+}
+
+// Add coef * field(ci, cj) of an L row into row m of M = -L, resolving walls
+// (dropped) and ghosts (mirrored onto the adjacent unknown).
+__device__ __forceinline__ void add_ref(const Geom& g, double* row, int comp, int ci, int cj, double coef) {
+    const int nvx = g.ny * (g.nx - 1);
+    if (comp == 0) {
+        if (cj <= 0 || cj >= g.nx) return;
+        if (ci == 0) { ci = 1; coef *= g.mir[2]; }
+        else if (ci == g.ny + 1) { ci = g.ny; coef *= g.mir[3]; }
+        row[(ci - 1) * (g.nx - 1) + (cj - 1)] -= coef;
+    } else {
+        if (ci <= 0 || ci >= g.ny) return;
+        if (cj == 0) { cj = 1; coef *= g.mir[0]; }
+        else if (cj == g.nx + 1) { cj = g.nx; coef *= g.mir[1]; }
+        row[nvx + (ci - 1) * g.nx + (cj - 1)] -= coef;
+    }
+}
+
+__global__ void k_coarse_assemble(Geom g, const double* __restrict__ eb, const double* __restrict__ ep,
+                                  double* __restrict__ M, int n) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    double* row = M + (size_t)m * n;
+    for (int q = 0; q < n; ++q) row[q] = 0.0;
+    int comp, i, j;
+    unknown_to_node(g, m, comp, i, j);
+    const int P = g.pitch;
+    const int c = i * P + j;
+    const double idx2 = 1.0 / (g.dx * g.dx), idy2 = 1.0 / (g.dy * g.dy), idxy = 1.0 / (g.dx * g.dy);
+    if (comp == 0) {
+        const double er = ep[c + 1], el = ep[c], bt = eb[c], bb = eb[c - P];
+        add_ref(g, row, 0, i, j + 1, 2 * er * idx2);
+        add_ref(g, row, 0, i, j, -2 * (er + el) * idx2 - (bt + bb) * idy2);
+        add_ref(g, row, 0, i, j - 1, 2 * el * idx2);
+        add_ref(g, row, 0, i + 1, j, bt * idy2);
+        add_ref(g, row, 0, i - 1, j, bb * idy2);
+        add_ref(g, row, 1, i, j + 1, bt * idxy);
+        add_ref(g, row, 1, i, j, -bt * idxy);
+        add_ref(g, row, 1, i - 1, j + 1, -bb * idxy);
+        add_ref(g, row, 1, i - 1, j, bb * idxy);
+    } else {
+        const double et = ep[c + P], eb_ = ep[c], br = eb[c], bl = eb[c - 1];
+        add_ref(g, row, 1, i + 1, j, 2 * et * idy2);
+        add_ref(g, row, 1, i, j, -2 * (et + eb_) * idy2 - (br + bl) * idx2);
+        add_ref(g, row, 1, i - 1, j, 2 * eb_ * idy2);
+        add_ref(g, row, 1, i, j + 1, br * idx2);
+        add_ref(g, row, 1, i, j - 1, bl * idx2);
+        add_ref(g, row, 0, i + 1, j, br * idxy);
+        add_ref(g, row, 0, i, j, -br * idxy);
+        add_ref(g, row, 0, i + 1, j - 1, -bl * idxy);
+        add_ref(g, row, 0, i, j - 1, bl * idxy);
+    }
+}
+
+// In-place Gauss-Jordan inverse of an SPD matrix (no pivoting needed), one
+// workgroup of 1024 threads; column k is staged in LDS before each step.
+__global__ __launch_bounds__(1024) void k_gauss_jordan(double* __restrict__ M, int n) {
+    extern __shared__ double colk[];
+    const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int nwave = nthr >> 6;
+    for (int k = 0; k < n; ++k) {
+        for (int i = tid; i < n; i += nthr) colk[i] = M[(size_t)i * n + k];
+        __syncthreads();
+        const double rd = 1.0 / colk[k];
+        for (int j = tid; j < n; j += nthr)
+            if (j != k) M[(size_t)k * n + j] *= rd;
+        __syncthreads();
+        for (int i = wave; i < n; i += nwave) {
+            if (i == k) continue;
+            const double f = colk[i];
+            double* ri = M + (size_t)i * n;
+            const double* rk = M + (size_t)k * n;
+            for (int j = lane; j < n; j += 64) {
+                if (j != k) ri[j] -= f * rk[j];
+                else ri[j] = -f * rd;
+            }
+        }
+        if (tid == 0) M[(size_t)k * n + k] = rd;
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_coarse_solve(Geom g, const double* __restrict__ Minv,
+                                                      const T* __restrict__ rx, const T* __restrict__ ry,
+                                                      T* __restrict__ ex, T* __restrict__ ey, int n) {
+    extern __shared__ double rs[];
+    const int tid = threadIdx.x;
+    const int P = g.pitch;
+    for (int m = tid; m < n; m += blockDim.x) {
+        int comp, i, j;
+        unknown_to_node(g, m, comp, i, j);
+        rs[m] = (double)(comp == 0 ? rx[i * P + j] : ry[i * P + j]);
+    }
+    __syncthreads();
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int nwave = blockDim.x >> 6;
+    for (int m = wave; m < n; m += nwave) {
+        const double* row = Minv + (size_t)m * n;
+        double s = 0.0;
+        for (int q = lane; q < n; q += 64) s += row[q] * rs[q];
+        s = wave_sum(s);
+        if (lane == 0) {
+            // L e = r  <=>  e = -(-L)^{-1} r
+            const T e = (T)(-s);
+            int comp, i, j;
+            unknown_to_node(g, m, comp, i, j);
+            const int c = i * P + j;
+            if (comp == 0) {
+                ex[c] = e;
+                if (i == 1) ex[c - P] = (T)g.mir[2] * e;
+                if (i == g.ny) ex[c + P] = (T)g.mir[3] * e;
+            } else {
+                ey[c] = e;
+                if (j == 1) ey[c - 1] = (T)g.mir[0] * e;
+                if (j == g.nx) ey[c + 1] = (T)g.mir[1] * e;
+            }
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_coarse_assemble(const Geom& g, const double* eb, const double* ep, double* M, hipStream_t st) {
+    const int n = coarse_unknowns(g);
+    hipLaunchKernelGGL(k_coarse_assemble, dim3((n + 127) / 128), dim3(128), 0, st, g, eb, ep, M, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_gauss_jordan(double* M, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), (size_t)n * sizeof(double), st, M, n);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_coarse_solve(const Geom& g, const double* Minv, const T* rx, const T* ry, T* ex, T* ey,
+                               hipStream_t st) {
+    const int n = coarse_unknowns(g);
+    hipLaunchKernelGGL(k_coarse_solve<T>, dim3(1), dim3(1024), (size_t)n * sizeof(double), st, g, Minv, rx, ry,
+                       ex, ey, n);
+    return hipGetLastError();
+}
+
+template hipError_t launch_coarse_solve<float>(const Geom&, const double*, const float*, const float*, float*,
+                                               float*, hipStream_t);
+template hipError_t launch_coarse_solve<double>(const Geom&, const double*, const double*, const double*,
+                                                double*, double*, hipStream_t);
+
+}  // namespace tph

@@ -1,0 +1,104 @@
+// Host-side launchers of the HIP kernels (one translation unit per family).
+// Every launcher enqueues on `st` and returns the launch status.
+#pragma once
+#include "common.h"
+
+namespace tph {
+
+// ---------------------------------------------------------------- stencil.hip
+// out = scale * (b - A x)  (b may be null: out = scale * (-A x) if negate, else scale * A x)
+// scale = sqrt(energy weight) when `energy` is set, else 1.  Writes equation
+// rows only.  partial (nullable): per-block sums of out^2, nblk entries.
+enum class ResMode { kResidual = 0, kApply = 1 };
+hipError_t launch_outer_residual(const Geom& g, Vec3 x, const Vec3* b, const double* eb, const double* ep,
+                                 Vec3 out, ResMode mode, bool energy, double* partial, int* nblk_out,
+                                 hipStream_t st);
+// walls to zero, ghosts mirrored, for a solution-type vx / vy pair
+template <typename T>
+hipError_t launch_fill_bc(const Geom& g, T* vx, T* vy, hipStream_t st);
+// every entry of a velocity correction pair to zero
+template <typename T>
+hipError_t launch_zero_vel(const Geom& g, T* ex, T* ey, hipStream_t st);
+// damped Jacobi sweep: e_out = e_in + omega (r - L e_in) / diag (e_in == null: zero guess)
+template <typename T>
+hipError_t launch_jacobi(const Geom& g, const T* ex_in, const T* ey_in, T* ex_out, T* ey_out,
+                         const T* rx, const T* ry, const T* eb, const T* ep, T omega, hipStream_t st);
+// one colour half-sweep of damped Gauss-Seidel on component comp (0 vx, 1 vy), colour col
+template <typename T>
+hipError_t launch_gs_half(const Geom& g, int comp, int col, T* ex, T* ey, const T* rx, const T* ry,
+                          const T* eb, const T* ep, T omega, bool zero_guess, hipStream_t st);
+// t = r - L e (velocity rows)
+template <typename T>
+hipError_t launch_vel_residual(const Geom& g, const T* ex, const T* ey, const T* rx, const T* ry,
+                               const T* eb, const T* ep, T* tx, T* ty, hipStream_t st);
+// preconditioner entry: level-0 right-hand side r = v / sqrt(w_v) (energy) or v
+template <typename T>
+hipError_t launch_precond_in(const Geom& g, Vec3 v, const double* eb, const double* ep, bool energy,
+                             T* rx, T* ry, hipStream_t st);
+// preconditioner exit: z_v = (double) e; z_p = alpha eta_p (r_p - D z_v)
+template <typename T>
+hipError_t launch_precond_out(const Geom& g, const T* ex, const T* ey, Vec3 v, const double* ep,
+                              bool energy, double alpha, Vec3 z, hipStream_t st);
+// right-hand side f = -rho g (+ extra) at velocity rows, 0 at continuity rows
+hipError_t launch_rhs(const Geom& g, const double* rho, double gx, double gy, const double* fxe,
+                      const double* fye, Vec3 b, hipStream_t st);
+// per-block counts of invalid coefficients: [bad eta, nonfinite rho/force]
+hipError_t launch_check_coeffs(const Geom& g, const double* eb, const double* ep, const double* rho,
+                               const double* fxe, const double* fye, double* partial, int* nblk_out,
+                               hipStream_t st);
+// coefficient gradient (adjoint): outputs nullable
+hipError_t launch_coeff_gradient(const Geom& g, Vec3 x, Vec3 lam, double gx, double gy,
+                                 double* g_eb, double* g_ep, double* g_rho, hipStream_t st);
+// adjoint right-hand side: fold gradients of ghost entries onto their interior owners
+hipError_t launch_fold_ghost_grad(const Geom& g, Vec3 v, hipStream_t st);
+// cast a field of the level (whole array)
+hipError_t launch_cast_f64_f32(const double* src, float* dst, size_t n, hipStream_t st);
+
+// --------------------------------------------------------------- transfer.hip
+// coarse viscosities from fine ones (normalised bilinear gather; geometric = log-mean)
+hipError_t launch_restrict_eta(const Geom& gf, const Geom& gc, const double* ebf, const double* epf,
+                               double* ebc, double* epc, bool geometric, hipStream_t st);
+template <typename T>
+hipError_t launch_restrict_res(const Geom& gf, const Geom& gc, const T* tx, const T* ty, T* rx, T* ry,
+                               hipStream_t st);
+template <typename T>
+hipError_t launch_prolong_add(const Geom& gf, const Geom& gc, const T* ecx, const T* ecy, T* ex, T* ey,
+                              hipStream_t st);
+
+// ----------------------------------------------------------------- coarse.hip
+int coarse_unknowns(const Geom& g);
+// dense M = -L (n x n row-major, FP64) of the level, then in-place inverse
+hipError_t launch_coarse_assemble(const Geom& g, const double* eb, const double* ep, double* M,
+                                  hipStream_t st);
+hipError_t launch_gauss_jordan(double* M, int n, hipStream_t st);
+// e = L^{-1} r = -M^{-1} r with M^{-1} stored; r, e level fields (ghosts of e written)
+template <typename T>
+hipError_t launch_coarse_solve(const Geom& g, const double* Minv, const T* rx, const T* ry, T* ex, T* ey,
+                               hipStream_t st);
+
+// ----------------------------------------------------------------- krylov.hip
+int flat_blocks(size_t n);
+// partial[i * nblk + b] = sum over block b of V_i . w   (i < nv <= 8)
+hipError_t launch_multidot(const double* V0, size_t vstride, int nv, const double* w, size_t n,
+                           double* partial, int nblk, hipStream_t st);
+// w -= sum_i h[i] V_i, then partial[i * nblk + b] = block sums of V_i . w (nv entries)
+// and, when norm_slot >= 0, partial[norm_slot * nblk + b] = block sums of w . w
+hipError_t launch_axpy_dot(double* w, const double* V0, size_t vstride, int nv, const double* h,
+                           size_t n, bool want_dots, int norm_slot, double* partial, int nblk,
+                           hipStream_t st);
+// out[i] = sum_b partial[i * nblk + b], i < k  (fixed order: deterministic)
+hipError_t launch_reduce_rows(const double* partial, int nblk, int k, double* out, hipStream_t st);
+// dst = src / sqrt(*nrm2)
+hipError_t launch_scale_by_rnorm(double* dst, const double* src, size_t n, const double* nrm2,
+                                 hipStream_t st);
+// dst = src * (1 / *beta)
+hipError_t launch_scale_by_rbeta(double* dst, const double* src, size_t n, const double* beta,
+                                 hipStream_t st);
+// x += sum_j y[j] Z_j  (k <= 8 per launch)
+hipError_t launch_update_x(double* x, const double* Z0, size_t zstride, int k, const double* y,
+                           size_t n, hipStream_t st);
+// sum of p over cells -> partial; then p -= mean
+hipError_t launch_p_sum(const Geom& g, const double* p, double* partial, int* nblk_out, hipStream_t st);
+hipError_t launch_p_shift(const Geom& g, double* p, const double* sum, hipStream_t st);
+
+}  // namespace tph

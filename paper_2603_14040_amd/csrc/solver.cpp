@@ -1,0 +1,744 @@
+// Host side of the solver: level hierarchy, V-cycle driver, flexible GMRES
+// and the C ABI declared in include/tephra.h.
+//
+// Method (Ch. 4): FGMRES(m) in FP64 on A x = b (Sec. "Comparison with
+// FGMRES") with the Uzawa step as variable right preconditioner (Sec. "Uzawa
+// Iteration as a Fixed Point Method"), one geometric-multigrid V-cycle on L
+// inside it (Sec. "Multigrid Cycles").  The Krylov inner product is the
+// energy inner product of Sec. "Residual Norms": the basis is stored scaled
+// by W^(1/2), W = diag(-L)^(-1) (+) eta_p / (2/dx^2 + 2/dy^2), so plain
+// Euclidean dot products give energy norms and the least-squares residual
+// estimate is the relative energy residual itself.  Each restart recomputes
+// the true FP64 residual, which is the iterative-refinement step of the
+// mixed-precision mode.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/tephra.h"
+#include "common.h"
+#include "kernels.h"
+
+using namespace tph;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+void set_error(const std::string& m) { g_last_error = m; }
+
+#define TPH_HIP(call)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess) {                                                             \
+            set_error(std::string("HIP error in ") + #call + ": " + hipGetErrorString(e_)); \
+            return TPH_ERR_HIP;                                                             \
+        }                                                                                   \
+    } while (0)
+
+#define TPH_TRY(expr)                          \
+    do {                                       \
+        tph_status s_ = (expr);                \
+        if (s_ != TPH_OK) return s_;           \
+    } while (0)
+
+// slots of the device scalar buffer
+constexpr int kSlotH1 = 0;                        // kMaxRestart + 1 entries
+constexpr int kSlotH2 = kSlotH1 + kMaxRestart + 1;
+constexpr int kSlotNrm = kSlotH2 + kMaxRestart + 1;
+constexpr int kSlotY = kSlotNrm + 1;              // kMaxRestart entries
+constexpr int kSlotMisc = kSlotY + kMaxRestart;   // 8 entries
+constexpr int kScalars = kSlotMisc + 8;
+
+struct LevelBuf {
+    Geom g;
+    double* eb64 = nullptr;
+    double* ep64 = nullptr;
+    void* eb = nullptr;          // viscosities in the V-cycle type
+    void* ep = nullptr;
+    void* ex[2] = {nullptr, nullptr};
+    void* ey[2] = {nullptr, nullptr};
+    void* rx = nullptr;
+    void* ry = nullptr;
+    void* tx = nullptr;
+    void* ty = nullptr;
+    int nu_pre = 0, nu_post = 0;
+};
+
+}  // namespace
+
+struct tph_solver {
+    tph_desc d{};
+    hipStream_t st = nullptr;
+    int nlev = 0;
+    LevelBuf lev[kMaxLevels];
+    double* Minv = nullptr;
+    int ncoarse = 0;
+    size_t F = 0;                // elements of one field allocation
+    size_t n3 = 0;               // elements of a three-field vector
+    double* x = nullptr;         // solution vector
+    double* b = nullptr;         // right-hand side of set_coefficients
+    double* b2 = nullptr;        // right-hand side of a solve_rhs / adjoint call
+    double* t1 = nullptr;        // scratch vectors
+    double* t2 = nullptr;
+    double* V = nullptr;         // (m + 1) basis vectors
+    double* Z = nullptr;         // m preconditioned vectors
+    double* rho = nullptr;       // staged fields (FP64)
+    double* fxe = nullptr;
+    double* fye = nullptr;
+    double* gtmp[3] = {nullptr, nullptr, nullptr};
+    double* partial = nullptr;   // reduction partials
+    size_t partial_len = 0;
+    double* dscal = nullptr;     // device scalars
+    double* hscal = nullptr;     // pinned host mirror
+    double gx = 0, gy = 0;
+    bool has_fx = false, has_fy = false;
+    bool ready = false;
+    double bnorm = 0;
+    double t_setup_ms = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<void*> dev_allocs;
+    bool mixed() const { return d.precision == TPH_MIXED; }
+};
+
+namespace {
+
+Vec3 vec3(const tph_solver* s, double* raw) { return Vec3{raw + (kAlign - 1), s->F}; }
+
+tph_status dev_alloc(tph_solver* s, void** p, size_t bytes) {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        set_error("device allocation of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? TPH_ERR_OOM : TPH_ERR_HIP;
+    }
+    s->dev_allocs.push_back(*p);
+    TPH_HIP(hipMemsetAsync(*p, 0, bytes, s->st));
+    return TPH_OK;
+}
+
+// one field of level geometry g in element type of `bytes_per`; returns base (entry (0,0))
+tph_status alloc_field(tph_solver* s, const Geom& g, size_t bytes_per, void** base) {
+    void* raw = nullptr;
+    TPH_TRY(dev_alloc(s, &raw, field_alloc(g) * bytes_per));
+    *base = (char*)raw + (kAlign - 1) * bytes_per;
+    return TPH_OK;
+}
+
+int level_sweeps(int nu, double growth, int l) {
+    const double v = std::ceil(nu * std::pow(growth, l) - 1e-9);
+    return (int)std::min(v, 256.0);
+}
+
+tph_status validate_desc(const tph_desc* d, int* nlev_out) {
+    if (!d) { set_error("desc is NULL"); return TPH_ERR_INVALID; }
+    if (d->nx < 2 || d->ny < 2) { set_error("nx and ny must be >= 2"); return TPH_ERR_INVALID; }
+    if ((int64_t)(d->nx + 2) * (d->ny + 2) > (int64_t)1 << 30) { set_error("grid too large"); return TPH_ERR_INVALID; }
+    if (!(d->lx > 0) || !(d->ly > 0) || !std::isfinite(d->lx) || !std::isfinite(d->ly)) {
+        set_error("lx and ly must be positive and finite");
+        return TPH_ERR_INVALID;
+    }
+    for (int w = 0; w < 4; ++w)
+        if (d->bc[w] != TPH_FREE_SLIP && d->bc[w] != TPH_NO_SLIP) { set_error("bad boundary condition"); return TPH_ERR_INVALID; }
+    if (d->precision != TPH_FP64 && d->precision != TPH_MIXED) { set_error("bad precision"); return TPH_ERR_INVALID; }
+    if (d->smoother != TPH_SMOOTH_JACOBI && d->smoother != TPH_SMOOTH_GS) { set_error("bad smoother"); return TPH_ERR_INVALID; }
+    if (d->eta_mean != TPH_MEAN_ARITHMETIC && d->eta_mean != TPH_MEAN_GEOMETRIC) { set_error("bad eta_mean"); return TPH_ERR_INVALID; }
+    if (d->nu_pre < 0 || d->nu_post < 0 || d->nu_pre > 256 || d->nu_post > 256) { set_error("bad sweep counts"); return TPH_ERR_INVALID; }
+    if (!(d->nu_growth >= 1.0) || d->nu_growth > 4.0) { set_error("nu_growth must be in [1, 4]"); return TPH_ERR_INVALID; }
+    if (!(d->omega > 0.0) || d->omega > 2.0) { set_error("omega must be in (0, 2]"); return TPH_ERR_INVALID; }
+    if (!(d->alpha > 0.0) || !std::isfinite(d->alpha)) { set_error("alpha must be positive"); return TPH_ERR_INVALID; }
+    if (!(d->rtol > 0.0) || !(d->rtol < 1.0)) { set_error("rtol must be in (0, 1)"); return TPH_ERR_INVALID; }
+    if (d->restart < 1 || d->restart > kMaxRestart) { set_error("restart must be in [1, 64]"); return TPH_ERR_INVALID; }
+    if (d->max_iters < 1) { set_error("max_iters must be >= 1"); return TPH_ERR_INVALID; }
+    int nlev = d->levels;
+    if (nlev == 0) {
+        nlev = 1;
+        int nx = d->nx, ny = d->ny;
+        while (nx % 2 == 0 && ny % 2 == 0 && nx / 2 >= 8 && ny / 2 >= 8 && nlev < kMaxLevels) {
+            nx /= 2;
+            ny /= 2;
+            ++nlev;
+        }
+    }
+    if (nlev < 1 || nlev > kMaxLevels) { set_error("levels must be in [1, 16]"); return TPH_ERR_INVALID; }
+    const int f = 1 << (nlev - 1);
+    if (d->nx % f || d->ny % f) { set_error("nx and ny must be divisible by 2^(levels-1)"); return TPH_ERR_INVALID; }
+    const int cx = d->nx / f, cy = d->ny / f;
+    if (cx < 2 || cy < 2) { set_error("coarsest level must have at least 2 x 2 cells"); return TPH_ERR_INVALID; }
+    const int nc = cy * (cx - 1) + (cy - 1) * cx;
+    if (nc > 4096) { set_error("coarsest level too large for the dense FP64 solve (max 4096 unknowns)"); return TPH_ERR_INVALID; }
+    *nlev_out = nlev;
+    return TPH_OK;
+}
+
+template <typename T>
+T* as(void* p) { return (T*)p; }
+
+// ----------------------------------------------------------------- V-cycle
+template <typename T>
+tph_status vcycle(tph_solver* s, int l, int* cur_out) {
+    LevelBuf& L = s->lev[l];
+    const Geom& g = L.g;
+    hipStream_t st = s->st;
+    T* eb = as<T>(L.eb);
+    T* ep = as<T>(L.ep);
+    T* rx = as<T>(L.rx);
+    T* ry = as<T>(L.ry);
+    const T om = (T)s->d.omega;
+    if (l == s->nlev - 1) {
+        TPH_HIP(launch_coarse_solve<T>(g, s->Minv, rx, ry, as<T>(L.ex[0]), as<T>(L.ey[0]), st));
+        *cur_out = 0;
+        return TPH_OK;
+    }
+    int cur = 0;
+    const bool jac = s->d.smoother == TPH_SMOOTH_JACOBI;
+    auto sweeps = [&](int nu, bool from_zero) -> tph_status {
+        for (int k = 0; k < nu; ++k) {
+            const bool z = from_zero && k == 0;
+            if (jac) {
+                const int out = z ? 0 : 1 - cur;
+                TPH_HIP(launch_jacobi<T>(g, z ? nullptr : as<T>(L.ex[cur]), z ? nullptr : as<T>(L.ey[cur]),
+                                         as<T>(L.ex[out]), as<T>(L.ey[out]), rx, ry, eb, ep, om, st));
+                cur = out;
+            } else {
+                T* ex = as<T>(L.ex[cur]);
+                T* ey = as<T>(L.ey[cur]);
+                TPH_HIP(launch_gs_half<T>(g, 0, 0, ex, ey, rx, ry, eb, ep, om, z, st));
+                TPH_HIP(launch_gs_half<T>(g, 0, 1, ex, ey, rx, ry, eb, ep, om, false, st));
+                TPH_HIP(launch_gs_half<T>(g, 1, 0, ex, ey, rx, ry, eb, ep, om, false, st));
+                TPH_HIP(launch_gs_half<T>(g, 1, 1, ex, ey, rx, ry, eb, ep, om, false, st));
+            }
+        }
+        return TPH_OK;
+    };
+    if (L.nu_pre == 0) {
+        TPH_HIP(launch_zero_vel<T>(g, as<T>(L.ex[0]), as<T>(L.ey[0]), st));
+        cur = 0;
+    } else {
+        TPH_TRY(sweeps(L.nu_pre, true));
+    }
+    TPH_HIP(launch_vel_residual<T>(g, as<T>(L.ex[cur]), as<T>(L.ey[cur]), rx, ry, eb, ep, as<T>(L.tx),
+                                   as<T>(L.ty), st));
+    LevelBuf& C = s->lev[l + 1];
+    TPH_HIP(launch_restrict_res<T>(g, C.g, as<T>(L.tx), as<T>(L.ty), as<T>(C.rx), as<T>(C.ry), st));
+    int ccur = 0;
+    TPH_TRY(vcycle<T>(s, l + 1, &ccur));
+    TPH_HIP(launch_prolong_add<T>(g, C.g, as<T>(C.ex[ccur]), as<T>(C.ey[ccur]), as<T>(L.ex[cur]), as<T>(L.ey[cur]),
+                                  st));
+    TPH_TRY(sweeps(L.nu_post, false));
+    *cur_out = cur;
+    return TPH_OK;
+}
+
+template <typename T>
+tph_status precondition_t(tph_solver* s, double* vraw, double* zraw, bool energy) {
+    LevelBuf& L = s->lev[0];
+    const Vec3 v = vec3(s, vraw), z = vec3(s, zraw);
+    TPH_HIP(launch_precond_in<T>(L.g, v, L.eb64, L.ep64, energy, as<T>(L.rx), as<T>(L.ry), s->st));
+    int cur = 0;
+    TPH_TRY(vcycle<T>(s, 0, &cur));
+    TPH_HIP(launch_precond_out<T>(L.g, as<T>(L.ex[cur]), as<T>(L.ey[cur]), v, L.ep64, energy, s->d.alpha, z, s->st));
+    return TPH_OK;
+}
+
+tph_status precondition(tph_solver* s, double* vraw, double* zraw, bool energy) {
+    return s->mixed() ? precondition_t<float>(s, vraw, zraw, energy) : precondition_t<double>(s, vraw, zraw, energy);
+}
+
+// reduce partial rows on the device and copy `k` results to the host mirror at slot
+tph_status reduce_to(tph_solver* s, int nblk, int k, int slot) {
+    TPH_HIP(launch_reduce_rows(s->partial, nblk, k, s->dscal + slot, s->st));
+    return TPH_OK;
+}
+
+tph_status fetch(tph_solver* s, int slot, int k) {
+    TPH_HIP(hipMemcpyAsync(s->hscal + slot, s->dscal + slot, k * sizeof(double), hipMemcpyDeviceToHost, s->st));
+    TPH_HIP(hipStreamSynchronize(s->st));
+    return TPH_OK;
+}
+
+// ||W^(1/2) (b - A x)||^2 into dscal[slot]; out receives the scaled residual
+tph_status energy_residual_vec(tph_solver* s, double* xraw, double* braw, double* outraw, int slot) {
+    const LevelBuf& L = s->lev[0];
+    int nblk = 0;
+    Vec3 b = vec3(s, braw);
+    TPH_HIP(launch_outer_residual(L.g, vec3(s, xraw), &b, L.eb64, L.ep64, vec3(s, outraw), ResMode::kResidual, true,
+                                  s->partial, &nblk, s->st));
+    return reduce_to(s, nblk, 1, slot);
+}
+
+tph_status copy_in(tph_solver* s, const Geom& g, double* base, const double* user) {
+    const size_t w = (size_t)(g.nx + 2) * sizeof(double);
+    TPH_HIP(hipMemcpy2DAsync(base, (size_t)g.pitch * sizeof(double), user, w, w, g.ny + 2, hipMemcpyDeviceToDevice,
+                             s->st));
+    return TPH_OK;
+}
+
+tph_status copy_out(tph_solver* s, const Geom& g, double* user, const double* base) {
+    const size_t w = (size_t)(g.nx + 2) * sizeof(double);
+    TPH_HIP(hipMemcpy2DAsync(user, w, base, (size_t)g.pitch * sizeof(double), w, g.ny + 2, hipMemcpyDeviceToDevice,
+                             s->st));
+    return TPH_OK;
+}
+
+tph_status load_solution(tph_solver* s, double* raw, const double* vx, const double* vy, const double* p) {
+    const Geom& g = s->lev[0].g;
+    Vec3 x = vec3(s, raw);
+    if (vx) TPH_TRY(copy_in(s, g, x.vx(), vx)); else TPH_HIP(hipMemsetAsync(raw, 0, s->F * sizeof(double), s->st));
+    if (vy) TPH_TRY(copy_in(s, g, x.vy(), vy)); else TPH_HIP(hipMemsetAsync(raw + s->F, 0, s->F * sizeof(double), s->st));
+    if (p) TPH_TRY(copy_in(s, g, x.p(), p)); else TPH_HIP(hipMemsetAsync(raw + 2 * s->F, 0, s->F * sizeof(double), s->st));
+    TPH_HIP(launch_fill_bc<double>(g, x.vx(), x.vy(), s->st));
+    return TPH_OK;
+}
+
+tph_status store_solution(tph_solver* s, const double* raw, double* vx, double* vy, double* p) {
+    const Geom& g = s->lev[0].g;
+    Vec3 x = vec3(s, (double*)raw);
+    if (vx) TPH_TRY(copy_out(s, g, vx, x.vx()));
+    if (vy) TPH_TRY(copy_out(s, g, vy, x.vy()));
+    if (p) TPH_TRY(copy_out(s, g, p, x.p()));
+    return TPH_OK;
+}
+
+// p -= mean(p) over the cells
+tph_status remove_pressure_mean(tph_solver* s, double* raw) {
+    const Geom& g = s->lev[0].g;
+    Vec3 x = vec3(s, raw);
+    int nblk = 0;
+    TPH_HIP(launch_p_sum(g, x.p(), s->partial, &nblk, s->st));
+    TPH_TRY(reduce_to(s, nblk, 1, kSlotMisc + 1));
+    TPH_HIP(launch_p_shift(g, x.p(), s->dscal + kSlotMisc + 1, s->st));
+    return TPH_OK;
+}
+
+// --------------------------------------------------------------- FGMRES
+tph_status fgmres(tph_solver* s, double* braw, tph_info* info) {
+    const int m = s->d.restart;
+    const size_t n3 = s->n3;
+    const int nblk_flat = flat_blocks(n3);
+    auto Vk = [&](int k) { return s->V + (size_t)k * n3; };
+    auto Zk = [&](int k) { return s->Z + (size_t)k * n3; };
+    const auto t0 = std::chrono::steady_clock::now();
+
+    // ||W^(1/2) b||: residual of x = 0
+    {
+        TPH_HIP(hipMemsetAsync(s->t2, 0, n3 * sizeof(double), s->st));
+        TPH_TRY(energy_residual_vec(s, s->t2, braw, s->t1, kSlotMisc));
+        TPH_TRY(fetch(s, kSlotMisc, 1));
+    }
+    const double bnorm = std::sqrt(s->hscal[kSlotMisc]);
+    if (!std::isfinite(bnorm)) { set_error("right-hand side is not finite"); return TPH_ERR_NONFINITE; }
+
+    int its = 0, restarts = 0;
+    double est = 0.0, true_res = 0.0;
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m);
+    tph_status result = TPH_NOT_CONVERGED;
+    while (true) {
+        // true residual r = W^(1/2) (b - A x) into V_0
+        TPH_TRY(energy_residual_vec(s, s->x, braw, Vk(0), kSlotMisc));
+        TPH_TRY(fetch(s, kSlotMisc, 1));
+        const double beta = std::sqrt(s->hscal[kSlotMisc]);
+        if (!std::isfinite(beta)) { set_error("non-finite residual during the solve"); return TPH_ERR_NONFINITE; }
+        true_res = bnorm > 0 ? beta / bnorm : beta;
+        if (bnorm == 0.0 || true_res <= s->d.rtol) { result = TPH_OK; break; }
+        if (its >= s->d.max_iters) break;
+        ++restarts;
+        TPH_HIP(launch_scale_by_rnorm(Vk(0), Vk(0), n3, s->dscal + kSlotMisc, s->st));
+        std::fill(gv.begin(), gv.end(), 0.0);
+        gv[0] = beta;
+        int jdone = 0;
+        for (int j = 0; j < m; ++j) {
+            TPH_TRY(precondition(s, Vk(j), Zk(j), true));
+            const LevelBuf& L = s->lev[0];
+            TPH_HIP(launch_outer_residual(L.g, vec3(s, Zk(j)), nullptr, L.eb64, L.ep64, vec3(s, Vk(j + 1)),
+                                          ResMode::kApply, true, nullptr, nullptr, s->st));
+            double* w = Vk(j + 1);
+            // classical Gram-Schmidt, twice
+            TPH_HIP(launch_multidot(Vk(0), n3, j + 1, w, n3, s->partial, nblk_flat, s->st));
+            TPH_TRY(reduce_to(s, nblk_flat, j + 1, kSlotH1));
+            TPH_HIP(launch_axpy_dot(w, Vk(0), n3, j + 1, s->dscal + kSlotH1, n3, true, -1, s->partial, nblk_flat,
+                                    s->st));
+            TPH_TRY(reduce_to(s, nblk_flat, j + 1, kSlotH2));
+            TPH_HIP(launch_axpy_dot(w, Vk(0), n3, j + 1, s->dscal + kSlotH2, n3, false, 0, s->partial, nblk_flat,
+                                    s->st));
+            TPH_TRY(reduce_to(s, nblk_flat, 1, kSlotNrm));
+            TPH_HIP(launch_scale_by_rnorm(w, w, n3, s->dscal + kSlotNrm, s->st));
+            TPH_HIP(hipMemcpyAsync(s->hscal, s->dscal, (size_t)(kSlotNrm + 1) * sizeof(double), hipMemcpyDeviceToHost,
+                                   s->st));
+            TPH_HIP(hipStreamSynchronize(s->st));
+            double* col = &H[(size_t)j * (m + 1)];
+            for (int i = 0; i <= j; ++i) col[i] = s->hscal[kSlotH1 + i] + s->hscal[kSlotH2 + i];
+            const double hn = std::sqrt(s->hscal[kSlotNrm]);
+            col[j + 1] = hn;
+            if (!std::isfinite(hn)) { set_error("non-finite value in the Krylov basis"); return TPH_ERR_NONFINITE; }
+            for (int i = 0; i < j; ++i) {
+                const double a = cs[i] * col[i] + sn[i] * col[i + 1];
+                col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+                col[i] = a;
+            }
+            const double rr = std::hypot(col[j], col[j + 1]);
+            cs[j] = rr > 0 ? col[j] / rr : 1.0;
+            sn[j] = rr > 0 ? col[j + 1] / rr : 0.0;
+            col[j] = rr;
+            col[j + 1] = 0.0;
+            gv[j + 1] = -sn[j] * gv[j];
+            gv[j] = cs[j] * gv[j];
+            est = std::fabs(gv[j + 1]) / bnorm;
+            if (info && info->history && its < info->history_len) info->history[its] = est;
+            ++its;
+            jdone = j + 1;
+            if (est <= s->d.rtol || its >= s->d.max_iters || hn == 0.0) break;
+        }
+        // y = R^{-1} g, x += Z y
+        for (int i = jdone - 1; i >= 0; --i) {
+            double t = gv[i];
+            for (int k = i + 1; k < jdone; ++k) t -= H[(size_t)k * (m + 1) + i] * y[k];
+            y[i] = t / H[(size_t)i * (m + 1) + i];
+        }
+        TPH_HIP(hipMemcpyAsync(s->dscal + kSlotY, y.data(), jdone * sizeof(double), hipMemcpyHostToDevice, s->st));
+        TPH_HIP(launch_update_x(s->x, s->Z, n3, jdone, s->dscal + kSlotY, n3, s->st));
+    }
+    TPH_TRY(remove_pressure_mean(s, s->x));
+    TPH_HIP(hipStreamSynchronize(s->st));
+    const auto t1 = std::chrono::steady_clock::now();
+    if (info) {
+        info->iters = its;
+        info->restarts = restarts;
+        info->res_energy = true_res;
+        info->res_estimate = its ? est : true_res;
+        info->t_setup_ms = s->t_setup_ms;
+        info->t_solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    }
+    if (result == TPH_NOT_CONVERGED)
+        set_error("FGMRES reached max_iters with relative energy residual " + std::to_string(true_res));
+    return result;
+}
+
+tph_status require_ready(tph_solver* s) {
+    if (!s) { set_error("solver is NULL"); return TPH_ERR_INVALID; }
+    if (!s->ready) { set_error("tph_set_coefficients has not succeeded on this solver"); return TPH_ERR_INVALID; }
+    return TPH_OK;
+}
+
+template <typename T>
+tph_status alloc_level_t(tph_solver* s, LevelBuf& L, bool share64) {
+    if (share64) {
+        L.eb = L.eb64;
+        L.ep = L.ep64;
+    } else {
+        TPH_TRY(alloc_field(s, L.g, sizeof(T), &L.eb));
+        TPH_TRY(alloc_field(s, L.g, sizeof(T), &L.ep));
+    }
+    for (int k = 0; k < 2; ++k) {
+        TPH_TRY(alloc_field(s, L.g, sizeof(T), &L.ex[k]));
+        TPH_TRY(alloc_field(s, L.g, sizeof(T), &L.ey[k]));
+    }
+    TPH_TRY(alloc_field(s, L.g, sizeof(T), &L.rx));
+    TPH_TRY(alloc_field(s, L.g, sizeof(T), &L.ry));
+    TPH_TRY(alloc_field(s, L.g, sizeof(T), &L.tx));
+    TPH_TRY(alloc_field(s, L.g, sizeof(T), &L.ty));
+    return TPH_OK;
+}
+
+tph_status create_impl(const tph_desc* desc, void* stream, tph_solver* s) {
+    int nlev = 0;
+    TPH_TRY(validate_desc(desc, &nlev));
+    s->d = *desc;
+    s->st = (hipStream_t)stream;
+    s->nlev = nlev;
+    for (int l = 0; l < nlev; ++l) {
+        Geom& g = s->lev[l].g;
+        g.nx = desc->nx >> l;
+        g.ny = desc->ny >> l;
+        g.pitch = pitch_for(g.nx);
+        g.dx = desc->lx / g.nx;
+        g.dy = desc->ly / g.ny;
+        for (int w = 0; w < 4; ++w) g.mir[w] = desc->bc[w] == TPH_FREE_SLIP ? 1.0f : -1.0f;
+        s->lev[l].nu_pre = level_sweeps(desc->nu_pre, desc->nu_growth, l);
+        s->lev[l].nu_post = level_sweeps(desc->nu_post, desc->nu_growth, l);
+        TPH_TRY(alloc_field(s, g, sizeof(double), (void**)&s->lev[l].eb64));
+        TPH_TRY(alloc_field(s, g, sizeof(double), (void**)&s->lev[l].ep64));
+        if (s->mixed()) TPH_TRY(alloc_level_t<float>(s, s->lev[l], false));
+        else TPH_TRY(alloc_level_t<double>(s, s->lev[l], true));
+    }
+    const Geom& g0 = s->lev[0].g;
+    s->F = field_alloc(g0);
+    s->n3 = 3 * s->F;
+    const size_t vb = s->n3 * sizeof(double);
+    TPH_TRY(dev_alloc(s, (void**)&s->x, vb));
+    TPH_TRY(dev_alloc(s, (void**)&s->b, vb));
+    TPH_TRY(dev_alloc(s, (void**)&s->b2, vb));
+    TPH_TRY(dev_alloc(s, (void**)&s->t1, vb));
+    TPH_TRY(dev_alloc(s, (void**)&s->t2, vb));
+    TPH_TRY(dev_alloc(s, (void**)&s->V, vb * (desc->restart + 1)));
+    TPH_TRY(dev_alloc(s, (void**)&s->Z, vb * desc->restart));
+    void* p = nullptr;
+    TPH_TRY(alloc_field(s, g0, sizeof(double), &p)); s->rho = (double*)p;
+    TPH_TRY(alloc_field(s, g0, sizeof(double), &p)); s->fxe = (double*)p;
+    TPH_TRY(alloc_field(s, g0, sizeof(double), &p)); s->fye = (double*)p;
+    for (int k = 0; k < 3; ++k) { TPH_TRY(alloc_field(s, g0, sizeof(double), &p)); s->gtmp[k] = (double*)p; }
+    const int nb_cells = (int)(((g0.nx + 2 + 63) / 64) * ((g0.ny + 2 + 3) / 4));
+    s->partial_len = (size_t)std::max(nb_cells * 2, (kMaxRestart + 2) * 2048);
+    TPH_TRY(dev_alloc(s, (void**)&s->partial, s->partial_len * sizeof(double)));
+    TPH_TRY(dev_alloc(s, (void**)&s->dscal, kScalars * sizeof(double)));
+    s->ncoarse = coarse_unknowns(s->lev[nlev - 1].g);
+    TPH_TRY(dev_alloc(s, (void**)&s->Minv, (size_t)s->ncoarse * s->ncoarse * sizeof(double)));
+    TPH_HIP(hipHostMalloc((void**)&s->hscal, kScalars * sizeof(double), hipHostMallocDefault));
+    TPH_HIP(hipEventCreate(&s->ev0));
+    TPH_HIP(hipEventCreate(&s->ev1));
+    TPH_HIP(hipStreamSynchronize(s->st));
+    return TPH_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+void tph_desc_default(tph_desc* d, int32_t nx, int32_t ny) {
+    if (!d) return;
+    std::memset(d, 0, sizeof(*d));
+    d->nx = nx;
+    d->ny = ny;
+    d->lx = 1.0;
+    d->ly = 1.0;
+    for (int w = 0; w < 4; ++w) d->bc[w] = TPH_FREE_SLIP;
+    d->precision = TPH_MIXED;
+    d->levels = 0;
+    d->smoother = TPH_SMOOTH_GS;
+    d->nu_pre = 2;
+    d->nu_post = 2;
+    d->nu_growth = 2.0;
+    d->omega = 1.0;
+    d->alpha = 1.0;
+    d->eta_mean = TPH_MEAN_ARITHMETIC;
+    d->rtol = 1e-8;
+    d->restart = 20;
+    d->max_iters = 500;
+}
+
+tph_status tph_create(const tph_desc* desc, void* hip_stream, tph_solver** out) {
+    g_last_error.clear();
+    if (!out) { set_error("out is NULL"); return TPH_ERR_INVALID; }
+    *out = nullptr;
+    int nlev = 0;
+    TPH_TRY(validate_desc(desc, &nlev));       // host-only checks before any HIP call
+    tph_solver* s = new tph_solver();
+    const tph_status st = create_impl(desc, hip_stream, s);
+    if (st != TPH_OK) {
+        const std::string msg = g_last_error;
+        tph_destroy(s);
+        g_last_error = msg;
+        return st;
+    }
+    *out = s;
+    return TPH_OK;
+}
+
+tph_status tph_set_coefficients(tph_solver* s, const double* eta_b, const double* eta_p, const double* rho_b,
+                                double gx, double gy, const double* fx_extra, const double* fy_extra) {
+    g_last_error.clear();
+    if (!s) { set_error("solver is NULL"); return TPH_ERR_INVALID; }
+    if (!eta_b || !eta_p || !rho_b) { set_error("eta_b, eta_p and rho_b are required"); return TPH_ERR_INVALID; }
+    if (!std::isfinite(gx) || !std::isfinite(gy)) { set_error("gravity must be finite"); return TPH_ERR_INVALID; }
+    s->ready = false;
+    const Geom& g0 = s->lev[0].g;
+    TPH_HIP(hipEventRecord(s->ev0, s->st));
+    TPH_TRY(copy_in(s, g0, s->lev[0].eb64, eta_b));
+    TPH_TRY(copy_in(s, g0, s->lev[0].ep64, eta_p));
+    TPH_TRY(copy_in(s, g0, s->rho, rho_b));
+    s->has_fx = fx_extra != nullptr;
+    s->has_fy = fy_extra != nullptr;
+    if (fx_extra) TPH_TRY(copy_in(s, g0, s->fxe, fx_extra));
+    if (fy_extra) TPH_TRY(copy_in(s, g0, s->fye, fy_extra));
+    int nblk = 0;
+    TPH_HIP(launch_check_coeffs(g0, s->lev[0].eb64, s->lev[0].ep64, s->rho, s->has_fx ? s->fxe : nullptr,
+                                s->has_fy ? s->fye : nullptr, s->partial, &nblk, s->st));
+    TPH_HIP(launch_reduce_rows(s->partial, nblk, 2, s->dscal + kSlotMisc + 2, s->st));
+    s->gx = gx;
+    s->gy = gy;
+    TPH_HIP(launch_rhs(g0, s->rho, gx, gy, s->has_fx ? s->fxe : nullptr, s->has_fy ? s->fye : nullptr,
+                       vec3(s, s->b), s->st));
+    for (int l = 1; l < s->nlev; ++l)
+        TPH_HIP(launch_restrict_eta(s->lev[l - 1].g, s->lev[l].g, s->lev[l - 1].eb64, s->lev[l - 1].ep64,
+                                    s->lev[l].eb64, s->lev[l].ep64, s->d.eta_mean == TPH_MEAN_GEOMETRIC, s->st));
+    if (s->mixed()) {
+        for (int l = 0; l < s->nlev; ++l) {
+            const size_t n = field_alloc(s->lev[l].g);
+            TPH_HIP(launch_cast_f64_f32(s->lev[l].eb64 - (kAlign - 1), (float*)s->lev[l].eb - (kAlign - 1), n, s->st));
+            TPH_HIP(launch_cast_f64_f32(s->lev[l].ep64 - (kAlign - 1), (float*)s->lev[l].ep - (kAlign - 1), n, s->st));
+        }
+    }
+    const LevelBuf& C = s->lev[s->nlev - 1];
+    TPH_HIP(launch_coarse_assemble(C.g, C.eb64, C.ep64, s->Minv, s->st));
+    TPH_HIP(launch_gauss_jordan(s->Minv, s->ncoarse, s->st));
+    TPH_HIP(hipEventRecord(s->ev1, s->st));
+    TPH_TRY(fetch(s, kSlotMisc + 2, 2));
+    float ms = 0.f;
+    TPH_HIP(hipEventElapsedTime(&ms, s->ev0, s->ev1));
+    s->t_setup_ms = ms;
+    if (s->hscal[kSlotMisc + 2] != 0.0) {
+        set_error("viscosity must be finite and positive (" + std::to_string((long long)s->hscal[kSlotMisc + 2]) +
+                  " bad entries)");
+        return TPH_ERR_INVALID;
+    }
+    if (s->hscal[kSlotMisc + 3] != 0.0) { set_error("density or extra force is not finite"); return TPH_ERR_NONFINITE; }
+    s->ready = true;
+    return TPH_OK;
+}
+
+tph_status tph_solve(tph_solver* s, double* vx, double* vy, double* p, tph_info* info) {
+    g_last_error.clear();
+    TPH_TRY(require_ready(s));
+    if (!vx || !vy || !p) { set_error("vx, vy and p are required"); return TPH_ERR_INVALID; }
+    TPH_TRY(load_solution(s, s->x, vx, vy, p));
+    const tph_status r = fgmres(s, s->b, info);
+    if (r < 0) return r;
+    TPH_TRY(store_solution(s, s->x, vx, vy, p));
+    TPH_HIP(hipStreamSynchronize(s->st));
+    return r;
+}
+
+tph_status tph_solve_rhs(tph_solver* s, const double* fx, const double* fy, const double* fp, double* vx, double* vy,
+                         double* p, tph_info* info) {
+    g_last_error.clear();
+    TPH_TRY(require_ready(s));
+    if (!vx || !vy || !p) { set_error("vx, vy and p are required"); return TPH_ERR_INVALID; }
+    TPH_TRY(load_solution(s, s->b2, fx, fy, fp));
+    TPH_TRY(load_solution(s, s->x, vx, vy, p));
+    const tph_status r = fgmres(s, s->b2, info);
+    if (r < 0) return r;
+    TPH_TRY(store_solution(s, s->x, vx, vy, p));
+    TPH_HIP(hipStreamSynchronize(s->st));
+    return r;
+}
+
+tph_status tph_apply(tph_solver* s, const double* vx, const double* vy, const double* p, double* ax, double* ay,
+                     double* ap) {
+    g_last_error.clear();
+    TPH_TRY(require_ready(s));
+    if (!vx || !vy || !p || !ax || !ay || !ap) { set_error("all six arrays are required"); return TPH_ERR_INVALID; }
+    TPH_TRY(load_solution(s, s->t2, vx, vy, p));
+    const LevelBuf& L = s->lev[0];
+    TPH_HIP(launch_outer_residual(L.g, vec3(s, s->t2), nullptr, L.eb64, L.ep64, vec3(s, s->t1), ResMode::kApply,
+                                  false, nullptr, nullptr, s->st));
+    TPH_TRY(store_solution(s, s->t1, ax, ay, ap));
+    TPH_HIP(hipStreamSynchronize(s->st));
+    return TPH_OK;
+}
+
+tph_status tph_precondition(tph_solver* s, const double* rx, const double* ry, const double* rp, double* zx,
+                            double* zy, double* zp) {
+    g_last_error.clear();
+    TPH_TRY(require_ready(s));
+    if (!rx || !ry || !rp || !zx || !zy || !zp) { set_error("all six arrays are required"); return TPH_ERR_INVALID; }
+    const Geom& g = s->lev[0].g;
+    Vec3 r = vec3(s, s->t2);
+    TPH_TRY(copy_in(s, g, r.vx(), rx));
+    TPH_TRY(copy_in(s, g, r.vy(), ry));
+    TPH_TRY(copy_in(s, g, r.p(), rp));
+    TPH_HIP(hipMemsetAsync(s->t1, 0, s->n3 * sizeof(double), s->st));
+    TPH_TRY(precondition(s, s->t2, s->t1, false));
+    TPH_TRY(store_solution(s, s->t1, zx, zy, zp));
+    TPH_HIP(hipStreamSynchronize(s->st));
+    return TPH_OK;
+}
+
+tph_status tph_energy_residual(tph_solver* s, const double* vx, const double* vy, const double* p, double* out) {
+    g_last_error.clear();
+    TPH_TRY(require_ready(s));
+    if (!vx || !vy || !p || !out) { set_error("vx, vy, p and out are required"); return TPH_ERR_INVALID; }
+    TPH_TRY(load_solution(s, s->t2, vx, vy, p));
+    TPH_TRY(energy_residual_vec(s, s->t2, s->b, s->t1, kSlotMisc));
+    TPH_HIP(hipMemsetAsync(s->t2, 0, s->n3 * sizeof(double), s->st));
+    TPH_TRY(energy_residual_vec(s, s->t2, s->b, s->t1, kSlotMisc + 1));
+    TPH_TRY(fetch(s, kSlotMisc, 2));
+    const double num = s->hscal[kSlotMisc], den = s->hscal[kSlotMisc + 1];
+    *out = den > 0 ? std::sqrt(num / den) : std::sqrt(num);
+    return TPH_OK;
+}
+
+tph_status tph_level_shape(tph_solver* s, int32_t level, int32_t* nx, int32_t* ny) {
+    g_last_error.clear();
+    if (!s) { set_error("solver is NULL"); return TPH_ERR_INVALID; }
+    if (level < 0 || level >= s->nlev) { set_error("level out of range"); return TPH_ERR_INVALID; }
+    if (nx) *nx = s->lev[level].g.nx;
+    if (ny) *ny = s->lev[level].g.ny;
+    return TPH_OK;
+}
+
+tph_status tph_level_viscosity(tph_solver* s, int32_t level, double* eta_b, double* eta_p) {
+    g_last_error.clear();
+    TPH_TRY(require_ready(s));
+    if (level < 0 || level >= s->nlev) { set_error("level out of range"); return TPH_ERR_INVALID; }
+    const LevelBuf& L = s->lev[level];
+    if (eta_b) TPH_TRY(copy_out(s, L.g, eta_b, L.eb64));
+    if (eta_p) TPH_TRY(copy_out(s, L.g, eta_p, L.ep64));
+    TPH_HIP(hipStreamSynchronize(s->st));
+    return TPH_OK;
+}
+
+tph_status tph_solve_adjoint(tph_solver* s, const double* gvx, const double* gvy, const double* gp, double* lvx,
+                             double* lvy, double* lp, tph_info* info) {
+    g_last_error.clear();
+    TPH_TRY(require_ready(s));
+    if (!lvx || !lvy || !lp) { set_error("lvx, lvy and lp are required"); return TPH_ERR_INVALID; }
+    // A is symmetric: the adjoint solve is the forward solve with right-hand side g
+    TPH_HIP(hipMemsetAsync(s->b2, 0, s->n3 * sizeof(double), s->st));
+    const Geom& g = s->lev[0].g;
+    Vec3 r = vec3(s, s->b2);
+    if (gvx) TPH_TRY(copy_in(s, g, r.vx(), gvx));
+    if (gvy) TPH_TRY(copy_in(s, g, r.vy(), gvy));
+    if (gp) TPH_TRY(copy_in(s, g, r.p(), gp));
+    // the output pressure of a solve is mean-free and ghosts mirror their owners:
+    // project the incoming gradient accordingly (this also makes the system consistent)
+    TPH_HIP(launch_fold_ghost_grad(g, r, s->st));
+    TPH_TRY(remove_pressure_mean(s, s->b2));
+    TPH_HIP(hipMemsetAsync(s->x, 0, s->n3 * sizeof(double), s->st));
+    const tph_status st = fgmres(s, s->b2, info);
+    if (st < 0) return st;
+    TPH_TRY(store_solution(s, s->x, lvx, lvy, lp));
+    TPH_HIP(hipStreamSynchronize(s->st));
+    return st;
+}
+
+tph_status tph_coeff_gradient(tph_solver* s, const double* vx, const double* vy, const double* p, const double* lvx,
+                              const double* lvy, const double* lp, double* g_eta_b, double* g_eta_p, double* g_rho_b) {
+    g_last_error.clear();
+    TPH_TRY(require_ready(s));
+    if (!vx || !vy || !lvx || !lvy) { set_error("forward and adjoint velocities are required"); return TPH_ERR_INVALID; }
+    const Geom& g = s->lev[0].g;
+    TPH_TRY(load_solution(s, s->t1, vx, vy, p));
+    TPH_TRY(load_solution(s, s->t2, lvx, lvy, lp));
+    for (int k = 0; k < 3; ++k)
+        TPH_HIP(hipMemsetAsync(s->gtmp[k] - (kAlign - 1), 0, field_alloc(g) * sizeof(double), s->st));
+    TPH_HIP(launch_coeff_gradient(g, vec3(s, s->t1), vec3(s, s->t2), s->gx, s->gy, g_eta_b ? s->gtmp[0] : nullptr,
+                                  g_eta_p ? s->gtmp[1] : nullptr, g_rho_b ? s->gtmp[2] : nullptr, s->st));
+    if (g_eta_b) TPH_TRY(copy_out(s, g, g_eta_b, s->gtmp[0]));
+    if (g_eta_p) TPH_TRY(copy_out(s, g, g_eta_p, s->gtmp[1]));
+    if (g_rho_b) TPH_TRY(copy_out(s, g, g_rho_b, s->gtmp[2]));
+    TPH_HIP(hipStreamSynchronize(s->st));
+    return TPH_OK;
+}
+
+void tph_destroy(tph_solver* s) {
+    if (!s) return;
+    if (s->st || !s->dev_allocs.empty()) (void)hipStreamSynchronize(s->st);
+    for (void* p : s->dev_allocs) (void)hipFree(p);
+    if (s->hscal) (void)hipHostFree(s->hscal);
+    if (s->ev0) (void)hipEventDestroy(s->ev0);
+    if (s->ev1) (void)hipEventDestroy(s->ev1);
+    delete s;
+}
+
+const char* tph_last_error(void) { return g_last_error.c_str(); }
+
+const char* tph_version(void) { return "tephra 0.1.0 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,70 @@
+"""The C ABI library loads and exports every function of include/tephra.h;
+descriptor validation happens on the host before any HIP call (no GPU needed)."""
+import ctypes
+import os
+
+import pytest
+
+from paper_2603_14040_amd import _lib
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libtephra.so is not built (run __graft_entry__.build())")
+    return _lib.load()
+
+
+def test_exports_every_declared_function(lib):
+    names = _lib.header_functions()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert missing == []
+
+
+def test_struct_layout_matches_header(lib):
+    # tph_desc: offsets follow the C layout (doubles 8-aligned)
+    assert _lib.Desc.lx.offset == 8 and _lib.Desc.bc.offset == 24
+    assert _lib.Desc.nu_growth.offset == 64 and _lib.Desc.rtol.offset == 96
+    assert ctypes.sizeof(_lib.Desc) == 144
+    d = _lib.Desc()
+    lib.tph_desc_default(ctypes.byref(d), 64, 32)
+    assert (d.nx, d.ny, d.lx, d.precision, d.restart) == (64, 32, 1.0, _lib.MIXED, 20)
+    assert d.rtol == 1e-8 and d.nu_growth == 2.0
+
+
+def _create(lib, **kw):
+    d = _lib.Desc()
+    lib.tph_desc_default(ctypes.byref(d), kw.pop("nx", 64), kw.pop("ny", 64))
+    for k, v in kw.items():
+        setattr(d, k, v)
+    h = ctypes.c_void_p()
+    st = lib.tph_create(ctypes.byref(d), None, ctypes.byref(h))
+    return st, h, lib.tph_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(nx=1), "nx and ny"),
+    (dict(precision=7), "precision"),
+    (dict(levels=6, nx=48, ny=48), "divisible"),
+    (dict(levels=1, nx=128, ny=128), "coarsest level too large"),
+    (dict(restart=0), "restart"),
+    (dict(restart=65), "restart"),
+    (dict(omega=0.0), "omega"),
+    (dict(rtol=0.0), "rtol"),
+    (dict(nu_growth=0.5), "nu_growth"),
+    (dict(lx=-1.0), "lx and ly"),
+])
+def test_invalid_descriptor_rejected_on_host(lib, kw, needle):
+    st, h, msg = _create(lib, **kw)
+    assert st == -1 and not h.value
+    assert needle in msg
+
+
+def test_null_arguments_rejected(lib):
+    assert lib.tph_create(None, None, None) == -1
+    assert lib.tph_set_coefficients(None, None, None, None, 0.0, -1.0, None, None) == -1
+    assert "NULL" in lib.tph_last_error().decode()
+    assert lib.tph_solve(None, None, None, None, None) == -1
+    lib.tph_destroy(None)
+    assert lib.tph_version().decode().startswith("tephra")
