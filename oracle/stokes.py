@@ -32,7 +32,8 @@ Readings adopted where the text is silent or inconsistent
   pressure decrease along gravity, which contradicts the lithostatic
   initial guess of Ch. 4 "Viscosity Rescaling and Initial Guess".
 * Pressure is unique up to a constant (Ch. 4 "Pressure Nullspace
-  Elimination"); the oracle borders the matrix with the zero-mean constraint.
+  Elimination"); the oracle fixes one cell's pressure, which that section
+  states is equivalent to the zero-mean condition, then removes the mean.
 
 Index convention: arrays are (ny+2) x (nx+2); vx unknowns i in [1, ny],
 j in [1, nx-1]; vy unknowns i in [1, ny-1], j in [1, nx]; p unknowns
@@ -273,18 +274,30 @@ def bordered(g: Grid, A: sp.spmatrix) -> sp.csr_matrix:
 
 
 def solve_system(g: Grid, A: sp.spmatrix, b: np.ndarray):
-    """Direct solve (SuperLU, one refinement step) of A x = b with sum(p) = 0.
+    """Direct solve (SuperLU, one refinement step) of A x = b, zero-mean p.
 
-    Returns (x, multiplier of the zero-mean constraint)."""
-    K = bordered(g, A)
-    lu = spla.splu(K.tocsc())
-    rhs_b = np.concatenate([b, [0.0]])
-    sol = lu.solve(rhs_b)
+    The constant-pressure null space is removed by fixing the pressure of the
+    last cell at zero (Ch. 4 "Pressure Nullspace Elimination": fixing one
+    node is equivalent to the zero-mean condition), which drops that cell's
+    continuity row and pressure column; the mean is subtracted afterwards.
+    For a consistent right-hand side (pressure rows summing to zero, as for
+    every body-force problem) the dropped row is implied by the others.
+    Returns (x, residual of the dropped row).
+    """
+    nv = g.n_vx + g.n_vy
+    keep = np.arange(g.n - 1)
+    Ar = A[keep][:, keep].tocsc()
+    lu = spla.splu(Ar)
+    br = b[keep]
+    xr = lu.solve(br)
     # one step of iterative refinement with the same factors: partial
     # pivoting on the indefinite saddle-point matrix leaves a residual well
     # above the rounding floor, one correction removes it
-    sol = sol + lu.solve(rhs_b - K @ sol)
-    return sol[:-1], sol[-1]
+    xr = xr + lu.solve(br - Ar @ xr)
+    x = np.concatenate([xr, [0.0]])
+    dropped = float(b[-1] - A.getrow(g.n - 1).dot(x)[0])
+    x[nv:] -= x[nv:].mean()
+    return x, dropped
 
 
 @dataclass
@@ -293,7 +306,7 @@ class Solution:
     vy: np.ndarray
     p: np.ndarray
     x: np.ndarray
-    multiplier: float
+    dropped_residual: float
     residual_energy: float
 
 

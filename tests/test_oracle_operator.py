@@ -163,7 +163,7 @@ def test_hydrostatic_closed_form(g_vec, bc):
     assert np.abs(sol.vx).max() < 1e-12 * scale
     assert np.abs(sol.vy).max() < 1e-12 * scale
     assert np.abs(sol.p[1:ny + 1, 1:nx + 1] - pex).max() < 1e-12 * scale
-    assert abs(sol.multiplier) < 1e-12
+    assert abs(sol.dropped_residual) < 1e-12 * scale
 
 
 def _mms_fields():
