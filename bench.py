@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Throughput of the MI355X Stokes solver on its headline workload.
+
+One step = the whole hot path over one problem: coefficient setup
+(viscosity restriction down the hierarchy, right-hand side, FP64 coarsest
+factorisation) plus one solve from a zero initial guess to a relative energy
+residual of 1e-8 (FGMRES + V-cycle/Uzawa preconditioner).  Workload: the
+random-viscosity problem on a 1024 x 1024-cell grid (log10 viscosity a
+Gaussian random field, correlation length 0.05, contrast 1e4; density
+1 - 0.01 log10(eta) + N(0, 0.01); free slip; g = (0, -1)).  Inputs are
+synthetic, seeded, and resident in HBM before timing starts.
+
+`value` is the mixed-precision throughput (FP32 V-cycle, FP64 outer Krylov,
+residual, refinement and coarsest solve) in cells per second; the plain FP64
+solve is timed beside it (`fp64`).  The roofline entry describes the dominant
+kernel, the finest-level smoother, timed with HIP events on the solver's own
+stream.  The CPU baseline is the FP64 oracle (assembled matrix + SuperLU) on
+a bounded sample of the same recipe.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+METRIC = "Stokes solve cells/s to 1e-8 rel. residual + HBM GB/s; mixed vs FP64 on 1 GPU"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1024, help="cells per side")
+    ap.add_argument("--fp64-steps", type=int, default=None, help="timed FP64 steps (default: --steps)")
+    ap.add_argument("--kernel-reps", type=int, default=200)
+    ap.add_argument("--cpu-n", type=int, default=256, help="oracle sample size (cells per side)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs (--gpus > 1) are not "
+                                   "supported (see DESIGN.md for how the solve would shard)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import paper_2603_14040_amd as tph
+    import workloads as wl
+
+    if not torch.cuda.is_available():
+        log("bench.py needs a GPU")
+        sys.exit(1)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    n = args.n
+    cells = n * n
+    log(f"[bench] building the random-viscosity workload {n}x{n}")
+    pr = wl.random_viscosity(n)
+    to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    eb, ep, rho = to(pr.eta_b), to(pr.eta_p), to(pr.rho_b)
+
+    def run(precision, steps, warmup, tag):
+        s = tph.Solver(n, n, precision=precision, device=dev)
+        vx, vy, p = s.zeros(), s.zeros(), s.zeros()
+
+        def step():
+            vx.zero_(); vy.zero_(); p.zero_()
+            s.set_coefficients(eb, ep, rho, pr.gx, pr.gy)
+            return s.solve(vx, vy, p)[3]
+
+        for _ in range(warmup):
+            info = step()
+        torch.cuda.synchronize()
+        infos = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            infos.append(step())
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        for inf in infos:
+            if inf.status != "TPH_OK":
+                raise RuntimeError(f"{tag} solve did not converge: {inf}")
+        ms = 1e3 * dt / steps
+        log(f"[bench] {tag}: {ms:.2f} ms/step, iters {infos[-1].iters}, res {infos[-1].res_energy:.2e}, "
+            f"setup {infos[-1].t_setup_ms:.2f} ms, solve {infos[-1].t_solve_ms:.2f} ms")
+        return s, ms, infos
+
+    s_mix, ms_mix, inf_mix = run(tph.MIXED, args.steps, args.warmup, "mixed")
+    s64, ms_64, inf_64 = run(tph.FP64, args.fp64_steps or args.steps, 1, "fp64")
+
+    # dominant kernel: finest-level smoother of the mixed path, HIP events on the solver stream
+    kern = {}
+    names = {tph._lib.KERNEL_SMOOTH: "smooth_l0", tph._lib.KERNEL_APPLY: "apply_fp64",
+             tph._lib.KERNEL_RESIDUAL: "residual_l0", tph._lib.KERNEL_RESTRICT: "restrict_l0",
+             tph._lib.KERNEL_PROLONG: "prolong_l0"}
+    for kind, name in names.items():
+        ms, by = s_mix.time_kernel(kind, args.kernel_reps)
+        kern[name] = {"us": round(ms * 1e3, 3), "bytes": by, "GBps": round(by / (ms * 1e-3) / 1e9, 1)}
+    dom = kern["smooth_l0"]
+    achieved = dom["bytes"] / (dom["us"] * 1e-6) / 1e9
+
+    # device-to-device copy bandwidth in the same run (context for the roofline)
+    buf = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(buf)
+    dst.copy_(buf)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        dst.copy_(buf)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * buf.numel() * 4 * 20 / (time.perf_counter() - t0) / 1e9
+    del buf, dst
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import stokes as ost
+        m = args.cpu_n
+        log(f"[bench] CPU oracle on the {m}x{m} sample")
+        sp_ = wl.random_viscosity(m)
+        g = ost.Grid(m, m)
+        t0 = time.perf_counter()
+        sol = ost.solve(g, sp_.eta_b, sp_.eta_p, sp_.rho_b, sp_.gx, sp_.gy)
+        dt = time.perf_counter() - t0
+        cpu = {"value": m * m / dt, "unit": "cells/s", "cores": 1, "kind": "oracle",
+               "sample": f"random-viscosity recipe at {m}x{m} cells (same correlation length 0.05 and "
+                         f"contrast 1e4), one FP64 assembled-matrix SuperLU solve ({dt:.1f} s, energy "
+                         f"residual {sol.residual_energy:.1e}); SuperLU is single-threaded",
+               "seconds": round(dt, 2)}
+
+    out = {
+        "metric": METRIC,
+        "value": cells / (ms_mix * 1e-3),
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_mix,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 V-cycle + f64 Krylov/residual (mixed)",
+        "data": "synthetic",
+        "config": {"workload": f"random-viscosity {n}x{n} cells, log10 eta Gaussian random field "
+                               f"(corr. length 0.05, contrast 1e4), free slip, FGMRES(20) + "
+                               f"{s_mix.levels}-level V-cycle, relative energy residual 1e-8",
+                   "cells": cells, "levels": s_mix.levels, "precision": "mixed", "global_batch": 1},
+        "iters": inf_mix[-1].iters,
+        "res_energy": inf_mix[-1].res_energy,
+        "setup_ms": inf_mix[-1].t_setup_ms,
+        "solve_ms": inf_mix[-1].t_solve_ms,
+        "fp64": {"value": cells / (ms_64 * 1e-3), "ms_per_step": ms_64, "iters": inf_64[-1].iters,
+                 "res_energy": inf_64[-1].res_energy},
+        "mixed_speedup_vs_fp64": ms_64 / ms_mix,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "finest-level smoother launch (Gauss-Seidel colour half-sweep, FP32)",
+                     "algorithmic_bytes_per_launch": dom["bytes"], "us_per_launch": dom["us"]},
+        "kernels": kern,
+        "copy_GBps": round(copy_gbs, 1),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

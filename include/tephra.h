@@ -102,7 +102,13 @@ typedef struct tph_desc {
     double rtol;           /* relative energy residual target                 */
     int32_t restart;       /* FGMRES restart length m (1..64)                 */
     int32_t max_iters;     /* total FGMRES iterations                         */
-    int32_t reserved[8];   /* must be zero                                    */
+    int32_t uzawa_steps;   /* Uzawa sweeps per preconditioner application (1..8):
+                              z <- z + M^{-1}(r - A z), the fixed-point map of the
+                              splitting A = M - N applied this many times         */
+    int32_t fused;         /* 1: LDS-tiled fused smoother / residual-restriction
+                              kernels and the single-workgroup coarse tail;
+                              0: one kernel per colour half-sweep (reference)    */
+    int32_t reserved[6];   /* must be zero                                    */
 } tph_desc;
 
 typedef struct tph_info {
@@ -120,8 +126,9 @@ typedef struct tph_solver tph_solver;
 
 /* Fill *d with the defaults for an nx x ny unit-square free-slip problem:
  * mixed precision, automatic levels, coloured Gauss-Seidel (omega 1) with 2
- * sweeps doubling per level, alpha 1, arithmetic coarse viscosity,
- * rtol 1e-8, restart 20, max_iters 500. */
+ * pre- and 2 post-sweeps on every level, alpha 1, arithmetic coarse
+ * viscosity, two Uzawa sweeps per preconditioner application, fused
+ * kernels, rtol 1e-8, restart 20, max_iters 500. */
 void tph_desc_default(tph_desc* d, int32_t nx, int32_t ny);
 
 /* Create a solver for the grid in *desc; hip_stream is a hipStream_t (NULL:
@@ -158,11 +165,13 @@ tph_status tph_solve_rhs(tph_solver* s, const double* fx, const double* fy, cons
 tph_status tph_apply(tph_solver* s, const double* vx, const double* vy, const double* p,
                      double* ax, double* ay, double* ap);
 
-/* One application of the Uzawa preconditioner M^{-1} (Sec. "Uzawa Iteration
- * as a Fixed Point Method", M = [[L, 0], [D, (alpha eta_p)^{-1}]]): z_v = one
- * V-cycle on L r_v = z_v from zero, in the solver's precision; z_p =
- * alpha eta_p (r_p - D z_v).  With levels = 1 the V-cycle is the exact FP64
- * solve.  Inputs are residual-type arrays, outputs solution-type arrays. */
+/* One application of the Uzawa preconditioner (Sec. "Uzawa Iteration as a
+ * Fixed Point Method", M = [[L, 0], [D, (alpha eta_p)^{-1}]]): starting from
+ * z = 0, desc.uzawa_steps times z <- z + M^{-1}(r - A z), where one M^{-1}
+ * application is z_v = one V-cycle on L z_v = r_v from zero (in the solver's
+ * precision) and z_p = alpha eta_p (r_p - D z_v).  With levels = 1 and one
+ * step this is the exact block-triangular solve.  Inputs are residual-type
+ * arrays, outputs solution-type arrays. */
 tph_status tph_precondition(tph_solver* s, const double* rx, const double* ry, const double* rp,
                             double* zx, double* zy, double* zp);
 
@@ -193,6 +202,24 @@ tph_status tph_solve_adjoint(tph_solver* s, const double* gvx, const double* gvy
 tph_status tph_coeff_gradient(tph_solver* s, const double* vx, const double* vy, const double* p,
                               const double* lvx, const double* lvy, const double* lp,
                               double* g_eta_b, double* g_eta_p, double* g_rho_b);
+
+/* Kernels that tph_time_kernel can time. */
+enum {
+    TPH_KERNEL_SMOOTH = 0,   /* one finest-level smoother launch (Jacobi sweep or one GS colour half-sweep) */
+    TPH_KERNEL_APPLY = 1,    /* FP64 matrix-free operator apply with energy scaling (Krylov step) */
+    TPH_KERNEL_RESIDUAL = 2, /* finest-level velocity residual r - L e in the V-cycle type */
+    TPH_KERNEL_RESTRICT = 3, /* finest -> second level residual restriction */
+    TPH_KERNEL_PROLONG = 4   /* second -> finest level prolongation and correction */
+};
+
+/* Measurement hook: run `reps` back-to-back launches of one hot-path kernel
+ * on the solver's stream between two HIP events and return the mean
+ * duration per launch (*ms_per_launch) and the algorithmic bytes one launch
+ * must move (*bytes_per_launch: each field word the operation reads or
+ * writes, counted once).  Requires tph_set_coefficients; the kernels operate
+ * on the solver's own workspace (the correction arrays are modified). */
+tph_status tph_time_kernel(tph_solver* s, int32_t kind, int32_t reps, double* ms_per_launch,
+                           double* bytes_per_launch);
 
 /* Release everything the solver owns.  NULL is allowed. */
 void tph_destroy(tph_solver* s);

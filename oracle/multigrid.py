@@ -38,6 +38,17 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from .stokes import Grid, assemble, index_maps, fill_ghosts, S, N, W, E
+from .stokes import to_vector as st_to_vector, to_arrays as st_to_arrays_sol
+
+
+def st_to_arrays_res(g: Grid, x: np.ndarray):
+    """Residual-type arrays (zero outside the equation rows) from a vector."""
+    shp = (g.ny + 2, g.nx + 2)
+    ax, ay, ap = np.zeros(shp), np.zeros(shp), np.zeros(shp)
+    ax[1:g.ny + 1, 1:g.nx] = x[:g.n_vx].reshape(g.ny, g.nx - 1)
+    ay[1:g.ny, 1:g.nx + 1] = x[g.n_vx:g.n_vx + g.n_vy].reshape(g.ny - 1, g.nx)
+    ap[1:g.ny + 1, 1:g.nx + 1] = x[g.n_vx + g.n_vy:].reshape(g.ny, g.nx)
+    return ax, ay, ap
 
 # ---------------------------------------------------------------------------
 # node coordinates of the four staggered grids (1D, separable)
@@ -257,6 +268,20 @@ def precondition(levs: List[Level], prm: MGParams, rx, ry, rp):
     sl = (slice(1, g.ny + 1), slice(1, g.nx + 1))
     zp[sl] = prm.alpha * levs[0].eta_p[sl] * (rp[sl] - dz[sl])
     return zx, zy, zp
+
+
+def uzawa_preconditioner(levs: List[Level], prm: MGParams, A, rx, ry, rp, steps: int):
+    """`steps` sweeps of the Uzawa fixed-point iteration x <- x + M^{-1}(b - A x)
+    from x = 0 (Sec. "Uzawa Iteration as a Fixed Point Method", preconditioned
+    Richardson form), with b = (r_v, r_p)."""
+    g = levs[0].g
+    r = st_to_vector(g, rx, ry, rp)
+    z = np.zeros_like(r)
+    for _ in range(steps):
+        tx, ty, tp = st_to_arrays_res(g, r - A @ z)
+        dx_, dy_, dp_ = precondition(levs, prm, tx, ty, tp)
+        z = z + st_to_vector(g, dx_, dy_, dp_)
+    return st_to_arrays_sol(g, z)
 
 
 def default_schedule(levels: int, nu: int = 2, growth: float = 1.0):

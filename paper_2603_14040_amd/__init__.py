@@ -56,9 +56,10 @@ class Solver:
     def __init__(self, nx: int, ny: int, lx: float = 1.0, ly: float = 1.0,
                  bc: Sequence[int] = (FREE_SLIP,) * 4, precision: int = MIXED,
                  levels: int = 0, smoother: int = SMOOTH_GS, nu_pre: int = 2, nu_post: int = 2,
-                 nu_growth: float = 2.0, omega: float = 1.0, alpha: float = 1.0,
+                 nu_growth: float = 1.0, omega: float = 1.0, alpha: float = 1.0,
                  eta_mean: int = MEAN_ARITHMETIC, rtol: float = 1e-8, restart: int = 20,
-                 max_iters: int = 500, device: Optional[torch.device] = None,
+                 max_iters: int = 500, uzawa_steps: int = 2, fused: bool = True,
+                 device: Optional[torch.device] = None,
                  stream: Optional[torch.cuda.Stream] = None):
         lib = _lib.load()
         d = _lib.Desc()
@@ -75,6 +76,8 @@ class Solver:
         d.eta_mean = int(eta_mean)
         d.rtol = float(rtol)
         d.restart, d.max_iters = int(restart), int(max_iters)
+        d.uzawa_steps = int(uzawa_steps)
+        d.fused = 1 if fused else 0
         self.desc = d
         self.nx, self.ny = nx, ny
         self.shape = (ny + 2, nx + 2)
@@ -212,6 +215,14 @@ class Solver:
                                          ctypes.byref(info))
         _lib.check("tph_solve_adjoint", st, allow_not_converged=True)
         return lx, ly, lp, self._info(info, st, [])
+
+    def time_kernel(self, kind: int, reps: int = 50):
+        """(ms per launch, algorithmic bytes per launch) of one hot-path kernel."""
+        ms, by = ctypes.c_double(), ctypes.c_double()
+        self._sync_in()
+        _lib.check("tph_time_kernel", self._lib.tph_time_kernel(self._h, int(kind), int(reps), ctypes.byref(ms),
+                                                                ctypes.byref(by)))
+        return ms.value, by.value
 
     def coeff_gradient(self, vx, vy, p, lvx, lvy, lp):
         gb, gp, gr = self.zeros(), self.zeros(), self.zeros()

@@ -21,6 +21,7 @@ FREE_SLIP, NO_SLIP = 0, 1
 FP64, MIXED = 0, 1
 SMOOTH_JACOBI, SMOOTH_GS = 0, 1
 MEAN_ARITHMETIC, MEAN_GEOMETRIC = 0, 1
+KERNEL_SMOOTH, KERNEL_APPLY, KERNEL_RESIDUAL, KERNEL_RESTRICT, KERNEL_PROLONG = 0, 1, 2, 3, 4
 
 
 class Desc(ctypes.Structure):
@@ -29,7 +30,8 @@ class Desc(ctypes.Structure):
                 ("smoother", c_int32), ("nu_pre", c_int32), ("nu_post", c_int32),
                 ("nu_growth", c_double), ("omega", c_double), ("alpha", c_double),
                 ("eta_mean", c_int32), ("rtol", c_double), ("restart", c_int32),
-                ("max_iters", c_int32), ("reserved", c_int32 * 8)]
+                ("max_iters", c_int32), ("uzawa_steps", c_int32), ("fused", c_int32),
+                ("reserved", c_int32 * 6)]
 
 
 class Info(ctypes.Structure):
@@ -78,6 +80,7 @@ def load(path: str = LIB_PATH):
         "tph_level_shape": (c_int32, [P, c_int32, POINTER(c_int32), POINTER(c_int32)]),
         "tph_solve_adjoint": (c_int32, [P, P, P, P, P, P, P, POINTER(Info)]),
         "tph_coeff_gradient": (c_int32, [P, P, P, P, P, P, P, P, P, P]),
+        "tph_time_kernel": (c_int32, [P, c_int32, c_int32, POINTER(c_double), POINTER(c_double)]),
         "tph_destroy": (None, [P]),
         "tph_last_error": (c_char_p, []),
         "tph_version": (c_char_p, []),

@@ -10,9 +10,10 @@ namespace tph {
 // scale = sqrt(energy weight) when `energy` is set, else 1.  Writes equation
 // rows only.  partial (nullable): per-block sums of out^2, nblk entries.
 enum class ResMode { kResidual = 0, kApply = 1 };
+// b_scaled: b holds W^(1/2) b (an energy-scaled Krylov vector) and is unscaled on the fly
 hipError_t launch_outer_residual(const Geom& g, Vec3 x, const Vec3* b, const double* eb, const double* ep,
                                  Vec3 out, ResMode mode, bool energy, double* partial, int* nblk_out,
-                                 hipStream_t st);
+                                 hipStream_t st, bool b_scaled = false);
 // walls to zero, ghosts mirrored, for a solution-type vx / vy pair
 template <typename T>
 hipError_t launch_fill_bc(const Geom& g, T* vx, T* vy, hipStream_t st);
@@ -36,9 +37,10 @@ template <typename T>
 hipError_t launch_precond_in(const Geom& g, Vec3 v, const double* eb, const double* ep, bool energy,
                              T* rx, T* ry, hipStream_t st);
 // preconditioner exit: z_v = (double) e; z_p = alpha eta_p (r_p - D z_v)
+// (accumulate: z_v += e, z_p += alpha eta_p (r_p - D e))
 template <typename T>
 hipError_t launch_precond_out(const Geom& g, const T* ex, const T* ey, Vec3 v, const double* ep,
-                              bool energy, double alpha, Vec3 z, hipStream_t st);
+                              bool energy, double alpha, Vec3 z, hipStream_t st, bool accumulate = false);
 // right-hand side f = -rho g (+ extra) at velocity rows, 0 at continuity rows
 hipError_t launch_rhs(const Geom& g, const double* rho, double gx, double gy, const double* fxe,
                       const double* fye, Vec3 b, hipStream_t st);
@@ -78,9 +80,10 @@ hipError_t launch_coarse_solve(const Geom& g, const double* Minv, const T* rx, c
 
 // ----------------------------------------------------------------- krylov.hip
 int flat_blocks(size_t n);
-// partial[i * nblk + b] = sum over block b of V_i . w   (i < nv <= 8)
+// partial[i * nblk + b] = sum over block b of V_i . w (any nv, in chunks of 8); when
+// norm_slot >= 0 also partial[norm_slot * nblk + b] = block sums of w . w
 hipError_t launch_multidot(const double* V0, size_t vstride, int nv, const double* w, size_t n,
-                           double* partial, int nblk, hipStream_t st);
+                           double* partial, int nblk, hipStream_t st, int norm_slot = -1);
 // w -= sum_i h[i] V_i, then partial[i * nblk + b] = block sums of V_i . w (nv entries)
 // and, when norm_slot >= 0, partial[norm_slot * nblk + b] = block sums of w . w
 hipError_t launch_axpy_dot(double* w, const double* V0, size_t vstride, int nv, const double* h,
@@ -100,5 +103,36 @@ hipError_t launch_update_x(double* x, const double* Z0, size_t zstride, int k, c
 // sum of p over cells -> partial; then p -= mean
 hipError_t launch_p_sum(const Geom& g, const double* p, double* partial, int* nblk_out, hipStream_t st);
 hipError_t launch_p_shift(const Geom& g, double* p, const double* sum, hipStream_t st);
+
+// ------------------------------------------------------------------ fused.hip
+template <typename T>
+struct CoarseArgs {
+    int nl;                          // levels handled: 0 = top (read rx, ry; write ex, ey), nl-1 = coarsest
+    int nc;                          // unknowns of the coarsest level (dense FP64 solve)
+    int smoother;                    // TPH_SMOOTH_*
+    T omega;
+    Geom g[kMaxLevels];
+    const T* eb[kMaxLevels];
+    const T* ep[kMaxLevels];
+    int nu_pre[kMaxLevels];
+    int nu_post[kMaxLevels];
+    const T* rx;
+    const T* ry;
+    T* ex;
+    T* ey;
+    const double* Minv;
+};
+template <typename T>
+size_t coarse_cycle_lds_bytes(const Geom* g, int nl, int nc);
+// mode: 0 plain sweep, 1 from a zero initial guess, 2 prolongation + correction then sweep
+template <typename T>
+hipError_t launch_smooth_tile(const Geom& g, const Geom* gc, int smoother, int mode, const T* exi, const T* eyi,
+                              T* exo, T* eyo, const T* rx, const T* ry, const T* eb, const T* ep, const T* ecx,
+                              const T* ecy, T omega, hipStream_t st);
+template <typename T>
+hipError_t launch_res_restrict(const Geom& gf, const Geom& gc, const T* ex, const T* ey, const T* rx, const T* ry,
+                               const T* eb, const T* ep, T* rcx, T* rcy, hipStream_t st);
+template <typename T>
+hipError_t launch_coarse_cycle(const CoarseArgs<T>& a, size_t lds_bytes, int max_lds, hipStream_t st);
 
 }  // namespace tph

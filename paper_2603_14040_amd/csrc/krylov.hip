@@ -1,7 +1,7 @@
 // FP64 Krylov vector kernels for flexible GMRES (Sec. "Comparison with
-// FGMRES"): multi-vector dot products, fused axpy + dot (classical
-// Gram-Schmidt with one re-orthogonalisation), normalisation and the
-// solution update.  Vectors are flat (vx | vy | p) arrays whose entries
+// FGMRES"): multi-vector dot products (with the vector's own norm in the
+// same pass), fused axpy + norm (classical Gram-Schmidt with a second pass
+// only on cancellation), normalisation and the solution update.  Vectors are flat (vx | vy | p) arrays whose entries
 // outside the equation rows are zero, so every kernel is a plain 1D stream.
 // Reductions are two-stage with a fixed block count and fixed summation
 // order: results are bitwise reproducible run to run (no atomics).
@@ -23,15 +23,17 @@ constexpr int kNV = 8;
 
 __global__ __launch_bounds__(256) void k_multidot(const double* __restrict__ V0, size_t vstride, int nv,
                                                  const double* __restrict__ w, size_t n,
-                                                 double* __restrict__ partial, int nblk) {
+                                                 double* __restrict__ partial, int nblk, int norm_slot) {
     double acc[kNV];
 #pragma unroll
     for (int v = 0; v < kNV; ++v) acc[v] = 0.0;
+    double nacc = 0.0;
     for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
         const double wv = w[t];
 #pragma unroll
         for (int v = 0; v < kNV; ++v)
             if (v < nv) acc[v] += V0[v * vstride + t] * wv;
+        nacc += wv * wv;
     }
 #pragma unroll
     for (int v = 0; v < kNV; ++v) {
@@ -39,6 +41,10 @@ __global__ __launch_bounds__(256) void k_multidot(const double* __restrict__ V0,
             const double s = block_sum(acc[v]);
             if (threadIdx.x == 0) partial[(size_t)v * nblk + blockIdx.x] = s;
         }
+    }
+    if (norm_slot >= 0) {
+        const double s = block_sum(nacc);
+        if (threadIdx.x == 0) partial[(size_t)norm_slot * nblk + blockIdx.x] = s;
     }
 }
 
@@ -140,11 +146,13 @@ __global__ __launch_bounds__(256) void k_p_shift(Geom g, double* __restrict__ p,
 }  // namespace
 
 hipError_t launch_multidot(const double* V0, size_t vstride, int nv, const double* w, size_t n, double* partial,
-                           int nblk, hipStream_t st) {
+                           int nblk, hipStream_t st, int norm_slot) {
     for (int v0 = 0; v0 < nv; v0 += kNV) {
         const int c = nv - v0 < kNV ? nv - v0 : kNV;
+        // the norm slot is an absolute row index; offset it for this chunk's partial base
+        const int ns = (v0 == 0 && norm_slot >= 0) ? norm_slot : -1;
         hipLaunchKernelGGL(k_multidot, dim3(nblk), dim3(256), 0, st, V0 + v0 * vstride, vstride, c, w, n,
-                           partial + (size_t)v0 * nblk, nblk);
+                           partial + (size_t)v0 * nblk, nblk, ns);
     }
     return hipGetLastError();
 }
@@ -163,7 +171,7 @@ hipError_t launch_axpy_dot(double* w, const double* V0, size_t vstride, int nv, 
         hipLaunchKernelGGL(k_axpy_dot, dim3(nblk), dim3(256), 0, st, w, V0 + v0 * vstride, vstride, c, h + v0, n, 0,
                            last ? norm_slot : -1, partial, nblk);
     }
-    if (want_dots) return launch_multidot(V0, vstride, nv, w, n, partial, nblk, st);
+    if (want_dots) return launch_multidot(V0, vstride, nv, w, n, partial, nblk, st, -1);
     return hipGetLastError();
 }
 

@@ -80,6 +80,9 @@ struct tph_solver {
     LevelBuf lev[kMaxLevels];
     double* Minv = nullptr;
     int ncoarse = 0;
+    int lc = -1;                 // first level handled by the single-workgroup coarse kernel (-1: none)
+    size_t lc_lds = 0;           // its LDS bytes
+    int max_lds = 65536;         // device limit of LDS per workgroup
     size_t F = 0;                // elements of one field allocation
     size_t n3 = 0;               // elements of a three-field vector
     double* x = nullptr;         // solution vector
@@ -87,6 +90,7 @@ struct tph_solver {
     double* b2 = nullptr;        // right-hand side of a solve_rhs / adjoint call
     double* t1 = nullptr;        // scratch vectors
     double* t2 = nullptr;
+    double* t3 = nullptr;        // inner residual of the multi-step preconditioner
     double* V = nullptr;         // (m + 1) basis vectors
     double* Z = nullptr;         // m preconditioned vectors
     double* rho = nullptr;       // staged fields (FP64)
@@ -102,6 +106,7 @@ struct tph_solver {
     bool ready = false;
     double bnorm = 0;
     double t_setup_ms = 0;
+    long long reorth_count = 0;  // second Gram-Schmidt passes taken (diagnostic)
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::vector<void*> dev_allocs;
     bool mixed() const { return d.precision == TPH_MIXED; }
@@ -156,6 +161,8 @@ tph_status validate_desc(const tph_desc* d, int* nlev_out) {
     if (!(d->rtol > 0.0) || !(d->rtol < 1.0)) { set_error("rtol must be in (0, 1)"); return TPH_ERR_INVALID; }
     if (d->restart < 1 || d->restart > kMaxRestart) { set_error("restart must be in [1, 64]"); return TPH_ERR_INVALID; }
     if (d->max_iters < 1) { set_error("max_iters must be >= 1"); return TPH_ERR_INVALID; }
+    if (d->uzawa_steps < 1 || d->uzawa_steps > 8) { set_error("uzawa_steps must be in [1, 8]"); return TPH_ERR_INVALID; }
+    if (d->fused != 0 && d->fused != 1) { set_error("fused must be 0 or 1"); return TPH_ERR_INVALID; }
     int nlev = d->levels;
     if (nlev == 0) {
         nlev = 1;
@@ -236,14 +243,109 @@ tph_status vcycle(tph_solver* s, int l, int* cur_out) {
     return TPH_OK;
 }
 
+// V-cycle with the fused kernels: LDS-tiled smoothing sweeps (first one
+// from zero, first post-sweep with the prolongation fused in), fused
+// residual + restriction, and the coarse tail in one workgroup.
+template <typename T>
+tph_status vcycle_fused(tph_solver* s, int l, int* cur_out) {
+    LevelBuf& L = s->lev[l];
+    const Geom& g = L.g;
+    hipStream_t st = s->st;
+    T* eb = as<T>(L.eb);
+    T* ep = as<T>(L.ep);
+    T* rx = as<T>(L.rx);
+    T* ry = as<T>(L.ry);
+    const T om = (T)s->d.omega;
+    const int sm = s->d.smoother;
+    if (l == s->lc) {
+        CoarseArgs<T> a{};
+        a.nl = s->nlev - l;
+        a.nc = s->ncoarse;
+        a.smoother = sm;
+        a.omega = om;
+        for (int q = 0; q < a.nl; ++q) {
+            const LevelBuf& Q = s->lev[l + q];
+            a.g[q] = Q.g;
+            a.eb[q] = as<T>(Q.eb);
+            a.ep[q] = as<T>(Q.ep);
+            a.nu_pre[q] = Q.nu_pre;
+            a.nu_post[q] = Q.nu_post;
+        }
+        a.rx = rx;
+        a.ry = ry;
+        a.ex = as<T>(L.ex[0]);
+        a.ey = as<T>(L.ey[0]);
+        a.Minv = s->Minv;
+        TPH_HIP(launch_coarse_cycle<T>(a, s->lc_lds, s->max_lds, st));
+        *cur_out = 0;
+        return TPH_OK;
+    }
+    if (l == s->nlev - 1) {
+        TPH_HIP(launch_coarse_solve<T>(g, s->Minv, rx, ry, as<T>(L.ex[0]), as<T>(L.ey[0]), st));
+        *cur_out = 0;
+        return TPH_OK;
+    }
+    int cur = 0;
+    if (L.nu_pre == 0) {
+        TPH_HIP(launch_zero_vel<T>(g, as<T>(L.ex[0]), as<T>(L.ey[0]), st));
+    } else {
+        TPH_HIP(launch_smooth_tile<T>(g, nullptr, sm, 1, nullptr, nullptr, as<T>(L.ex[0]), as<T>(L.ey[0]), rx, ry, eb,
+                                      ep, nullptr, nullptr, om, st));
+        for (int k = 1; k < L.nu_pre; ++k) {
+            TPH_HIP(launch_smooth_tile<T>(g, nullptr, sm, 0, as<T>(L.ex[cur]), as<T>(L.ey[cur]), as<T>(L.ex[1 - cur]),
+                                          as<T>(L.ey[1 - cur]), rx, ry, eb, ep, nullptr, nullptr, om, st));
+            cur = 1 - cur;
+        }
+    }
+    LevelBuf& C = s->lev[l + 1];
+    TPH_HIP(launch_res_restrict<T>(g, C.g, as<T>(L.ex[cur]), as<T>(L.ey[cur]), rx, ry, eb, ep, as<T>(C.rx),
+                                   as<T>(C.ry), st));
+    int ccur = 0;
+    TPH_TRY(vcycle_fused<T>(s, l + 1, &ccur));
+    if (L.nu_post == 0) {
+        TPH_HIP(launch_prolong_add<T>(g, C.g, as<T>(C.ex[ccur]), as<T>(C.ey[ccur]), as<T>(L.ex[cur]),
+                                      as<T>(L.ey[cur]), st));
+    } else {
+        TPH_HIP(launch_smooth_tile<T>(g, &C.g, sm, 2, as<T>(L.ex[cur]), as<T>(L.ey[cur]), as<T>(L.ex[1 - cur]),
+                                      as<T>(L.ey[1 - cur]), rx, ry, eb, ep, as<T>(C.ex[ccur]), as<T>(C.ey[ccur]), om,
+                                      st));
+        cur = 1 - cur;
+        for (int k = 1; k < L.nu_post; ++k) {
+            TPH_HIP(launch_smooth_tile<T>(g, nullptr, sm, 0, as<T>(L.ex[cur]), as<T>(L.ey[cur]), as<T>(L.ex[1 - cur]),
+                                          as<T>(L.ey[1 - cur]), rx, ry, eb, ep, nullptr, nullptr, om, st));
+            cur = 1 - cur;
+        }
+    }
+    *cur_out = cur;
+    return TPH_OK;
+}
+
+// z = M^{-1} v applied uzawa_steps times as a stationary iteration from z = 0:
+// step 1: z = M^{-1} r; step k: z += M^{-1} (r - A z).  `energy`: v holds
+// W^(1/2) r (a Krylov basis vector).
 template <typename T>
 tph_status precondition_t(tph_solver* s, double* vraw, double* zraw, bool energy) {
     LevelBuf& L = s->lev[0];
     const Vec3 v = vec3(s, vraw), z = vec3(s, zraw);
-    TPH_HIP(launch_precond_in<T>(L.g, v, L.eb64, L.ep64, energy, as<T>(L.rx), as<T>(L.ry), s->st));
-    int cur = 0;
-    TPH_TRY(vcycle<T>(s, 0, &cur));
-    TPH_HIP(launch_precond_out<T>(L.g, as<T>(L.ex[cur]), as<T>(L.ey[cur]), v, L.ep64, energy, s->d.alpha, z, s->st));
+    const bool fused = s->d.fused == 1;
+    for (int step = 0; step < s->d.uzawa_steps; ++step) {
+        Vec3 src = v;
+        bool src_scaled = energy;
+        if (step > 0) {
+            // t = r - A z (FP64), with r unscaled on the fly from v
+            const Vec3 t = vec3(s, s->t3);
+            TPH_HIP(launch_outer_residual(L.g, z, &v, L.eb64, L.ep64, t, ResMode::kResidual, false, nullptr, nullptr,
+                                          s->st, energy));
+            src = t;
+            src_scaled = false;
+        }
+        TPH_HIP(launch_precond_in<T>(L.g, src, L.eb64, L.ep64, src_scaled, as<T>(L.rx), as<T>(L.ry), s->st));
+        int cur = 0;
+        if (fused) TPH_TRY(vcycle_fused<T>(s, 0, &cur));
+        else TPH_TRY(vcycle<T>(s, 0, &cur));
+        TPH_HIP(launch_precond_out<T>(L.g, as<T>(L.ex[cur]), as<T>(L.ey[cur]), src, L.ep64, src_scaled, s->d.alpha, z,
+                                      s->st, step > 0));
+    }
     return TPH_OK;
 }
 
@@ -339,6 +441,11 @@ tph_status fgmres(tph_solver* s, double* braw, tph_info* info) {
     double est = 0.0, true_res = 0.0;
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m);
     tph_status result = TPH_NOT_CONVERGED;
+    // stagnation guard: below the FP64 rounding floor of b - A x the true
+    // residual stops decreasing; give up after three restarts without a 10% gain
+    double best_true = HUGE_VAL;
+    int stalled = 0;
+    bool stagnated = false;
     while (true) {
         // true residual r = W^(1/2) (b - A x) into V_0
         TPH_TRY(energy_residual_vec(s, s->x, braw, Vk(0), kSlotMisc));
@@ -348,6 +455,12 @@ tph_status fgmres(tph_solver* s, double* braw, tph_info* info) {
         true_res = bnorm > 0 ? beta / bnorm : beta;
         if (bnorm == 0.0 || true_res <= s->d.rtol) { result = TPH_OK; break; }
         if (its >= s->d.max_iters) break;
+        if (true_res > 0.9 * best_true) {
+            if (++stalled >= 3) { stagnated = true; break; }
+        } else {
+            stalled = 0;
+        }
+        best_true = std::min(best_true, true_res);
         ++restarts;
         TPH_HIP(launch_scale_by_rnorm(Vk(0), Vk(0), n3, s->dscal + kSlotMisc, s->st));
         std::fill(gv.begin(), gv.end(), 0.0);
@@ -359,21 +472,33 @@ tph_status fgmres(tph_solver* s, double* braw, tph_info* info) {
             TPH_HIP(launch_outer_residual(L.g, vec3(s, Zk(j)), nullptr, L.eb64, L.ep64, vec3(s, Vk(j + 1)),
                                           ResMode::kApply, true, nullptr, nullptr, s->st));
             double* w = Vk(j + 1);
-            // classical Gram-Schmidt, twice
-            TPH_HIP(launch_multidot(Vk(0), n3, j + 1, w, n3, s->partial, nblk_flat, s->st));
-            TPH_TRY(reduce_to(s, nblk_flat, j + 1, kSlotH1));
-            TPH_HIP(launch_axpy_dot(w, Vk(0), n3, j + 1, s->dscal + kSlotH1, n3, true, -1, s->partial, nblk_flat,
-                                    s->st));
-            TPH_TRY(reduce_to(s, nblk_flat, j + 1, kSlotH2));
-            TPH_HIP(launch_axpy_dot(w, Vk(0), n3, j + 1, s->dscal + kSlotH2, n3, false, 0, s->partial, nblk_flat,
+            // classical Gram-Schmidt with selective re-orthogonalisation: one
+            // projection pass, and a second only when the norm drops below
+            // 1/sqrt(2) of its value before the projection (cancellation)
+            TPH_HIP(launch_multidot(Vk(0), n3, j + 1, w, n3, s->partial, nblk_flat, s->st, j + 1));
+            TPH_TRY(reduce_to(s, nblk_flat, j + 2, kSlotH1));        // h (j+1) and |w|^2 at kSlotH1 + j + 1
+            TPH_HIP(launch_axpy_dot(w, Vk(0), n3, j + 1, s->dscal + kSlotH1, n3, false, 0, s->partial, nblk_flat,
                                     s->st));
             TPH_TRY(reduce_to(s, nblk_flat, 1, kSlotNrm));
-            TPH_HIP(launch_scale_by_rnorm(w, w, n3, s->dscal + kSlotNrm, s->st));
             TPH_HIP(hipMemcpyAsync(s->hscal, s->dscal, (size_t)(kSlotNrm + 1) * sizeof(double), hipMemcpyDeviceToHost,
                                    s->st));
             TPH_HIP(hipStreamSynchronize(s->st));
             double* col = &H[(size_t)j * (m + 1)];
-            for (int i = 0; i <= j; ++i) col[i] = s->hscal[kSlotH1 + i] + s->hscal[kSlotH2 + i];
+            for (int i = 0; i <= j; ++i) col[i] = s->hscal[kSlotH1 + i];
+            const double w2_before = s->hscal[kSlotH1 + j + 1];
+            if (s->hscal[kSlotNrm] < 0.5 * w2_before) {
+                TPH_HIP(launch_multidot(Vk(0), n3, j + 1, w, n3, s->partial, nblk_flat, s->st));
+                TPH_TRY(reduce_to(s, nblk_flat, j + 1, kSlotH2));
+                TPH_HIP(launch_axpy_dot(w, Vk(0), n3, j + 1, s->dscal + kSlotH2, n3, false, 0, s->partial, nblk_flat,
+                                        s->st));
+                TPH_TRY(reduce_to(s, nblk_flat, 1, kSlotNrm));
+                TPH_HIP(hipMemcpyAsync(s->hscal, s->dscal, (size_t)(kSlotNrm + 1) * sizeof(double),
+                                       hipMemcpyDeviceToHost, s->st));
+                TPH_HIP(hipStreamSynchronize(s->st));
+                for (int i = 0; i <= j; ++i) col[i] += s->hscal[kSlotH2 + i];
+                ++s->reorth_count;
+            }
+            TPH_HIP(launch_scale_by_rnorm(w, w, n3, s->dscal + kSlotNrm, s->st));
             const double hn = std::sqrt(s->hscal[kSlotNrm]);
             col[j + 1] = hn;
             if (!std::isfinite(hn)) { set_error("non-finite value in the Krylov basis"); return TPH_ERR_NONFINITE; }
@@ -416,7 +541,8 @@ tph_status fgmres(tph_solver* s, double* braw, tph_info* info) {
         info->t_solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
     }
     if (result == TPH_NOT_CONVERGED)
-        set_error("FGMRES reached max_iters with relative energy residual " + std::to_string(true_res));
+        set_error(std::string(stagnated ? "FGMRES stagnated (rounding floor of the residual)" : "FGMRES reached max_iters") +
+                  " with relative energy residual " + std::to_string(true_res));
     return result;
 }
 
@@ -476,6 +602,7 @@ tph_status create_impl(const tph_desc* desc, void* stream, tph_solver* s) {
     TPH_TRY(dev_alloc(s, (void**)&s->b2, vb));
     TPH_TRY(dev_alloc(s, (void**)&s->t1, vb));
     TPH_TRY(dev_alloc(s, (void**)&s->t2, vb));
+    TPH_TRY(dev_alloc(s, (void**)&s->t3, vb));
     TPH_TRY(dev_alloc(s, (void**)&s->V, vb * (desc->restart + 1)));
     TPH_TRY(dev_alloc(s, (void**)&s->Z, vb * desc->restart));
     void* p = nullptr;
@@ -488,11 +615,114 @@ tph_status create_impl(const tph_desc* desc, void* stream, tph_solver* s) {
     TPH_TRY(dev_alloc(s, (void**)&s->partial, s->partial_len * sizeof(double)));
     TPH_TRY(dev_alloc(s, (void**)&s->dscal, kScalars * sizeof(double)));
     s->ncoarse = coarse_unknowns(s->lev[nlev - 1].g);
+    {
+        int dev = 0, lim = 0;
+        TPH_HIP(hipGetDevice(&dev));
+        if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && lim > 0)
+            s->max_lds = lim;
+    }
+    s->lc = -1;
+    if (desc->fused && nlev >= 2 && s->ncoarse <= 2048) {
+        // highest level (smallest index) whose tail fits in one workgroup's LDS
+        // and whose per-sweep work suits one workgroup (<= 64 x 64 cells)
+        const size_t budget = (size_t)std::min(s->max_lds, 160 * 1024) - 1024;
+        for (int l = 0; l < nlev - 1; ++l) {
+            Geom gs[kMaxLevels];
+            for (int q = l; q < nlev; ++q) gs[q - l] = s->lev[q].g;
+            const size_t need = s->mixed() ? coarse_cycle_lds_bytes<float>(gs, nlev - l, s->ncoarse)
+                                           : coarse_cycle_lds_bytes<double>(gs, nlev - l, s->ncoarse);
+            if (s->lev[l].g.nx * s->lev[l].g.ny <= 64 * 64 && need <= budget) {
+                s->lc = l;
+                s->lc_lds = need;
+                break;
+            }
+        }
+    }
     TPH_TRY(dev_alloc(s, (void**)&s->Minv, (size_t)s->ncoarse * s->ncoarse * sizeof(double)));
     TPH_HIP(hipHostMalloc((void**)&s->hscal, kScalars * sizeof(double), hipHostMallocDefault));
     TPH_HIP(hipEventCreate(&s->ev0));
     TPH_HIP(hipEventCreate(&s->ev1));
     TPH_HIP(hipStreamSynchronize(s->st));
+    return TPH_OK;
+}
+
+// Back-to-back launches of one kernel between two events on the solver's stream.
+template <typename T>
+tph_status time_kernel_t(tph_solver* s, int kind, int reps, double* ms, double* bytes) {
+    LevelBuf& L = s->lev[0];
+    const Geom& g = L.g;
+    hipStream_t st = s->st;
+    const double cells = (double)g.nx * g.ny;
+    const double W = sizeof(T);
+    T* eb = as<T>(L.eb);
+    T* ep = as<T>(L.ep);
+    const T om = (T)s->d.omega;
+    double words = 0.0;
+    auto one = [&](int r) -> tph_status {
+        switch (kind) {
+            case TPH_KERNEL_SMOOTH:
+                if (s->d.fused) {
+                    const int a = r & 1;
+                    TPH_HIP(launch_smooth_tile<T>(g, nullptr, s->d.smoother, 0, as<T>(L.ex[a]), as<T>(L.ey[a]),
+                                                  as<T>(L.ex[1 - a]), as<T>(L.ey[1 - a]), as<T>(L.rx), as<T>(L.ry), eb,
+                                                  ep, nullptr, nullptr, om, st));
+                } else if (s->d.smoother == TPH_SMOOTH_JACOBI) {
+                    const int a = r & 1;
+                    TPH_HIP(launch_jacobi<T>(g, as<T>(L.ex[a]), as<T>(L.ey[a]), as<T>(L.ex[1 - a]), as<T>(L.ey[1 - a]),
+                                             as<T>(L.rx), as<T>(L.ry), eb, ep, om, st));
+                } else {
+                    TPH_HIP(launch_gs_half<T>(g, (r >> 1) & 1, r & 1, as<T>(L.ex[0]), as<T>(L.ey[0]), as<T>(L.rx),
+                                              as<T>(L.ry), eb, ep, om, false, st));
+                }
+                break;
+            case TPH_KERNEL_APPLY:
+                TPH_HIP(launch_outer_residual(g, vec3(s, s->Z), nullptr, L.eb64, L.ep64, vec3(s, s->t1),
+                                              ResMode::kApply, true, nullptr, nullptr, st));
+                break;
+            case TPH_KERNEL_RESIDUAL:
+                TPH_HIP(launch_vel_residual<T>(g, as<T>(L.ex[0]), as<T>(L.ey[0]), as<T>(L.rx), as<T>(L.ry), eb, ep,
+                                               as<T>(L.tx), as<T>(L.ty), st));
+                break;
+            case TPH_KERNEL_RESTRICT:
+                if (s->d.fused)
+                    TPH_HIP(launch_res_restrict<T>(g, s->lev[1].g, as<T>(L.ex[0]), as<T>(L.ey[0]), as<T>(L.rx),
+                                                   as<T>(L.ry), eb, ep, as<T>(s->lev[1].rx), as<T>(s->lev[1].ry), st));
+                else
+                    TPH_HIP(launch_restrict_res<T>(g, s->lev[1].g, as<T>(L.tx), as<T>(L.ty), as<T>(s->lev[1].rx),
+                                                   as<T>(s->lev[1].ry), st));
+                break;
+            default:
+                TPH_HIP(launch_prolong_add<T>(g, s->lev[1].g, as<T>(s->lev[1].ex[0]), as<T>(s->lev[1].ey[0]),
+                                              as<T>(L.ex[0]), as<T>(L.ey[0]), st));
+                break;
+        }
+        return TPH_OK;
+    };
+    switch (kind) {
+        case TPH_KERNEL_SMOOTH:
+            // Jacobi: read e (2), r (2), eta_b, eta_p; write e (2).  GS colour
+            // half-sweep: read both velocities, eta_b, eta_p and half of one r;
+            // write half of one component.
+            // a fused sweep (either smoother) reads e, r, eta_b, eta_p and writes e
+            words = (s->d.fused || s->d.smoother == TPH_SMOOTH_JACOBI) ? 8.0 : 5.0;
+            break;
+        case TPH_KERNEL_APPLY: words = 8.0; break;          // read vx, vy, p, eta_b, eta_p; write 3
+        case TPH_KERNEL_RESIDUAL: words = 8.0; break;       // read e (2), r (2), eta_b, eta_p; write t (2)
+        case TPH_KERNEL_RESTRICT:                           // fused: read e, r, eta_b, eta_p, write 2 coarse (1/4)
+            words = s->d.fused ? 6.5 : 2.5;                 // separate: read t (2), write 2 coarse
+            break;
+        default: words = 5.0; break;                        // read 2 coarse (1/4), e (2); write e (2)
+    }
+    const double wbytes = kind == TPH_KERNEL_APPLY ? 8.0 : W;
+    TPH_TRY(one(0));                                     // warm
+    TPH_HIP(hipEventRecord(s->ev0, st));
+    for (int r = 0; r < reps; ++r) TPH_TRY(one(r));
+    TPH_HIP(hipEventRecord(s->ev1, st));
+    TPH_HIP(hipEventSynchronize(s->ev1));
+    float el = 0.f;
+    TPH_HIP(hipEventElapsedTime(&el, s->ev0, s->ev1));
+    if (ms) *ms = (double)el / reps;
+    if (bytes) *bytes = words * wbytes * cells;
     return TPH_OK;
 }
 
@@ -514,13 +744,15 @@ void tph_desc_default(tph_desc* d, int32_t nx, int32_t ny) {
     d->smoother = TPH_SMOOTH_GS;
     d->nu_pre = 2;
     d->nu_post = 2;
-    d->nu_growth = 2.0;
+    d->nu_growth = 1.0;
     d->omega = 1.0;
     d->alpha = 1.0;
     d->eta_mean = TPH_MEAN_ARITHMETIC;
     d->rtol = 1e-8;
     d->restart = 20;
     d->max_iters = 500;
+    d->uzawa_steps = 2;
+    d->fused = 1;
 }
 
 tph_status tph_create(const tph_desc* desc, void* hip_stream, tph_solver** out) {
@@ -725,6 +957,23 @@ tph_status tph_coeff_gradient(tph_solver* s, const double* vx, const double* vy,
     if (g_rho_b) TPH_TRY(copy_out(s, g, g_rho_b, s->gtmp[2]));
     TPH_HIP(hipStreamSynchronize(s->st));
     return TPH_OK;
+}
+
+tph_status tph_time_kernel(tph_solver* s, int32_t kind, int32_t reps, double* ms_per_launch,
+                           double* bytes_per_launch) {
+    g_last_error.clear();
+    TPH_TRY(require_ready(s));
+    if (reps < 1 || kind < TPH_KERNEL_SMOOTH || kind > TPH_KERNEL_PROLONG) {
+        set_error("bad kernel kind or repetition count");
+        return TPH_ERR_INVALID;
+    }
+    if ((kind == TPH_KERNEL_RESTRICT || kind == TPH_KERNEL_PROLONG) && s->nlev < 2) {
+        set_error("transfer kernels need at least two levels");
+        return TPH_ERR_INVALID;
+    }
+    const tph_status st = s->mixed() ? time_kernel_t<float>(s, kind, reps, ms_per_launch, bytes_per_launch)
+                                     : time_kernel_t<double>(s, kind, reps, ms_per_launch, bytes_per_launch);
+    return st;
 }
 
 void tph_destroy(tph_solver* s) {

@@ -24,7 +24,7 @@ inline dim3 grid_cells(const Geom& g) { return dim3((g.nx + BX - 1) / BX, (g.ny 
 __global__ __launch_bounds__(256) void k_outer_residual(Geom g, Vec3 x, Vec3 b, int has_b,
                                                        const double* __restrict__ eb,
                                                        const double* __restrict__ ep, Vec3 out,
-                                                       int apply, int energy, double* partial) {
+                                                       int apply, int energy, double* partial, int bscaled) {
     const int j = blockIdx.x * BX + threadIdx.x + 1;
     const int i = blockIdx.y * BY + threadIdx.y + 1;
     const LevelC<double> k = level_consts<double>(g);
@@ -37,22 +37,31 @@ __global__ __launch_bounds__(256) void k_outer_residual(Geom g, Vec3 x, Vec3 b, 
         const double* p = x.p();
         if (j < g.nx) {
             const double a = lx_row(vx, vy, eb, ep, c, P, k.idx, k.idy) - (p[c + 1] - p[c]) * k.idx;
-            double r = apply ? a : ((has_b ? b.vx()[c] : 0.0) - a);
-            if (energy) r *= 1.0 / sqrt(-lx_diag(eb, ep, c, P, i, g.ny, k));
+            const double sq = (energy || bscaled) ? sqrt(-lx_diag(eb, ep, c, P, i, g.ny, k)) : 1.0;
+            double bv = has_b ? b.vx()[c] : 0.0;
+            if (bscaled) bv *= sq;
+            double r = apply ? a : (bv - a);
+            if (energy) r *= 1.0 / sq;
             out.vx()[c] = r;
             acc += r * r;
         }
         if (i < g.ny) {
             const double a = ly_row(vx, vy, eb, ep, c, P, k.idx, k.idy) - (p[c + P] - p[c]) * k.idy;
-            double r = apply ? a : ((has_b ? b.vy()[c] : 0.0) - a);
-            if (energy) r *= 1.0 / sqrt(-ly_diag(eb, ep, c, P, j, g.nx, k));
+            const double sq = (energy || bscaled) ? sqrt(-ly_diag(eb, ep, c, P, j, g.nx, k)) : 1.0;
+            double bv = has_b ? b.vy()[c] : 0.0;
+            if (bscaled) bv *= sq;
+            double r = apply ? a : (bv - a);
+            if (energy) r *= 1.0 / sq;
             out.vy()[c] = r;
             acc += r * r;
         }
         {
             const double a = (vx[c] - vx[c - 1]) * k.idx + (vy[c] - vy[c - P]) * k.idy;
-            double r = apply ? a : ((has_b ? b.p()[c] : 0.0) - a);
-            if (energy) r *= sqrt(wp_weight(ep[c], k));
+            const double sw = (energy || bscaled) ? sqrt(wp_weight(ep[c], k)) : 1.0;
+            double bv = has_b ? b.p()[c] : 0.0;
+            if (bscaled) bv /= sw;
+            double r = apply ? a : (bv - a);
+            if (energy) r *= sw;
             out.p()[c] = r;
             acc += r * r;
         }
@@ -217,7 +226,7 @@ __global__ __launch_bounds__(256) void k_precond_in(Geom g, Vec3 v, const double
 template <typename T>
 __global__ __launch_bounds__(256) void k_precond_out(Geom g, const T* __restrict__ ex, const T* __restrict__ ey,
                                                     Vec3 v, const double* __restrict__ ep, int energy,
-                                                    double alpha, Vec3 z) {
+                                                    double alpha, Vec3 z, int acc) {
     const int j = blockIdx.x * BX + threadIdx.x + 1;
     const int i = blockIdx.y * BY + threadIdx.y + 1;
     if (i > g.ny || j > g.nx) return;
@@ -227,20 +236,23 @@ __global__ __launch_bounds__(256) void k_precond_out(Geom g, const T* __restrict
     double* zx = z.vx();
     double* zy = z.vy();
     if (j < g.nx) {
-        zx[c] = (double)ex[c];
-        if (i == 1) zx[c - P] = (double)ex[c - P];
-        if (i == g.ny) zx[c + P] = (double)ex[c + P];
+        const double e = acc ? zx[c] + (double)ex[c] : (double)ex[c];
+        zx[c] = e;
+        if (i == 1) zx[c - P] = (double)g.mir[2] * e;
+        if (i == g.ny) zx[c + P] = (double)g.mir[3] * e;
     }
     if (i < g.ny) {
-        zy[c] = (double)ey[c];
-        if (j == 1) zy[c - 1] = (double)ey[c - 1];
-        if (j == g.nx) zy[c + 1] = (double)ey[c + 1];
+        const double e = acc ? zy[c] + (double)ey[c] : (double)ey[c];
+        zy[c] = e;
+        if (j == 1) zy[c - 1] = (double)g.mir[0] * e;
+        if (j == g.nx) zy[c + 1] = (double)g.mir[1] * e;
     }
-    // divergence from the (cast) velocity correction; walls read as zero
+    // divergence of this step's (cast) velocity correction; walls read as zero
     const double div = ((double)ex[c] - (double)ex[c - 1]) * k.idx + ((double)ey[c] - (double)ey[c - P]) * k.idy;
     double rp = v.p()[c];
     if (energy) rp *= 1.0 / sqrt(wp_weight(ep[c], k));
-    z.p()[c] = alpha * ep[c] * (rp - div);
+    const double dp = alpha * ep[c] * (rp - div);
+    z.p()[c] = acc ? z.p()[c] + dp : dp;
 }
 
 __global__ __launch_bounds__(256) void k_rhs(Geom g, const double* __restrict__ rho, double gx, double gy,
@@ -367,12 +379,12 @@ __global__ void k_cast_f64_f32(const double* __restrict__ s, float* __restrict__
 
 hipError_t launch_outer_residual(const Geom& g, Vec3 x, const Vec3* b, const double* eb, const double* ep,
                                  Vec3 out, ResMode mode, bool energy, double* partial, int* nblk_out,
-                                 hipStream_t st) {
+                                 hipStream_t st, bool b_scaled) {
     const dim3 grid = grid_cells(g);
     if (nblk_out) *nblk_out = (int)(grid.x * grid.y);
     Vec3 bb = b ? *b : Vec3{nullptr, 0};
     hipLaunchKernelGGL(k_outer_residual, grid, dim3(BX, BY), 0, st, g, x, bb, b ? 1 : 0, eb, ep, out,
-                       mode == ResMode::kApply ? 1 : 0, energy ? 1 : 0, partial);
+                       mode == ResMode::kApply ? 1 : 0, energy ? 1 : 0, partial, b_scaled ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -422,9 +434,9 @@ hipError_t launch_precond_in(const Geom& g, Vec3 v, const double* eb, const doub
 
 template <typename T>
 hipError_t launch_precond_out(const Geom& g, const T* ex, const T* ey, Vec3 v, const double* ep, bool energy,
-                              double alpha, Vec3 z, hipStream_t st) {
+                              double alpha, Vec3 z, hipStream_t st, bool accumulate) {
     hipLaunchKernelGGL(k_precond_out<T>, grid_cells(g), dim3(BX, BY), 0, st, g, ex, ey, v, ep, energy ? 1 : 0,
-                       alpha, z);
+                       alpha, z, accumulate ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -474,7 +486,7 @@ hipError_t launch_cast_f64_f32(const double* src, float* dst, size_t n, hipStrea
     template hipError_t launch_precond_in<T>(const Geom&, Vec3, const double*, const double*, bool, T*, T*,  \
                                              hipStream_t);                                                   \
     template hipError_t launch_precond_out<T>(const Geom&, const T*, const T*, Vec3, const double*, bool,    \
-                                              double, Vec3, hipStream_t);
+                                              double, Vec3, hipStream_t, bool);
 TPH_INST(float)
 TPH_INST(double)
 #undef TPH_INST

@@ -30,7 +30,7 @@ def test_struct_layout_matches_header(lib):
     d = _lib.Desc()
     lib.tph_desc_default(ctypes.byref(d), 64, 32)
     assert (d.nx, d.ny, d.lx, d.precision, d.restart) == (64, 32, 1.0, _lib.MIXED, 20)
-    assert d.rtol == 1e-8 and d.nu_growth == 2.0
+    assert d.rtol == 1e-8 and d.nu_growth == 1.0 and d.uzawa_steps == 2 and d.fused == 1
 
 
 def _create(lib, **kw):
@@ -54,6 +54,8 @@ def _create(lib, **kw):
     (dict(rtol=0.0), "rtol"),
     (dict(nu_growth=0.5), "nu_growth"),
     (dict(lx=-1.0), "lx and ly"),
+    (dict(uzawa_steps=0), "uzawa_steps"),
+    (dict(fused=3), "fused"),
 ])
 def test_invalid_descriptor_rejected_on_host(lib, kw, needle):
     st, h, msg = _create(lib, **kw)

@@ -90,24 +90,31 @@ def test_level_viscosities_match_oracle(mean):
 
 
 PRECOND_CASES = [
-    # (nx, ny, bc, levels, smoother, nu, growth, omega, alpha)
-    (16, 16, (0, 0, 0, 0), 1, tph.SMOOTH_JACOBI, 1, 1.0, 0.6, 1.0),
-    (16, 16, (0, 0, 0, 0), 2, tph.SMOOTH_JACOBI, 1, 1.0, 0.6, 1.0),
-    (32, 24, (1, 1, 0, 0), 3, tph.SMOOTH_JACOBI, 2, 2.0, 0.6, 1.5),
-    (32, 32, (0, 0, 0, 0), 3, tph.SMOOTH_GS, 2, 2.0, 1.0, 1.0),
-    (80, 48, (0, 1, 1, 0), 4, tph.SMOOTH_GS, 1, 2.0, 0.9, 2.0),
-    (130, 34, (1, 0, 0, 1), 2, tph.SMOOTH_JACOBI, 0, 1.0, 0.6, 1.0),
+    # (nx, ny, bc, levels, smoother, nu, growth, omega, alpha, steps)
+    (16, 16, (0, 0, 0, 0), 1, tph.SMOOTH_JACOBI, 1, 1.0, 0.6, 1.0, 1),
+    (16, 16, (0, 0, 0, 0), 2, tph.SMOOTH_JACOBI, 1, 1.0, 0.6, 1.0, 1),
+    (32, 24, (1, 1, 0, 0), 3, tph.SMOOTH_JACOBI, 2, 2.0, 0.6, 1.5, 1),
+    (32, 32, (0, 0, 0, 0), 3, tph.SMOOTH_GS, 2, 2.0, 1.0, 1.0, 2),
+    (80, 48, (0, 1, 1, 0), 4, tph.SMOOTH_GS, 1, 2.0, 0.9, 2.0, 1),
+    (130, 34, (1, 0, 0, 1), 2, tph.SMOOTH_JACOBI, 0, 1.0, 0.6, 1.0, 1),
+    # sizes that run the LDS-tiled fine-level kernels (ragged tiles), the
+    # fused residual-restriction and the single-workgroup coarse tail
+    (256, 192, (0, 0, 0, 0), 4, tph.SMOOTH_GS, 2, 1.0, 1.0, 1.0, 2),
+    (200, 72, (1, 0, 1, 1), 3, tph.SMOOTH_GS, 1, 1.0, 0.9, 1.0, 1),
+    (192, 128, (0, 1, 0, 1), 3, tph.SMOOTH_JACOBI, 2, 1.0, 0.7, 1.2, 3),
+    (136, 136, (1, 1, 1, 1), 4, tph.SMOOTH_GS, 3, 1.0, 1.0, 1.0, 1),
 ]
 
 
+@pytest.mark.parametrize("fused", [0, 1])
 @pytest.mark.parametrize("prec", [tph.FP64, tph.MIXED])
 @pytest.mark.parametrize("case", PRECOND_CASES)
-def test_preconditioner_matches_oracle_vcycle(case, prec):
-    nx, ny, bc, levels, sm, nu, growth, omega, alpha = case
+def test_preconditioner_matches_oracle_vcycle(case, prec, fused):
+    nx, ny, bc, levels, sm, nu, growth, omega, alpha, steps = case
     eb, ep, rho = wl.random_fields(nx, ny, seed=nx * 7 + ny, eta_decades=2)
     rx, ry, rp = wl.random_state(nx, ny, seed=nx + 1)
     s = solver_for(nx, ny, bc=bc, precision=prec, levels=levels, smoother=sm, nu_pre=nu, nu_post=nu,
-                   nu_growth=growth, omega=omega, alpha=alpha)
+                   nu_growth=growth, omega=omega, alpha=alpha, uzawa_steps=steps, fused=bool(fused))
     s.set_coefficients(T(eb), T(ep), T(rho))
     zx, zy, zp = s.precondition(T(rx), T(ry), T(rp))
     sched = [min(256, math.ceil(nu * growth ** l - 1e-9)) for l in range(levels)]
@@ -115,16 +122,22 @@ def test_preconditioner_matches_oracle_vcycle(case, prec):
                       smoother="jacobi" if sm == tph.SMOOTH_JACOBI else "gs", alpha=alpha)
     g = st.Grid(nx, ny, 1.0, 1.0, bc)
     levs = mg.build_hierarchy(g, eb, ep, prm)
-    ox, oy, op = mg.precondition(levs, prm, rx, ry, rp)
-    tol = 1e-11 if prec == tph.FP64 else 2e-5
+    if steps == 1:
+        ox, oy, op = mg.precondition(levs, prm, rx, ry, rp)
+    else:
+        ox, oy, op = mg.uzawa_preconditioner(levs, prm, st.assemble(g, eb, ep), rx, ry, rp, steps)
+    tol = 1e-11 if prec == tph.FP64 else 5e-5
     gx_, gy_, gp_ = N(zx), N(zy), N(zp)
-    v_ref = np.concatenate([ox.ravel(), oy.ravel()])
-    v_got = np.concatenate([gx_.ravel(), gy_.ravel()])
-    assert np.linalg.norm(v_got - v_ref) / np.linalg.norm(v_ref) < tol
-    assert np.linalg.norm(gp_ - op) / np.linalg.norm(op) < tol
+    v_ref = np.concatenate([ox[1:ny + 1, 1:nx].ravel(), oy[1:ny, 1:nx + 1].ravel()])
+    v_got = np.concatenate([gx_[1:ny + 1, 1:nx].ravel(), gy_[1:ny, 1:nx + 1].ravel()])
+    ev = np.linalg.norm(v_got - v_ref) / np.linalg.norm(v_ref)
+    epr = np.linalg.norm(gp_[1:ny + 1, 1:nx + 1] - op[1:ny + 1, 1:nx + 1]) / np.linalg.norm(op[1:ny + 1, 1:nx + 1])
+    print(f"[precond] rel err v {ev:.2e} p {epr:.2e}", flush=True)
+    assert ev < tol and epr < tol
     # output contract: walls zero, ghosts mirrored
     assert np.all(gx_[:, 0] == 0) and np.all(gx_[:, nx] == 0)
-    assert np.allclose(gx_[0, 1:nx], (1 if bc[2] == 0 else -1) * gx_[1, 1:nx], rtol=0, atol=0)
+    assert np.array_equal(gx_[0, 1:nx], (1 if bc[2] == 0 else -1) * gx_[1, 1:nx])
+    assert np.array_equal(gy_[1:ny, nx + 1], (1 if bc[1] == 0 else -1) * gy_[1:ny, nx])
 
 
 def _check_solution_contract(nx, ny, bc, vx, vy, p):
@@ -148,15 +161,20 @@ SOLVE_CASES = [
 ]
 
 
+@pytest.mark.parametrize("fused", [0, 1])
 @pytest.mark.parametrize("prec", [tph.FP64, tph.MIXED])
 @pytest.mark.parametrize("name,make", SOLVE_CASES)
-def test_solve_matches_oracle(name, make, prec):
+def test_solve_matches_oracle(name, make, prec, fused):
     pr = make()
     g = st.Grid(pr.nx, pr.ny, pr.lx, pr.ly, pr.bc)
     ref = st.solve(g, pr.eta_b, pr.eta_p, pr.rho_b, pr.gx, pr.gy)
-    s = solver_for(pr.nx, pr.ny, pr.lx, pr.ly, pr.bc, precision=prec, rtol=1e-12, max_iters=2000)
+    s = solver_for(pr.nx, pr.ny, pr.lx, pr.ly, pr.bc, precision=prec, rtol=1e-12, max_iters=2000,
+                   fused=bool(fused))
     s.set_coefficients(T(pr.eta_b), T(pr.eta_p), T(pr.rho_b), pr.gx, pr.gy)
     vx, vy, p, info = s.solve()
+    # 1e-12 can sit below the FP64 rounding floor of the residual: either it is
+    # reached, or the solver stops on stagnation within a few restarts
+    assert info.status == "TPH_OK" or (info.res_energy < 1e-10 and info.restarts < 40)
     print(f"[{name}] prec={prec} iters={info.iters} restarts={info.restarts} res={info.res_energy:.3e}", flush=True)
     vx, vy, p = N(vx), N(vy), N(p)
     ev, ep_ = st.parity_errors(g, ref, vx, vy, p)

@@ -258,3 +258,28 @@ def test_coarse_viscosity_means():
     gb, gp = mg.coarse_viscosity(g, eb, ep, mean="geometric")
     assert gp[2, 2] == pytest.approx(np.exp(np.sum(w4 * np.log(ep[2:6, 2:6]))), rel=1e-13)
     assert np.all(cb[:5, :5] > 0) and np.all(cp[1:5, 1:5] > 0)
+
+
+def test_uzawa_steps_converge_to_exact_solution():
+    """Many sweeps of the stationary Uzawa iteration with an exact velocity
+    solve converge to A^{-1} b (contraction shown above), and one sweep is the
+    single preconditioner application."""
+    n = 8
+    g = st.Grid(n, n)
+    eb, ep, _ = wl.random_fields(n, n, seed=4, eta_decades=1)
+    prm = mg.MGParams(levels=1, nu_pre=[1], nu_post=[1], alpha=1.0)
+    levs = mg.build_hierarchy(g, eb, ep, prm)
+    A = st.assemble(g, eb, ep)
+    rx, ry, rp = wl.random_state(n, n, seed=2)
+    rp[1:n + 1, 1:n + 1] -= rp[1:n + 1, 1:n + 1].mean()        # consistent right-hand side
+    one = mg.uzawa_preconditioner(levs, prm, A, rx, ry, rp, 1)
+    ref1 = mg.precondition(levs, prm, rx, ry, rp)
+    for a, b in zip(one, ref1):
+        assert np.allclose(a, b, rtol=1e-13, atol=1e-13)
+    zx, zy, zp = mg.uzawa_preconditioner(levs, prm, A, rx, ry, rp, 250)
+    b = st.to_vector(g, rx, ry, rp)
+    x, _ = st.solve_system(g, A, b)
+    got = st.to_vector(g, zx, zy, zp)
+    nv = g.n_vx + g.n_vy
+    got[nv:] -= got[nv:].mean()
+    assert np.allclose(got, x, rtol=1e-8, atol=1e-8 * np.abs(x).max())
