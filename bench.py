@@ -45,6 +45,8 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--cpu-n", type=int, default=256, help="oracle sample size (cells per side)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", type=int, default=256, help="problems in the batched workload (0: skip)")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-gradient workload")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -124,6 +126,76 @@ def main():
     copy_gbs = 2 * buf.numel() * 4 * 20 / (time.perf_counter() - t0) / 1e9
     del buf, dst
 
+    # batched workload: independent sinkers of sizes {64, 128, 256, 512}, one batched solve
+    batch = None
+    if args.batch > 0:
+        del s64
+        probs = wl.batch_sinkers(args.batch, seed=4)
+        log(f"[bench] batched workload: {len(probs)} problems, {sum(p.cells for p in probs)} cells")
+        t0 = time.perf_counter()
+        bat = tph.Batch([(p.nx, p.ny) for p in probs], device=dev, precision=tph.MIXED, restart=16)
+        t_create = time.perf_counter() - t0
+        ebs = [to(p.eta_b) for p in probs]
+        eps = [to(p.eta_p) for p in probs]
+        rhs_ = [to(p.rho_b) for p in probs]
+        gxy = [(p.gx, p.gy) for p in probs]
+        outs = bat.zeros(), bat.zeros(), bat.zeros()
+
+        def bstep():
+            for o in outs:
+                for t in o:
+                    t.zero_()
+            bat.set_coefficients(ebs, eps, rhs_, gxy)
+            return bat.solve(*outs)[3]
+
+        bstep()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        binf = bstep()
+        torch.cuda.synchronize()
+        bdt = time.perf_counter() - t0
+        bcells = sum(p.cells for p in probs)
+        its = [i.iters for i in binf]
+        batch = {"workload": f"{len(probs)} centred sinkers, sizes 64..512 (seed 4), contrast 10^U(1,4), mixed",
+                 "cells": bcells, "value": bcells / bdt, "unit": "cells/s", "ms_per_step": 1e3 * bdt,
+                 "iters_max": max(its), "iters_mean": sum(its) / len(its),
+                 "converged": sum(1 for i in binf if i.res_energy <= 1e-8), "create_s": round(t_create, 2)}
+        log(f"[bench] batch: {1e3 * bdt:.1f} ms, {bcells / bdt:.3e} cells/s, iterations max {max(its)}")
+        bat.close()
+        del bat, outs, ebs, eps, rhs_
+
+    # adjoint workload: gradient of the surface-velocity misfit on the 1024^2 field
+    adjoint = None
+    if not args.no_adjoint:
+        base, m, m_true, cells_ = wl.adjoint_problem(n)
+        eb_t, ep_t = wl.logvisc_to_eta(m_true, n, n)
+        sa = tph.Solver(n, n, precision=tph.MIXED, device=dev)
+        sa.set_coefficients(to(eb_t), to(ep_t), rho, pr.gx, pr.gy)
+        vxt = sa.solve()[0]
+        target = vxt[n, 1:n].clone()
+        ebg = to(pr.eta_b).requires_grad_(True)
+        epg = to(pr.eta_p).requires_grad_(True)
+
+        def astep():
+            vx_, vy_, p_ = tph.StokesFunction.apply(ebg, epg, rho, sa, pr.gx, pr.gy)
+            J = 0.5 * (1.0 / n) * torch.sum((vx_[n, 1:n] - target) ** 2)
+            J.backward()
+            return J
+
+        astep()
+        ebg.grad = None
+        epg.grad = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        astep()
+        torch.cuda.synchronize()
+        adt = time.perf_counter() - t0
+        adjoint = {"workload": f"misfit gradient w.r.t. viscosity, {n}x{n} random field, mixed, forward + adjoint "
+                               f"solve + gradient kernel", "ms_per_step": 1e3 * adt,
+                   "cells_per_s": 2 * cells / adt}
+        log(f"[bench] adjoint gradient: {1e3 * adt:.1f} ms")
+        sa.close()
+
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import stokes as ost
@@ -170,6 +242,8 @@ def main():
                      "algorithmic_bytes_per_launch": dom["bytes"], "us_per_launch": dom["us"]},
         "kernels": kern,
         "copy_GBps": round(copy_gbs, 1),
+        "batched": batch,
+        "adjoint": adjoint,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

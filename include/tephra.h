@@ -224,6 +224,28 @@ tph_status tph_time_kernel(tph_solver* s, int32_t kind, int32_t reps, double* ms
 /* Release everything the solver owns.  NULL is allowed. */
 void tph_destroy(tph_solver* s);
 
+/* ---------------------------------------------------------------- batches
+ * Many independent problems of uneven grid sizes solved together: every
+ * V-cycle phase is one launch for the whole batch (work lists of (problem,
+ * tile) items), the coarse tails run one workgroup per problem, and the
+ * device work of one FGMRES iteration is captured once as a hipGraph and
+ * replayed; converged problems are masked on the device.  All problems must
+ * share precision, smoother, sweep counts (>= 1, nu_growth 1), omega, alpha,
+ * eta_mean, restart, max_iters, uzawa_steps and rtol, use fused kernels, and
+ * be large enough to have a coarse tail of at least one level (any grid whose
+ * automatic hierarchy has >= 2 levels).  Pointer-array arguments are HOST
+ * arrays of `count` DEVICE pointers with the single-problem conventions. */
+typedef struct tph_batch tph_batch;
+
+tph_status tph_batch_create(int32_t count, const tph_desc* descs, void* hip_stream, tph_batch** out);
+/* gxy: host array of 2 * count doubles (gx, gy per problem). */
+tph_status tph_batch_set_coefficients(tph_batch* b, const double* const* eta_b, const double* const* eta_p,
+                                      const double* const* rho_b, const double* gxy);
+/* vx, vy, p: in = initial guesses, out = solutions; infos: host array of
+ * `count` (nullable).  Returns TPH_NOT_CONVERGED if any problem did not. */
+tph_status tph_batch_solve(tph_batch* b, double* const* vx, double* const* vy, double* const* p, tph_info* infos);
+void tph_batch_destroy(tph_batch* b);
+
 /* Message of the calling thread's last error ("" if none). */
 const char* tph_last_error(void);
 

@@ -17,7 +17,7 @@ from . import _lib
 from ._lib import (FP64, FREE_SLIP, MEAN_ARITHMETIC, MEAN_GEOMETRIC, MIXED, NO_SLIP,
                    SMOOTH_GS, SMOOTH_JACOBI, TephraError)
 
-__all__ = ["Solver", "SolveInfo", "StokesFunction", "solve", "FP64", "MIXED", "FREE_SLIP",
+__all__ = ["Solver", "Batch", "SolveInfo", "StokesFunction", "solve", "FP64", "MIXED", "FREE_SLIP",
            "NO_SLIP", "SMOOTH_GS", "SMOOTH_JACOBI", "MEAN_ARITHMETIC", "MEAN_GEOMETRIC",
            "TephraError", "library"]
 
@@ -232,6 +232,103 @@ class Solver:
             self._p(lvx, "lvx"), self._p(lvy, "lvy"), self._p(lp, "lp"),
             self._p(gb, "g_eta_b"), self._p(gp, "g_eta_p"), self._p(gr, "g_rho_b")))
         return gb, gp, gr
+
+
+def _desc(lib, nx, ny, lx=1.0, ly=1.0, bc=(FREE_SLIP,) * 4, precision=MIXED, levels=0, smoother=SMOOTH_GS,
+          nu_pre=2, nu_post=2, nu_growth=1.0, omega=1.0, alpha=1.0, eta_mean=MEAN_ARITHMETIC, rtol=1e-8,
+          restart=20, max_iters=500, uzawa_steps=2, fused=True):
+    d = _lib.Desc()
+    lib.tph_desc_default(ctypes.byref(d), nx, ny)
+    d.lx, d.ly = float(lx), float(ly)
+    for w in range(4):
+        d.bc[w] = int(bc[w])
+    d.precision, d.levels, d.smoother = int(precision), int(levels), int(smoother)
+    d.nu_pre, d.nu_post, d.nu_growth = int(nu_pre), int(nu_post), float(nu_growth)
+    d.omega, d.alpha, d.eta_mean, d.rtol = float(omega), float(alpha), int(eta_mean), float(rtol)
+    d.restart, d.max_iters, d.uzawa_steps, d.fused = int(restart), int(max_iters), int(uzawa_steps), int(bool(fused))
+    return d
+
+
+class Batch:
+    """Independent problems of uneven sizes solved together (tph_batch_*).
+
+    ``shapes`` is a list of (nx, ny), (nx, ny, lx, ly) or (nx, ny, lx, ly,
+    bc); the keyword parameters are shared by every problem (see
+    tph_batch_create).
+    """
+
+    def __init__(self, shapes, device: Optional[torch.device] = None,
+                 stream: Optional[torch.cuda.Stream] = None, **params):
+        lib = _lib.load()
+        self._lib = lib
+        self.count = len(shapes)
+        self.rtol = float(params.get("rtol", 1e-8))
+        descs = (_lib.Desc * self.count)()
+        self.shapes = []
+        for k, sh in enumerate(shapes):
+            nx, ny = int(sh[0]), int(sh[1])
+            lx, ly = (float(sh[2]), float(sh[3])) if len(sh) > 2 else (1.0, 1.0)
+            kw = dict(params)
+            if len(sh) > 4:
+                kw["bc"] = tuple(sh[4])          # per-problem boundary conditions
+            descs[k] = _desc(lib, nx, ny, lx, ly, **kw)
+            self.shapes.append((ny + 2, nx + 2))
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            h = ctypes.c_void_p()
+            _lib.check("tph_batch_create", lib.tph_batch_create(self.count, descs,
+                                                                ctypes.c_void_p(self.stream.cuda_stream),
+                                                                ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.tph_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _ptrs(self, tensors, name):
+        if len(tensors) != self.count:
+            raise ValueError(f"{name}: expected {self.count} tensors")
+        arr = (ctypes.c_void_p * self.count)()
+        for k, t in enumerate(tensors):
+            arr[k] = _ptr(t, self.shapes[k], f"{name}[{k}]")
+        return arr
+
+    def _sync_in(self):
+        if self.stream != torch.cuda.current_stream(self.device):
+            self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def set_coefficients(self, eta_b, eta_p, rho_b, gxy):
+        g = (ctypes.c_double * (2 * self.count))()
+        for k, (gx, gy) in enumerate(gxy):
+            g[2 * k], g[2 * k + 1] = float(gx), float(gy)
+        self._sync_in()
+        _lib.check("tph_batch_set_coefficients", self._lib.tph_batch_set_coefficients(
+            self._h, self._ptrs(eta_b, "eta_b"), self._ptrs(eta_p, "eta_p"), self._ptrs(rho_b, "rho_b"), g))
+
+    def zeros(self):
+        return [torch.zeros(s, dtype=torch.float64, device=self.device) for s in self.shapes]
+
+    def solve(self, vx=None, vy=None, p=None):
+        vx = self.zeros() if vx is None else vx
+        vy = self.zeros() if vy is None else vy
+        p = self.zeros() if p is None else p
+        infos = (_lib.Info * self.count)()
+        self._sync_in()
+        st = self._lib.tph_batch_solve(self._h, self._ptrs(vx, "vx"), self._ptrs(vy, "vy"), self._ptrs(p, "p"), infos)
+        _lib.check("tph_batch_solve", st, allow_not_converged=True)
+        out = [SolveInfo("TPH_OK" if infos[k].res_energy <= self.rtol else "TPH_NOT_CONVERGED", infos[k].iters,
+                         infos[k].restarts, infos[k].res_energy, infos[k].res_estimate, infos[k].t_setup_ms,
+                         infos[k].t_solve_ms)
+               for k in range(self.count)]
+        return vx, vy, p, out
 
 
 def solve(eta_b, eta_p, rho_b, gx: float = 0.0, gy: float = -1.0, lx: float = 1.0, ly: float = 1.0,

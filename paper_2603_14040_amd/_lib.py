@@ -82,6 +82,10 @@ def load(path: str = LIB_PATH):
         "tph_coeff_gradient": (c_int32, [P, P, P, P, P, P, P, P, P, P]),
         "tph_time_kernel": (c_int32, [P, c_int32, c_int32, POINTER(c_double), POINTER(c_double)]),
         "tph_destroy": (None, [P]),
+        "tph_batch_create": (c_int32, [c_int32, POINTER(Desc), P, POINTER(P)]),
+        "tph_batch_set_coefficients": (c_int32, [P, POINTER(P), POINTER(P), POINTER(P), POINTER(c_double)]),
+        "tph_batch_solve": (c_int32, [P, POINTER(P), POINTER(P), POINTER(P), POINTER(Info)]),
+        "tph_batch_destroy": (None, [P]),
         "tph_last_error": (c_char_p, []),
         "tph_version": (c_char_p, []),
     }

@@ -1,0 +1,574 @@
+// Device bodies of the fused multigrid kernels, shared by the single-problem
+// kernels (fused.hip) and the batched kernels (batch.hip).
+//
+// smooth_tile_body: one full smoothing sweep on an LDS tile.
+//   Gauss-Seidel: the four colour half-sweeps (vx red, vx black, vy red,
+//   vy black) run inside the tile; each half-sweep needs the result of the
+//   previous one one node further out, so the tile loads a halo of 4 nodes
+//   and updates shrinking regions (halo 3, 2, 1, 0).  The sweep reads the
+//   old iterate from one buffer and writes the interior of the tile to the
+//   other, so overlapping tiles never see each other's new values and the
+//   result equals the four separate half-sweeps exactly.
+//   Jacobi: one stage, halo 1.
+//   Modes: plain, zero initial guess (no load of the iterate), and
+//   prolongation + correction fused into the load (bilinear coarse-to-fine
+//   interpolation from an LDS window of the coarse correction, ghosts
+//   re-mirrored).
+// res_restrict_body: residual r - L e on the fine footprint of a tile of
+//   coarse cells, kept in LDS, then the normalised restriction (gather form
+//   of Alg. "4-Color Parallel Restriction"); the fine residual never goes
+//   to memory.
+// coarse_cycle_body: the V-cycle on every level from a small level down to
+//   the coarsest in one workgroup, all fields resident in LDS, ending in the
+//   FP64 dense solve.
+#pragma once
+#include "kernels.h"
+#include "reduce.h"
+#include "stencil.h"
+
+namespace tph {
+namespace dev {
+
+
+enum { kModePlain = 0, kModeZero = 1, kModeProlong = 2 };
+enum { kSmJacobi = 0, kSmGS = 1 };
+
+// bilinear prolongation of the coarse vx / vy correction to fine node (i, j)
+// (same weights as k_prolong_add; coarse ghosts hold mirrored values)
+template <typename T>
+__device__ __forceinline__ T prolong_vx(const T* __restrict__ ec, int Pc, int i, int j) {
+    const int I0 = (i + 1) >> 1;
+    const int I1 = (i & 1) ? I0 - 1 : I0 + 1;
+    const int J = j >> 1;
+    if ((j & 1) == 0) return (T)0.75 * ec[I0 * Pc + J] + (T)0.25 * ec[I1 * Pc + J];
+    return (T)0.375 * (ec[I0 * Pc + J] + ec[I0 * Pc + J + 1]) + (T)0.125 * (ec[I1 * Pc + J] + ec[I1 * Pc + J + 1]);
+}
+
+template <typename T>
+__device__ __forceinline__ T prolong_vy(const T* __restrict__ ec, int Pc, int i, int j) {
+    const int J0 = (j + 1) >> 1;
+    const int J1 = (j & 1) ? J0 - 1 : J0 + 1;
+    const int I = i >> 1;
+    if ((i & 1) == 0) return (T)0.75 * ec[I * Pc + J0] + (T)0.25 * ec[I * Pc + J1];
+    return (T)0.375 * (ec[I * Pc + J0] + ec[(I + 1) * Pc + J0]) + (T)0.125 * (ec[I * Pc + J1] + ec[(I + 1) * Pc + J1]);
+}
+
+// Workgroups are dispatched to the 8 XCDs round-robin by flat id.  Map the
+// flat id so that XCD x gets a contiguous run of tiles (a band of tile rows):
+// halo re-reads and the next kernel's reads of this band then hit that
+// XCD's own L2.  Bijective for any tile count.
+__device__ __forceinline__ void xcd_tile(int& bx, int& by) {
+    const int nbx = gridDim.x;
+    const int n = nbx * gridDim.y;
+    const int b = blockIdx.y * nbx + blockIdx.x;
+    const int x = b & 7, k = b >> 3;
+    const int q = n >> 3, r = n & 7;
+    const int t = x * q + (x < r ? x : r) + k;
+    by = t / nbx;
+    bx = t - by * nbx;
+}
+
+__device__ __forceinline__ bool is_vx(const Geom& g, int i, int j) { return i >= 1 && i <= g.ny && j >= 1 && j < g.nx; }
+__device__ __forceinline__ bool is_vy(const Geom& g, int i, int j) { return i >= 1 && i < g.ny && j >= 1 && j <= g.nx; }
+
+// ---------------------------------------------------------------------------
+// smoothing sweep on an LDS tile
+// ---------------------------------------------------------------------------
+template <typename T, int TW, int TH, int SM, int MODE>
+__device__ __forceinline__ void smooth_tile_body(const Geom& g, const Geom& gc, const T* __restrict__ exi,
+                                                 const T* __restrict__ eyi, T* __restrict__ exo,
+                                                 T* __restrict__ eyo, const T* __restrict__ rx,
+                                                 const T* __restrict__ ry, const T* __restrict__ eb,
+                                                 const T* __restrict__ ep, const T* __restrict__ ecx,
+                                                 const T* __restrict__ ecy, T omega, int tbx, int tby) {
+    constexpr int H = SM == kSmGS ? 4 : 1;
+    constexpr int RW = TW + 2 * H;
+    constexpr int RH = TH + 2 * H;
+    constexpr int RN = RW * RH;
+    // coarse window for the fused prolongation (rows/columns of the coarse grid)
+    constexpr int CR = MODE == kModeProlong ? RH / 2 + 4 : 1;
+    constexpr int CC = MODE == kModeProlong ? RW / 2 + 4 : 1;
+    __shared__ T sx[RN], sy[RN], srx[RN], sry[RN], sb[RN], sp[RN];
+    __shared__ T scx[CR * CC], scy[CR * CC];
+    const int tid = threadIdx.x;
+    const int i0 = 1 + tby * TH;
+    const int j0 = 1 + tbx * TW;
+    const int gi0 = i0 - H, gj0 = j0 - H;
+    const int P = g.pitch;
+    const LevelC<T> k = level_consts<T>(g);
+    // first coarse row / column of the window: floor(gi0 / 2) - 1 (gi0 may be negative)
+    const int ci0 = ((gi0 + 16) >> 1) - 8 - 1;
+    const int cj0 = ((gj0 + 16) >> 1) - 8 - 1;
+    if (MODE == kModeProlong) {
+        for (int q = tid; q < CR * CC; q += 256) {
+            const int a = q / CC, b = q - (q / CC) * CC;
+            const int I = ci0 + a, J = cj0 + b;
+            const bool in = I >= 0 && I <= gc.ny + 1 && J >= 0 && J <= gc.nx + 1;
+            scx[q] = in ? ecx[I * gc.pitch + J] : (T)0;
+            scy[q] = in ? ecy[I * gc.pitch + J] : (T)0;
+        }
+        __syncthreads();
+    }
+
+    for (int q = tid; q < RN; q += 256) {
+        const int a = q / RW, b = q - (q / RW) * RW;
+        const int gi = gi0 + a, gj = gj0 + b;
+        const bool in = gi >= 0 && gi <= g.ny + 1 && gj >= 0 && gj <= g.nx + 1;
+        const int c = gi * P + gj;
+        sb[q] = in ? eb[c] : (T)0;
+        sp[q] = in ? ep[c] : (T)0;
+        srx[q] = in ? rx[c] : (T)0;
+        sry[q] = in ? ry[c] : (T)0;
+        if (MODE == kModeZero) {
+            sx[q] = (T)0;
+            sy[q] = (T)0;
+        } else {
+            T vx = in ? exi[c] : (T)0;
+            T vy = in ? eyi[c] : (T)0;
+            if (MODE == kModeProlong) {
+                // coarse indices are taken relative to the LDS window
+                if (is_vx(g, gi, gj)) vx += prolong_vx(scx - ci0 * CC - cj0, CC, gi, gj);
+                if (is_vy(g, gi, gj)) vy += prolong_vy(scy - ci0 * CC - cj0, CC, gi, gj);
+            }
+            sx[q] = vx;
+            sy[q] = vy;
+        }
+    }
+    __syncthreads();
+    if (MODE == kModeProlong) {
+        // ghosts mirror the corrected interior values
+        for (int q = tid; q < RN; q += 256) {
+            const int a = q / RW, b = q - (q / RW) * RW;
+            const int gi = gi0 + a, gj = gj0 + b;
+            if (gj >= 1 && gj < g.nx) {
+                if (gi == 0 && a + 1 < RH) sx[q] = k.mirS * sx[q + RW];
+                if (gi == g.ny + 1 && a >= 1) sx[q] = k.mirN * sx[q - RW];
+            }
+            if (gi >= 1 && gi < g.ny) {
+                if (gj == 0 && b + 1 < RW) sy[q] = k.mirW * sy[q + 1];
+                if (gj == g.nx + 1 && b >= 1) sy[q] = k.mirE * sy[q - 1];
+            }
+        }
+        __syncthreads();
+    }
+
+    if (SM == kSmGS) {
+        // stage s: component (s >> 1), colour (s & 1), halo 3 - s
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int comp = s >> 1, col = s & 1, h = 3 - s;
+            const int rows = TH + 2 * h, half = (TW + 2 * h) / 2;
+            const int a0 = H - h, b0 = H - h;
+            for (int q = tid; q < rows * half; q += 256) {
+                const int ar = q / half, bb = q - (q / half) * half;
+                const int a = a0 + ar;
+                const int p0 = (gi0 + a + gj0 + b0) & 1;
+                const int b = b0 + 2 * bb + (col ^ p0);
+                const int gi = gi0 + a, gj = gj0 + b;
+                const int c = a * RW + b;
+                if (comp == 0) {
+                    if (!is_vx(g, gi, gj)) continue;
+                    const T d = lx_diag(sb, sp, c, RW, gi, g.ny, k);
+                    const T res = srx[c] - lx_row(sx, sy, sb, sp, c, RW, k.idx, k.idy);
+                    sx[c] = sx[c] + omega * res / d;
+                } else {
+                    if (!is_vy(g, gi, gj)) continue;
+                    const T d = ly_diag(sb, sp, c, RW, gj, g.nx, k);
+                    const T res = sry[c] - ly_row(sx, sy, sb, sp, c, RW, k.idx, k.idy);
+                    sy[c] = sy[c] + omega * res / d;
+                }
+            }
+            __syncthreads();
+        }
+        for (int q = tid; q < TW * TH; q += 256) {
+            const int a = H + q / TW, b = H + (q - (q / TW) * TW);
+            const int gi = gi0 + a, gj = gj0 + b;
+            const int c = a * RW + b;
+            const int cg = gi * P + gj;
+            if (is_vx(g, gi, gj)) {
+                const T e = sx[c];
+                exo[cg] = e;
+                if (gi == 1) exo[cg - P] = k.mirS * e;
+                if (gi == g.ny) exo[cg + P] = k.mirN * e;
+            }
+            if (is_vy(g, gi, gj)) {
+                const T e = sy[c];
+                eyo[cg] = e;
+                if (gj == 1) eyo[cg - 1] = k.mirW * e;
+                if (gj == g.nx) eyo[cg + 1] = k.mirE * e;
+            }
+        }
+    } else {
+        for (int q = tid; q < TW * TH; q += 256) {
+            const int a = H + q / TW, b = H + (q - (q / TW) * TW);
+            const int gi = gi0 + a, gj = gj0 + b;
+            const int c = a * RW + b;
+            const int cg = gi * P + gj;
+            if (is_vx(g, gi, gj)) {
+                const T d = lx_diag(sb, sp, c, RW, gi, g.ny, k);
+                const T e = sx[c] + omega * (srx[c] - lx_row(sx, sy, sb, sp, c, RW, k.idx, k.idy)) / d;
+                exo[cg] = e;
+                if (gi == 1) exo[cg - P] = k.mirS * e;
+                if (gi == g.ny) exo[cg + P] = k.mirN * e;
+            }
+            if (is_vy(g, gi, gj)) {
+                const T d = ly_diag(sb, sp, c, RW, gj, g.nx, k);
+                const T e = sy[c] + omega * (sry[c] - ly_row(sx, sy, sb, sp, c, RW, k.idx, k.idy)) / d;
+                eyo[cg] = e;
+                if (gj == 1) eyo[cg - 1] = k.mirW * e;
+                if (gj == g.nx) eyo[cg + 1] = k.mirE * e;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// fused residual + restriction
+// ---------------------------------------------------------------------------
+template <typename T, int CTW, int CTH>
+__device__ __forceinline__ void res_restrict_body(const Geom& g, const Geom& gc, const T* __restrict__ ex,
+                                                  const T* __restrict__ ey, const T* __restrict__ rx,
+                                                  const T* __restrict__ ry, const T* __restrict__ eb,
+                                                  const T* __restrict__ ep, T* __restrict__ rcx,
+                                                  T* __restrict__ rcy, int tbx, int tby) {
+    constexpr int NT = CTW * CTH;
+    constexpr int RR = 2 * CTH + 2, RC = 2 * CTW + 2;   // fine residual footprint
+    constexpr int LR = RR + 2, LC = RC + 2;             // loaded region
+    constexpr int LN = LR * LC, RN = RR * RC;
+    __shared__ T sx[LN], sy[LN], sb[LN], sp[LN], stx[RN], sty[RN];
+    const int tid = threadIdx.x;
+    const int I0 = 1 + tby * CTH, J0 = 1 + tbx * CTW;
+    const int fi0 = 2 * I0 - 2, fj0 = 2 * J0 - 2;       // first residual row / column
+    const int li0 = fi0 - 1, lj0 = fj0 - 1;             // first loaded row / column
+    const int P = g.pitch;
+    const LevelC<T> k = level_consts<T>(g);
+    for (int q = tid; q < LN; q += NT) {
+        const int a = q / LC, b = q - (q / LC) * LC;
+        const int gi = li0 + a, gj = lj0 + b;
+        const bool in = gi >= 0 && gi <= g.ny + 1 && gj >= 0 && gj <= g.nx + 1;
+        const int c = gi * P + gj;
+        sx[q] = in ? ex[c] : (T)0;
+        sy[q] = in ? ey[c] : (T)0;
+        sb[q] = in ? eb[c] : (T)0;
+        sp[q] = in ? ep[c] : (T)0;
+    }
+    __syncthreads();
+    for (int q = tid; q < RN; q += NT) {
+        const int a = q / RC, b = q - (q / RC) * RC;
+        const int gi = fi0 + a, gj = fj0 + b;
+        const int cl = (a + 1) * LC + (b + 1);
+        const int cg = gi * P + gj;
+        stx[q] = is_vx(g, gi, gj) ? rx[cg] - lx_row(sx, sy, sb, sp, cl, LC, k.idx, k.idy) : (T)0;
+        sty[q] = is_vy(g, gi, gj) ? ry[cg] - ly_row(sx, sy, sb, sp, cl, LC, k.idx, k.idy) : (T)0;
+    }
+    __syncthreads();
+    const int I = I0 + tid / CTW, J = J0 + (tid - (tid / CTW) * CTW);
+    if (I > gc.ny || J > gc.nx) return;
+    const int C = I * gc.pitch + J;
+    if (J < gc.nx) {
+        T s = (T)0, wy = (T)0;
+        for (int a4 = 0; a4 < 4; ++a4) {
+            const int i = 2 * I - 2 + a4;
+            if (i < 1 || i > g.ny) continue;
+            const T w = (a4 == 1 || a4 == 2) ? (T)0.75 : (T)0.25;
+            const int c = (i - fi0) * RC + (2 * J - fj0);
+            s += w * ((T)0.5 * stx[c - 1] + stx[c] + (T)0.5 * stx[c + 1]);
+            wy += w;
+        }
+        rcx[C] = s / ((T)2 * wy);
+    }
+    if (I < gc.ny) {
+        T s = (T)0, wx = (T)0;
+        for (int b4 = 0; b4 < 4; ++b4) {
+            const int j = 2 * J - 2 + b4;
+            if (j < 1 || j > g.nx) continue;
+            const T w = (b4 == 1 || b4 == 2) ? (T)0.75 : (T)0.25;
+            const int c = (2 * I - fi0) * RC + (j - fj0);
+            s += w * ((T)0.5 * sty[c - RC] + sty[c] + (T)0.5 * sty[c + RC]);
+            wx += w;
+        }
+        rcy[C] = s / ((T)2 * wx);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// coarse tail of the V-cycle in one workgroup
+// ---------------------------------------------------------------------------
+template <typename T>
+struct LGeo {            // a level inside LDS: tight pitch nx + 2
+    int nx, ny, P;
+    T idx, idy, idx2, idy2;
+};
+
+template <typename T>
+__device__ void cc_gs_half(const LGeo<T>& L, const LevelC<T>& k, int comp, int col, T* ex, T* ey, const T* rx,
+                           const T* ry, const T* eb, const T* ep, T omega) {
+    const int ncol = comp == 0 ? L.nx - 1 : L.nx;
+    const int nrow = comp == 0 ? L.ny : L.ny - 1;
+    const int n = nrow * ncol;
+    for (int q = threadIdx.x; q < n; q += blockDim.x) {
+        const int i = 1 + q / ncol, j = 1 + (q - (q / ncol) * ncol);
+        if (((i + j) & 1) != col) continue;
+        const int c = i * L.P + j;
+        if (comp == 0) {
+            const T d = lx_diag(eb, ep, c, L.P, i, L.ny, k);
+            const T e = ex[c] + omega * (rx[c] - lx_row(ex, ey, eb, ep, c, L.P, k.idx, k.idy)) / d;
+            ex[c] = e;
+            if (i == 1) ex[c - L.P] = k.mirS * e;
+            if (i == L.ny) ex[c + L.P] = k.mirN * e;
+        } else {
+            const T d = ly_diag(eb, ep, c, L.P, j, L.nx, k);
+            const T e = ey[c] + omega * (ry[c] - ly_row(ex, ey, eb, ep, c, L.P, k.idx, k.idy)) / d;
+            ey[c] = e;
+            if (j == 1) ey[c - 1] = k.mirW * e;
+            if (j == L.nx) ey[c + 1] = k.mirE * e;
+        }
+    }
+}
+
+// Jacobi sweep in place: new values held in registers across a barrier
+template <typename T>
+__device__ void cc_jacobi(const LGeo<T>& L, const LevelC<T>& k, T* ex, T* ey, const T* rx, const T* ry,
+                          const T* eb, const T* ep, T omega) {
+    constexpr int KMAX = 8;
+    T nvx[KMAX], nvy[KMAX];
+    const int n = L.ny * L.nx;
+    int t = 0;
+    for (int q = threadIdx.x; q < n && t < KMAX; q += blockDim.x, ++t) {
+        const int i = 1 + q / L.nx, j = 1 + (q - (q / L.nx) * L.nx);
+        const int c = i * L.P + j;
+        nvx[t] = (j < L.nx) ? ex[c] + omega * (rx[c] - lx_row(ex, ey, eb, ep, c, L.P, k.idx, k.idy)) /
+                                          lx_diag(eb, ep, c, L.P, i, L.ny, k)
+                            : (T)0;
+        nvy[t] = (i < L.ny) ? ey[c] + omega * (ry[c] - ly_row(ex, ey, eb, ep, c, L.P, k.idx, k.idy)) /
+                                          ly_diag(eb, ep, c, L.P, j, L.nx, k)
+                            : (T)0;
+    }
+    __syncthreads();
+    t = 0;
+    for (int q = threadIdx.x; q < n && t < KMAX; q += blockDim.x, ++t) {
+        const int i = 1 + q / L.nx, j = 1 + (q - (q / L.nx) * L.nx);
+        const int c = i * L.P + j;
+        if (j < L.nx) {
+            ex[c] = nvx[t];
+            if (i == 1) ex[c - L.P] = k.mirS * nvx[t];
+            if (i == L.ny) ex[c + L.P] = k.mirN * nvx[t];
+        }
+        if (i < L.ny) {
+            ey[c] = nvy[t];
+            if (j == 1) ey[c - 1] = k.mirW * nvy[t];
+            if (j == L.nx) ey[c + 1] = k.mirE * nvy[t];
+        }
+    }
+    __syncthreads();
+}
+
+// FP32: 1024 threads; FP64: 512 threads so the kernel fits 256 VGPRs without spilling
+template <typename T>
+constexpr int coarse_threads() { return sizeof(T) == 4 ? 1024 : 512; }
+
+template <typename T>
+__device__ __forceinline__ void coarse_cycle_body(const CoarseArgs<T>& A) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* sm = (T*)smem_raw;
+    const int nl = A.nl;
+    // per-level tables live in LDS (not in per-lane arrays, which would go
+    // to scratch when indexed by the level number)
+    __shared__ LGeo<T> L[kMaxLevels];
+    __shared__ LevelC<T> K[kMaxLevels];
+    __shared__ int foff[kMaxLevels];
+    __shared__ int s_top_off;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    if (tid == 0) {
+        int off = 0;
+        for (int l = 0; l < nl; ++l) {
+            L[l].nx = A.g[l].nx;
+            L[l].ny = A.g[l].ny;
+            L[l].P = A.g[l].nx + 2;
+            K[l] = level_consts<T>(A.g[l]);
+            foff[l] = off;
+            off += 6 * (L[l].ny + 2) * L[l].P;
+        }
+        s_top_off = off;
+    }
+    __syncthreads();
+    // field q of level l: ex, ey, rx, ry, eb, ep
+    auto F = [&](int l, int q) -> T* { return sm + foff[l] + q * (L[l].ny + 2) * L[l].P; };
+    const int ntop = (L[0].ny + 2) * L[0].P;
+    T* tx = sm + s_top_off;
+    T* ty = tx + ntop;
+    const size_t off_end = (size_t)s_top_off + 2 * (size_t)ntop;
+    double* rs = (double*)(sm + ((off_end * sizeof(T) + 7) / 8) * 8 / sizeof(T));
+
+    // load viscosities of every level and the right-hand side of the top level; zero the rest
+    for (int l = 0; l < nl; ++l) {
+        const int P = L[l].P;
+        const int n = (L[l].ny + 2) * P;
+        const int Pg = A.g[l].pitch;
+        const T* geb = A.eb[l];
+        const T* gep = A.ep[l];
+        T *ex = F(l, 0), *ey = F(l, 1), *rx = F(l, 2), *ry = F(l, 3), *eb = F(l, 4), *ep = F(l, 5);
+        for (int q = tid; q < n; q += nthr) {
+            const int i = q / P, j = q - (q / P) * P;
+            const int cg = i * Pg + j;
+            ex[q] = (T)0;
+            ey[q] = (T)0;
+            rx[q] = l == 0 ? A.rx[cg] : (T)0;
+            ry[q] = l == 0 ? A.ry[cg] : (T)0;
+            eb[q] = geb[cg];
+            ep[q] = gep[cg];
+        }
+    }
+    __syncthreads();
+
+    auto smooth = [&](int l, int nu) {
+        T *ex = F(l, 0), *ey = F(l, 1), *rx = F(l, 2), *ry = F(l, 3), *eb = F(l, 4), *ep = F(l, 5);
+        for (int s = 0; s < nu; ++s) {
+            if (A.smoother == kSmGS) {
+                for (int h = 0; h < 4; ++h) {
+                    cc_gs_half(L[l], K[l], h >> 1, h & 1, ex, ey, rx, ry, eb, ep, A.omega);
+                    __syncthreads();
+                }
+            } else {
+                cc_jacobi(L[l], K[l], ex, ey, rx, ry, eb, ep, A.omega);
+            }
+        }
+    };
+
+    // ---- down: smooth, residual, restrict
+    for (int l = 0; l < nl - 1; ++l) {
+        smooth(l, A.nu_pre[l]);
+        const LGeo<T>& G = L[l];
+        T *ex = F(l, 0), *ey = F(l, 1), *rx = F(l, 2), *ry = F(l, 3), *eb = F(l, 4), *ep = F(l, 5);
+        const int n = (G.ny + 2) * G.P;
+        for (int q = tid; q < n; q += nthr) {
+            const int i = q / G.P, j = q - (q / G.P) * G.P;
+            const bool vx = i >= 1 && i <= G.ny && j >= 1 && j < G.nx;
+            const bool vy = i >= 1 && i < G.ny && j >= 1 && j <= G.nx;
+            tx[q] = vx ? rx[q] - lx_row(ex, ey, eb, ep, q, G.P, K[l].idx, K[l].idy) : (T)0;
+            ty[q] = vy ? ry[q] - ly_row(ex, ey, eb, ep, q, G.P, K[l].idx, K[l].idy) : (T)0;
+        }
+        __syncthreads();
+        const LGeo<T>& C = L[l + 1];
+        T *rcx = F(l + 1, 2), *rcy = F(l + 1, 3);
+        const int nc = C.ny * C.nx;
+        for (int q = tid; q < nc; q += nthr) {
+            const int I = 1 + q / C.nx, J = 1 + (q - (q / C.nx) * C.nx);
+            const int Cc = I * C.P + J;
+            if (J < C.nx) {
+                T s = (T)0, wy = (T)0;
+                for (int a4 = 0; a4 < 4; ++a4) {
+                    const int i = 2 * I - 2 + a4;
+                    if (i < 1 || i > G.ny) continue;
+                    const T w = (a4 == 1 || a4 == 2) ? (T)0.75 : (T)0.25;
+                    const int c = i * G.P + 2 * J;
+                    s += w * ((T)0.5 * tx[c - 1] + tx[c] + (T)0.5 * tx[c + 1]);
+                    wy += w;
+                }
+                rcx[Cc] = s / ((T)2 * wy);
+            }
+            if (I < C.ny) {
+                T s = (T)0, wx = (T)0;
+                for (int b4 = 0; b4 < 4; ++b4) {
+                    const int j = 2 * J - 2 + b4;
+                    if (j < 1 || j > G.nx) continue;
+                    const T w = (b4 == 1 || b4 == 2) ? (T)0.75 : (T)0.25;
+                    const int c = 2 * I * G.P + j;
+                    s += w * ((T)0.5 * ty[c - G.P] + ty[c] + (T)0.5 * ty[c + G.P]);
+                    wx += w;
+                }
+                rcy[Cc] = s / ((T)2 * wx);
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- coarsest: e = -(-L)^{-1} r in FP64 (one wavefront per row)
+    {
+        const int l = nl - 1;
+        const LGeo<T>& G = L[l];
+        T *ex = F(l, 0), *ey = F(l, 1), *rx = F(l, 2), *ry = F(l, 3);
+        const int nvx = G.ny * (G.nx - 1);
+        const int n = A.nc;
+        for (int m = tid; m < n; m += nthr) {
+            int i, j;
+            if (m < nvx) { i = 1 + m / (G.nx - 1); j = 1 + m % (G.nx - 1); rs[m] = (double)rx[i * G.P + j]; }
+            else { const int mm = m - nvx; i = 1 + mm / G.nx; j = 1 + mm % G.nx; rs[m] = (double)ry[i * G.P + j]; }
+        }
+        __syncthreads();
+        const int lane = tid & 63, wave = tid >> 6, nwave = nthr >> 6;
+        for (int m = wave; m < n; m += nwave) {
+            const double* row = A.Minv + (size_t)m * n;
+            double s = 0.0;
+            for (int q = lane; q < n; q += 64) s += row[q] * rs[q];
+            s = wave_sum(s);
+            if (lane == 0) {
+                const T e = (T)(-s);
+                int i, j;
+                if (m < nvx) {
+                    i = 1 + m / (G.nx - 1); j = 1 + m % (G.nx - 1);
+                    const int c = i * G.P + j;
+                    ex[c] = e;
+                    if (i == 1) ex[c - G.P] = K[l].mirS * e;
+                    if (i == G.ny) ex[c + G.P] = K[l].mirN * e;
+                } else {
+                    const int mm = m - nvx;
+                    i = 1 + mm / G.nx; j = 1 + mm % G.nx;
+                    const int c = i * G.P + j;
+                    ey[c] = e;
+                    if (j == 1) ey[c - 1] = K[l].mirW * e;
+                    if (j == G.nx) ey[c + 1] = K[l].mirE * e;
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- up: prolong + correct, post-smooth
+    for (int l = nl - 2; l >= 0; --l) {
+        const LGeo<T>& G = L[l];
+        const LGeo<T>& C = L[l + 1];
+        T *ex = F(l, 0), *ey = F(l, 1);
+        const T *ecx = F(l + 1, 0), *ecy = F(l + 1, 1);
+        const int n = G.ny * G.nx;
+        for (int q = tid; q < n; q += nthr) {
+            const int i = 1 + q / G.nx, j = 1 + (q - (q / G.nx) * G.nx);
+            const int c = i * G.P + j;
+            if (j < G.nx) {
+                const T e = ex[c] + prolong_vx(ecx, C.P, i, j);
+                ex[c] = e;
+                if (i == 1) ex[c - G.P] = K[l].mirS * e;
+                if (i == G.ny) ex[c + G.P] = K[l].mirN * e;
+            }
+            if (i < G.ny) {
+                const T e = ey[c] + prolong_vy(ecy, C.P, i, j);
+                ey[c] = e;
+                if (j == 1) ey[c - 1] = K[l].mirW * e;
+                if (j == G.nx) ey[c + 1] = K[l].mirE * e;
+            }
+        }
+        __syncthreads();
+        smooth(l, A.nu_post[l]);
+    }
+
+    // ---- write the top-level correction (every entry: walls zero, ghosts mirrored)
+    {
+        const int n = (L[0].ny + 2) * L[0].P;
+        const int Pg = A.g[0].pitch;
+        for (int q = tid; q < n; q += nthr) {
+            const int i = q / L[0].P, j = q - (q / L[0].P) * L[0].P;
+            A.ex[i * Pg + j] = F(0, 0)[q];
+            A.ey[i * Pg + j] = F(0, 1)[q];
+        }
+    }
+}
+
+template <typename T>
+constexpr int tile_h() { return sizeof(T) == 4 ? 16 : 8; }
+template <typename T>
+constexpr int rr_tile_h() { return sizeof(T) == 4 ? 8 : 4; }
+constexpr int kTileW = 64;
+constexpr int kRRTileW = 32;
+
+}  // namespace dev
+}  // namespace tph

@@ -24,6 +24,7 @@
 #include "../../include/tephra.h"
 #include "common.h"
 #include "kernels.h"
+#include "solver_internal.h"
 
 using namespace tph;
 
@@ -625,7 +626,8 @@ tph_status create_impl(const tph_desc* desc, void* stream, tph_solver* s) {
     if (desc->fused && nlev >= 2 && s->ncoarse <= 2048) {
         // highest level (smallest index) whose tail fits in one workgroup's LDS
         // and whose per-sweep work suits one workgroup (<= 64 x 64 cells)
-        const size_t budget = (size_t)std::min(s->max_lds, 160 * 1024) - 1024;
+        // leave room for the kernel's static LDS (per-level tables, a few KB)
+        const size_t budget = (size_t)std::min(s->max_lds, 160 * 1024) - 8 * 1024;
         for (int l = 0; l < nlev - 1; ++l) {
             Geom gs[kMaxLevels];
             for (int q = l; q < nlev; ++q) gs[q - l] = s->lev[q].g;
@@ -727,6 +729,51 @@ tph_status time_kernel_t(tph_solver* s, int kind, int reps, double* ms, double* 
 }
 
 }  // namespace
+
+// ============================================================ internal view
+TphSolverView tph_internal_view(const tph_solver* s) {
+    TphSolverView v{};
+    v.nlev = s->nlev;
+    v.lc = s->lc;
+    v.lc_lds = s->lc_lds;
+    v.ncoarse = s->ncoarse;
+    for (int l = 0; l < s->nlev; ++l) {
+        const LevelBuf& L = s->lev[l];
+        v.g[l] = L.g;
+        v.eb[l] = L.eb;
+        v.ep[l] = L.ep;
+        for (int k = 0; k < 2; ++k) {
+            v.ex[l][k] = L.ex[k];
+            v.ey[l][k] = L.ey[k];
+        }
+        v.rx[l] = L.rx;
+        v.ry[l] = L.ry;
+        v.nu_pre[l] = L.nu_pre;
+        v.nu_post[l] = L.nu_post;
+    }
+    v.Minv = s->Minv;
+    v.eb64 = s->lev[0].eb64;
+    v.ep64 = s->lev[0].ep64;
+    v.x = s->x;
+    v.b = s->b;
+    v.V = s->V;
+    v.Z = s->Z;
+    v.t3 = s->t3;
+    v.F = s->F;
+    v.n3 = s->n3;
+    return v;
+}
+
+void tph_internal_set_error(const std::string& msg) { g_last_error = msg; }
+
+tph_status tph_internal_load_solution(tph_solver* s, const double* vx, const double* vy, const double* p) {
+    return load_solution(s, s->x, vx, vy, p);
+}
+
+tph_status tph_internal_finish_solution(tph_solver* s, double* vx, double* vy, double* p) {
+    TPH_TRY(remove_pressure_mean(s, s->x));
+    return store_solution(s, s->x, vx, vy, p);
+}
 
 // ====================================================================== C ABI
 extern "C" {

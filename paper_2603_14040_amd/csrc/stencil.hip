@@ -12,6 +12,7 @@
 #include "kernels.h"
 #include "reduce.h"
 #include "stencil.h"
+#include "stencil_dev.h"
 
 namespace tph {
 namespace {
@@ -27,45 +28,7 @@ __global__ __launch_bounds__(256) void k_outer_residual(Geom g, Vec3 x, Vec3 b, 
                                                        int apply, int energy, double* partial, int bscaled) {
     const int j = blockIdx.x * BX + threadIdx.x + 1;
     const int i = blockIdx.y * BY + threadIdx.y + 1;
-    const LevelC<double> k = level_consts<double>(g);
-    const int P = g.pitch;
-    double acc = 0.0;
-    if (i <= g.ny && j <= g.nx) {
-        const int c = i * P + j;
-        const double* vx = x.vx();
-        const double* vy = x.vy();
-        const double* p = x.p();
-        if (j < g.nx) {
-            const double a = lx_row(vx, vy, eb, ep, c, P, k.idx, k.idy) - (p[c + 1] - p[c]) * k.idx;
-            const double sq = (energy || bscaled) ? sqrt(-lx_diag(eb, ep, c, P, i, g.ny, k)) : 1.0;
-            double bv = has_b ? b.vx()[c] : 0.0;
-            if (bscaled) bv *= sq;
-            double r = apply ? a : (bv - a);
-            if (energy) r *= 1.0 / sq;
-            out.vx()[c] = r;
-            acc += r * r;
-        }
-        if (i < g.ny) {
-            const double a = ly_row(vx, vy, eb, ep, c, P, k.idx, k.idy) - (p[c + P] - p[c]) * k.idy;
-            const double sq = (energy || bscaled) ? sqrt(-ly_diag(eb, ep, c, P, j, g.nx, k)) : 1.0;
-            double bv = has_b ? b.vy()[c] : 0.0;
-            if (bscaled) bv *= sq;
-            double r = apply ? a : (bv - a);
-            if (energy) r *= 1.0 / sq;
-            out.vy()[c] = r;
-            acc += r * r;
-        }
-        {
-            const double a = (vx[c] - vx[c - 1]) * k.idx + (vy[c] - vy[c - P]) * k.idy;
-            const double sw = (energy || bscaled) ? sqrt(wp_weight(ep[c], k)) : 1.0;
-            double bv = has_b ? b.p()[c] : 0.0;
-            if (bscaled) bv /= sw;
-            double r = apply ? a : (bv - a);
-            if (energy) r *= sw;
-            out.p()[c] = r;
-            acc += r * r;
-        }
-    }
+    const double acc = outer_residual_cell(g, x, b, has_b, eb, ep, out, apply, energy, bscaled, i, j);
     if (partial) {
         const double s = block_sum(acc);
         if (threadIdx.x == 0 && threadIdx.y == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = s;
@@ -207,20 +170,7 @@ __global__ __launch_bounds__(256) void k_precond_in(Geom g, Vec3 v, const double
                                                    T* __restrict__ rx, T* __restrict__ ry) {
     const int j = blockIdx.x * BX + threadIdx.x + 1;
     const int i = blockIdx.y * BY + threadIdx.y + 1;
-    if (i > g.ny || j > g.nx) return;
-    const LevelC<double> k = level_consts<double>(g);
-    const int P = g.pitch;
-    const int c = i * P + j;
-    if (j < g.nx) {
-        double r = v.vx()[c];
-        if (energy) r *= sqrt(-lx_diag(eb, ep, c, P, i, g.ny, k));
-        rx[c] = (T)r;
-    }
-    if (i < g.ny) {
-        double r = v.vy()[c];
-        if (energy) r *= sqrt(-ly_diag(eb, ep, c, P, j, g.nx, k));
-        ry[c] = (T)r;
-    }
+    precond_in_cell<T>(g, v, eb, ep, energy, rx, ry, i, j);
 }
 
 template <typename T>
@@ -229,30 +179,7 @@ __global__ __launch_bounds__(256) void k_precond_out(Geom g, const T* __restrict
                                                     double alpha, Vec3 z, int acc) {
     const int j = blockIdx.x * BX + threadIdx.x + 1;
     const int i = blockIdx.y * BY + threadIdx.y + 1;
-    if (i > g.ny || j > g.nx) return;
-    const LevelC<double> k = level_consts<double>(g);
-    const int P = g.pitch;
-    const int c = i * P + j;
-    double* zx = z.vx();
-    double* zy = z.vy();
-    if (j < g.nx) {
-        const double e = acc ? zx[c] + (double)ex[c] : (double)ex[c];
-        zx[c] = e;
-        if (i == 1) zx[c - P] = (double)g.mir[2] * e;
-        if (i == g.ny) zx[c + P] = (double)g.mir[3] * e;
-    }
-    if (i < g.ny) {
-        const double e = acc ? zy[c] + (double)ey[c] : (double)ey[c];
-        zy[c] = e;
-        if (j == 1) zy[c - 1] = (double)g.mir[0] * e;
-        if (j == g.nx) zy[c + 1] = (double)g.mir[1] * e;
-    }
-    // divergence of this step's (cast) velocity correction; walls read as zero
-    const double div = ((double)ex[c] - (double)ex[c - 1]) * k.idx + ((double)ey[c] - (double)ey[c - P]) * k.idy;
-    double rp = v.p()[c];
-    if (energy) rp *= 1.0 / sqrt(wp_weight(ep[c], k));
-    const double dp = alpha * ep[c] * (rp - div);
-    z.p()[c] = acc ? z.p()[c] + dp : dp;
+    precond_out_cell<T>(g, ex, ey, v, ep, energy, alpha, z, acc, i, j);
 }
 
 __global__ __launch_bounds__(256) void k_rhs(Geom g, const double* __restrict__ rho, double gx, double gy,

@@ -296,3 +296,83 @@ def test_adjoint_gradient_matches_oracle(bc):
                          (rho.grad, "g_rho_b", (slice(0, n + 1), slice(0, n + 1)))):
         a, b = N(got)[sl], ref[key][sl]
         assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-6, key
+
+
+@pytest.mark.parametrize("prec", [tph.FP64, tph.MIXED])
+def test_batched_solve_matches_oracle(prec):
+    """Uneven problems in one batch: each result matches its own oracle solve."""
+    probs = [wl.sinker(64, radius=0.12, eta_in=30.0),
+             wl.sinker(32, radius=0.2, eta_in=10.0),
+             wl.random_viscosity(64, ell=0.15, contrast=100.0),
+             wl.sinker(128, radius=0.08, eta_in=1e3),
+             wl.sinker(48, ny=32, lx=1.5, ly=1.0, center=(0.6, 0.5), eta_in=5.0),
+             wl.sinker(64, radius=0.15, eta_in=200.0, bc=(1, 1, 0, 1))]
+    shapes = [(p.nx, p.ny, p.lx, p.ly, p.bc) for p in probs]
+    print(f"[batch] prec={prec} shapes={shapes}", flush=True)
+    bat = tph.Batch(shapes, device=DEV, precision=prec, rtol=1e-11, max_iters=2000, restart=16)
+    bat.set_coefficients([T(p.eta_b) for p in probs], [T(p.eta_p) for p in probs],
+                         [T(p.rho_b) for p in probs], [(p.gx, p.gy) for p in probs])
+    vx, vy, pp, infos = bat.solve()
+    for k, pr in enumerate(probs):
+        g = st.Grid(pr.nx, pr.ny, pr.lx, pr.ly, pr.bc)
+        ref = st.solve(g, pr.eta_b, pr.eta_p, pr.rho_b, pr.gx, pr.gy)
+        ev, epr = st.parity_errors(g, ref, N(vx[k]), N(vy[k]), N(pp[k]))
+        print(f"[batch] problem {k} {pr.nx}x{pr.ny}: iters {infos[k].iters} res {infos[k].res_energy:.2e} "
+              f"err v {ev:.2e} p {epr:.2e}", flush=True)
+        assert infos[k].res_energy < 1e-10
+        assert ev < 1e-6 and epr < 1e-6
+        _check_solution_contract(pr.nx, pr.ny, pr.bc, N(vx[k]), N(vy[k]), N(pp[k]))
+    # a second solve on the same batch (graph replay, masks reset) gives the same answer
+    vx2, vy2, pp2, infos2 = bat.solve()
+    for k in range(len(probs)):
+        assert np.array_equal(N(vx[k]), N(vx2[k])) and np.array_equal(N(pp[k]), N(pp2[k]))
+    bat.close()
+
+
+def _eta_from_logvisc(m, n):
+    """eta_p = 10**m at cell centres; eta_b = 10**(mean of m over the touching cells) (torch, differentiable)."""
+    ep = torch.ones((n + 2, n + 2), dtype=torch.float64, device=m.device)
+    ep = ep.index_put((torch.arange(1, n + 1, device=m.device)[:, None],
+                       torch.arange(1, n + 1, device=m.device)[None, :]), 10.0 ** m)
+    mp = torch.nn.functional.pad(m, (1, 1, 1, 1))
+    one = torch.nn.functional.pad(torch.ones_like(m), (1, 1, 1, 1))
+    s = mp[:-1, :-1] + mp[1:, :-1] + mp[:-1, 1:] + mp[1:, 1:]
+    c = one[:-1, :-1] + one[1:, :-1] + one[:-1, 1:] + one[1:, 1:]
+    eb = torch.nn.functional.pad(10.0 ** (s / c), (0, 1, 0, 1), value=1.0)
+    return eb, ep
+
+
+def test_adjoint_gradient_finite_differences_full_size():
+    """Surface-velocity misfit on the 1024^2 random field: d J / d log10(eta)
+    from the adjoint solve against central differences (h = 1e-3) on 64
+    seeded cells, all solves mixed precision at a tight tolerance."""
+    n = 1024
+    base, m, m_true, cells = wl.adjoint_problem(n)
+    s = solver_for(n, n, precision=tph.MIXED, rtol=1e-11, max_iters=3000)
+    rho = T(base.rho_b)
+    eb_t, ep_t = wl.logvisc_to_eta(m_true, n, n)
+    s.set_coefficients(T(eb_t), T(ep_t), rho, base.gx, base.gy)
+    target = s.solve()[0][n, 1:n].clone()
+
+    def J_of(mm):
+        eb, ep = _eta_from_logvisc(mm, n)
+        vx, vy, p = tph.StokesFunction.apply(eb, ep, rho, s, base.gx, base.gy)
+        return 0.5 * (1.0 / n) * torch.sum((vx[n, 1:n] - target) ** 2)
+
+    mt = T(m).requires_grad_(True)
+    J = J_of(mt)
+    J.backward()
+    grad = N(mt.grad)
+    gmax = np.abs(grad).max()
+    h = 1e-3
+    errs = []
+    with torch.no_grad():
+        for (ci, cj) in cells:
+            i, j = int(ci) - 1, int(cj) - 1
+            mp_, mm_ = T(m), T(m)
+            mp_[i, j] += h
+            mm_[i, j] -= h
+            fd = (float(J_of(mp_)) - float(J_of(mm_))) / (2 * h)
+            errs.append(abs(grad[i, j] - fd) / max(abs(fd), 1e-3 * gmax))
+    print(f"[adjoint-fd] J={float(J):.4e} max rel err {max(errs):.2e} median {np.median(errs):.2e}", flush=True)
+    assert max(errs) < 1e-4
