@@ -205,7 +205,8 @@ tph_status tph_coeff_gradient(tph_solver* s, const double* vx, const double* vy,
 
 /* Kernels that tph_time_kernel can time. */
 enum {
-    TPH_KERNEL_SMOOTH = 0,   /* one finest-level smoother launch (Jacobi sweep or one GS colour half-sweep) */
+    TPH_KERNEL_SMOOTH = 0,   /* one finest-level smoother launch (fused: one full sweep on LDS tiles;
+                                otherwise a Jacobi sweep or one GS colour half-sweep) */
     TPH_KERNEL_APPLY = 1,    /* FP64 matrix-free operator apply with energy scaling (Krylov step) */
     TPH_KERNEL_RESIDUAL = 2, /* finest-level velocity residual r - L e in the V-cycle type */
     TPH_KERNEL_RESTRICT = 3, /* finest -> second level residual restriction */
@@ -220,6 +221,22 @@ enum {
  * on the solver's own workspace (the correction arrays are modified). */
 tph_status tph_time_kernel(tph_solver* s, int32_t kind, int32_t reps, double* ms_per_launch,
                            double* bytes_per_launch);
+
+/* Measurement hook for the smoother inside real solves.  While enabled
+ * (enable = 1), every finest-level smoothing launch of the fused V-cycle
+ * (desc.fused = 1) made by later solves on this handle is bracketed by a pair
+ * of HIP events on the solver's stream; up to 8192 launches are recorded
+ * between two reads, later ones are counted in *dropped.  The events are
+ * created on the first enable and live as long as the handle.
+ * tph_kernel_timing_read waits for the stream, returns the number of timed
+ * launches, their summed duration in ms and their summed algorithmic bytes
+ * (per cell: zero-guess sweep 6 words = read r (2), eta_b, eta_p, write e
+ * (2); sweep from an iterate 8 words; sweep with fused prolongation 8.5
+ * words, the coarse correction being a quarter of two fields), then resets
+ * the counters.  Timing adds two event records per launch to the stream. */
+tph_status tph_kernel_timing(tph_solver* s, int32_t enable);
+tph_status tph_kernel_timing_read(tph_solver* s, int32_t* launches, double* total_ms, double* total_bytes,
+                                  int32_t* dropped);
 
 /* Release everything the solver owns.  NULL is allowed. */
 void tph_destroy(tph_solver* s);

@@ -224,6 +224,17 @@ class Solver:
                                                                 ctypes.byref(by)))
         return ms.value, by.value
 
+    def kernel_timing(self, enable: bool = True):
+        """Bracket every finest-level smoothing launch of later solves with HIP events."""
+        _lib.check("tph_kernel_timing", self._lib.tph_kernel_timing(self._h, 1 if enable else 0))
+
+    def kernel_timing_read(self):
+        """(launches, total ms, total algorithmic bytes, dropped) since the last read; resets."""
+        n, ms, by, dr = ctypes.c_int32(), ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+        _lib.check("tph_kernel_timing_read", self._lib.tph_kernel_timing_read(
+            self._h, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by), ctypes.byref(dr)))
+        return n.value, ms.value, by.value, dr.value
+
     def coeff_gradient(self, vx, vy, p, lvx, lvy, lp):
         gb, gp, gr = self.zeros(), self.zeros(), self.zeros()
         self._sync_in()

@@ -81,6 +81,9 @@ def load(path: str = LIB_PATH):
         "tph_solve_adjoint": (c_int32, [P, P, P, P, P, P, P, POINTER(Info)]),
         "tph_coeff_gradient": (c_int32, [P, P, P, P, P, P, P, P, P, P]),
         "tph_time_kernel": (c_int32, [P, c_int32, c_int32, POINTER(c_double), POINTER(c_double)]),
+        "tph_kernel_timing": (c_int32, [P, c_int32]),
+        "tph_kernel_timing_read": (c_int32, [P, POINTER(c_int32), POINTER(c_double), POINTER(c_double),
+                                             POINTER(c_int32)]),
         "tph_destroy": (None, [P]),
         "tph_batch_create": (c_int32, [c_int32, POINTER(Desc), P, POINTER(P)]),
         "tph_batch_set_coefficients": (c_int32, [P, POINTER(P), POINTER(P), POINTER(P), POINTER(c_double)]),

@@ -109,6 +109,12 @@ struct tph_solver {
     double t_setup_ms = 0;
     long long reorth_count = 0;  // second Gram-Schmidt passes taken (diagnostic)
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // optional event timing of the finest-level smoother inside solves
+    bool ktime = false;
+    std::vector<hipEvent_t> kev;  // 2 per recorded launch
+    int kev_used = 0;
+    int kdropped = 0;
+    double kbytes = 0.0;
     std::vector<void*> dev_allocs;
     bool mixed() const { return d.precision == TPH_MIXED; }
 };
@@ -116,6 +122,25 @@ struct tph_solver {
 namespace {
 
 Vec3 vec3(const tph_solver* s, double* raw) { return Vec3{raw + (kAlign - 1), s->F}; }
+
+constexpr int kMaxTimedLaunches = 8192;
+
+// event bracket of one finest-level smoothing launch (only while timing is on)
+bool ktic(tph_solver* s, int l) {
+    if (!s->ktime || l != 0) return false;
+    if (s->kev_used + 2 > (int)s->kev.size()) {
+        ++s->kdropped;
+        return false;
+    }
+    return hipEventRecord(s->kev[s->kev_used], s->st) == hipSuccess;
+}
+
+void ktoc(tph_solver* s, bool on, double words, size_t wbytes) {
+    if (!on) return;
+    if (hipEventRecord(s->kev[s->kev_used + 1], s->st) != hipSuccess) return;
+    s->kev_used += 2;
+    s->kbytes += words * (double)s->lev[0].g.nx * (double)s->lev[0].g.ny * (double)wbytes;
+}
 
 tph_status dev_alloc(tph_solver* s, void** p, size_t bytes) {
     hipError_t e = hipMalloc(p, bytes);
@@ -290,11 +315,15 @@ tph_status vcycle_fused(tph_solver* s, int l, int* cur_out) {
     if (L.nu_pre == 0) {
         TPH_HIP(launch_zero_vel<T>(g, as<T>(L.ex[0]), as<T>(L.ey[0]), st));
     } else {
+        bool tk = ktic(s, l);
         TPH_HIP(launch_smooth_tile<T>(g, nullptr, sm, 1, nullptr, nullptr, as<T>(L.ex[0]), as<T>(L.ey[0]), rx, ry, eb,
                                       ep, nullptr, nullptr, om, st));
+        ktoc(s, tk, 6.0, sizeof(T));
         for (int k = 1; k < L.nu_pre; ++k) {
+            tk = ktic(s, l);
             TPH_HIP(launch_smooth_tile<T>(g, nullptr, sm, 0, as<T>(L.ex[cur]), as<T>(L.ey[cur]), as<T>(L.ex[1 - cur]),
                                           as<T>(L.ey[1 - cur]), rx, ry, eb, ep, nullptr, nullptr, om, st));
+            ktoc(s, tk, 8.0, sizeof(T));
             cur = 1 - cur;
         }
     }
@@ -307,13 +336,17 @@ tph_status vcycle_fused(tph_solver* s, int l, int* cur_out) {
         TPH_HIP(launch_prolong_add<T>(g, C.g, as<T>(C.ex[ccur]), as<T>(C.ey[ccur]), as<T>(L.ex[cur]),
                                       as<T>(L.ey[cur]), st));
     } else {
+        bool tk = ktic(s, l);
         TPH_HIP(launch_smooth_tile<T>(g, &C.g, sm, 2, as<T>(L.ex[cur]), as<T>(L.ey[cur]), as<T>(L.ex[1 - cur]),
                                       as<T>(L.ey[1 - cur]), rx, ry, eb, ep, as<T>(C.ex[ccur]), as<T>(C.ey[ccur]), om,
                                       st));
+        ktoc(s, tk, 8.5, sizeof(T));
         cur = 1 - cur;
         for (int k = 1; k < L.nu_post; ++k) {
+            tk = ktic(s, l);
             TPH_HIP(launch_smooth_tile<T>(g, nullptr, sm, 0, as<T>(L.ex[cur]), as<T>(L.ey[cur]), as<T>(L.ex[1 - cur]),
                                           as<T>(L.ey[1 - cur]), rx, ry, eb, ep, nullptr, nullptr, om, st));
+            ktoc(s, tk, 8.0, sizeof(T));
             cur = 1 - cur;
         }
     }
@@ -1023,6 +1056,50 @@ tph_status tph_time_kernel(tph_solver* s, int32_t kind, int32_t reps, double* ms
     return st;
 }
 
+tph_status tph_kernel_timing(tph_solver* s, int32_t enable) {
+    g_last_error.clear();
+    if (!s) { set_error("null handle"); return TPH_ERR_INVALID; }
+    if (enable != 0 && enable != 1) { set_error("enable must be 0 or 1"); return TPH_ERR_INVALID; }
+    if (enable && s->kev.empty()) {
+        s->kev.assign(2 * kMaxTimedLaunches, nullptr);
+        for (auto& e : s->kev) {
+            const hipError_t err = hipEventCreate(&e);
+            if (err != hipSuccess) {
+                for (auto& q : s->kev)
+                    if (q) (void)hipEventDestroy(q);
+                s->kev.clear();
+                set_error(std::string("hipEventCreate: ") + hipGetErrorString(err));
+                return TPH_ERR_HIP;
+            }
+        }
+    }
+    s->ktime = enable == 1;
+    return TPH_OK;
+}
+
+tph_status tph_kernel_timing_read(tph_solver* s, int32_t* launches, double* total_ms, double* total_bytes,
+                                  int32_t* dropped) {
+    g_last_error.clear();
+    if (!s) { set_error("null handle"); return TPH_ERR_INVALID; }
+    double ms = 0.0;
+    if (s->kev_used > 0) {
+        TPH_HIP(hipEventSynchronize(s->kev[s->kev_used - 1]));
+        for (int q = 0; q < s->kev_used; q += 2) {
+            float t = 0.0f;
+            TPH_HIP(hipEventElapsedTime(&t, s->kev[q], s->kev[q + 1]));
+            ms += t;
+        }
+    }
+    if (launches) *launches = s->kev_used / 2;
+    if (total_ms) *total_ms = ms;
+    if (total_bytes) *total_bytes = s->kbytes;
+    if (dropped) *dropped = s->kdropped;
+    s->kev_used = 0;
+    s->kdropped = 0;
+    s->kbytes = 0.0;
+    return TPH_OK;
+}
+
 void tph_destroy(tph_solver* s) {
     if (!s) return;
     if (s->st || !s->dev_allocs.empty()) (void)hipStreamSynchronize(s->st);
@@ -1030,6 +1107,8 @@ void tph_destroy(tph_solver* s) {
     if (s->hscal) (void)hipHostFree(s->hscal);
     if (s->ev0) (void)hipEventDestroy(s->ev0);
     if (s->ev1) (void)hipEventDestroy(s->ev1);
+    for (auto& e : s->kev)
+        if (e) (void)hipEventDestroy(e);
     delete s;
 }
 
