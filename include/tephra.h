@@ -108,7 +108,17 @@ typedef struct tph_desc {
     int32_t fused;         /* 1: LDS-tiled fused smoother / residual-restriction
                               kernels and the single-workgroup coarse tail;
                               0: one kernel per colour half-sweep (reference)    */
-    int32_t reserved[6];   /* must be zero                                    */
+    int32_t msweep;        /* levels whose smoothing runs in multi-sweep LDS passes
+                              (bit l = level l): up to two Gauss-Seidel sweeps per
+                              launch, the last pre-smoothing pass also forming the
+                              residual and restricting it, the first post-smoothing
+                              pass applying the prolongation; -1 = every level but
+                              the finest.  Used with fused = 1 and the Gauss-Seidel
+                              smoother, ignored otherwise                         */
+    int32_t tile_shape;    /* levels whose LDS tiles use the small shape (bit l);
+                              -1 = levels where the large shape gives fewer than
+                              512 tiles                                           */
+    int32_t reserved[4];   /* must be zero                                    */
 } tph_desc;
 
 typedef struct tph_info {
@@ -128,7 +138,8 @@ typedef struct tph_solver tph_solver;
  * mixed precision, automatic levels, coloured Gauss-Seidel (omega 1) with 2
  * pre- and 2 post-sweeps on every level, alpha 1, arithmetic coarse
  * viscosity, two Uzawa sweeps per preconditioner application, fused
- * kernels, rtol 1e-8, restart 20, max_iters 500. */
+ * kernels with the default multi-sweep levels and tile shapes (-1), rtol
+ * 1e-8, restart 20, max_iters 500. */
 void tph_desc_default(tph_desc* d, int32_t nx, int32_t ny);
 
 /* Create a solver for the grid in *desc; hip_stream is a hipStream_t (NULL:

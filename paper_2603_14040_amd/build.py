@@ -20,7 +20,8 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libtephra.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["stencil.hip", "transfer.hip", "coarse.hip", "krylov.hip", "fused.hip", "batch.hip", "solver.cpp"]
+SOURCES = ["stencil.hip", "transfer.hip", "coarse.hip", "krylov.hip", "fused.hip", "msweep_f32.hip", "msweep_f64.hip",
+           "batch.hip", "solver.cpp"]
 
 ARCH = "gfx950"
 CFLAGS = [

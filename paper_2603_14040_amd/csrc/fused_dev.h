@@ -30,7 +30,7 @@ namespace tph {
 namespace dev {
 
 
-enum { kModePlain = 0, kModeZero = 1, kModeProlong = 2 };
+enum { kModePlain = kTilePlain, kModeZero = kTileZero, kModeProlong = kTileProlong };
 enum { kSmJacobi = 0, kSmGS = 1 };
 
 // bilinear prolongation of the coarse vx / vy correction to fine node (i, j)
@@ -72,35 +72,33 @@ __device__ __forceinline__ bool is_vx(const Geom& g, int i, int j) { return i >=
 __device__ __forceinline__ bool is_vy(const Geom& g, int i, int j) { return i >= 1 && i < g.ny && j >= 1 && j <= g.nx; }
 
 // ---------------------------------------------------------------------------
-// smoothing sweep on an LDS tile
+// LDS tiles.  A tile of TW x TH nodes (origin (i0, j0) = (1 + tby TH,
+// 1 + tbx TW)) is held with a halo of H nodes: the iterate (sx, sy) and the
+// viscosities (sb, sp).  The right-hand side r is only ever needed at the
+// node being updated, so it is read from memory there and takes no LDS.
 // ---------------------------------------------------------------------------
-template <typename T, int TW, int TH, int SM, int MODE>
-__device__ __forceinline__ void smooth_tile_body(const Geom& g, const Geom& gc, const T* __restrict__ exi,
-                                                 const T* __restrict__ eyi, T* __restrict__ exo,
-                                                 T* __restrict__ eyo, const T* __restrict__ rx,
-                                                 const T* __restrict__ ry, const T* __restrict__ eb,
-                                                 const T* __restrict__ ep, const T* __restrict__ ecx,
-                                                 const T* __restrict__ ecy, T omega, int tbx, int tby) {
-    constexpr int H = SM == kSmGS ? 4 : 1;
-    constexpr int RW = TW + 2 * H;
-    constexpr int RH = TH + 2 * H;
+template <int RH>
+constexpr int prolong_rows() { return RH / 2 + 4; }
+
+// load the iterate (zero / from memory / from memory + prolongated coarse
+// correction) and the viscosities of the region starting at (gi0, gj0)
+template <typename T, int RW, int RH, int MODE>
+__device__ __forceinline__ void tile_load(const Geom& g, const Geom& gc, int gi0, int gj0, const T* __restrict__ exi,
+                                          const T* __restrict__ eyi, const T* __restrict__ eb,
+                                          const T* __restrict__ ep, const T* __restrict__ ecx,
+                                          const T* __restrict__ ecy, T* sx, T* sy, T* sb, T* sp, T* scx, T* scy,
+                                          const LevelC<T>& k) {
     constexpr int RN = RW * RH;
-    // coarse window for the fused prolongation (rows/columns of the coarse grid)
-    constexpr int CR = MODE == kModeProlong ? RH / 2 + 4 : 1;
-    constexpr int CC = MODE == kModeProlong ? RW / 2 + 4 : 1;
-    __shared__ T sx[RN], sy[RN], srx[RN], sry[RN], sb[RN], sp[RN];
-    __shared__ T scx[CR * CC], scy[CR * CC];
+    constexpr int CR = prolong_rows<RH>(), CC = prolong_rows<RW>();
     const int tid = threadIdx.x;
-    const int i0 = 1 + tby * TH;
-    const int j0 = 1 + tbx * TW;
-    const int gi0 = i0 - H, gj0 = j0 - H;
+    const int nt = blockDim.x;
     const int P = g.pitch;
-    const LevelC<T> k = level_consts<T>(g);
-    // first coarse row / column of the window: floor(gi0 / 2) - 1 (gi0 may be negative)
-    const int ci0 = ((gi0 + 16) >> 1) - 8 - 1;
-    const int cj0 = ((gj0 + 16) >> 1) - 8 - 1;
+    // first coarse row / column of the prolongation window: floor(gi0 / 2) - 1
+    // (gi0 may be negative; the +64 keeps the shift on a non-negative value)
+    const int ci0 = ((gi0 + 64) >> 1) - 32 - 1;
+    const int cj0 = ((gj0 + 64) >> 1) - 32 - 1;
     if (MODE == kModeProlong) {
-        for (int q = tid; q < CR * CC; q += 256) {
+        for (int q = tid; q < CR * CC; q += nt) {
             const int a = q / CC, b = q - (q / CC) * CC;
             const int I = ci0 + a, J = cj0 + b;
             const bool in = I >= 0 && I <= gc.ny + 1 && J >= 0 && J <= gc.nx + 1;
@@ -109,16 +107,13 @@ __device__ __forceinline__ void smooth_tile_body(const Geom& g, const Geom& gc, 
         }
         __syncthreads();
     }
-
-    for (int q = tid; q < RN; q += 256) {
+    for (int q = tid; q < RN; q += nt) {
         const int a = q / RW, b = q - (q / RW) * RW;
         const int gi = gi0 + a, gj = gj0 + b;
         const bool in = gi >= 0 && gi <= g.ny + 1 && gj >= 0 && gj <= g.nx + 1;
         const int c = gi * P + gj;
         sb[q] = in ? eb[c] : (T)0;
         sp[q] = in ? ep[c] : (T)0;
-        srx[q] = in ? rx[c] : (T)0;
-        sry[q] = in ? ry[c] : (T)0;
         if (MODE == kModeZero) {
             sx[q] = (T)0;
             sy[q] = (T)0;
@@ -137,7 +132,7 @@ __device__ __forceinline__ void smooth_tile_body(const Geom& g, const Geom& gc, 
     __syncthreads();
     if (MODE == kModeProlong) {
         // ghosts mirror the corrected interior values
-        for (int q = tid; q < RN; q += 256) {
+        for (int q = tid; q < RN; q += nt) {
             const int a = q / RW, b = q - (q / RW) * RW;
             const int gi = gi0 + a, gj = gj0 + b;
             if (gj >= 1 && gj < g.nx) {
@@ -151,75 +146,221 @@ __device__ __forceinline__ void smooth_tile_body(const Geom& g, const Geom& gc, 
         }
         __syncthreads();
     }
+}
 
-    if (SM == kSmGS) {
-        // stage s: component (s >> 1), colour (s & 1), halo 3 - s
+// NSTAGE colour half-sweeps (stage s: component (s >> 1) & 1, colour s & 1,
+// i.e. vx red, vx black, vy red, vy black, repeated).  Each stage needs the
+// previous one's values one node further out, so stage s updates the nodes
+// within H - 1 - s of the tile.  A wall-adjacent node refreshes its own
+// ghost right away; only that node reads the ghost, so the next sweep in
+// the tile sees the mirror of the latest value, as a sweep over the whole
+// grid with ghosts refilled between sweeps does.
+template <typename T, int TW, int TH, int H, int NSTAGE>
+__device__ __forceinline__ void gs_stages(const Geom& g, int gi0, int gj0, T* sx, T* sy, const T* sb, const T* sp,
+                                          const T* __restrict__ rx, const T* __restrict__ ry, T omega,
+                                          const LevelC<T>& k) {
+    constexpr int RW = TW + 2 * H, RH = TH + 2 * H;
+    const int tid = threadIdx.x;
+    const int nt = blockDim.x;
+    const int P = g.pitch;
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int comp = s >> 1, col = s & 1, h = 3 - s;
-            const int rows = TH + 2 * h, half = (TW + 2 * h) / 2;
-            const int a0 = H - h, b0 = H - h;
-            for (int q = tid; q < rows * half; q += 256) {
-                const int ar = q / half, bb = q - (q / half) * half;
-                const int a = a0 + ar;
-                const int p0 = (gi0 + a + gj0 + b0) & 1;
-                const int b = b0 + 2 * bb + (col ^ p0);
-                const int gi = gi0 + a, gj = gj0 + b;
-                const int c = a * RW + b;
-                if (comp == 0) {
-                    if (!is_vx(g, gi, gj)) continue;
-                    const T d = lx_diag(sb, sp, c, RW, gi, g.ny, k);
-                    const T res = srx[c] - lx_row(sx, sy, sb, sp, c, RW, k.idx, k.idy);
-                    sx[c] = sx[c] + omega * res / d;
-                } else {
-                    if (!is_vy(g, gi, gj)) continue;
-                    const T d = ly_diag(sb, sp, c, RW, gj, g.nx, k);
-                    const T res = sry[c] - ly_row(sx, sy, sb, sp, c, RW, k.idx, k.idy);
-                    sy[c] = sy[c] + omega * res / d;
-                }
-            }
-            __syncthreads();
-        }
-        for (int q = tid; q < TW * TH; q += 256) {
-            const int a = H + q / TW, b = H + (q - (q / TW) * TW);
+    for (int s = 0; s < NSTAGE; ++s) {
+        const int comp = (s >> 1) & 1, col = s & 1, h = H - 1 - s;
+        const int rows = TH + 2 * h, half = (TW + 2 * h) / 2;
+        const int a0 = H - h, b0 = H - h;
+        for (int q = tid; q < rows * half; q += nt) {
+            const int ar = q / half, bb = q - (q / half) * half;
+            const int a = a0 + ar;
+            const int p0 = (gi0 + a + gj0 + b0) & 1;
+            const int b = b0 + 2 * bb + (col ^ p0);
             const int gi = gi0 + a, gj = gj0 + b;
             const int c = a * RW + b;
-            const int cg = gi * P + gj;
-            if (is_vx(g, gi, gj)) {
-                const T e = sx[c];
-                exo[cg] = e;
-                if (gi == 1) exo[cg - P] = k.mirS * e;
-                if (gi == g.ny) exo[cg + P] = k.mirN * e;
-            }
-            if (is_vy(g, gi, gj)) {
-                const T e = sy[c];
-                eyo[cg] = e;
-                if (gj == 1) eyo[cg - 1] = k.mirW * e;
-                if (gj == g.nx) eyo[cg + 1] = k.mirE * e;
-            }
-        }
-    } else {
-        for (int q = tid; q < TW * TH; q += 256) {
-            const int a = H + q / TW, b = H + (q - (q / TW) * TW);
-            const int gi = gi0 + a, gj = gj0 + b;
-            const int c = a * RW + b;
-            const int cg = gi * P + gj;
-            if (is_vx(g, gi, gj)) {
+            if (comp == 0) {
+                if (!is_vx(g, gi, gj)) continue;
                 const T d = lx_diag(sb, sp, c, RW, gi, g.ny, k);
-                const T e = sx[c] + omega * (srx[c] - lx_row(sx, sy, sb, sp, c, RW, k.idx, k.idy)) / d;
-                exo[cg] = e;
-                if (gi == 1) exo[cg - P] = k.mirS * e;
-                if (gi == g.ny) exo[cg + P] = k.mirN * e;
-            }
-            if (is_vy(g, gi, gj)) {
+                const T res = rx[gi * P + gj] - lx_row(sx, sy, sb, sp, c, RW, k.idx, k.idy);
+                const T e = sx[c] + omega * res / d;
+                sx[c] = e;
+                if (gi == 1 && a >= 1) sx[c - RW] = k.mirS * e;
+                if (gi == g.ny && a + 1 < RH) sx[c + RW] = k.mirN * e;
+            } else {
+                if (!is_vy(g, gi, gj)) continue;
                 const T d = ly_diag(sb, sp, c, RW, gj, g.nx, k);
-                const T e = sy[c] + omega * (sry[c] - ly_row(sx, sy, sb, sp, c, RW, k.idx, k.idy)) / d;
-                eyo[cg] = e;
-                if (gj == 1) eyo[cg - 1] = k.mirW * e;
-                if (gj == g.nx) eyo[cg + 1] = k.mirE * e;
+                const T res = ry[gi * P + gj] - ly_row(sx, sy, sb, sp, c, RW, k.idx, k.idy);
+                const T e = sy[c] + omega * res / d;
+                sy[c] = e;
+                if (gj == 1 && b >= 1) sy[c - 1] = k.mirW * e;
+                if (gj == g.nx && b + 1 < RW) sy[c + 1] = k.mirE * e;
             }
+        }
+        __syncthreads();
+    }
+}
+
+// write the tile's own nodes (and the ghosts they own) to memory
+template <typename T, int TW, int TH, int H>
+__device__ __forceinline__ void tile_store(const Geom& g, int gi0, int gj0, const T* sx, const T* sy,
+                                           T* __restrict__ exo, T* __restrict__ eyo, const LevelC<T>& k) {
+    constexpr int RW = TW + 2 * H;
+    const int P = g.pitch;
+    for (int q = threadIdx.x; q < TW * TH; q += blockDim.x) {
+        const int a = H + q / TW, b = H + (q - (q / TW) * TW);
+        const int gi = gi0 + a, gj = gj0 + b;
+        const int c = a * RW + b;
+        const int cg = gi * P + gj;
+        if (is_vx(g, gi, gj)) {
+            const T e = sx[c];
+            exo[cg] = e;
+            if (gi == 1) exo[cg - P] = k.mirS * e;
+            if (gi == g.ny) exo[cg + P] = k.mirN * e;
+        }
+        if (is_vy(g, gi, gj)) {
+            const T e = sy[c];
+            eyo[cg] = e;
+            if (gj == 1) eyo[cg - 1] = k.mirW * e;
+            if (gj == g.nx) eyo[cg + 1] = k.mirE * e;
         }
     }
+}
+
+// normalised restriction of the fine residual held in LDS (stx, sty of
+// row length RC, first row / column fi0, fj0) to coarse cell (I, J)
+// (gather form of Alg. "4-Color Parallel Restriction", factor 2)
+template <typename T, int RC>
+__device__ __forceinline__ void restrict_cell(const Geom& g, const Geom& gc, const T* stx, const T* sty, int fi0,
+                                              int fj0, int I, int J, T* __restrict__ rcx, T* __restrict__ rcy) {
+    const int C = I * gc.pitch + J;
+    if (J < gc.nx) {
+        T s = (T)0, wy = (T)0;
+        for (int a4 = 0; a4 < 4; ++a4) {
+            const int i = 2 * I - 2 + a4;
+            if (i < 1 || i > g.ny) continue;
+            const T w = (a4 == 1 || a4 == 2) ? (T)0.75 : (T)0.25;
+            const int c = (i - fi0) * RC + (2 * J - fj0);
+            s += w * ((T)0.5 * stx[c - 1] + stx[c] + (T)0.5 * stx[c + 1]);
+            wy += w;
+        }
+        rcx[C] = s / ((T)2 * wy);
+    }
+    if (I < gc.ny) {
+        T s = (T)0, wx = (T)0;
+        for (int b4 = 0; b4 < 4; ++b4) {
+            const int j = 2 * J - 2 + b4;
+            if (j < 1 || j > g.nx) continue;
+            const T w = (b4 == 1 || b4 == 2) ? (T)0.75 : (T)0.25;
+            const int c = (2 * I - fi0) * RC + (j - fj0);
+            s += w * ((T)0.5 * sty[c - RC] + sty[c] + (T)0.5 * sty[c + RC]);
+            wx += w;
+        }
+        rcy[C] = s / ((T)2 * wx);
+    }
+}
+
+// Gauss-Seidel on an LDS tile: NS full sweeps in one pass (halo 4 NS), the
+// first from zero, from the iterate in memory, or from the iterate plus the
+// prolongated coarse correction (MODE).  The tile reads the old iterate and
+// writes its own nodes to the other buffer, so overlapping tiles never see
+// each other's new values and the result equals NS sweeps over the whole
+// grid exactly.  With RR the pass continues (halo 4 NS + 2) with the
+// residual r - L e on the tile grown by one node and the restriction of the
+// coarse cells the tile covers (TW x TH fine = TW/2 x TH/2 coarse): the
+// down leg of a V-cycle level in one launch, the fine residual never going
+// to memory.
+template <typename T, int TW, int TH, int NS, int MODE, int RR>
+__device__ __forceinline__ void gs_tile_body(const Geom& g, const Geom& gc, const T* __restrict__ exi,
+                                             const T* __restrict__ eyi, T* __restrict__ exo, T* __restrict__ eyo,
+                                             const T* __restrict__ rx, const T* __restrict__ ry,
+                                             const T* __restrict__ eb, const T* __restrict__ ep,
+                                             const T* __restrict__ ecx, const T* __restrict__ ecy,
+                                             T* __restrict__ rcx, T* __restrict__ rcy, T omega, int tbx, int tby) {
+    static_assert(TW % 2 == 0 && TH % 2 == 0, "tiles cover whole coarse cells");
+    static_assert(!(RR && MODE == kModeProlong), "the down leg starts from zero or an iterate");
+    constexpr int H = 4 * NS + (RR ? 2 : 0);
+    constexpr int RW = TW + 2 * H, RH = TH + 2 * H, RN = RW * RH;
+    constexpr int CN = MODE == kModeProlong ? prolong_rows<RH>() * prolong_rows<RW>() : 1;
+    constexpr int TRW = RR ? TW + 2 : 1, TRH = RR ? TH + 2 : 1;
+    static_assert((4 * RN + 2 * CN + 2 * TRW * TRH) * sizeof(T) <= 65536, "tile exceeds 64 KB of LDS");
+    __shared__ T sx[RN], sy[RN], sb[RN], sp[RN];
+    __shared__ T scx[CN], scy[CN];
+    __shared__ T stx[TRW * TRH], sty[TRW * TRH];
+    const int i0 = 1 + tby * TH, j0 = 1 + tbx * TW;
+    const int gi0 = i0 - H, gj0 = j0 - H;
+    const LevelC<T> k = level_consts<T>(g);
+    tile_load<T, RW, RH, MODE>(g, gc, gi0, gj0, exi, eyi, eb, ep, ecx, ecy, sx, sy, sb, sp, scx, scy, k);
+    gs_stages<T, TW, TH, H, 4 * NS>(g, gi0, gj0, sx, sy, sb, sp, rx, ry, omega, k);
+    tile_store<T, TW, TH, H>(g, gi0, gj0, sx, sy, exo, eyo, k);
+    if (RR) {
+        const int P = g.pitch;
+        for (int q = threadIdx.x; q < TRW * TRH; q += blockDim.x) {
+            const int a = q / TRW, b = q - (q / TRW) * TRW;
+            const int gi = i0 - 1 + a, gj = j0 - 1 + b;
+            const int c = (a + H - 1) * RW + (b + H - 1);
+            stx[q] = is_vx(g, gi, gj) ? rx[gi * P + gj] - lx_row(sx, sy, sb, sp, c, RW, k.idx, k.idy) : (T)0;
+            sty[q] = is_vy(g, gi, gj) ? ry[gi * P + gj] - ly_row(sx, sy, sb, sp, c, RW, k.idx, k.idy) : (T)0;
+        }
+        __syncthreads();
+        const int I0 = 1 + tby * (TH / 2), J0 = 1 + tbx * (TW / 2);
+        for (int q = threadIdx.x; q < (TH / 2) * (TW / 2); q += blockDim.x) {
+            const int I = I0 + q / (TW / 2), J = J0 + (q - (q / (TW / 2)) * (TW / 2));
+            if (I > gc.ny || J > gc.nx) continue;
+            restrict_cell<T, TRW>(g, gc, stx, sty, i0 - 1, j0 - 1, I, J, rcx, rcy);
+        }
+    }
+}
+
+// one damped Jacobi sweep on an LDS tile (halo 1)
+template <typename T, int TW, int TH, int MODE>
+__device__ __forceinline__ void jacobi_tile_body(const Geom& g, const Geom& gc, const T* __restrict__ exi,
+                                                 const T* __restrict__ eyi, T* __restrict__ exo,
+                                                 T* __restrict__ eyo, const T* __restrict__ rx,
+                                                 const T* __restrict__ ry, const T* __restrict__ eb,
+                                                 const T* __restrict__ ep, const T* __restrict__ ecx,
+                                                 const T* __restrict__ ecy, T omega, int tbx, int tby) {
+    constexpr int H = 1;
+    constexpr int RW = TW + 2 * H, RH = TH + 2 * H, RN = RW * RH;
+    constexpr int CN = MODE == kModeProlong ? prolong_rows<RH>() * prolong_rows<RW>() : 1;
+    __shared__ T sx[RN], sy[RN], sb[RN], sp[RN];
+    __shared__ T scx[CN], scy[CN];
+    const int i0 = 1 + tby * TH, j0 = 1 + tbx * TW;
+    const int gi0 = i0 - H, gj0 = j0 - H;
+    const int P = g.pitch;
+    const LevelC<T> k = level_consts<T>(g);
+    tile_load<T, RW, RH, MODE>(g, gc, gi0, gj0, exi, eyi, eb, ep, ecx, ecy, sx, sy, sb, sp, scx, scy, k);
+    for (int q = threadIdx.x; q < TW * TH; q += blockDim.x) {
+        const int a = H + q / TW, b = H + (q - (q / TW) * TW);
+        const int gi = gi0 + a, gj = gj0 + b;
+        const int c = a * RW + b;
+        const int cg = gi * P + gj;
+        if (is_vx(g, gi, gj)) {
+            const T d = lx_diag(sb, sp, c, RW, gi, g.ny, k);
+            const T e = sx[c] + omega * (rx[cg] - lx_row(sx, sy, sb, sp, c, RW, k.idx, k.idy)) / d;
+            exo[cg] = e;
+            if (gi == 1) exo[cg - P] = k.mirS * e;
+            if (gi == g.ny) exo[cg + P] = k.mirN * e;
+        }
+        if (is_vy(g, gi, gj)) {
+            const T d = ly_diag(sb, sp, c, RW, gj, g.nx, k);
+            const T e = sy[c] + omega * (ry[cg] - ly_row(sx, sy, sb, sp, c, RW, k.idx, k.idy)) / d;
+            eyo[cg] = e;
+            if (gj == 1) eyo[cg - 1] = k.mirW * e;
+            if (gj == g.nx) eyo[cg + 1] = k.mirE * e;
+        }
+    }
+}
+
+// one smoothing sweep on an LDS tile (either smoother)
+template <typename T, int TW, int TH, int SM, int MODE>
+__device__ __forceinline__ void smooth_tile_body(const Geom& g, const Geom& gc, const T* __restrict__ exi,
+                                                 const T* __restrict__ eyi, T* __restrict__ exo,
+                                                 T* __restrict__ eyo, const T* __restrict__ rx,
+                                                 const T* __restrict__ ry, const T* __restrict__ eb,
+                                                 const T* __restrict__ ep, const T* __restrict__ ecx,
+                                                 const T* __restrict__ ecy, T omega, int tbx, int tby) {
+    if (SM == kSmGS)
+        gs_tile_body<T, TW, TH, 1, MODE, 0>(g, gc, exi, eyi, exo, eyo, rx, ry, eb, ep, ecx, ecy, nullptr, nullptr,
+                                            omega, tbx, tby);
+    else
+        jacobi_tile_body<T, TW, TH, MODE>(g, gc, exi, eyi, exo, eyo, rx, ry, eb, ep, ecx, ecy, omega, tbx, tby);
 }
 
 // ---------------------------------------------------------------------------
@@ -264,31 +405,7 @@ __device__ __forceinline__ void res_restrict_body(const Geom& g, const Geom& gc,
     __syncthreads();
     const int I = I0 + tid / CTW, J = J0 + (tid - (tid / CTW) * CTW);
     if (I > gc.ny || J > gc.nx) return;
-    const int C = I * gc.pitch + J;
-    if (J < gc.nx) {
-        T s = (T)0, wy = (T)0;
-        for (int a4 = 0; a4 < 4; ++a4) {
-            const int i = 2 * I - 2 + a4;
-            if (i < 1 || i > g.ny) continue;
-            const T w = (a4 == 1 || a4 == 2) ? (T)0.75 : (T)0.25;
-            const int c = (i - fi0) * RC + (2 * J - fj0);
-            s += w * ((T)0.5 * stx[c - 1] + stx[c] + (T)0.5 * stx[c + 1]);
-            wy += w;
-        }
-        rcx[C] = s / ((T)2 * wy);
-    }
-    if (I < gc.ny) {
-        T s = (T)0, wx = (T)0;
-        for (int b4 = 0; b4 < 4; ++b4) {
-            const int j = 2 * J - 2 + b4;
-            if (j < 1 || j > g.nx) continue;
-            const T w = (b4 == 1 || b4 == 2) ? (T)0.75 : (T)0.25;
-            const int c = (2 * I - fi0) * RC + (j - fj0);
-            s += w * ((T)0.5 * sty[c - RC] + sty[c] + (T)0.5 * sty[c + RC]);
-            wx += w;
-        }
-        rcy[C] = s / ((T)2 * wx);
-    }
+    restrict_cell<T, RC>(g, gc, stx, sty, fi0, fj0, I, J, rcx, rcy);
 }
 
 // ---------------------------------------------------------------------------

@@ -125,6 +125,7 @@ struct CoarseArgs {
 template <typename T>
 size_t coarse_cycle_lds_bytes(const Geom* g, int nl, int nc);
 // mode: 0 plain sweep, 1 from a zero initial guess, 2 prolongation + correction then sweep
+enum TileMode { kTilePlain = 0, kTileZero = 1, kTileProlong = 2 };
 template <typename T>
 hipError_t launch_smooth_tile(const Geom& g, const Geom* gc, int smoother, int mode, const T* exi, const T* eyi,
                               T* exo, T* eyo, const T* rx, const T* ry, const T* eb, const T* ep, const T* ecx,
@@ -134,5 +135,12 @@ hipError_t launch_res_restrict(const Geom& gf, const Geom& gc, const T* ex, cons
                                const T* eb, const T* ep, T* rcx, T* rcy, hipStream_t st);
 template <typename T>
 hipError_t launch_coarse_cycle(const CoarseArgs<T>& a, size_t lds_bytes, int max_lds, hipStream_t st);
+// Gauss-Seidel on LDS tiles, ns (1 or 2) full sweeps per pass; mode as
+// above; rr = 1 adds the residual and its restriction to the coarse level gc
+// (rcx, rcy); shape 0 / 1 selects the large / small tile
+template <typename T>
+hipError_t launch_gs_tile(const Geom& g, const Geom& gc, int ns, int mode, int rr, int shape, const T* exi,
+                          const T* eyi, T* exo, T* eyo, const T* rx, const T* ry, const T* eb, const T* ep,
+                          const T* ecx, const T* ecy, T* rcx, T* rcy, T omega, hipStream_t st);
 
 }  // namespace tph

@@ -82,6 +82,8 @@ struct tph_solver {
     double* Minv = nullptr;
     int ncoarse = 0;
     int lc = -1;                 // first level handled by the single-workgroup coarse kernel (-1: none)
+    unsigned msw_mask = 0;       // levels smoothed in multi-sweep passes (resolved desc.msweep)
+    unsigned shape_mask = 0;     // levels using the small tile shape (resolved desc.tile_shape)
     size_t lc_lds = 0;           // its LDS bytes
     int max_lds = 65536;         // device limit of LDS per workgroup
     size_t F = 0;                // elements of one field allocation
@@ -189,6 +191,7 @@ tph_status validate_desc(const tph_desc* d, int* nlev_out) {
     if (d->max_iters < 1) { set_error("max_iters must be >= 1"); return TPH_ERR_INVALID; }
     if (d->uzawa_steps < 1 || d->uzawa_steps > 8) { set_error("uzawa_steps must be in [1, 8]"); return TPH_ERR_INVALID; }
     if (d->fused != 0 && d->fused != 1) { set_error("fused must be 0 or 1"); return TPH_ERR_INVALID; }
+    if (d->msweep < -1 || d->tile_shape < -1) { set_error("msweep and tile_shape must be -1 or a level mask"); return TPH_ERR_INVALID; }
     int nlev = d->levels;
     if (nlev == 0) {
         nlev = 1;
@@ -269,6 +272,63 @@ tph_status vcycle(tph_solver* s, int l, int* cur_out) {
     return TPH_OK;
 }
 
+template <typename T>
+tph_status vcycle_fused(tph_solver* s, int l, int* cur_out);
+
+// One level of the fused V-cycle in multi-sweep passes: pre-smoothing from
+// zero in passes of up to two Gauss-Seidel sweeps, the last one also forming
+// the residual and restricting it to the next level; after the coarse
+// correction, post-smoothing in passes of up to two sweeps, the first one
+// applying the prolongation.  Same sweeps, same result as the one-sweep
+// launches; fewer launches and one read of r and eta per pass.
+template <typename T>
+tph_status vcycle_msweep(tph_solver* s, int l, int* cur_out) {
+    LevelBuf& L = s->lev[l];
+    LevelBuf& C = s->lev[l + 1];
+    const Geom& g = L.g;
+    hipStream_t st = s->st;
+    T* eb = as<T>(L.eb);
+    T* ep = as<T>(L.ep);
+    T* rx = as<T>(L.rx);
+    T* ry = as<T>(L.ry);
+    const T om = (T)s->d.omega;
+    const int shape = (int)((s->shape_mask >> l) & 1u);
+    int cur = 0;
+    int mode = kTileZero;
+    for (int left = L.nu_pre; left > 0;) {
+        const int ns = left >= 2 ? 2 : 1;
+        const int rr = left == ns ? 1 : 0;
+        const bool zero = mode == kTileZero;
+        const int dst = zero ? 0 : 1 - cur;
+        const bool tk = ktic(s, l);
+        TPH_HIP(launch_gs_tile<T>(g, C.g, ns, mode, rr, shape, zero ? nullptr : as<T>(L.ex[cur]),
+                                  zero ? nullptr : as<T>(L.ey[cur]), as<T>(L.ex[dst]), as<T>(L.ey[dst]), rx, ry, eb, ep,
+                                  nullptr, nullptr, rr ? as<T>(C.rx) : nullptr, rr ? as<T>(C.ry) : nullptr, om, st));
+        ktoc(s, tk, (zero ? 6.0 : 8.0) + (rr ? 0.5 : 0.0), sizeof(T));
+        cur = dst;
+        mode = kTilePlain;
+        left -= ns;
+    }
+    int ccur = 0;
+    TPH_TRY(vcycle_fused<T>(s, l + 1, &ccur));
+    mode = kTileProlong;
+    for (int left = L.nu_post; left > 0;) {
+        const int ns = left >= 2 ? 2 : 1;
+        const bool pro = mode == kTileProlong;
+        const bool tk = ktic(s, l);
+        TPH_HIP(launch_gs_tile<T>(g, C.g, ns, mode, 0, shape, as<T>(L.ex[cur]), as<T>(L.ey[cur]), as<T>(L.ex[1 - cur]),
+                                  as<T>(L.ey[1 - cur]), rx, ry, eb, ep, pro ? as<T>(C.ex[ccur]) : nullptr,
+                                  pro ? as<T>(C.ey[ccur]) : nullptr, nullptr, nullptr, om, st));
+        ktoc(s, tk, pro ? 8.5 : 8.0, sizeof(T));
+        cur = 1 - cur;
+        mode = kTilePlain;
+        left -= ns;
+    }
+    *cur_out = cur;
+    return TPH_OK;
+}
+
+
 // V-cycle with the fused kernels: LDS-tiled smoothing sweeps (first one
 // from zero, first post-sweep with the prolongation fused in), fused
 // residual + restriction, and the coarse tail in one workgroup.
@@ -312,6 +372,7 @@ tph_status vcycle_fused(tph_solver* s, int l, int* cur_out) {
         return TPH_OK;
     }
     int cur = 0;
+    if (((s->msw_mask >> l) & 1u) && L.nu_pre > 0 && L.nu_post > 0) return vcycle_msweep<T>(s, l, cur_out);
     if (L.nu_pre == 0) {
         TPH_HIP(launch_zero_vel<T>(g, as<T>(L.ex[0]), as<T>(L.ey[0]), st));
     } else {
@@ -673,6 +734,22 @@ tph_status create_impl(const tph_desc* desc, void* stream, tph_solver* s) {
             }
         }
     }
+    s->msw_mask = 0;
+    s->shape_mask = 0;
+    if (desc->fused && desc->smoother == TPH_SMOOTH_GS) {
+        const unsigned all = nlev >= 32 ? ~0u : ((1u << nlev) - 1u);
+        s->msw_mask = desc->msweep < 0 ? (all & ~1u) : ((unsigned)desc->msweep & all);
+        if (desc->tile_shape >= 0) {
+            s->shape_mask = (unsigned)desc->tile_shape & all;
+        } else {
+            for (int l = 0; l < nlev; ++l) {
+                const Geom& g = s->lev[l].g;
+                const int tw = 64, th = s->mixed() ? 16 : 8;
+                const long tiles = (long)((g.nx + tw - 1) / tw) * ((g.ny + th - 1) / th);
+                if (tiles < 512) s->shape_mask |= 1u << l;
+            }
+        }
+    }
     TPH_TRY(dev_alloc(s, (void**)&s->Minv, (size_t)s->ncoarse * s->ncoarse * sizeof(double)));
     TPH_HIP(hipHostMalloc((void**)&s->hscal, kScalars * sizeof(double), hipHostMallocDefault));
     TPH_HIP(hipEventCreate(&s->ev0));
@@ -833,6 +910,8 @@ void tph_desc_default(tph_desc* d, int32_t nx, int32_t ny) {
     d->max_iters = 500;
     d->uzawa_steps = 2;
     d->fused = 1;
+    d->msweep = -1;
+    d->tile_shape = -1;
 }
 
 tph_status tph_create(const tph_desc* desc, void* hip_stream, tph_solver** out) {

@@ -140,6 +140,48 @@ def test_preconditioner_matches_oracle_vcycle(case, prec, fused):
     assert np.array_equal(gy_[1:ny, nx + 1], (1 if bc[1] == 0 else -1) * gy_[1:ny, nx])
 
 
+# level plans of the fused V-cycle: (msweep mask, tile_shape mask); -1 = all
+PLANS = [(0, 0), (-1, -1), (0xFFFF, 0), (0xFFFF, 0xFFFF)]
+
+
+@pytest.mark.parametrize("plan", PLANS)
+@pytest.mark.parametrize("prec", [tph.FP64, tph.MIXED])
+@pytest.mark.parametrize("case", [c for c in PRECOND_CASES if c[4] == tph.SMOOTH_GS])
+def test_multisweep_plans_match_oracle_vcycle(case, prec, plan):
+    """Multi-sweep passes (two Gauss-Seidel sweeps per launch, residual and
+    restriction fused into the last pre-smoothing pass, prolongation into the
+    first post-smoothing pass) on every level, on none, and with either tile
+    shape: the same V-cycle as the oracle's."""
+    nx, ny, bc, levels, sm, nu, growth, omega, alpha, steps = case
+    eb, ep, rho = wl.random_fields(nx, ny, seed=nx * 5 + ny, eta_decades=2)
+    rx, ry, rp = wl.random_state(nx, ny, seed=nx + 3)
+    msw, shp = plan
+    s = solver_for(nx, ny, bc=bc, precision=prec, levels=levels, smoother=sm, nu_pre=nu, nu_post=nu,
+                   nu_growth=growth, omega=omega, alpha=alpha, uzawa_steps=steps, fused=True, msweep=msw,
+                   tile_shape=shp)
+    s.set_coefficients(T(eb), T(ep), T(rho))
+    zx, zy, zp = s.precondition(T(rx), T(ry), T(rp))
+    sched = [min(256, math.ceil(nu * growth ** l - 1e-9)) for l in range(levels)]
+    prm = mg.MGParams(levels=levels, nu_pre=sched, nu_post=sched, omega=omega, smoother="gs", alpha=alpha)
+    g = st.Grid(nx, ny, 1.0, 1.0, bc)
+    levs = mg.build_hierarchy(g, eb, ep, prm)
+    if steps == 1:
+        ox, oy, op = mg.precondition(levs, prm, rx, ry, rp)
+    else:
+        ox, oy, op = mg.uzawa_preconditioner(levs, prm, st.assemble(g, eb, ep), rx, ry, rp, steps)
+    tol = 1e-11 if prec == tph.FP64 else 5e-5
+    gx_, gy_, gp_ = N(zx), N(zy), N(zp)
+    v_ref = np.concatenate([ox[1:ny + 1, 1:nx].ravel(), oy[1:ny, 1:nx + 1].ravel()])
+    v_got = np.concatenate([gx_[1:ny + 1, 1:nx].ravel(), gy_[1:ny, 1:nx + 1].ravel()])
+    ev = np.linalg.norm(v_got - v_ref) / np.linalg.norm(v_ref)
+    epr = np.linalg.norm(gp_[1:ny + 1, 1:nx + 1] - op[1:ny + 1, 1:nx + 1]) / np.linalg.norm(op[1:ny + 1, 1:nx + 1])
+    print(f"[msweep {plan}] rel err v {ev:.2e} p {epr:.2e}", flush=True)
+    assert ev < tol and epr < tol
+    assert np.all(gx_[:, 0] == 0) and np.all(gx_[:, nx] == 0)
+    assert np.array_equal(gx_[0, 1:nx], (1 if bc[2] == 0 else -1) * gx_[1, 1:nx])
+    assert np.array_equal(gy_[1:ny, nx + 1], (1 if bc[1] == 0 else -1) * gy_[1:ny, nx])
+
+
 def _check_solution_contract(nx, ny, bc, vx, vy, p):
     assert np.all(vx[:, 0] == 0) and np.all(vx[:, nx] == 0)
     assert np.all(vy[0, :] == 0) and np.all(vy[ny, :] == 0)
