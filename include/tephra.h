@@ -198,6 +198,14 @@ tph_status tph_level_viscosity(tph_solver* s, int32_t level, double* eta_b, doub
 /* Number of levels actually used, and level l's cell counts. */
 tph_status tph_level_shape(tph_solver* s, int32_t level, int32_t* nx, int32_t* ny);
 
+/* How level l is processed by the fused V-cycle (desc.fused = 1):
+ * *kind = 0: one-sweep LDS tile launches (plus the fused residual-restriction),
+ *         1: multi-sweep LDS passes, 2: inside the single-workgroup coarse
+ *         tail, 3: coarsest level without the coarse tail (dense solve);
+ * *shape = 1 if its tiles use the small shape.  With desc.fused = 0 every
+ * level reports kind 0.  Either output may be NULL. */
+tph_status tph_level_plan(tph_solver* s, int32_t level, int32_t* kind, int32_t* shape);
+
 /* Adjoint solve A^T lam = g (A is symmetric, so this is the forward solver
  * with right-hand side g = (gvx, gvy, gp)); lam is written zero-mean in
  * pressure.  Any of gvx, gvy, gp may be NULL (zero). */

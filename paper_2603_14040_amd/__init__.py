@@ -131,6 +131,14 @@ class Solver:
         _lib.check("tph_level_shape", self._lib.tph_level_shape(self._h, level, ctypes.byref(nx), ctypes.byref(ny)))
         return nx.value, ny.value
 
+    LEVEL_KINDS = ("tiles", "multisweep", "coarse_tail", "dense")
+
+    def level_plan(self, level: int) -> Tuple[str, int]:
+        """(kernel kind, tile shape) of one level: see tph_level_plan."""
+        k, s = ctypes.c_int32(), ctypes.c_int32()
+        _lib.check("tph_level_plan", self._lib.tph_level_plan(self._h, level, ctypes.byref(k), ctypes.byref(s)))
+        return self.LEVEL_KINDS[k.value], s.value
+
     def set_coefficients(self, eta_b, eta_p, rho_b, gx: float = 0.0, gy: float = -1.0,
                          fx_extra=None, fy_extra=None):
         self._sync_in()

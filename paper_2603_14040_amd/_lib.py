@@ -78,6 +78,7 @@ def load(path: str = LIB_PATH):
         "tph_energy_residual": (c_int32, [P, P, P, P, POINTER(c_double)]),
         "tph_level_viscosity": (c_int32, [P, c_int32, P, P]),
         "tph_level_shape": (c_int32, [P, c_int32, POINTER(c_int32), POINTER(c_int32)]),
+        "tph_level_plan": (c_int32, [P, c_int32, POINTER(c_int32), POINTER(c_int32)]),
         "tph_solve_adjoint": (c_int32, [P, P, P, P, P, P, P, POINTER(Info)]),
         "tph_coeff_gradient": (c_int32, [P, P, P, P, P, P, P, P, P, P]),
         "tph_time_kernel": (c_int32, [P, c_int32, c_int32, POINTER(c_double), POINTER(c_double)]),
@@ -105,3 +106,7 @@ def check(fn: str, status: int, allow_not_converged: bool = False) -> int:
         return status
     msg = _lib.tph_last_error().decode() if _lib is not None else ""
     raise TephraError(fn, status, msg)
+
+
+def version() -> str:
+    return load().tph_version().decode()

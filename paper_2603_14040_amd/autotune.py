@@ -1,0 +1,241 @@
+"""Autotuner of the solver's kernel plan and sweep schedule.
+
+The converged answer of a solve does not depend on any parameter tuned
+here: the V-cycle/Uzawa step is only the preconditioner of the flexible
+Krylov iteration, which converges to the same discrete solution (the
+paper's Sec. "Comparison with FGMRES" and its multigrid sections).  The
+parameters trade work per iteration against the number of iterations and
+map the work onto the chip differently, so the fastest choice depends on
+the grid, the viscosity structure and the device.  The tuner measures
+whole solves of the caller's own problem and keeps the fastest.
+
+Knobs (all of them descriptor fields of tph_create):
+  * per LDS-tiled level: one-sweep tile launches or multi-sweep passes
+    (``msweep`` bit), large or small tile shape (``tile_shape`` bit);
+  * smoothing sweeps per level (nu_pre = nu_post);
+  * Uzawa sweeps per preconditioner application (``uzawa_steps``);
+  * FGMRES restart length.
+
+Search: coordinate descent from the library defaults; each knob in turn
+takes every candidate value with the others fixed, and a candidate is
+adopted when it is faster by more than ``rel_gain``; passes repeat until
+one changes nothing (at most ``rounds``).  A candidate is timed as the
+median of ``reps`` solves from a zero initial guess to the target
+residual, after one untimed solve; one that does not converge is
+discarded.  Results go to a JSON database keyed by grid, precision,
+device and library version.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import statistics
+import tempfile
+import time
+from dataclasses import dataclass, field
+from typing import Callable, Dict, Iterable, List, Optional, Sequence, Tuple
+
+Params = Dict[str, object]
+
+
+# ---------------------------------------------------------------------------
+# search (pure host logic)
+# ---------------------------------------------------------------------------
+@dataclass
+class Knob:
+    name: str
+    candidates: Sequence[object]
+
+
+@dataclass
+class SearchResult:
+    params: Params
+    cost: float
+    trials: List[Tuple[Params, float]] = field(default_factory=list)
+
+
+def coordinate_search(measure: Callable[[Params], float], knobs: Sequence[Knob], start: Params,
+                      rounds: int = 2, rel_gain: float = 0.02) -> SearchResult:
+    """Coordinate descent over ``knobs`` from ``start``.
+
+    ``measure`` returns the cost of a full parameter set (math.inf when the
+    configuration is unusable).  Every distinct parameter set is measured
+    at most once.
+    """
+    cache: Dict[str, float] = {}
+    trials: List[Tuple[Params, float]] = []
+
+    def cost(p: Params) -> float:
+        key = json.dumps(p, sort_keys=True)
+        if key not in cache:
+            c = float(measure(dict(p)))
+            cache[key] = c
+            trials.append((dict(p), c))
+        return cache[key]
+
+    best = dict(start)
+    best_cost = cost(best)
+    for _ in range(max(1, rounds)):
+        changed = False
+        for kn in knobs:
+            for v in kn.candidates:
+                if best.get(kn.name) == v:
+                    continue
+                cand = dict(best)
+                cand[kn.name] = v
+                c = cost(cand)
+                if c < best_cost * (1.0 - rel_gain):
+                    best, best_cost, changed = cand, c, True
+        if not changed:
+            break
+    return SearchResult(best, best_cost, trials)
+
+
+# ---------------------------------------------------------------------------
+# database
+# ---------------------------------------------------------------------------
+def default_db_path() -> str:
+    return os.environ.get("TEPHRA_TUNING_DB", os.path.join(os.path.expanduser("~"), ".cache", "tephra_tuning.json"))
+
+
+class TuningDB:
+    """JSON file of tuned parameter sets (written atomically)."""
+
+    def __init__(self, path: Optional[str] = None):
+        self.path = path or default_db_path()
+        self.entries: Dict[str, dict] = {}
+        if os.path.exists(self.path):
+            with open(self.path) as fh:
+                data = json.load(fh)
+            if not isinstance(data, dict):
+                raise ValueError(f"{self.path}: not a tuning database")
+            self.entries = data
+
+    @staticmethod
+    def key(nx: int, ny: int, precision: int, device: str, version: str, tag: str = "") -> str:
+        return f"{nx}x{ny}|prec{precision}|{device}|{version}" + (f"|{tag}" if tag else "")
+
+    def get(self, key: str) -> Optional[dict]:
+        return self.entries.get(key)
+
+    def put(self, key: str, entry: dict) -> None:
+        self.entries[key] = entry
+        d = os.path.dirname(os.path.abspath(self.path))
+        os.makedirs(d, exist_ok=True)
+        fd, tmp = tempfile.mkstemp(dir=d, prefix=".tuning", suffix=".json")
+        with os.fdopen(fd, "w") as fh:
+            json.dump(self.entries, fh, indent=1, sort_keys=True)
+        os.replace(tmp, self.path)
+
+
+# ---------------------------------------------------------------------------
+# parameter sets <-> solver descriptor
+# ---------------------------------------------------------------------------
+def plan_to_masks(plan: Sequence[Tuple[int, int]], levels: Sequence[int]) -> Tuple[int, int]:
+    """Per-tile-level (multisweep, small shape) choices -> (msweep, tile_shape) masks."""
+    msw = shp = 0
+    for (m, s), l in zip(plan, levels):
+        msw |= (1 << l) if m else 0
+        shp |= (1 << l) if s else 0
+    return msw, shp
+
+
+def solver_kwargs(p: Params, tile_levels: Sequence[int]) -> dict:
+    """Solver keyword arguments of a parameter set."""
+    plan = [tuple(p[f"L{l}"]) for l in tile_levels]
+    msw, shp = plan_to_masks(plan, tile_levels)
+    return dict(nu_pre=int(p["nu"]), nu_post=int(p["nu"]), uzawa_steps=int(p["uzawa_steps"]),
+                restart=int(p["restart"]), msweep=msw, tile_shape=shp)
+
+
+def knobs_for(tile_levels: Sequence[int], nus=(1, 2, 3), uzawa=(1, 2, 3), restarts=(10, 20, 30)) -> List[Knob]:
+    ks = [Knob(f"L{l}", [(0, 0), (0, 1), (1, 0), (1, 1)]) for l in tile_levels]
+    ks += [Knob("nu", list(nus)), Knob("uzawa_steps", list(uzawa)), Knob("restart", list(restarts))]
+    return ks
+
+
+# ---------------------------------------------------------------------------
+# tuning a problem on the GPU
+# ---------------------------------------------------------------------------
+def tune(eta_b, eta_p, rho_b, gx: float = 0.0, gy: float = -1.0, *, precision: Optional[int] = None,
+         lx: float = 1.0, ly: float = 1.0, bc=(0, 0, 0, 0), rtol: float = 1e-8, reps: int = 3, rounds: int = 2,
+         rel_gain: float = 0.02, db: Optional[TuningDB] = None, tag: str = "", device=None,
+         knobs: Optional[Sequence[Knob]] = None, log: Optional[Callable[[str], None]] = None) -> dict:
+    """Tune the solve of one problem (device FP64 arrays of shape (ny+2, nx+2)).
+
+    Returns the database entry: ``params`` (Solver keyword arguments),
+    ``ms`` (median solve time), ``iters``, ``trials`` and ``seconds``
+    spent.  With ``db`` the entry is stored under the problem's key.
+    """
+    import torch
+    from . import MIXED, Solver, _lib
+
+    precision = MIXED if precision is None else precision
+    ny, nx = eta_b.shape[0] - 2, eta_b.shape[1] - 2
+    device = eta_b.device if device is None else device
+    t_start = time.perf_counter()
+
+    base = Solver(nx, ny, lx, ly, bc=bc, precision=precision, rtol=rtol, device=device)
+    nlev = base.levels
+    plan0 = [base.level_plan(l) for l in range(nlev)]
+    tile_levels = [l for l, (k, _) in enumerate(plan0) if k in ("tiles", "multisweep")]
+    d = base.desc
+    start: Params = {"nu": int(d.nu_pre), "uzawa_steps": int(d.uzawa_steps), "restart": int(d.restart)}
+    for l in tile_levels:
+        k, s = plan0[l]
+        start[f"L{l}"] = (1 if k == "multisweep" else 0, int(s))
+    base.close()
+    del base
+
+    iters: Dict[str, int] = {}
+
+    def measure(p: Params) -> float:
+        kw = solver_kwargs(p, tile_levels)
+        s = Solver(nx, ny, lx, ly, bc=bc, precision=precision, rtol=rtol, device=device, **kw)
+        try:
+            s.set_coefficients(eta_b, eta_p, rho_b, gx, gy)
+            vx, vy, pp = s.zeros(), s.zeros(), s.zeros()
+            ts = []
+            for r in range(reps + 1):
+                vx.zero_(); vy.zero_(); pp.zero_()
+                torch.cuda.synchronize(device)
+                t0 = time.perf_counter()
+                info = s.solve(vx, vy, pp)[3]
+                torch.cuda.synchronize(device)
+                if info.status != "TPH_OK":
+                    return math.inf
+                if r > 0:
+                    ts.append(time.perf_counter() - t0)
+            c = statistics.median(ts) * 1e3
+            iters[json.dumps(p, sort_keys=True)] = info.iters
+            if log:
+                log(f"[tune] {p} -> {c:.2f} ms, {info.iters} iterations")
+            return c
+        finally:
+            s.close()
+
+    res = coordinate_search(measure, knobs if knobs is not None else knobs_for(tile_levels), start, rounds=rounds,
+                            rel_gain=rel_gain)
+    best_kw = solver_kwargs(res.params, tile_levels)
+    entry = {"params": best_kw, "ms": res.cost, "iters": iters.get(json.dumps(res.params, sort_keys=True)),
+             "default_ms": res.trials[0][1], "trials": len(res.trials),
+             "seconds": round(time.perf_counter() - t_start, 2),
+             "search": {k: (list(v) if isinstance(v, tuple) else v) for k, v in res.params.items()}}
+    if db is not None:
+        db.put(TuningDB.key(nx, ny, precision, device_name(device), _lib.version(), tag), entry)
+    return entry
+
+
+def device_name(device=None) -> str:
+    import torch
+    return torch.cuda.get_device_name(device).strip() or "gpu"
+
+
+def lookup(nx: int, ny: int, precision: int, db: Optional[TuningDB] = None, tag: str = "",
+           device=None) -> Optional[dict]:
+    """Tuned Solver keyword arguments for this grid and device, or None."""
+    from . import _lib
+    db = db or TuningDB()
+    e = db.get(TuningDB.key(nx, ny, precision, device_name(device), _lib.version(), tag))
+    return dict(e["params"]) if e else None

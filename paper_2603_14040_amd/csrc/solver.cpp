@@ -1064,6 +1064,22 @@ tph_status tph_level_shape(tph_solver* s, int32_t level, int32_t* nx, int32_t* n
     return TPH_OK;
 }
 
+tph_status tph_level_plan(tph_solver* s, int32_t level, int32_t* kind, int32_t* shape) {
+    g_last_error.clear();
+    if (!s) { set_error("solver is NULL"); return TPH_ERR_INVALID; }
+    if (level < 0 || level >= s->nlev) { set_error("level out of range"); return TPH_ERR_INVALID; }
+    int k = 0;
+    if (s->d.fused) {
+        const LevelBuf& L = s->lev[level];
+        if (s->lc >= 0 && level >= s->lc) k = 2;
+        else if (level == s->nlev - 1) k = 3;
+        else if (((s->msw_mask >> level) & 1u) && L.nu_pre > 0 && L.nu_post > 0) k = 1;
+    }
+    if (kind) *kind = k;
+    if (shape) *shape = (int32_t)((s->shape_mask >> level) & 1u);
+    return TPH_OK;
+}
+
 tph_status tph_level_viscosity(tph_solver* s, int32_t level, double* eta_b, double* eta_p) {
     g_last_error.clear();
     TPH_TRY(require_ready(s));
