@@ -10,6 +10,12 @@ Gaussian random field, correlation length 0.05, contrast 1e4; density
 1 - 0.01 log10(eta) + N(0, 0.01); free slip; g = (0, -1)).  Inputs are
 synthetic, seeded, and resident in HBM before timing starts.
 
+Before timing, the autotuner (paper_2603_14040_amd.autotune) measures whole
+solves of this problem and picks the per-level kernel plan, the sweeps, the
+Uzawa steps and the restart length, for each precision (untimed; the answer
+does not depend on these choices).  `tuned` reports the choice, its time and
+the library defaults' time.
+
 `value` is the mixed-precision throughput (FP32 V-cycle, FP64 outer Krylov,
 residual, refinement and coarsest solve) in cells per second; the plain FP64
 solve is timed beside it (`fp64`).  The roofline entry describes the dominant
@@ -43,7 +49,12 @@ def main():
     ap.add_argument("--n", type=int, default=1024, help="cells per side")
     ap.add_argument("--fp64-steps", type=int, default=None, help="timed FP64 steps (default: --steps)")
     ap.add_argument("--kernel-reps", type=int, default=200)
-    ap.add_argument("--cpu-n", type=int, default=256, help="oracle sample size (cells per side)")
+    ap.add_argument("--cpu-n", type=int, default=384, help="oracle sample size (cells per side)")
+    ap.add_argument("--no-tune", action="store_true", help="library defaults instead of autotuned parameters")
+    ap.add_argument("--tune-reps", type=int, default=2, help="timed solves per autotuner candidate")
+    ap.add_argument("--tuning-db", default=None, help="JSON tuning database to store (and with --reuse-tuning, "
+                                                       "read) the tuned parameters")
+    ap.add_argument("--reuse-tuning", action="store_true", help="take tuned parameters from --tuning-db if present")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=256, help="problems in the batched workload (0: skip)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-gradient workload")
@@ -74,8 +85,28 @@ def main():
     to = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     eb, ep, rho = to(pr.eta_b), to(pr.eta_p), to(pr.rho_b)
 
+    # autotuned kernel plan and schedule (untimed; the answer does not depend on it)
+    from paper_2603_14040_amd import autotune
+    tuned = {}
+    for prec, tag in ((tph.MIXED, "mixed"), (tph.FP64, "fp64")):
+        if args.no_tune or (prec == tph.FP64 and args.fp64_steps == 0):
+            tuned[tag] = {"params": {}, "ms": None, "default_ms": None, "trials": 0, "seconds": 0.0}
+            continue
+        db = autotune.TuningDB(args.tuning_db) if args.tuning_db else None
+        key = autotune.TuningDB.key(n, n, prec, autotune.device_name(dev), tph._lib.version(), "grf") if db else None
+        if db is not None and args.reuse_tuning and db.get(key):
+            tuned[tag] = db.get(key)
+            log(f"[bench] {tag}: parameters from {args.tuning_db}")
+            continue
+        log(f"[bench] autotuning the {tag} solve")
+        tuned[tag] = autotune.tune(eb, ep, rho, pr.gx, pr.gy, precision=prec, reps=args.tune_reps, device=dev,
+                                   db=db, tag="grf")
+        log(f"[bench] {tag}: tuned {tuned[tag]['params']} {tuned[tag]['ms']:.2f} ms "
+            f"(defaults {tuned[tag]['default_ms']:.2f} ms, {tuned[tag]['trials']} trials, "
+            f"{tuned[tag]['seconds']:.1f} s)")
+
     def run(precision, steps, warmup, tag):
-        s = tph.Solver(n, n, precision=precision, device=dev)
+        s = tph.Solver(n, n, precision=precision, device=dev, **tuned[tag]["params"])
         vx, vy, p = s.zeros(), s.zeros(), s.zeros()
 
         def step():
@@ -109,7 +140,11 @@ def main():
 
     live = [0, 0.0, 0.0, 0]
     s_mix, ms_mix, inf_mix = run(tph.MIXED, args.steps, args.warmup, "mixed")
-    s64, ms_64, inf_64 = run(tph.FP64, args.fp64_steps or args.steps, 1, "fp64")
+    fp64_steps = args.steps if args.fp64_steps is None else args.fp64_steps
+    s64 = None
+    if fp64_steps > 0:
+        s64, ms_64, inf_64 = run(tph.FP64, fp64_steps, 1, "fp64")
+    plan0 = s_mix.level_plan(0)
 
     # dominant kernel: finest-level smoother of the mixed path, HIP events on the solver stream
     kern = {}
@@ -117,6 +152,8 @@ def main():
              tph._lib.KERNEL_RESIDUAL: "residual_l0", tph._lib.KERNEL_RESTRICT: "restrict_l0",
              tph._lib.KERNEL_PROLONG: "prolong_l0"}
     for kind, name in names.items():
+        if args.kernel_reps <= 0:
+            break
         ms, by = s_mix.time_kernel(kind, args.kernel_reps)
         kern[name] = {"us": round(ms * 1e3, 3), "bytes": by, "GBps": round(by / (ms * 1e-3) / 1e9, 1)}
     # the roofline figure comes from the launches inside the timed solves
@@ -141,7 +178,7 @@ def main():
     # batched workload: independent sinkers of sizes {64, 128, 256, 512}, one batched solve
     batch = None
     if args.batch > 0:
-        del s64
+        s64 = None
         probs = wl.batch_sinkers(args.batch, seed=4)
         log(f"[bench] batched workload: {len(probs)} problems, {sum(p.cells for p in probs)} cells")
         t0 = time.perf_counter()
@@ -238,20 +275,24 @@ def main():
         "dtype": "f32 V-cycle + f64 Krylov/residual (mixed)",
         "data": "synthetic",
         "config": {"workload": f"random-viscosity {n}x{n} cells, log10 eta Gaussian random field "
-                               f"(corr. length 0.05, contrast 1e4), free slip, FGMRES(20) + "
+                               f"(corr. length 0.05, contrast 1e4), free slip, FGMRES({s_mix.desc.restart}) + "
                                f"{s_mix.levels}-level V-cycle, relative energy residual 1e-8",
                    "cells": cells, "levels": s_mix.levels, "precision": "mixed", "global_batch": 1},
         "iters": inf_mix[-1].iters,
         "res_energy": inf_mix[-1].res_energy,
         "setup_ms": inf_mix[-1].t_setup_ms,
         "solve_ms": inf_mix[-1].t_solve_ms,
-        "fp64": {"value": cells / (ms_64 * 1e-3), "ms_per_step": ms_64, "iters": inf_64[-1].iters,
-                 "res_energy": inf_64[-1].res_energy},
-        "mixed_speedup_vs_fp64": ms_64 / ms_mix,
+        "fp64": ({"value": cells / (ms_64 * 1e-3), "ms_per_step": ms_64, "iters": inf_64[-1].iters,
+                  "res_energy": inf_64[-1].res_energy} if fp64_steps > 0 else None),
+        "mixed_speedup_vs_fp64": ms_64 / ms_mix if fp64_steps > 0 else None,
+        "tuned": tuned,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "finest-level Gauss-Seidel sweep on LDS tiles (FP32; zero-guess, plain and "
-                               "prolongation modes), HIP events on the solver stream inside the timed solves",
+                     "kernel": ("finest-level Gauss-Seidel on LDS tiles (FP32, " +
+                                ("multi-sweep passes with fused residual-restriction / prolongation"
+                                 if plan0[0] == "multisweep" else "one sweep per launch") +
+                                f", tile shape {plan0[1]}), HIP events on the solver stream inside the "
+                                "timed solves"),
                      "launches": n_l, "dropped": drop_l, "us_per_launch": round(us_live, 3),
                      "algorithmic_bytes_per_launch": by_l / n_l},
         "kernels": kern,

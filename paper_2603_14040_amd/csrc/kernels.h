@@ -90,7 +90,10 @@ hipError_t launch_axpy_dot(double* w, const double* V0, size_t vstride, int nv, 
                            size_t n, bool want_dots, int norm_slot, double* partial, int nblk,
                            hipStream_t st);
 // out[i] = sum_b partial[i * nblk + b], i < k  (fixed order: deterministic)
-hipError_t launch_reduce_rows(const double* partial, int nblk, int k, double* out, hipStream_t st);
+// row sums of partial (k rows of nblk) into out; also into host_out (a device
+// pointer to mapped coherent host memory) when it is not null
+hipError_t launch_reduce_rows(const double* partial, int nblk, int k, double* out, hipStream_t st,
+                              double* host_out = nullptr);
 // dst = src / sqrt(*nrm2)
 hipError_t launch_scale_by_rnorm(double* dst, const double* src, size_t n, const double* nrm2,
                                  hipStream_t st);

@@ -91,12 +91,15 @@ __global__ __launch_bounds__(256) void k_axpy_dot(double* __restrict__ w, const 
 }
 
 __global__ __launch_bounds__(256) void k_reduce_rows(const double* __restrict__ partial, int nblk,
-                                                    double* __restrict__ out) {
+                                                    double* __restrict__ out, double* __restrict__ host_out) {
     const double* row = partial + (size_t)blockIdx.x * nblk;
     double s = 0.0;
     for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += row[b];
     s = block_sum(s);
-    if (threadIdx.x == 0) out[blockIdx.x] = s;
+    if (threadIdx.x == 0) {
+        out[blockIdx.x] = s;
+        if (host_out) host_out[blockIdx.x] = s;   // visible to the host once the stream has synchronised
+    }
 }
 
 __global__ __launch_bounds__(256) void k_scale_rnorm(double* __restrict__ dst, const double* __restrict__ src,
@@ -175,8 +178,9 @@ hipError_t launch_axpy_dot(double* w, const double* V0, size_t vstride, int nv, 
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_rows(const double* partial, int nblk, int k, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce_rows, dim3(k), dim3(256), 0, st, partial, nblk, out);
+hipError_t launch_reduce_rows(const double* partial, int nblk, int k, double* out, hipStream_t st,
+                              double* host_out) {
+    hipLaunchKernelGGL(k_reduce_rows, dim3(k), dim3(256), 0, st, partial, nblk, out, host_out);
     return hipGetLastError();
 }
 

@@ -103,7 +103,8 @@ struct tph_solver {
     double* partial = nullptr;   // reduction partials
     size_t partial_len = 0;
     double* dscal = nullptr;     // device scalars
-    double* hscal = nullptr;     // pinned host mirror
+    double* hscal = nullptr;     // pinned host mirror (mapped, coherent)
+    double* hscal_dev = nullptr; // its device address: reductions write results there directly
     double gx = 0, gy = 0;
     bool has_fx = false, has_fy = false;
     bool ready = false;
@@ -448,9 +449,16 @@ tph_status precondition(tph_solver* s, double* vraw, double* zraw, bool energy) 
     return s->mixed() ? precondition_t<float>(s, vraw, zraw, energy) : precondition_t<double>(s, vraw, zraw, energy);
 }
 
-// reduce partial rows on the device and copy `k` results to the host mirror at slot
-tph_status reduce_to(tph_solver* s, int nblk, int k, int slot) {
-    TPH_HIP(launch_reduce_rows(s->partial, nblk, k, s->dscal + slot, s->st));
+// reduce partial rows into `k` device scalars at slot; with to_host the same
+// kernel also writes them into the mapped host mirror (no copy launch), read
+// by the host after wait()
+tph_status reduce_to(tph_solver* s, int nblk, int k, int slot, bool to_host = false) {
+    TPH_HIP(launch_reduce_rows(s->partial, nblk, k, s->dscal + slot, s->st, to_host ? s->hscal_dev + slot : nullptr));
+    return TPH_OK;
+}
+
+tph_status wait(tph_solver* s) {
+    TPH_HIP(hipStreamSynchronize(s->st));
     return TPH_OK;
 }
 
@@ -461,13 +469,14 @@ tph_status fetch(tph_solver* s, int slot, int k) {
 }
 
 // ||W^(1/2) (b - A x)||^2 into dscal[slot]; out receives the scaled residual
-tph_status energy_residual_vec(tph_solver* s, double* xraw, double* braw, double* outraw, int slot) {
+tph_status energy_residual_vec(tph_solver* s, double* xraw, double* braw, double* outraw, int slot,
+                               bool to_host = false) {
     const LevelBuf& L = s->lev[0];
     int nblk = 0;
     Vec3 b = vec3(s, braw);
     TPH_HIP(launch_outer_residual(L.g, vec3(s, xraw), &b, L.eb64, L.ep64, vec3(s, outraw), ResMode::kResidual, true,
                                   s->partial, &nblk, s->st));
-    return reduce_to(s, nblk, 1, slot);
+    return reduce_to(s, nblk, 1, slot, to_host);
 }
 
 tph_status copy_in(tph_solver* s, const Geom& g, double* base, const double* user) {
@@ -526,8 +535,8 @@ tph_status fgmres(tph_solver* s, double* braw, tph_info* info) {
     // ||W^(1/2) b||: residual of x = 0
     {
         TPH_HIP(hipMemsetAsync(s->t2, 0, n3 * sizeof(double), s->st));
-        TPH_TRY(energy_residual_vec(s, s->t2, braw, s->t1, kSlotMisc));
-        TPH_TRY(fetch(s, kSlotMisc, 1));
+        TPH_TRY(energy_residual_vec(s, s->t2, braw, s->t1, kSlotMisc, true));
+        TPH_TRY(wait(s));
     }
     const double bnorm = std::sqrt(s->hscal[kSlotMisc]);
     if (!std::isfinite(bnorm)) { set_error("right-hand side is not finite"); return TPH_ERR_NONFINITE; }
@@ -543,8 +552,8 @@ tph_status fgmres(tph_solver* s, double* braw, tph_info* info) {
     bool stagnated = false;
     while (true) {
         // true residual r = W^(1/2) (b - A x) into V_0
-        TPH_TRY(energy_residual_vec(s, s->x, braw, Vk(0), kSlotMisc));
-        TPH_TRY(fetch(s, kSlotMisc, 1));
+        TPH_TRY(energy_residual_vec(s, s->x, braw, Vk(0), kSlotMisc, true));
+        TPH_TRY(wait(s));
         const double beta = std::sqrt(s->hscal[kSlotMisc]);
         if (!std::isfinite(beta)) { set_error("non-finite residual during the solve"); return TPH_ERR_NONFINITE; }
         true_res = bnorm > 0 ? beta / bnorm : beta;
@@ -571,25 +580,21 @@ tph_status fgmres(tph_solver* s, double* braw, tph_info* info) {
             // projection pass, and a second only when the norm drops below
             // 1/sqrt(2) of its value before the projection (cancellation)
             TPH_HIP(launch_multidot(Vk(0), n3, j + 1, w, n3, s->partial, nblk_flat, s->st, j + 1));
-            TPH_TRY(reduce_to(s, nblk_flat, j + 2, kSlotH1));        // h (j+1) and |w|^2 at kSlotH1 + j + 1
+            TPH_TRY(reduce_to(s, nblk_flat, j + 2, kSlotH1, true));  // h (j+1) and |w|^2 at kSlotH1 + j + 1
             TPH_HIP(launch_axpy_dot(w, Vk(0), n3, j + 1, s->dscal + kSlotH1, n3, false, 0, s->partial, nblk_flat,
                                     s->st));
-            TPH_TRY(reduce_to(s, nblk_flat, 1, kSlotNrm));
-            TPH_HIP(hipMemcpyAsync(s->hscal, s->dscal, (size_t)(kSlotNrm + 1) * sizeof(double), hipMemcpyDeviceToHost,
-                                   s->st));
-            TPH_HIP(hipStreamSynchronize(s->st));
+            TPH_TRY(reduce_to(s, nblk_flat, 1, kSlotNrm, true));
+            TPH_TRY(wait(s));
             double* col = &H[(size_t)j * (m + 1)];
             for (int i = 0; i <= j; ++i) col[i] = s->hscal[kSlotH1 + i];
             const double w2_before = s->hscal[kSlotH1 + j + 1];
             if (s->hscal[kSlotNrm] < 0.5 * w2_before) {
                 TPH_HIP(launch_multidot(Vk(0), n3, j + 1, w, n3, s->partial, nblk_flat, s->st));
-                TPH_TRY(reduce_to(s, nblk_flat, j + 1, kSlotH2));
+                TPH_TRY(reduce_to(s, nblk_flat, j + 1, kSlotH2, true));
                 TPH_HIP(launch_axpy_dot(w, Vk(0), n3, j + 1, s->dscal + kSlotH2, n3, false, 0, s->partial, nblk_flat,
                                         s->st));
-                TPH_TRY(reduce_to(s, nblk_flat, 1, kSlotNrm));
-                TPH_HIP(hipMemcpyAsync(s->hscal, s->dscal, (size_t)(kSlotNrm + 1) * sizeof(double),
-                                       hipMemcpyDeviceToHost, s->st));
-                TPH_HIP(hipStreamSynchronize(s->st));
+                TPH_TRY(reduce_to(s, nblk_flat, 1, kSlotNrm, true));
+                TPH_TRY(wait(s));
                 for (int i = 0; i <= j; ++i) col[i] += s->hscal[kSlotH2 + i];
                 ++s->reorth_count;
             }
@@ -751,7 +756,8 @@ tph_status create_impl(const tph_desc* desc, void* stream, tph_solver* s) {
         }
     }
     TPH_TRY(dev_alloc(s, (void**)&s->Minv, (size_t)s->ncoarse * s->ncoarse * sizeof(double)));
-    TPH_HIP(hipHostMalloc((void**)&s->hscal, kScalars * sizeof(double), hipHostMallocDefault));
+    TPH_HIP(hipHostMalloc((void**)&s->hscal, kScalars * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent));
+    TPH_HIP(hipHostGetDevicePointer((void**)&s->hscal_dev, s->hscal, 0));
     TPH_HIP(hipEventCreate(&s->ev0));
     TPH_HIP(hipEventCreate(&s->ev1));
     TPH_HIP(hipStreamSynchronize(s->st));
