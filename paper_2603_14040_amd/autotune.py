@@ -228,8 +228,11 @@ def tune(eta_b, eta_p, rho_b, gx: float = 0.0, gy: float = -1.0, *, precision: O
 
 
 def device_name(device=None) -> str:
+    """Architecture and compute-unit count of the device (stable across tools)."""
     import torch
-    return torch.cuda.get_device_name(device).strip() or "gpu"
+    pr = torch.cuda.get_device_properties(device)
+    arch = getattr(pr, "gcnArchName", "") or pr.name
+    return f"{arch.split(':')[0]}-{pr.multi_processor_count}cu"
 
 
 def lookup(nx: int, ny: int, precision: int, db: Optional[TuningDB] = None, tag: str = "",

@@ -80,6 +80,17 @@ __device__ __forceinline__ bool is_vy(const Geom& g, int i, int j) { return i >=
 template <int RH>
 constexpr int prolong_rows() { return RH / 2 + 4; }
 
+// Every LDS tile kernel runs 256 threads.  Loops over a tile region have a
+// compile-time trip count and are unrolled with all global loads of a phase
+// issued into registers before the first one is used: a tile is latency-
+// bound (few waves per CU at the finest level, a handful of tiles on the
+// small ones), and a load loop that waited for each load before issuing the
+// next would serialise one memory latency per iteration.
+constexpr int kTileThreads = 256;
+
+template <int N>
+constexpr int tile_iters() { return (N + kTileThreads - 1) / kTileThreads; }
+
 // load the iterate (zero / from memory / from memory + prolongated coarse
 // correction) and the viscosities of the region starting at (gi0, gj0)
 template <typename T, int RW, int RH, int MODE>
@@ -88,51 +99,81 @@ __device__ __forceinline__ void tile_load(const Geom& g, const Geom& gc, int gi0
                                           const T* __restrict__ ep, const T* __restrict__ ecx,
                                           const T* __restrict__ ecy, T* sx, T* sy, T* sb, T* sp, T* scx, T* scy,
                                           const LevelC<T>& k) {
-    constexpr int RN = RW * RH;
-    constexpr int CR = prolong_rows<RH>(), CC = prolong_rows<RW>();
+    constexpr int RN = RW * RH, IT = tile_iters<RN>();
+    constexpr int CR = prolong_rows<RH>(), CC = prolong_rows<RW>(), ITC = tile_iters<CR * CC>();
+    constexpr bool kIter = MODE != kModeZero;
     const int tid = threadIdx.x;
-    const int nt = blockDim.x;
     const int P = g.pitch;
+    T vb[IT], vp[IT], vx[kIter ? IT : 1], vy[kIter ? IT : 1];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int q = tid + it * kTileThreads;
+        const int a = q / RW, b = q - (q / RW) * RW;
+        const int gi = gi0 + a, gj = gj0 + b;
+        const bool in = q < RN && gi >= 0 && gi <= g.ny + 1 && gj >= 0 && gj <= g.nx + 1;
+        const int c = in ? gi * P + gj : 0;
+        vb[it] = in ? eb[c] : (T)0;
+        vp[it] = in ? ep[c] : (T)0;
+        if (kIter) {
+            vx[it] = in ? exi[c] : (T)0;
+            vy[it] = in ? eyi[c] : (T)0;
+        }
+    }
     // first coarse row / column of the prolongation window: floor(gi0 / 2) - 1
     // (gi0 may be negative; the +64 keeps the shift on a non-negative value)
     const int ci0 = ((gi0 + 64) >> 1) - 32 - 1;
     const int cj0 = ((gj0 + 64) >> 1) - 32 - 1;
     if (MODE == kModeProlong) {
-        for (int q = tid; q < CR * CC; q += nt) {
+        T wx[ITC], wy[ITC];
+#pragma unroll
+        for (int it = 0; it < ITC; ++it) {
+            const int q = tid + it * kTileThreads;
             const int a = q / CC, b = q - (q / CC) * CC;
             const int I = ci0 + a, J = cj0 + b;
-            const bool in = I >= 0 && I <= gc.ny + 1 && J >= 0 && J <= gc.nx + 1;
-            scx[q] = in ? ecx[I * gc.pitch + J] : (T)0;
-            scy[q] = in ? ecy[I * gc.pitch + J] : (T)0;
+            const bool in = q < CR * CC && I >= 0 && I <= gc.ny + 1 && J >= 0 && J <= gc.nx + 1;
+            const int c = in ? I * gc.pitch + J : 0;
+            wx[it] = in ? ecx[c] : (T)0;
+            wy[it] = in ? ecy[c] : (T)0;
+        }
+#pragma unroll
+        for (int it = 0; it < ITC; ++it) {
+            const int q = tid + it * kTileThreads;
+            if (q < CR * CC) {
+                scx[q] = wx[it];
+                scy[q] = wy[it];
+            }
         }
         __syncthreads();
     }
-    for (int q = tid; q < RN; q += nt) {
-        const int a = q / RW, b = q - (q / RW) * RW;
-        const int gi = gi0 + a, gj = gj0 + b;
-        const bool in = gi >= 0 && gi <= g.ny + 1 && gj >= 0 && gj <= g.nx + 1;
-        const int c = gi * P + gj;
-        sb[q] = in ? eb[c] : (T)0;
-        sp[q] = in ? ep[c] : (T)0;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int q = tid + it * kTileThreads;
+        if (q >= RN) continue;
+        sb[q] = vb[it];
+        sp[q] = vp[it];
         if (MODE == kModeZero) {
             sx[q] = (T)0;
             sy[q] = (T)0;
         } else {
-            T vx = in ? exi[c] : (T)0;
-            T vy = in ? eyi[c] : (T)0;
+            T ux = vx[it], uy = vy[it];
             if (MODE == kModeProlong) {
                 // coarse indices are taken relative to the LDS window
-                if (is_vx(g, gi, gj)) vx += prolong_vx(scx - ci0 * CC - cj0, CC, gi, gj);
-                if (is_vy(g, gi, gj)) vy += prolong_vy(scy - ci0 * CC - cj0, CC, gi, gj);
+                const int a = q / RW, b = q - (q / RW) * RW;
+                const int gi = gi0 + a, gj = gj0 + b;
+                if (is_vx(g, gi, gj)) ux += prolong_vx(scx - ci0 * CC - cj0, CC, gi, gj);
+                if (is_vy(g, gi, gj)) uy += prolong_vy(scy - ci0 * CC - cj0, CC, gi, gj);
             }
-            sx[q] = vx;
-            sy[q] = vy;
+            sx[q] = ux;
+            sy[q] = uy;
         }
     }
     __syncthreads();
     if (MODE == kModeProlong) {
         // ghosts mirror the corrected interior values
-        for (int q = tid; q < RN; q += nt) {
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int q = tid + it * kTileThreads;
+            if (q >= RN) continue;
             const int a = q / RW, b = q - (q / RW) * RW;
             const int gi = gi0 + a, gj = gj0 + b;
             if (gj >= 1 && gj < g.nx) {
@@ -148,46 +189,92 @@ __device__ __forceinline__ void tile_load(const Geom& g, const Geom& gc, int gi0
     }
 }
 
-// NSTAGE colour half-sweeps (stage s: component (s >> 1) & 1, colour s & 1,
-// i.e. vx red, vx black, vy red, vy black, repeated).  Each stage needs the
-// previous one's values one node further out, so stage s updates the nodes
-// within H - 1 - s of the tile.  A wall-adjacent node refreshes its own
-// ghost right away; only that node reads the ghost, so the next sweep in
-// the tile sees the mirror of the latest value, as a sweep over the whole
-// grid with ghosts refilled between sweeps does.
+// Shape of the colour stages of a tile: stage s (component (s >> 1) & 1,
+// colour s & 1, i.e. vx red, vx black, vy red, vy black, repeated) updates
+// the nodes within h = H - 1 - s of the tile; thread t takes the nodes
+// t, t + 256, ... of the stage's list (rows x half, one colour per row).
+template <int TW, int TH, int H, int NSTAGE>
+struct Stages {
+    static constexpr int rows(int s) { return TH + 2 * (H - 1 - s); }
+    static constexpr int half(int s) { return (TW + 2 * (H - 1 - s)) / 2; }
+    static constexpr int iters(int s) { return (rows(s) * half(s) + kTileThreads - 1) / kTileThreads; }
+    static constexpr int offset(int s) {
+        int o = 0;
+        for (int q = 0; q < s; ++q) o += iters(q);
+        return o;
+    }
+    static constexpr int total() { return offset(NSTAGE); }
+};
+
+// LDS coordinates (a, b) of item q of stage s
+template <int TW, int TH, int H>
+__device__ __forceinline__ void stage_node(int s, int q, int gi0, int gj0, int& a, int& b) {
+    const int h = H - 1 - s, col = s & 1;
+    const int half = (TW + 2 * h) / 2;
+    const int ar = q / half, bb = q - (q / half) * half;
+    const int a0 = H - h, b0 = H - h;
+    a = a0 + ar;
+    const int p0 = (gi0 + a + gj0 + b0) & 1;
+    b = b0 + 2 * bb + (col ^ p0);
+}
+
+// right-hand side of every node this thread updates, in stage order
 template <typename T, int TW, int TH, int H, int NSTAGE>
-__device__ __forceinline__ void gs_stages(const Geom& g, int gi0, int gj0, T* sx, T* sy, const T* sb, const T* sp,
-                                          const T* __restrict__ rx, const T* __restrict__ ry, T omega,
-                                          const LevelC<T>& k) {
-    constexpr int RW = TW + 2 * H, RH = TH + 2 * H;
+__device__ __forceinline__ void stage_rhs(const Geom& g, int gi0, int gj0, const T* __restrict__ rx,
+                                          const T* __restrict__ ry, T* rr) {
+    using S = Stages<TW, TH, H, NSTAGE>;
     const int tid = threadIdx.x;
-    const int nt = blockDim.x;
     const int P = g.pitch;
 #pragma unroll
     for (int s = 0; s < NSTAGE; ++s) {
-        const int comp = (s >> 1) & 1, col = s & 1, h = H - 1 - s;
-        const int rows = TH + 2 * h, half = (TW + 2 * h) / 2;
-        const int a0 = H - h, b0 = H - h;
-        for (int q = tid; q < rows * half; q += nt) {
-            const int ar = q / half, bb = q - (q / half) * half;
-            const int a = a0 + ar;
-            const int p0 = (gi0 + a + gj0 + b0) & 1;
-            const int b = b0 + 2 * bb + (col ^ p0);
+        const int comp = (s >> 1) & 1;
+#pragma unroll
+        for (int it = 0; it < S::iters(s); ++it) {
+            const int q = tid + it * kTileThreads;
+            int a, b;
+            stage_node<TW, TH, H>(s, q, gi0, gj0, a, b);
+            const int gi = gi0 + a, gj = gj0 + b;
+            const bool ok = q < S::rows(s) * S::half(s) && (comp == 0 ? is_vx(g, gi, gj) : is_vy(g, gi, gj));
+            const int c = ok ? gi * P + gj : 0;
+            rr[S::offset(s) + it] = ok ? (comp == 0 ? rx[c] : ry[c]) : (T)0;
+        }
+    }
+}
+
+// NSTAGE colour half-sweeps.  Each stage needs the previous one's values
+// one node further out, hence the shrinking regions.  A wall-adjacent node
+// refreshes its own ghost right away; only that node reads the ghost, so
+// the next sweep in the tile sees the mirror of the latest value, as a sweep
+// over the whole grid with ghosts refilled between sweeps does.
+template <typename T, int TW, int TH, int H, int NSTAGE>
+__device__ __forceinline__ void gs_stages(const Geom& g, int gi0, int gj0, T* sx, T* sy, const T* sb, const T* sp,
+                                          const T* rr, T omega, const LevelC<T>& k) {
+    using S = Stages<TW, TH, H, NSTAGE>;
+    constexpr int RW = TW + 2 * H, RH = TH + 2 * H;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int s = 0; s < NSTAGE; ++s) {
+        const int comp = (s >> 1) & 1;
+#pragma unroll
+        for (int it = 0; it < S::iters(s); ++it) {
+            const int q = tid + it * kTileThreads;
+            if (q >= S::rows(s) * S::half(s)) continue;
+            int a, b;
+            stage_node<TW, TH, H>(s, q, gi0, gj0, a, b);
             const int gi = gi0 + a, gj = gj0 + b;
             const int c = a * RW + b;
+            const T r = rr[S::offset(s) + it];
             if (comp == 0) {
                 if (!is_vx(g, gi, gj)) continue;
                 const T d = lx_diag(sb, sp, c, RW, gi, g.ny, k);
-                const T res = rx[gi * P + gj] - lx_row(sx, sy, sb, sp, c, RW, k.idx, k.idy);
-                const T e = sx[c] + omega * res / d;
+                const T e = sx[c] + omega * (r - lx_row(sx, sy, sb, sp, c, RW, k.idx, k.idy)) / d;
                 sx[c] = e;
                 if (gi == 1 && a >= 1) sx[c - RW] = k.mirS * e;
                 if (gi == g.ny && a + 1 < RH) sx[c + RW] = k.mirN * e;
             } else {
                 if (!is_vy(g, gi, gj)) continue;
                 const T d = ly_diag(sb, sp, c, RW, gj, g.nx, k);
-                const T res = ry[gi * P + gj] - ly_row(sx, sy, sb, sp, c, RW, k.idx, k.idy);
-                const T e = sy[c] + omega * res / d;
+                const T e = sy[c] + omega * (r - ly_row(sx, sy, sb, sp, c, RW, k.idx, k.idy)) / d;
                 sy[c] = e;
                 if (gj == 1 && b >= 1) sy[c - 1] = k.mirW * e;
                 if (gj == g.nx && b + 1 < RW) sy[c + 1] = k.mirE * e;
@@ -203,7 +290,10 @@ __device__ __forceinline__ void tile_store(const Geom& g, int gi0, int gj0, cons
                                            T* __restrict__ exo, T* __restrict__ eyo, const LevelC<T>& k) {
     constexpr int RW = TW + 2 * H;
     const int P = g.pitch;
-    for (int q = threadIdx.x; q < TW * TH; q += blockDim.x) {
+#pragma unroll
+    for (int it = 0; it < tile_iters<TW * TH>(); ++it) {
+        const int q = threadIdx.x + it * kTileThreads;
+        if (q >= TW * TH) continue;
         const int a = H + q / TW, b = H + (q - (q / TW) * TW);
         const int gi = gi0 + a, gj = gj0 + b;
         const int c = a * RW + b;
@@ -283,24 +373,47 @@ __device__ __forceinline__ void gs_tile_body(const Geom& g, const Geom& gc, cons
     __shared__ T sx[RN], sy[RN], sb[RN], sp[RN];
     __shared__ T scx[CN], scy[CN];
     __shared__ T stx[TRW * TRH], sty[TRW * TRH];
+    constexpr int NR = Stages<TW, TH, H, 4 * NS>::total();
+    constexpr int ITR = RR ? tile_iters<TRW * TRH>() : 1;
     const int i0 = 1 + tby * TH, j0 = 1 + tbx * TW;
     const int gi0 = i0 - H, gj0 = j0 - H;
+    const int P = g.pitch;
     const LevelC<T> k = level_consts<T>(g);
+    // right-hand sides first: they are in flight while the tile loads
+    T rr[NR];
+    stage_rhs<T, TW, TH, H, 4 * NS>(g, gi0, gj0, rx, ry, rr);
+    T rrx[ITR], rry[ITR];
+    if (RR) {
+#pragma unroll
+        for (int it = 0; it < ITR; ++it) {
+            const int q = threadIdx.x + it * kTileThreads;
+            const int a = q / TRW, b = q - (q / TRW) * TRW;
+            const int gi = i0 - 1 + a, gj = j0 - 1 + b;
+            const bool okx = q < TRW * TRH && is_vx(g, gi, gj), oky = q < TRW * TRH && is_vy(g, gi, gj);
+            rrx[it] = okx ? rx[gi * P + gj] : (T)0;
+            rry[it] = oky ? ry[gi * P + gj] : (T)0;
+        }
+    }
     tile_load<T, RW, RH, MODE>(g, gc, gi0, gj0, exi, eyi, eb, ep, ecx, ecy, sx, sy, sb, sp, scx, scy, k);
-    gs_stages<T, TW, TH, H, 4 * NS>(g, gi0, gj0, sx, sy, sb, sp, rx, ry, omega, k);
+    gs_stages<T, TW, TH, H, 4 * NS>(g, gi0, gj0, sx, sy, sb, sp, rr, omega, k);
     tile_store<T, TW, TH, H>(g, gi0, gj0, sx, sy, exo, eyo, k);
     if (RR) {
-        const int P = g.pitch;
-        for (int q = threadIdx.x; q < TRW * TRH; q += blockDim.x) {
+#pragma unroll
+        for (int it = 0; it < ITR; ++it) {
+            const int q = threadIdx.x + it * kTileThreads;
+            if (q >= TRW * TRH) continue;
             const int a = q / TRW, b = q - (q / TRW) * TRW;
             const int gi = i0 - 1 + a, gj = j0 - 1 + b;
             const int c = (a + H - 1) * RW + (b + H - 1);
-            stx[q] = is_vx(g, gi, gj) ? rx[gi * P + gj] - lx_row(sx, sy, sb, sp, c, RW, k.idx, k.idy) : (T)0;
-            sty[q] = is_vy(g, gi, gj) ? ry[gi * P + gj] - ly_row(sx, sy, sb, sp, c, RW, k.idx, k.idy) : (T)0;
+            stx[q] = is_vx(g, gi, gj) ? rrx[it] - lx_row(sx, sy, sb, sp, c, RW, k.idx, k.idy) : (T)0;
+            sty[q] = is_vy(g, gi, gj) ? rry[it] - ly_row(sx, sy, sb, sp, c, RW, k.idx, k.idy) : (T)0;
         }
         __syncthreads();
         const int I0 = 1 + tby * (TH / 2), J0 = 1 + tbx * (TW / 2);
-        for (int q = threadIdx.x; q < (TH / 2) * (TW / 2); q += blockDim.x) {
+#pragma unroll
+        for (int it = 0; it < tile_iters<(TH / 2) * (TW / 2)>(); ++it) {
+            const int q = threadIdx.x + it * kTileThreads;
+            if (q >= (TH / 2) * (TW / 2)) continue;
             const int I = I0 + q / (TW / 2), J = J0 + (q - (q / (TW / 2)) * (TW / 2));
             if (I > gc.ny || J > gc.nx) continue;
             restrict_cell<T, TRW>(g, gc, stx, sty, i0 - 1, j0 - 1, I, J, rcx, rcy);
@@ -321,26 +434,39 @@ __device__ __forceinline__ void jacobi_tile_body(const Geom& g, const Geom& gc, 
     constexpr int CN = MODE == kModeProlong ? prolong_rows<RH>() * prolong_rows<RW>() : 1;
     __shared__ T sx[RN], sy[RN], sb[RN], sp[RN];
     __shared__ T scx[CN], scy[CN];
+    constexpr int IT = tile_iters<TW * TH>();
     const int i0 = 1 + tby * TH, j0 = 1 + tbx * TW;
     const int gi0 = i0 - H, gj0 = j0 - H;
     const int P = g.pitch;
     const LevelC<T> k = level_consts<T>(g);
+    T rrx[IT], rry[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int q = threadIdx.x + it * kTileThreads;
+        const int a = H + q / TW, b = H + (q - (q / TW) * TW);
+        const int gi = gi0 + a, gj = gj0 + b;
+        rrx[it] = q < TW * TH && is_vx(g, gi, gj) ? rx[gi * P + gj] : (T)0;
+        rry[it] = q < TW * TH && is_vy(g, gi, gj) ? ry[gi * P + gj] : (T)0;
+    }
     tile_load<T, RW, RH, MODE>(g, gc, gi0, gj0, exi, eyi, eb, ep, ecx, ecy, sx, sy, sb, sp, scx, scy, k);
-    for (int q = threadIdx.x; q < TW * TH; q += blockDim.x) {
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int q = threadIdx.x + it * kTileThreads;
+        if (q >= TW * TH) continue;
         const int a = H + q / TW, b = H + (q - (q / TW) * TW);
         const int gi = gi0 + a, gj = gj0 + b;
         const int c = a * RW + b;
         const int cg = gi * P + gj;
         if (is_vx(g, gi, gj)) {
             const T d = lx_diag(sb, sp, c, RW, gi, g.ny, k);
-            const T e = sx[c] + omega * (rx[cg] - lx_row(sx, sy, sb, sp, c, RW, k.idx, k.idy)) / d;
+            const T e = sx[c] + omega * (rrx[it] - lx_row(sx, sy, sb, sp, c, RW, k.idx, k.idy)) / d;
             exo[cg] = e;
             if (gi == 1) exo[cg - P] = k.mirS * e;
             if (gi == g.ny) exo[cg + P] = k.mirN * e;
         }
         if (is_vy(g, gi, gj)) {
             const T d = ly_diag(sb, sp, c, RW, gj, g.nx, k);
-            const T e = sy[c] + omega * (ry[cg] - ly_row(sx, sy, sb, sp, c, RW, k.idx, k.idy)) / d;
+            const T e = sy[c] + omega * (rry[it] - ly_row(sx, sy, sb, sp, c, RW, k.idx, k.idy)) / d;
             eyo[cg] = e;
             if (gj == 1) eyo[cg - 1] = k.mirW * e;
             if (gj == g.nx) eyo[cg + 1] = k.mirE * e;
@@ -383,24 +509,48 @@ __device__ __forceinline__ void res_restrict_body(const Geom& g, const Geom& gc,
     const int li0 = fi0 - 1, lj0 = fj0 - 1;             // first loaded row / column
     const int P = g.pitch;
     const LevelC<T> k = level_consts<T>(g);
-    for (int q = tid; q < LN; q += NT) {
+    constexpr int ITL = (LN + NT - 1) / NT, ITR = (RN + NT - 1) / NT;
+    // every load of the tile in flight before the first use (see kTileThreads)
+    T vx[ITL], vy[ITL], vb[ITL], vp[ITL], rrx[ITR], rry[ITR];
+#pragma unroll
+    for (int it = 0; it < ITR; ++it) {
+        const int q = tid + it * NT;
+        const int a = q / RC, b = q - (q / RC) * RC;
+        const int gi = fi0 + a, gj = fj0 + b;
+        rrx[it] = q < RN && is_vx(g, gi, gj) ? rx[gi * P + gj] : (T)0;
+        rry[it] = q < RN && is_vy(g, gi, gj) ? ry[gi * P + gj] : (T)0;
+    }
+#pragma unroll
+    for (int it = 0; it < ITL; ++it) {
+        const int q = tid + it * NT;
         const int a = q / LC, b = q - (q / LC) * LC;
         const int gi = li0 + a, gj = lj0 + b;
-        const bool in = gi >= 0 && gi <= g.ny + 1 && gj >= 0 && gj <= g.nx + 1;
-        const int c = gi * P + gj;
-        sx[q] = in ? ex[c] : (T)0;
-        sy[q] = in ? ey[c] : (T)0;
-        sb[q] = in ? eb[c] : (T)0;
-        sp[q] = in ? ep[c] : (T)0;
+        const bool in = q < LN && gi >= 0 && gi <= g.ny + 1 && gj >= 0 && gj <= g.nx + 1;
+        const int c = in ? gi * P + gj : 0;
+        vx[it] = in ? ex[c] : (T)0;
+        vy[it] = in ? ey[c] : (T)0;
+        vb[it] = in ? eb[c] : (T)0;
+        vp[it] = in ? ep[c] : (T)0;
+    }
+#pragma unroll
+    for (int it = 0; it < ITL; ++it) {
+        const int q = tid + it * NT;
+        if (q >= LN) continue;
+        sx[q] = vx[it];
+        sy[q] = vy[it];
+        sb[q] = vb[it];
+        sp[q] = vp[it];
     }
     __syncthreads();
-    for (int q = tid; q < RN; q += NT) {
+#pragma unroll
+    for (int it = 0; it < ITR; ++it) {
+        const int q = tid + it * NT;
+        if (q >= RN) continue;
         const int a = q / RC, b = q - (q / RC) * RC;
         const int gi = fi0 + a, gj = fj0 + b;
         const int cl = (a + 1) * LC + (b + 1);
-        const int cg = gi * P + gj;
-        stx[q] = is_vx(g, gi, gj) ? rx[cg] - lx_row(sx, sy, sb, sp, cl, LC, k.idx, k.idy) : (T)0;
-        sty[q] = is_vy(g, gi, gj) ? ry[cg] - ly_row(sx, sy, sb, sp, cl, LC, k.idx, k.idy) : (T)0;
+        stx[q] = is_vx(g, gi, gj) ? rrx[it] - lx_row(sx, sy, sb, sp, cl, LC, k.idx, k.idy) : (T)0;
+        sty[q] = is_vy(g, gi, gj) ? rry[it] - ly_row(sx, sy, sb, sp, cl, LC, k.idx, k.idy) : (T)0;
     }
     __syncthreads();
     const int I = I0 + tid / CTW, J = J0 + (tid - (tid / CTW) * CTW);
