@@ -118,7 +118,12 @@ typedef struct tph_desc {
     int32_t tile_shape;    /* levels whose LDS tiles use the small shape (bit l);
                               -1 = levels where the large shape gives fewer than
                               512 tiles                                           */
-    int32_t reserved[4];   /* must be zero                                    */
+    int32_t coarse_level;  /* first level of the single-workgroup coarse tail
+                              (fused = 1): -1 = the finest level of at most
+                              64 x 64 cells whose tail fits in LDS; -2 = none (one
+                              launch per level down to the coarsest); l >= 0 =
+                              level l (rejected when it does not fit)          */
+    int32_t reserved[3];   /* must be zero                                    */
 } tph_desc;
 
 typedef struct tph_info {
@@ -243,16 +248,17 @@ tph_status tph_time_kernel(tph_solver* s, int32_t kind, int32_t reps, double* ms
 
 /* Measurement hook for the smoother inside real solves.  While enabled
  * (enable = 1), every finest-level smoothing launch of the fused V-cycle
- * (desc.fused = 1) made by later solves on this handle is bracketed by a pair
- * of HIP events on the solver's stream; up to 8192 launches are recorded
- * between two reads, later ones are counted in *dropped.  The events are
- * created on the first enable and live as long as the handle.
- * tph_kernel_timing_read waits for the stream, returns the number of timed
- * launches, their summed duration in ms and their summed algorithmic bytes
- * (per cell: zero-guess sweep 6 words = read r (2), eta_b, eta_p, write e
- * (2); sweep from an iterate 8 words; sweep with fused prolongation 8.5
- * words, the coarse correction being a quarter of two fields), then resets
- * the counters.  Timing adds two event records per launch to the stream. */
+ * (desc.fused = 1) made by later solves on this handle is launched with a
+ * pair of HIP events that take the kernel's own start and end time stamps
+ * (hipExtLaunchKernel); up to 8192 launches are recorded between two reads,
+ * later ones are counted in *dropped.  The events are created on the first
+ * enable and live as long as the handle.  tph_kernel_timing_read waits for
+ * the stream, returns the number of timed launches, their summed duration in
+ * ms and their summed algorithmic bytes (per cell: zero-guess sweep 6 words
+ * = read r (2), eta_b, eta_p, write e (2); sweep from an iterate 8 words;
+ * sweep with fused prolongation 8.5 words, the coarse correction being a
+ * quarter of two fields; plus 0.5 when the pass also restricts its residual),
+ * then resets the counters. */
 tph_status tph_kernel_timing(tph_solver* s, int32_t enable);
 tph_status tph_kernel_timing_read(tph_solver* s, int32_t* launches, double* total_ms, double* total_bytes,
                                   int32_t* dropped);

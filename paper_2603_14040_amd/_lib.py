@@ -31,7 +31,8 @@ class Desc(ctypes.Structure):
                 ("nu_growth", c_double), ("omega", c_double), ("alpha", c_double),
                 ("eta_mean", c_int32), ("rtol", c_double), ("restart", c_int32),
                 ("max_iters", c_int32), ("uzawa_steps", c_int32), ("fused", c_int32),
-                ("msweep", c_int32), ("tile_shape", c_int32), ("reserved", c_int32 * 4)]
+                ("msweep", c_int32), ("tile_shape", c_int32), ("coarse_level", c_int32),
+                ("reserved", c_int32 * 3)]
 
 
 class Info(ctypes.Structure):

@@ -12,9 +12,13 @@ whole solves of the caller's own problem and keeps the fastest.
 Knobs (all of them descriptor fields of tph_create):
   * per LDS-tiled level: one-sweep tile launches or multi-sweep passes
     (``msweep`` bit), large or small tile shape (``tile_shape`` bit);
-  * smoothing sweeps per level (nu_pre = nu_post);
+  * the first level of the single-workgroup coarse tail (``coarse_level``);
+  * pre- and post-smoothing sweeps and their growth per level (the paper's
+    level-dependent schedule, nu_l = ceil(nu * growth^l));
   * Uzawa sweeps per preconditioner application (``uzawa_steps``);
   * FGMRES restart length.
+Parameter sets that resolve to the same kernel plan on every level are
+measured once.
 
 Search: coordinate descent from the library defaults; each knob in turn
 takes every candidate value with the others fixed, and a candidate is
@@ -145,13 +149,19 @@ def solver_kwargs(p: Params, tile_levels: Sequence[int]) -> dict:
     """Solver keyword arguments of a parameter set."""
     plan = [tuple(p[f"L{l}"]) for l in tile_levels]
     msw, shp = plan_to_masks(plan, tile_levels)
-    return dict(nu_pre=int(p["nu"]), nu_post=int(p["nu"]), uzawa_steps=int(p["uzawa_steps"]),
-                restart=int(p["restart"]), msweep=msw, tile_shape=shp)
+    return dict(nu_pre=int(p["nu_pre"]), nu_post=int(p["nu_post"]), nu_growth=float(p.get("nu_growth", 1.0)),
+                uzawa_steps=int(p["uzawa_steps"]), restart=int(p["restart"]), msweep=msw, tile_shape=shp,
+                coarse_level=int(p.get("coarse_level", -1)))
 
 
-def knobs_for(tile_levels: Sequence[int], nus=(1, 2, 3), uzawa=(1, 2, 3), restarts=(10, 20, 30)) -> List[Knob]:
-    ks = [Knob(f"L{l}", [(0, 0), (0, 1), (1, 0), (1, 1)]) for l in tile_levels]
-    ks += [Knob("nu", list(nus)), Knob("uzawa_steps", list(uzawa)), Knob("restart", list(restarts))]
+def knobs_for(tile_levels: Sequence[int], coarse_levels: Sequence[int] = (), nus=(1, 2, 3),
+              growths=(1.0, 1.5, 2.0), uzawa=(1, 2, 3, 4, 5), restarts=(5, 8, 10, 15, 20, 30)) -> List[Knob]:
+    """Schedule knobs first (they move the iteration count), then the kernel plan."""
+    ks = [Knob("uzawa_steps", list(uzawa)), Knob("nu_pre", list(nus)), Knob("nu_post", list(nus)),
+          Knob("nu_growth", list(growths)), Knob("restart", list(restarts))]
+    if coarse_levels:
+        ks.append(Knob("coarse_level", [-1] + list(coarse_levels)))
+    ks += [Knob(f"L{l}", [(0, 0), (0, 1), (1, 0), (1, 1)]) for l in tile_levels]
     return ks
 
 
@@ -179,21 +189,36 @@ def tune(eta_b, eta_p, rho_b, gx: float = 0.0, gy: float = -1.0, *, precision: O
     base = Solver(nx, ny, lx, ly, bc=bc, precision=precision, rtol=rtol, device=device)
     nlev = base.levels
     plan0 = [base.level_plan(l) for l in range(nlev)]
-    tile_levels = [l for l, (k, _) in enumerate(plan0) if k in ("tiles", "multisweep")]
+    lc0 = next((l for l, (k, _) in enumerate(plan0) if k == "coarse_tail"), nlev - 1)
+    # levels that run tile kernels with the default coarse tail or one or two levels lower
+    tile_levels = [l for l in range(min(lc0 + 2, nlev - 1))]
+    coarse_levels = [l for l in (lc0 + 1, lc0 + 2) if l < nlev - 1 and lc0 < nlev - 1]
     d = base.desc
-    start: Params = {"nu": int(d.nu_pre), "uzawa_steps": int(d.uzawa_steps), "restart": int(d.restart)}
+    start: Params = {"nu_pre": int(d.nu_pre), "nu_post": int(d.nu_post), "nu_growth": float(d.nu_growth),
+                     "uzawa_steps": int(d.uzawa_steps), "restart": int(d.restart), "coarse_level": -1}
     for l in tile_levels:
         k, s = plan0[l]
         start[f"L{l}"] = (1 if k == "multisweep" else 0, int(s))
     base.close()
     del base
 
-    iters: Dict[str, int] = {}
+    iters: Dict[str, int] = {}       # effective plan -> iterations
+    seen: Dict[str, float] = {}       # effective plan -> cost
+    eff_of: Dict[str, str] = {}       # parameter set -> effective plan
 
     def measure(p: Params) -> float:
         kw = solver_kwargs(p, tile_levels)
-        s = Solver(nx, ny, lx, ly, bc=bc, precision=precision, rtol=rtol, device=device, **kw)
         try:
+            s = Solver(nx, ny, lx, ly, bc=bc, precision=precision, rtol=rtol, device=device, **kw)
+        except _lib.TephraError:
+            return math.inf            # e.g. a coarse tail that does not fit
+        try:
+            # the plan the solver actually runs: sets that differ only in ignored bits are one candidate
+            eff = json.dumps([kw["nu_pre"], kw["nu_post"], kw["nu_growth"], kw["uzawa_steps"], kw["restart"],
+                              [s.level_plan(l) for l in range(s.levels)]])
+            eff_of[json.dumps(p, sort_keys=True)] = eff
+            if eff in seen:
+                return seen[eff]
             s.set_coefficients(eta_b, eta_p, rho_b, gx, gy)
             vx, vy, pp = s.zeros(), s.zeros(), s.zeros()
             ts = []
@@ -204,21 +229,23 @@ def tune(eta_b, eta_p, rho_b, gx: float = 0.0, gy: float = -1.0, *, precision: O
                 info = s.solve(vx, vy, pp)[3]
                 torch.cuda.synchronize(device)
                 if info.status != "TPH_OK":
+                    seen[eff] = math.inf
                     return math.inf
                 if r > 0:
                     ts.append(time.perf_counter() - t0)
             c = statistics.median(ts) * 1e3
-            iters[json.dumps(p, sort_keys=True)] = info.iters
+            seen[eff] = c
+            iters[eff] = info.iters
             if log:
                 log(f"[tune] {p} -> {c:.2f} ms, {info.iters} iterations")
             return c
         finally:
             s.close()
 
-    res = coordinate_search(measure, knobs if knobs is not None else knobs_for(tile_levels), start, rounds=rounds,
-                            rel_gain=rel_gain)
+    res = coordinate_search(measure, knobs if knobs is not None else knobs_for(tile_levels, coarse_levels), start,
+                            rounds=rounds, rel_gain=rel_gain)
     best_kw = solver_kwargs(res.params, tile_levels)
-    entry = {"params": best_kw, "ms": res.cost, "iters": iters.get(json.dumps(res.params, sort_keys=True)),
+    entry = {"params": best_kw, "ms": res.cost, "iters": iters.get(eff_of.get(json.dumps(res.params, sort_keys=True))),
              "default_ms": res.trials[0][1], "trials": len(res.trials),
              "seconds": round(time.perf_counter() - t_start, 2),
              "search": {k: (list(v) if isinstance(v, tuple) else v) for k, v in res.params.items()}}

@@ -1,6 +1,8 @@
 // Single-problem launchers of the fused multigrid kernels (device bodies in
 // fused_dev.h): LDS-tiled smoothing sweep, fused residual + restriction,
 // single-workgroup coarse tail.
+#include <hip/hip_ext.h>
+
 #include "fused_dev.h"
 
 namespace tph {
@@ -52,13 +54,19 @@ size_t coarse_cycle_lds_bytes(const Geom* g, int nl, int nc) {
 template <typename T>
 hipError_t launch_smooth_tile(const Geom& g, const Geom* gc, int smoother, int mode, const T* exi, const T* eyi,
                               T* exo, T* eyo, const T* rx, const T* ry, const T* eb, const T* ep, const T* ecx,
-                              const T* ecy, T omega, hipStream_t st) {
+                              const T* ecy, T omega, hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
     constexpr int TW = kTileW, TH = tile_h<T>();
     const dim3 grid((g.nx + TW - 1) / TW, (g.ny + TH - 1) / TH);
     const Geom gcc = gc ? *gc : g;
-#define TPH_SMT(SM, MODE)                                                                                       \
-    hipLaunchKernelGGL((k_smooth_tile<T, TW, TH, SM, MODE>), grid, dim3(256), 0, st, g, gcc, exi, eyi, exo, eyo, \
-                       rx, ry, eb, ep, ecx, ecy, omega)
+#define TPH_SMT(SM, MODE)                                                                                        \
+    do {                                                                                                          \
+        if (t0)                                                                                                   \
+            hipExtLaunchKernelGGL((k_smooth_tile<T, TW, TH, SM, MODE>), grid, dim3(256), 0, st, t0, t1, 0, g, gcc, \
+                                  exi, eyi, exo, eyo, rx, ry, eb, ep, ecx, ecy, omega);                         \
+        else                                                                                                      \
+            hipLaunchKernelGGL((k_smooth_tile<T, TW, TH, SM, MODE>), grid, dim3(256), 0, st, g, gcc, exi, eyi,    \
+                               exo, eyo, rx, ry, eb, ep, ecx, ecy, omega);                                        \
+    } while (0)
     if (smoother == kSmGS) {
         if (mode == kModeZero) TPH_SMT(kSmGS, kModeZero);
         else if (mode == kModeProlong) TPH_SMT(kSmGS, kModeProlong);
@@ -102,7 +110,7 @@ hipError_t launch_coarse_cycle(const CoarseArgs<T>& a, size_t lds_bytes, int max
     template size_t coarse_cycle_lds_bytes<T>(const Geom*, int, int);                                             \
     template hipError_t launch_smooth_tile<T>(const Geom&, const Geom*, int, int, const T*, const T*, T*, T*,       \
                                               const T*, const T*, const T*, const T*, const T*, const T*, T,         \
-                                              hipStream_t);                                                         \
+                                              hipStream_t, hipEvent_t, hipEvent_t);                                 \
     template hipError_t launch_res_restrict<T>(const Geom&, const Geom&, const T*, const T*, const T*, const T*,    \
                                                const T*, const T*, T*, T*, hipStream_t);                            \
     template hipError_t launch_coarse_cycle<T>(const CoarseArgs<T>&, size_t, int, hipStream_t);

@@ -71,6 +71,32 @@ __device__ __forceinline__ void xcd_tile(int& bx, int& by) {
 __device__ __forceinline__ bool is_vx(const Geom& g, int i, int j) { return i >= 1 && i <= g.ny && j >= 1 && j < g.nx; }
 __device__ __forceinline__ bool is_vy(const Geom& g, int i, int j) { return i >= 1 && i < g.ny && j >= 1 && j <= g.nx; }
 
+// Node predicates inside an LDS tile.  IN marks an interior tile: the tile
+// and its whole halo lie in rows 1..ny-1 and columns 1..nx-1, so every node
+// is an unknown of both components, no node is wall-adjacent and no ghost
+// or wall is touched; the checks then vanish at compile time.
+template <bool IN>
+__device__ __forceinline__ bool ux_at(const Geom& g, int i, int j) { return IN || is_vx(g, i, j); }
+template <bool IN>
+__device__ __forceinline__ bool uy_at(const Geom& g, int i, int j) { return IN || is_vy(g, i, j); }
+
+template <bool IN, typename T>
+__device__ __forceinline__ T dx_at(const T* sb, const T* sp, int c, int RW, int gi, const Geom& g,
+                                   const LevelC<T>& k) {
+    return IN ? lx_diag_inner(sb, sp, c, RW, k) : lx_diag(sb, sp, c, RW, gi, g.ny, k);
+}
+template <bool IN, typename T>
+__device__ __forceinline__ T dy_at(const T* sb, const T* sp, int c, int RW, int gj, const Geom& g,
+                                   const LevelC<T>& k) {
+    return IN ? ly_diag_inner(sb, sp, c, RW, k) : ly_diag(sb, sp, c, RW, gj, g.nx, k);
+}
+
+// tile origin (gi0, gj0) and region RW x RH: is it an interior tile?
+template <int RW, int RH>
+__device__ __forceinline__ bool interior_tile(const Geom& g, int gi0, int gj0) {
+    return gi0 >= 1 && gj0 >= 1 && gi0 + RH <= g.ny && gj0 + RW <= g.nx;
+}
+
 // ---------------------------------------------------------------------------
 // LDS tiles.  A tile of TW x TH nodes (origin (i0, j0) = (1 + tby TH,
 // 1 + tbx TW)) is held with a halo of H nodes: the iterate (sx, sy) and the
@@ -93,7 +119,7 @@ constexpr int tile_iters() { return (N + kTileThreads - 1) / kTileThreads; }
 
 // load the iterate (zero / from memory / from memory + prolongated coarse
 // correction) and the viscosities of the region starting at (gi0, gj0)
-template <typename T, int RW, int RH, int MODE>
+template <typename T, int RW, int RH, int MODE, bool IN>
 __device__ __forceinline__ void tile_load(const Geom& g, const Geom& gc, int gi0, int gj0, const T* __restrict__ exi,
                                           const T* __restrict__ eyi, const T* __restrict__ eb,
                                           const T* __restrict__ ep, const T* __restrict__ ecx,
@@ -110,7 +136,7 @@ __device__ __forceinline__ void tile_load(const Geom& g, const Geom& gc, int gi0
         const int q = tid + it * kTileThreads;
         const int a = q / RW, b = q - (q / RW) * RW;
         const int gi = gi0 + a, gj = gj0 + b;
-        const bool in = q < RN && gi >= 0 && gi <= g.ny + 1 && gj >= 0 && gj <= g.nx + 1;
+        const bool in = q < RN && (IN || (gi >= 0 && gi <= g.ny + 1 && gj >= 0 && gj <= g.nx + 1));
         const int c = in ? gi * P + gj : 0;
         vb[it] = in ? eb[c] : (T)0;
         vp[it] = in ? ep[c] : (T)0;
@@ -160,15 +186,15 @@ __device__ __forceinline__ void tile_load(const Geom& g, const Geom& gc, int gi0
                 // coarse indices are taken relative to the LDS window
                 const int a = q / RW, b = q - (q / RW) * RW;
                 const int gi = gi0 + a, gj = gj0 + b;
-                if (is_vx(g, gi, gj)) ux += prolong_vx(scx - ci0 * CC - cj0, CC, gi, gj);
-                if (is_vy(g, gi, gj)) uy += prolong_vy(scy - ci0 * CC - cj0, CC, gi, gj);
+                if (ux_at<IN>(g, gi, gj)) ux += prolong_vx(scx - ci0 * CC - cj0, CC, gi, gj);
+                if (uy_at<IN>(g, gi, gj)) uy += prolong_vy(scy - ci0 * CC - cj0, CC, gi, gj);
             }
             sx[q] = ux;
             sy[q] = uy;
         }
     }
     __syncthreads();
-    if (MODE == kModeProlong) {
+    if (MODE == kModeProlong && !IN) {
         // ghosts mirror the corrected interior values
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
@@ -219,7 +245,7 @@ __device__ __forceinline__ void stage_node(int s, int q, int gi0, int gj0, int& 
 }
 
 // right-hand side of every node this thread updates, in stage order
-template <typename T, int TW, int TH, int H, int NSTAGE>
+template <typename T, int TW, int TH, int H, int NSTAGE, bool IN>
 __device__ __forceinline__ void stage_rhs(const Geom& g, int gi0, int gj0, const T* __restrict__ rx,
                                           const T* __restrict__ ry, T* rr) {
     using S = Stages<TW, TH, H, NSTAGE>;
@@ -234,7 +260,7 @@ __device__ __forceinline__ void stage_rhs(const Geom& g, int gi0, int gj0, const
             int a, b;
             stage_node<TW, TH, H>(s, q, gi0, gj0, a, b);
             const int gi = gi0 + a, gj = gj0 + b;
-            const bool ok = q < S::rows(s) * S::half(s) && (comp == 0 ? is_vx(g, gi, gj) : is_vy(g, gi, gj));
+            const bool ok = q < S::rows(s) * S::half(s) && (comp == 0 ? ux_at<IN>(g, gi, gj) : uy_at<IN>(g, gi, gj));
             const int c = ok ? gi * P + gj : 0;
             rr[S::offset(s) + it] = ok ? (comp == 0 ? rx[c] : ry[c]) : (T)0;
         }
@@ -242,11 +268,13 @@ __device__ __forceinline__ void stage_rhs(const Geom& g, int gi0, int gj0, const
 }
 
 // NSTAGE colour half-sweeps.  Each stage needs the previous one's values
-// one node further out, hence the shrinking regions.  A wall-adjacent node
-// refreshes its own ghost right away; only that node reads the ghost, so
-// the next sweep in the tile sees the mirror of the latest value, as a sweep
-// over the whole grid with ghosts refilled between sweeps does.
-template <typename T, int TW, int TH, int H, int NSTAGE>
+// one node further out, hence the shrinking regions.  With GHOSTS a
+// wall-adjacent node refreshes its own ghost right away; only that node
+// reads the ghost, so a later sweep (or the residual) in the same pass sees
+// the mirror of the latest value, as a sweep over the whole grid with
+// ghosts refilled between sweeps does.  A single sweep without residual
+// never re-reads a ghost, and the store writes the ghosts.
+template <typename T, int TW, int TH, int H, int NSTAGE, bool IN, bool GHOSTS>
 __device__ __forceinline__ void gs_stages(const Geom& g, int gi0, int gj0, T* sx, T* sy, const T* sb, const T* sp,
                                           const T* rr, T omega, const LevelC<T>& k) {
     using S = Stages<TW, TH, H, NSTAGE>;
@@ -265,19 +293,23 @@ __device__ __forceinline__ void gs_stages(const Geom& g, int gi0, int gj0, T* sx
             const int c = a * RW + b;
             const T r = rr[S::offset(s) + it];
             if (comp == 0) {
-                if (!is_vx(g, gi, gj)) continue;
-                const T d = lx_diag(sb, sp, c, RW, gi, g.ny, k);
-                const T e = sx[c] + omega * (r - lx_row(sx, sy, sb, sp, c, RW, k.idx, k.idy)) / d;
+                if (!ux_at<IN>(g, gi, gj)) continue;
+                const T d = dx_at<IN>(sb, sp, c, RW, gi, g, k);
+                const T e = relax(sx[c], omega, r - lx_row(sx, sy, sb, sp, c, RW, k.idx, k.idy), d);
                 sx[c] = e;
-                if (gi == 1 && a >= 1) sx[c - RW] = k.mirS * e;
-                if (gi == g.ny && a + 1 < RH) sx[c + RW] = k.mirN * e;
+                if (GHOSTS && !IN) {
+                    if (gi == 1 && a >= 1) sx[c - RW] = k.mirS * e;
+                    if (gi == g.ny && a + 1 < RH) sx[c + RW] = k.mirN * e;
+                }
             } else {
-                if (!is_vy(g, gi, gj)) continue;
-                const T d = ly_diag(sb, sp, c, RW, gj, g.nx, k);
-                const T e = sy[c] + omega * (r - ly_row(sx, sy, sb, sp, c, RW, k.idx, k.idy)) / d;
+                if (!uy_at<IN>(g, gi, gj)) continue;
+                const T d = dy_at<IN>(sb, sp, c, RW, gj, g, k);
+                const T e = relax(sy[c], omega, r - ly_row(sx, sy, sb, sp, c, RW, k.idx, k.idy), d);
                 sy[c] = e;
-                if (gj == 1 && b >= 1) sy[c - 1] = k.mirW * e;
-                if (gj == g.nx && b + 1 < RW) sy[c + 1] = k.mirE * e;
+                if (GHOSTS && !IN) {
+                    if (gj == 1 && b >= 1) sy[c - 1] = k.mirW * e;
+                    if (gj == g.nx && b + 1 < RW) sy[c + 1] = k.mirE * e;
+                }
             }
         }
         __syncthreads();
@@ -285,7 +317,7 @@ __device__ __forceinline__ void gs_stages(const Geom& g, int gi0, int gj0, T* sx
 }
 
 // write the tile's own nodes (and the ghosts they own) to memory
-template <typename T, int TW, int TH, int H>
+template <typename T, int TW, int TH, int H, bool IN>
 __device__ __forceinline__ void tile_store(const Geom& g, int gi0, int gj0, const T* sx, const T* sy,
                                            T* __restrict__ exo, T* __restrict__ eyo, const LevelC<T>& k) {
     constexpr int RW = TW + 2 * H;
@@ -298,17 +330,17 @@ __device__ __forceinline__ void tile_store(const Geom& g, int gi0, int gj0, cons
         const int gi = gi0 + a, gj = gj0 + b;
         const int c = a * RW + b;
         const int cg = gi * P + gj;
-        if (is_vx(g, gi, gj)) {
+        if (ux_at<IN>(g, gi, gj)) {
             const T e = sx[c];
             exo[cg] = e;
-            if (gi == 1) exo[cg - P] = k.mirS * e;
-            if (gi == g.ny) exo[cg + P] = k.mirN * e;
+            if (!IN && gi == 1) exo[cg - P] = k.mirS * e;
+            if (!IN && gi == g.ny) exo[cg + P] = k.mirN * e;
         }
-        if (is_vy(g, gi, gj)) {
+        if (uy_at<IN>(g, gi, gj)) {
             const T e = sy[c];
             eyo[cg] = e;
-            if (gj == 1) eyo[cg - 1] = k.mirW * e;
-            if (gj == g.nx) eyo[cg + 1] = k.mirE * e;
+            if (!IN && gj == 1) eyo[cg - 1] = k.mirW * e;
+            if (!IN && gj == g.nx) eyo[cg + 1] = k.mirE * e;
         }
     }
 }
@@ -356,6 +388,65 @@ __device__ __forceinline__ void restrict_cell(const Geom& g, const Geom& gc, con
 // coarse cells the tile covers (TW x TH fine = TW/2 x TH/2 coarse): the
 // down leg of a V-cycle level in one launch, the fine residual never going
 // to memory.
+template <typename T, int TW, int TH, int NS, int MODE, int RR, bool IN>
+__device__ __forceinline__ void gs_tile_run(const Geom& g, const Geom& gc, const T* __restrict__ exi,
+                                            const T* __restrict__ eyi, T* __restrict__ exo, T* __restrict__ eyo,
+                                            const T* __restrict__ rx, const T* __restrict__ ry,
+                                            const T* __restrict__ eb, const T* __restrict__ ep,
+                                            const T* __restrict__ ecx, const T* __restrict__ ecy,
+                                            T* __restrict__ rcx, T* __restrict__ rcy, T omega, int tbx, int tby,
+                                            T* sx, T* sy, T* sb, T* sp, T* scx, T* scy, T* stx, T* sty) {
+    constexpr int H = 4 * NS + (RR ? 2 : 0);
+    constexpr int RW = TW + 2 * H, RH = TH + 2 * H;
+    constexpr int TRW = RR ? TW + 2 : 1, TRH = RR ? TH + 2 : 1;
+    constexpr int NR = Stages<TW, TH, H, 4 * NS>::total();
+    constexpr int ITR = RR ? tile_iters<TRW * TRH>() : 1;
+    const int i0 = 1 + tby * TH, j0 = 1 + tbx * TW;
+    const int gi0 = i0 - H, gj0 = j0 - H;
+    const int P = g.pitch;
+    const LevelC<T> k = level_consts<T>(g);
+    // right-hand sides first: they are in flight while the tile loads
+    T rr[NR];
+    stage_rhs<T, TW, TH, H, 4 * NS, IN>(g, gi0, gj0, rx, ry, rr);
+    T rrx[ITR], rry[ITR];
+    if (RR) {
+#pragma unroll
+        for (int it = 0; it < ITR; ++it) {
+            const int q = threadIdx.x + it * kTileThreads;
+            const int a = q / TRW, b = q - (q / TRW) * TRW;
+            const int gi = i0 - 1 + a, gj = j0 - 1 + b;
+            const bool okx = q < TRW * TRH && ux_at<IN>(g, gi, gj), oky = q < TRW * TRH && uy_at<IN>(g, gi, gj);
+            rrx[it] = okx ? rx[gi * P + gj] : (T)0;
+            rry[it] = oky ? ry[gi * P + gj] : (T)0;
+        }
+    }
+    tile_load<T, RW, RH, MODE, IN>(g, gc, gi0, gj0, exi, eyi, eb, ep, ecx, ecy, sx, sy, sb, sp, scx, scy, k);
+    gs_stages<T, TW, TH, H, 4 * NS, IN, (NS > 1 || RR)>(g, gi0, gj0, sx, sy, sb, sp, rr, omega, k);
+    tile_store<T, TW, TH, H, IN>(g, gi0, gj0, sx, sy, exo, eyo, k);
+    if (RR) {
+#pragma unroll
+        for (int it = 0; it < ITR; ++it) {
+            const int q = threadIdx.x + it * kTileThreads;
+            if (q >= TRW * TRH) continue;
+            const int a = q / TRW, b = q - (q / TRW) * TRW;
+            const int gi = i0 - 1 + a, gj = j0 - 1 + b;
+            const int c = (a + H - 1) * RW + (b + H - 1);
+            stx[q] = ux_at<IN>(g, gi, gj) ? rrx[it] - lx_row(sx, sy, sb, sp, c, RW, k.idx, k.idy) : (T)0;
+            sty[q] = uy_at<IN>(g, gi, gj) ? rry[it] - ly_row(sx, sy, sb, sp, c, RW, k.idx, k.idy) : (T)0;
+        }
+        __syncthreads();
+        const int I0 = 1 + tby * (TH / 2), J0 = 1 + tbx * (TW / 2);
+#pragma unroll
+        for (int it = 0; it < tile_iters<(TH / 2) * (TW / 2)>(); ++it) {
+            const int q = threadIdx.x + it * kTileThreads;
+            if (q >= (TH / 2) * (TW / 2)) continue;
+            const int I = I0 + q / (TW / 2), J = J0 + (q - (q / (TW / 2)) * (TW / 2));
+            if (I > gc.ny || J > gc.nx) continue;
+            restrict_cell<T, TRW>(g, gc, stx, sty, i0 - 1, j0 - 1, I, J, rcx, rcy);
+        }
+    }
+}
+
 template <typename T, int TW, int TH, int NS, int MODE, int RR>
 __device__ __forceinline__ void gs_tile_body(const Geom& g, const Geom& gc, const T* __restrict__ exi,
                                              const T* __restrict__ eyi, T* __restrict__ exo, T* __restrict__ eyo,
@@ -373,52 +464,13 @@ __device__ __forceinline__ void gs_tile_body(const Geom& g, const Geom& gc, cons
     __shared__ T sx[RN], sy[RN], sb[RN], sp[RN];
     __shared__ T scx[CN], scy[CN];
     __shared__ T stx[TRW * TRH], sty[TRW * TRH];
-    constexpr int NR = Stages<TW, TH, H, 4 * NS>::total();
-    constexpr int ITR = RR ? tile_iters<TRW * TRH>() : 1;
-    const int i0 = 1 + tby * TH, j0 = 1 + tbx * TW;
-    const int gi0 = i0 - H, gj0 = j0 - H;
-    const int P = g.pitch;
-    const LevelC<T> k = level_consts<T>(g);
-    // right-hand sides first: they are in flight while the tile loads
-    T rr[NR];
-    stage_rhs<T, TW, TH, H, 4 * NS>(g, gi0, gj0, rx, ry, rr);
-    T rrx[ITR], rry[ITR];
-    if (RR) {
-#pragma unroll
-        for (int it = 0; it < ITR; ++it) {
-            const int q = threadIdx.x + it * kTileThreads;
-            const int a = q / TRW, b = q - (q / TRW) * TRW;
-            const int gi = i0 - 1 + a, gj = j0 - 1 + b;
-            const bool okx = q < TRW * TRH && is_vx(g, gi, gj), oky = q < TRW * TRH && is_vy(g, gi, gj);
-            rrx[it] = okx ? rx[gi * P + gj] : (T)0;
-            rry[it] = oky ? ry[gi * P + gj] : (T)0;
-        }
-    }
-    tile_load<T, RW, RH, MODE>(g, gc, gi0, gj0, exi, eyi, eb, ep, ecx, ecy, sx, sy, sb, sp, scx, scy, k);
-    gs_stages<T, TW, TH, H, 4 * NS>(g, gi0, gj0, sx, sy, sb, sp, rr, omega, k);
-    tile_store<T, TW, TH, H>(g, gi0, gj0, sx, sy, exo, eyo, k);
-    if (RR) {
-#pragma unroll
-        for (int it = 0; it < ITR; ++it) {
-            const int q = threadIdx.x + it * kTileThreads;
-            if (q >= TRW * TRH) continue;
-            const int a = q / TRW, b = q - (q / TRW) * TRW;
-            const int gi = i0 - 1 + a, gj = j0 - 1 + b;
-            const int c = (a + H - 1) * RW + (b + H - 1);
-            stx[q] = is_vx(g, gi, gj) ? rrx[it] - lx_row(sx, sy, sb, sp, c, RW, k.idx, k.idy) : (T)0;
-            sty[q] = is_vy(g, gi, gj) ? rry[it] - ly_row(sx, sy, sb, sp, c, RW, k.idx, k.idy) : (T)0;
-        }
-        __syncthreads();
-        const int I0 = 1 + tby * (TH / 2), J0 = 1 + tbx * (TW / 2);
-#pragma unroll
-        for (int it = 0; it < tile_iters<(TH / 2) * (TW / 2)>(); ++it) {
-            const int q = threadIdx.x + it * kTileThreads;
-            if (q >= (TH / 2) * (TW / 2)) continue;
-            const int I = I0 + q / (TW / 2), J = J0 + (q - (q / (TW / 2)) * (TW / 2));
-            if (I > gc.ny || J > gc.nx) continue;
-            restrict_cell<T, TRW>(g, gc, stx, sty, i0 - 1, j0 - 1, I, J, rcx, rcy);
-        }
-    }
+    // uniform per tile: interior tiles take the check-free path
+    if (interior_tile<RW, RH>(g, 1 + tby * TH - H, 1 + tbx * TW - H))
+        gs_tile_run<T, TW, TH, NS, MODE, RR, true>(g, gc, exi, eyi, exo, eyo, rx, ry, eb, ep, ecx, ecy, rcx, rcy,
+                                                   omega, tbx, tby, sx, sy, sb, sp, scx, scy, stx, sty);
+    else
+        gs_tile_run<T, TW, TH, NS, MODE, RR, false>(g, gc, exi, eyi, exo, eyo, rx, ry, eb, ep, ecx, ecy, rcx, rcy,
+                                                    omega, tbx, tby, sx, sy, sb, sp, scx, scy, stx, sty);
 }
 
 // one damped Jacobi sweep on an LDS tile (halo 1)
@@ -448,7 +500,7 @@ __device__ __forceinline__ void jacobi_tile_body(const Geom& g, const Geom& gc, 
         rrx[it] = q < TW * TH && is_vx(g, gi, gj) ? rx[gi * P + gj] : (T)0;
         rry[it] = q < TW * TH && is_vy(g, gi, gj) ? ry[gi * P + gj] : (T)0;
     }
-    tile_load<T, RW, RH, MODE>(g, gc, gi0, gj0, exi, eyi, eb, ep, ecx, ecy, sx, sy, sb, sp, scx, scy, k);
+    tile_load<T, RW, RH, MODE, false>(g, gc, gi0, gj0, exi, eyi, eb, ep, ecx, ecy, sx, sy, sb, sp, scx, scy, k);
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
         const int q = threadIdx.x + it * kTileThreads;
@@ -459,14 +511,14 @@ __device__ __forceinline__ void jacobi_tile_body(const Geom& g, const Geom& gc, 
         const int cg = gi * P + gj;
         if (is_vx(g, gi, gj)) {
             const T d = lx_diag(sb, sp, c, RW, gi, g.ny, k);
-            const T e = sx[c] + omega * (rrx[it] - lx_row(sx, sy, sb, sp, c, RW, k.idx, k.idy)) / d;
+            const T e = relax(sx[c], omega, rrx[it] - lx_row(sx, sy, sb, sp, c, RW, k.idx, k.idy), d);
             exo[cg] = e;
             if (gi == 1) exo[cg - P] = k.mirS * e;
             if (gi == g.ny) exo[cg + P] = k.mirN * e;
         }
         if (is_vy(g, gi, gj)) {
             const T d = ly_diag(sb, sp, c, RW, gj, g.nx, k);
-            const T e = sy[c] + omega * (rry[it] - ly_row(sx, sy, sb, sp, c, RW, k.idx, k.idy)) / d;
+            const T e = relax(sy[c], omega, rry[it] - ly_row(sx, sy, sb, sp, c, RW, k.idx, k.idy), d);
             eyo[cg] = e;
             if (gj == 1) eyo[cg - 1] = k.mirW * e;
             if (gj == g.nx) eyo[cg + 1] = k.mirE * e;
@@ -567,33 +619,42 @@ struct LGeo {            // a level inside LDS: tight pitch nx + 2
     T idx, idy, idx2, idy2;
 };
 
+// Loops of the coarse tail map threads to rows: 64 consecutive threads
+// share a row (32 for the colour sweeps, which take every other node), so
+// node indices come from shifts instead of divisions by a runtime width.
+
+// one Gauss-Seidel colour half-sweep of component comp, in place
 template <typename T>
 __device__ void cc_gs_half(const LGeo<T>& L, const LevelC<T>& k, int comp, int col, T* ex, T* ey, const T* rx,
                            const T* ry, const T* eb, const T* ep, T omega) {
     const int ncol = comp == 0 ? L.nx - 1 : L.nx;
     const int nrow = comp == 0 ? L.ny : L.ny - 1;
-    const int n = nrow * ncol;
-    for (int q = threadIdx.x; q < n; q += blockDim.x) {
-        const int i = 1 + q / ncol, j = 1 + (q - (q / ncol) * ncol);
-        if (((i + j) & 1) != col) continue;
-        const int c = i * L.P + j;
-        if (comp == 0) {
-            const T d = lx_diag(eb, ep, c, L.P, i, L.ny, k);
-            const T e = ex[c] + omega * (rx[c] - lx_row(ex, ey, eb, ep, c, L.P, k.idx, k.idy)) / d;
-            ex[c] = e;
-            if (i == 1) ex[c - L.P] = k.mirS * e;
-            if (i == L.ny) ex[c + L.P] = k.mirN * e;
-        } else {
-            const T d = ly_diag(eb, ep, c, L.P, j, L.nx, k);
-            const T e = ey[c] + omega * (ry[c] - ly_row(ex, ey, eb, ep, c, L.P, k.idx, k.idy)) / d;
-            ey[c] = e;
-            if (j == 1) ey[c - 1] = k.mirW * e;
-            if (j == L.nx) ey[c + 1] = k.mirE * e;
+    const int tid = threadIdx.x;
+    for (int i = 1 + (tid >> 5); i <= nrow; i += blockDim.x >> 5) {
+        // first column of colour col in row i: (i + j) & 1 == col
+        const int j0 = 1 + (((i + 1) & 1) != col ? 1 : 0);
+        for (int j = j0 + 2 * (tid & 31); j <= ncol; j += 64) {
+            const int c = i * L.P + j;
+            if (comp == 0) {
+                const T d = lx_diag(eb, ep, c, L.P, i, L.ny, k);
+                const T e = relax(ex[c], omega, rx[c] - lx_row(ex, ey, eb, ep, c, L.P, k.idx, k.idy), d);
+                ex[c] = e;
+                if (i == 1) ex[c - L.P] = k.mirS * e;
+                if (i == L.ny) ex[c + L.P] = k.mirN * e;
+            } else {
+                const T d = ly_diag(eb, ep, c, L.P, j, L.nx, k);
+                const T e = relax(ey[c], omega, ry[c] - ly_row(ex, ey, eb, ep, c, L.P, k.idx, k.idy), d);
+                ey[c] = e;
+                if (j == 1) ey[c - 1] = k.mirW * e;
+                if (j == L.nx) ey[c + 1] = k.mirE * e;
+            }
         }
     }
 }
 
-// Jacobi sweep in place: new values held in registers across a barrier
+// Jacobi sweep in place: new values held in registers across a barrier.
+// Flat mapping over the level's nx * ny nodes: the coarse tail holds at most
+// 64 x 64 cells, so a thread owns at most 4096 / blockDim.x <= KMAX nodes.
 template <typename T>
 __device__ void cc_jacobi(const LGeo<T>& L, const LevelC<T>& k, T* ex, T* ey, const T* rx, const T* ry,
                           const T* eb, const T* ep, T omega) {
@@ -604,11 +665,11 @@ __device__ void cc_jacobi(const LGeo<T>& L, const LevelC<T>& k, T* ex, T* ey, co
     for (int q = threadIdx.x; q < n && t < KMAX; q += blockDim.x, ++t) {
         const int i = 1 + q / L.nx, j = 1 + (q - (q / L.nx) * L.nx);
         const int c = i * L.P + j;
-        nvx[t] = (j < L.nx) ? ex[c] + omega * (rx[c] - lx_row(ex, ey, eb, ep, c, L.P, k.idx, k.idy)) /
-                                          lx_diag(eb, ep, c, L.P, i, L.ny, k)
+        nvx[t] = (j < L.nx) ? relax(ex[c], omega, rx[c] - lx_row(ex, ey, eb, ep, c, L.P, k.idx, k.idy),
+                                    lx_diag(eb, ep, c, L.P, i, L.ny, k))
                             : (T)0;
-        nvy[t] = (i < L.ny) ? ey[c] + omega * (ry[c] - ly_row(ex, ey, eb, ep, c, L.P, k.idx, k.idy)) /
-                                          ly_diag(eb, ep, c, L.P, j, L.nx, k)
+        nvy[t] = (i < L.ny) ? relax(ey[c], omega, ry[c] - ly_row(ex, ey, eb, ep, c, L.P, k.idx, k.idy),
+                                    ly_diag(eb, ep, c, L.P, j, L.nx, k))
                             : (T)0;
     }
     __syncthreads();
@@ -630,7 +691,6 @@ __device__ void cc_jacobi(const LGeo<T>& L, const LevelC<T>& k, T* ex, T* ey, co
     __syncthreads();
 }
 
-// FP32: 1024 threads; FP64: 512 threads so the kernel fits 256 VGPRs without spilling
 template <typename T>
 constexpr int coarse_threads() { return sizeof(T) == 4 ? 1024 : 512; }
 
@@ -646,6 +706,7 @@ __device__ __forceinline__ void coarse_cycle_body(const CoarseArgs<T>& A) {
     __shared__ int foff[kMaxLevels];
     __shared__ int s_top_off;
     const int tid = threadIdx.x, nthr = blockDim.x;
+    const int rt = tid >> 6, rs_ = nthr >> 6, ct = tid & 63;   // row-parallel mapping
     if (tid == 0) {
         int off = 0;
         for (int l = 0; l < nl; ++l) {
@@ -670,20 +731,20 @@ __device__ __forceinline__ void coarse_cycle_body(const CoarseArgs<T>& A) {
     // load viscosities of every level and the right-hand side of the top level; zero the rest
     for (int l = 0; l < nl; ++l) {
         const int P = L[l].P;
-        const int n = (L[l].ny + 2) * P;
         const int Pg = A.g[l].pitch;
         const T* geb = A.eb[l];
         const T* gep = A.ep[l];
         T *ex = F(l, 0), *ey = F(l, 1), *rx = F(l, 2), *ry = F(l, 3), *eb = F(l, 4), *ep = F(l, 5);
-        for (int q = tid; q < n; q += nthr) {
-            const int i = q / P, j = q - (q / P) * P;
-            const int cg = i * Pg + j;
-            ex[q] = (T)0;
-            ey[q] = (T)0;
-            rx[q] = l == 0 ? A.rx[cg] : (T)0;
-            ry[q] = l == 0 ? A.ry[cg] : (T)0;
-            eb[q] = geb[cg];
-            ep[q] = gep[cg];
+        for (int i = rt; i < L[l].ny + 2; i += rs_) {
+            for (int j = ct; j < P; j += 64) {
+                const int q = i * P + j, cg = i * Pg + j;
+                ex[q] = (T)0;
+                ey[q] = (T)0;
+                rx[q] = l == 0 ? A.rx[cg] : (T)0;
+                ry[q] = l == 0 ? A.ry[cg] : (T)0;
+                eb[q] = geb[cg];
+                ep[q] = gep[cg];
+            }
         }
     }
     __syncthreads();
@@ -707,50 +768,53 @@ __device__ __forceinline__ void coarse_cycle_body(const CoarseArgs<T>& A) {
         smooth(l, A.nu_pre[l]);
         const LGeo<T>& G = L[l];
         T *ex = F(l, 0), *ey = F(l, 1), *rx = F(l, 2), *ry = F(l, 3), *eb = F(l, 4), *ep = F(l, 5);
-        const int n = (G.ny + 2) * G.P;
-        for (int q = tid; q < n; q += nthr) {
-            const int i = q / G.P, j = q - (q / G.P) * G.P;
-            const bool vx = i >= 1 && i <= G.ny && j >= 1 && j < G.nx;
-            const bool vy = i >= 1 && i < G.ny && j >= 1 && j <= G.nx;
-            tx[q] = vx ? rx[q] - lx_row(ex, ey, eb, ep, q, G.P, K[l].idx, K[l].idy) : (T)0;
-            ty[q] = vy ? ry[q] - ly_row(ex, ey, eb, ep, q, G.P, K[l].idx, K[l].idy) : (T)0;
+        for (int i = rt; i < G.ny + 2; i += rs_) {
+            for (int j = ct; j < G.P; j += 64) {
+                const int q = i * G.P + j;
+                const bool vx = i >= 1 && i <= G.ny && j >= 1 && j < G.nx;
+                const bool vy = i >= 1 && i < G.ny && j >= 1 && j <= G.nx;
+                tx[q] = vx ? rx[q] - lx_row(ex, ey, eb, ep, q, G.P, K[l].idx, K[l].idy) : (T)0;
+                ty[q] = vy ? ry[q] - ly_row(ex, ey, eb, ep, q, G.P, K[l].idx, K[l].idy) : (T)0;
+            }
         }
         __syncthreads();
         const LGeo<T>& C = L[l + 1];
         T *rcx = F(l + 1, 2), *rcy = F(l + 1, 3);
-        const int nc = C.ny * C.nx;
-        for (int q = tid; q < nc; q += nthr) {
-            const int I = 1 + q / C.nx, J = 1 + (q - (q / C.nx) * C.nx);
-            const int Cc = I * C.P + J;
-            if (J < C.nx) {
-                T s = (T)0, wy = (T)0;
-                for (int a4 = 0; a4 < 4; ++a4) {
-                    const int i = 2 * I - 2 + a4;
-                    if (i < 1 || i > G.ny) continue;
-                    const T w = (a4 == 1 || a4 == 2) ? (T)0.75 : (T)0.25;
-                    const int c = i * G.P + 2 * J;
-                    s += w * ((T)0.5 * tx[c - 1] + tx[c] + (T)0.5 * tx[c + 1]);
-                    wy += w;
+        for (int I = 1 + rt; I <= C.ny; I += rs_) {
+            for (int J = 1 + ct; J <= C.nx; J += 64) {
+                const int Cc = I * C.P + J;
+                if (J < C.nx) {
+                    T s = (T)0, wy = (T)0;
+                    for (int a4 = 0; a4 < 4; ++a4) {
+                        const int i = 2 * I - 2 + a4;
+                        if (i < 1 || i > G.ny) continue;
+                        const T w = (a4 == 1 || a4 == 2) ? (T)0.75 : (T)0.25;
+                        const int c = i * G.P + 2 * J;
+                        s += w * ((T)0.5 * tx[c - 1] + tx[c] + (T)0.5 * tx[c + 1]);
+                        wy += w;
+                    }
+                    rcx[Cc] = s / ((T)2 * wy);
                 }
-                rcx[Cc] = s / ((T)2 * wy);
-            }
-            if (I < C.ny) {
-                T s = (T)0, wx = (T)0;
-                for (int b4 = 0; b4 < 4; ++b4) {
-                    const int j = 2 * J - 2 + b4;
-                    if (j < 1 || j > G.nx) continue;
-                    const T w = (b4 == 1 || b4 == 2) ? (T)0.75 : (T)0.25;
-                    const int c = 2 * I * G.P + j;
-                    s += w * ((T)0.5 * ty[c - G.P] + ty[c] + (T)0.5 * ty[c + G.P]);
-                    wx += w;
+                if (I < C.ny) {
+                    T s = (T)0, wx = (T)0;
+                    for (int b4 = 0; b4 < 4; ++b4) {
+                        const int j = 2 * J - 2 + b4;
+                        if (j < 1 || j > G.nx) continue;
+                        const T w = (b4 == 1 || b4 == 2) ? (T)0.75 : (T)0.25;
+                        const int c = 2 * I * G.P + j;
+                        s += w * ((T)0.5 * ty[c - G.P] + ty[c] + (T)0.5 * ty[c + G.P]);
+                        wx += w;
+                    }
+                    rcy[Cc] = s / ((T)2 * wx);
                 }
-                rcy[Cc] = s / ((T)2 * wx);
             }
         }
         __syncthreads();
     }
 
-    // ---- coarsest: e = -(-L)^{-1} r in FP64 (one wavefront per row)
+    // ---- coarsest: e = -(-L)^{-1} r in FP64.  16 threads per row of the
+    // inverse, each summing every 16th entry (loads unrolled so that they are
+    // in flight together), then a 16-lane shuffle reduction.
     {
         const int l = nl - 1;
         const LGeo<T>& G = L[l];
@@ -763,13 +827,15 @@ __device__ __forceinline__ void coarse_cycle_body(const CoarseArgs<T>& A) {
             else { const int mm = m - nvx; i = 1 + mm / G.nx; j = 1 + mm % G.nx; rs[m] = (double)ry[i * G.P + j]; }
         }
         __syncthreads();
-        const int lane = tid & 63, wave = tid >> 6, nwave = nthr >> 6;
-        for (int m = wave; m < n; m += nwave) {
+        const int sub = tid & 15, grp = tid >> 4, ngrp = nthr >> 4;
+        for (int m = grp; m < n; m += ngrp) {
             const double* row = A.Minv + (size_t)m * n;
             double s = 0.0;
-            for (int q = lane; q < n; q += 64) s += row[q] * rs[q];
-            s = wave_sum(s);
-            if (lane == 0) {
+#pragma unroll 8
+            for (int q = sub; q < n; q += 16) s += row[q] * rs[q];
+            // sum over the 16 lanes of the group (aligned groups inside a wave)
+            for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
+            if (sub == 0) {
                 const T e = (T)(-s);
                 int i, j;
                 if (m < nvx) {
@@ -797,21 +863,21 @@ __device__ __forceinline__ void coarse_cycle_body(const CoarseArgs<T>& A) {
         const LGeo<T>& C = L[l + 1];
         T *ex = F(l, 0), *ey = F(l, 1);
         const T *ecx = F(l + 1, 0), *ecy = F(l + 1, 1);
-        const int n = G.ny * G.nx;
-        for (int q = tid; q < n; q += nthr) {
-            const int i = 1 + q / G.nx, j = 1 + (q - (q / G.nx) * G.nx);
-            const int c = i * G.P + j;
-            if (j < G.nx) {
-                const T e = ex[c] + prolong_vx(ecx, C.P, i, j);
-                ex[c] = e;
-                if (i == 1) ex[c - G.P] = K[l].mirS * e;
-                if (i == G.ny) ex[c + G.P] = K[l].mirN * e;
-            }
-            if (i < G.ny) {
-                const T e = ey[c] + prolong_vy(ecy, C.P, i, j);
-                ey[c] = e;
-                if (j == 1) ey[c - 1] = K[l].mirW * e;
-                if (j == G.nx) ey[c + 1] = K[l].mirE * e;
+        for (int i = 1 + rt; i <= G.ny; i += rs_) {
+            for (int j = 1 + ct; j <= G.nx; j += 64) {
+                const int c = i * G.P + j;
+                if (j < G.nx) {
+                    const T e = ex[c] + prolong_vx(ecx, C.P, i, j);
+                    ex[c] = e;
+                    if (i == 1) ex[c - G.P] = K[l].mirS * e;
+                    if (i == G.ny) ex[c + G.P] = K[l].mirN * e;
+                }
+                if (i < G.ny) {
+                    const T e = ey[c] + prolong_vy(ecy, C.P, i, j);
+                    ey[c] = e;
+                    if (j == 1) ey[c - 1] = K[l].mirW * e;
+                    if (j == G.nx) ey[c + 1] = K[l].mirE * e;
+                }
             }
         }
         __syncthreads();
@@ -820,12 +886,15 @@ __device__ __forceinline__ void coarse_cycle_body(const CoarseArgs<T>& A) {
 
     // ---- write the top-level correction (every entry: walls zero, ghosts mirrored)
     {
-        const int n = (L[0].ny + 2) * L[0].P;
+        const int P = L[0].P;
         const int Pg = A.g[0].pitch;
-        for (int q = tid; q < n; q += nthr) {
-            const int i = q / L[0].P, j = q - (q / L[0].P) * L[0].P;
-            A.ex[i * Pg + j] = F(0, 0)[q];
-            A.ey[i * Pg + j] = F(0, 1)[q];
+        const T* sx = F(0, 0);
+        const T* sy = F(0, 1);
+        for (int i = rt; i < L[0].ny + 2; i += rs_) {
+            for (int j = ct; j < P; j += 64) {
+                A.ex[i * Pg + j] = sx[i * P + j];
+                A.ey[i * Pg + j] = sy[i * P + j];
+            }
         }
     }
 }

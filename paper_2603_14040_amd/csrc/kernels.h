@@ -132,7 +132,8 @@ enum TileMode { kTilePlain = 0, kTileZero = 1, kTileProlong = 2 };
 template <typename T>
 hipError_t launch_smooth_tile(const Geom& g, const Geom* gc, int smoother, int mode, const T* exi, const T* eyi,
                               T* exo, T* eyo, const T* rx, const T* ry, const T* eb, const T* ep, const T* ecx,
-                              const T* ecy, T omega, hipStream_t st);
+                              const T* ecy, T omega, hipStream_t st, hipEvent_t t0 = nullptr,
+                              hipEvent_t t1 = nullptr);
 template <typename T>
 hipError_t launch_res_restrict(const Geom& gf, const Geom& gc, const T* ex, const T* ey, const T* rx, const T* ry,
                                const T* eb, const T* ep, T* rcx, T* rcy, hipStream_t st);
@@ -140,10 +141,13 @@ template <typename T>
 hipError_t launch_coarse_cycle(const CoarseArgs<T>& a, size_t lds_bytes, int max_lds, hipStream_t st);
 // Gauss-Seidel on LDS tiles, ns (1 or 2) full sweeps per pass; mode as
 // above; rr = 1 adds the residual and its restriction to the coarse level gc
-// (rcx, rcy); shape 0 / 1 selects the large / small tile
+// (rcx, rcy); shape 0 / 1 selects the large / small tile.  The tile
+// launchers take optional events (t0, t1) that receive the start and end
+// time stamps of the kernel itself.
 template <typename T>
 hipError_t launch_gs_tile(const Geom& g, const Geom& gc, int ns, int mode, int rr, int shape, const T* exi,
                           const T* eyi, T* exo, T* eyo, const T* rx, const T* ry, const T* eb, const T* ep,
-                          const T* ecx, const T* ecy, T* rcx, T* rcy, T omega, hipStream_t st);
+                          const T* ecx, const T* ecy, T* rcx, T* rcy, T omega, hipStream_t st,
+                          hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 
 }  // namespace tph

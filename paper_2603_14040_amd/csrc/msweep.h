@@ -8,6 +8,8 @@
 //   shape 1: 32 x 8 (FP32) / 32 x 4 (FP64): four times the tiles, for
 //            levels too small to fill the chip with shape 0
 #pragma once
+#include <hip/hip_ext.h>
+
 #include "fused_dev.h"
 
 namespace tph {
@@ -37,29 +39,36 @@ __global__ __launch_bounds__(256) void k_gs_tile(Geom g, Geom gc, const T* __res
 template <typename T, int NS, int MODE, int RR, int SHAPE>
 hipError_t launch_one(const Geom& g, const Geom& gc, const T* exi, const T* eyi, T* exo, T* eyo, const T* rx,
                       const T* ry, const T* eb, const T* ep, const T* ecx, const T* ecy, T* rcx, T* rcy, T omega,
-                      hipStream_t st) {
+                      hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
     constexpr int TW = TileShape<T, NS, SHAPE>::TW, TH = TileShape<T, NS, SHAPE>::TH;
     const dim3 grid((g.nx + TW - 1) / TW, (g.ny + TH - 1) / TH);
-    hipLaunchKernelGGL((k_gs_tile<T, TW, TH, NS, MODE, RR>), grid, dim3(256), 0, st, g, gc, exi, eyi, exo, eyo, rx, ry,
-                       eb, ep, ecx, ecy, rcx, rcy, omega);
+    if (t0)
+        hipExtLaunchKernelGGL((k_gs_tile<T, TW, TH, NS, MODE, RR>), grid, dim3(256), 0, st, t0, t1, 0, g, gc, exi, eyi,
+                              exo, eyo, rx, ry, eb, ep, ecx, ecy, rcx, rcy, omega);
+    else
+        hipLaunchKernelGGL((k_gs_tile<T, TW, TH, NS, MODE, RR>), grid, dim3(256), 0, st, g, gc, exi, eyi, exo, eyo, rx,
+                           ry, eb, ep, ecx, ecy, rcx, rcy, omega);
     return hipGetLastError();
 }
 
 template <typename T, int NS, int MODE, int RR>
 hipError_t launch_shape(int shape, const Geom& g, const Geom& gc, const T* exi, const T* eyi, T* exo, T* eyo,
                         const T* rx, const T* ry, const T* eb, const T* ep, const T* ecx, const T* ecy, T* rcx, T* rcy,
-                        T omega, hipStream_t st) {
+                        T omega, hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
     if (shape == 0)
-        return launch_one<T, NS, MODE, RR, 0>(g, gc, exi, eyi, exo, eyo, rx, ry, eb, ep, ecx, ecy, rcx, rcy, omega, st);
-    return launch_one<T, NS, MODE, RR, 1>(g, gc, exi, eyi, exo, eyo, rx, ry, eb, ep, ecx, ecy, rcx, rcy, omega, st);
+        return launch_one<T, NS, MODE, RR, 0>(g, gc, exi, eyi, exo, eyo, rx, ry, eb, ep, ecx, ecy, rcx, rcy, omega, st,
+                                              t0, t1);
+    return launch_one<T, NS, MODE, RR, 1>(g, gc, exi, eyi, exo, eyo, rx, ry, eb, ep, ecx, ecy, rcx, rcy, omega, st,
+                                          t0, t1);
 }
 
 template <typename T, int NS>
 hipError_t launch_ns(int mode, int rr, int shape, const Geom& g, const Geom& gc, const T* exi, const T* eyi, T* exo,
                      T* eyo, const T* rx, const T* ry, const T* eb, const T* ep, const T* ecx, const T* ecy, T* rcx,
-                     T* rcy, T omega, hipStream_t st) {
-#define TPH_MSW(MODE, RR) \
-    launch_shape<T, NS, MODE, RR>(shape, g, gc, exi, eyi, exo, eyo, rx, ry, eb, ep, ecx, ecy, rcx, rcy, omega, st)
+                     T* rcy, T omega, hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
+#define TPH_MSW(MODE, RR)                                                                                             \
+    launch_shape<T, NS, MODE, RR>(shape, g, gc, exi, eyi, exo, eyo, rx, ry, eb, ep, ecx, ecy, rcx, rcy, omega, st, t0, \
+                                  t1)
     if (mode == kModeProlong) return TPH_MSW(kModeProlong, 0);
     if (mode == kModeZero) return rr ? TPH_MSW(kModeZero, 1) : TPH_MSW(kModeZero, 0);
     return rr ? TPH_MSW(kModePlain, 1) : TPH_MSW(kModePlain, 0);
@@ -71,7 +80,8 @@ hipError_t launch_ns(int mode, int rr, int shape, const Geom& g, const Geom& gc,
 template <typename T>
 hipError_t launch_gs_tile(const Geom& g, const Geom& gc, int ns, int mode, int rr, int shape, const T* exi,
                           const T* eyi, T* exo, T* eyo, const T* rx, const T* ry, const T* eb, const T* ep,
-                          const T* ecx, const T* ecy, T* rcx, T* rcy, T omega, hipStream_t st) {
+                          const T* ecx, const T* ecy, T* rcx, T* rcy, T omega, hipStream_t st, hipEvent_t t0,
+                          hipEvent_t t1) {
     if (ns < 1 || ns > 2 || mode < 0 || mode > 2 || rr < 0 || rr > 1 || shape < 0 || shape > 1 ||
         (rr && mode == kTileProlong))
         return hipErrorInvalidValue;
@@ -79,9 +89,9 @@ hipError_t launch_gs_tile(const Geom& g, const Geom& gc, int ns, int mode, int r
     if (mode == kTileProlong && (g.nx != 2 * gc.nx || g.ny != 2 * gc.ny)) return hipErrorInvalidValue;
     if (ns == 1)
         return msw::launch_ns<T, 1>(mode, rr, shape, g, gc, exi, eyi, exo, eyo, rx, ry, eb, ep, ecx, ecy, rcx, rcy,
-                                    omega, st);
+                                    omega, st, t0, t1);
     return msw::launch_ns<T, 2>(mode, rr, shape, g, gc, exi, eyi, exo, eyo, rx, ry, eb, ep, ecx, ecy, rcx, rcy, omega,
-                                st);
+                                st, t0, t1);
 }
 
 }  // namespace tph

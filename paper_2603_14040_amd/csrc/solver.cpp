@@ -128,19 +128,27 @@ Vec3 vec3(const tph_solver* s, double* raw) { return Vec3{raw + (kAlign - 1), s-
 
 constexpr int kMaxTimedLaunches = 8192;
 
-// event bracket of one finest-level smoothing launch (only while timing is on)
-bool ktic(tph_solver* s, int l) {
-    if (!s->ktime || l != 0) return false;
+// Timing of one finest-level smoothing launch (only while timing is on): the
+// launch receives a pair of events that take the kernel's own start and end
+// time stamps (hipExtLaunchKernel), so no marker packet sits between kernels.
+struct KTime {
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+};
+
+KTime ktic(tph_solver* s, int l) {
+    KTime k;
+    if (!s->ktime || l != 0) return k;
     if (s->kev_used + 2 > (int)s->kev.size()) {
         ++s->kdropped;
-        return false;
+        return k;
     }
-    return hipEventRecord(s->kev[s->kev_used], s->st) == hipSuccess;
+    k.t0 = s->kev[s->kev_used];
+    k.t1 = s->kev[s->kev_used + 1];
+    return k;
 }
 
-void ktoc(tph_solver* s, bool on, double words, size_t wbytes) {
-    if (!on) return;
-    if (hipEventRecord(s->kev[s->kev_used + 1], s->st) != hipSuccess) return;
+void ktoc(tph_solver* s, const KTime& k, double words, size_t wbytes) {
+    if (!k.t0) return;
     s->kev_used += 2;
     s->kbytes += words * (double)s->lev[0].g.nx * (double)s->lev[0].g.ny * (double)wbytes;
 }
@@ -193,6 +201,7 @@ tph_status validate_desc(const tph_desc* d, int* nlev_out) {
     if (d->uzawa_steps < 1 || d->uzawa_steps > 8) { set_error("uzawa_steps must be in [1, 8]"); return TPH_ERR_INVALID; }
     if (d->fused != 0 && d->fused != 1) { set_error("fused must be 0 or 1"); return TPH_ERR_INVALID; }
     if (d->msweep < -1 || d->tile_shape < -1) { set_error("msweep and tile_shape must be -1 or a level mask"); return TPH_ERR_INVALID; }
+    if (d->coarse_level < -2) { set_error("coarse_level must be -2, -1 or a level index"); return TPH_ERR_INVALID; }
     int nlev = d->levels;
     if (nlev == 0) {
         nlev = 1;
@@ -210,6 +219,13 @@ tph_status validate_desc(const tph_desc* d, int* nlev_out) {
     if (cx < 2 || cy < 2) { set_error("coarsest level must have at least 2 x 2 cells"); return TPH_ERR_INVALID; }
     const int nc = cy * (cx - 1) + (cy - 1) * cx;
     if (nc > 4096) { set_error("coarsest level too large for the dense FP64 solve (max 4096 unknowns)"); return TPH_ERR_INVALID; }
+    if (d->coarse_level >= 0) {
+        const int l = d->coarse_level;
+        if (l >= nlev - 1 || (int64_t)(d->nx >> l) * (d->ny >> l) > 64 * 64) {
+            set_error("coarse_level " + std::to_string(l) + " is not a level of at most 64 x 64 cells above the coarsest");
+            return TPH_ERR_INVALID;
+        }
+    }
     *nlev_out = nlev;
     return TPH_OK;
 }
@@ -301,10 +317,11 @@ tph_status vcycle_msweep(tph_solver* s, int l, int* cur_out) {
         const int rr = left == ns ? 1 : 0;
         const bool zero = mode == kTileZero;
         const int dst = zero ? 0 : 1 - cur;
-        const bool tk = ktic(s, l);
+        const KTime tk = ktic(s, l);
         TPH_HIP(launch_gs_tile<T>(g, C.g, ns, mode, rr, shape, zero ? nullptr : as<T>(L.ex[cur]),
                                   zero ? nullptr : as<T>(L.ey[cur]), as<T>(L.ex[dst]), as<T>(L.ey[dst]), rx, ry, eb, ep,
-                                  nullptr, nullptr, rr ? as<T>(C.rx) : nullptr, rr ? as<T>(C.ry) : nullptr, om, st));
+                                  nullptr, nullptr, rr ? as<T>(C.rx) : nullptr, rr ? as<T>(C.ry) : nullptr, om, st,
+                                  tk.t0, tk.t1));
         ktoc(s, tk, (zero ? 6.0 : 8.0) + (rr ? 0.5 : 0.0), sizeof(T));
         cur = dst;
         mode = kTilePlain;
@@ -316,10 +333,10 @@ tph_status vcycle_msweep(tph_solver* s, int l, int* cur_out) {
     for (int left = L.nu_post; left > 0;) {
         const int ns = left >= 2 ? 2 : 1;
         const bool pro = mode == kTileProlong;
-        const bool tk = ktic(s, l);
+        const KTime tk = ktic(s, l);
         TPH_HIP(launch_gs_tile<T>(g, C.g, ns, mode, 0, shape, as<T>(L.ex[cur]), as<T>(L.ey[cur]), as<T>(L.ex[1 - cur]),
                                   as<T>(L.ey[1 - cur]), rx, ry, eb, ep, pro ? as<T>(C.ex[ccur]) : nullptr,
-                                  pro ? as<T>(C.ey[ccur]) : nullptr, nullptr, nullptr, om, st));
+                                  pro ? as<T>(C.ey[ccur]) : nullptr, nullptr, nullptr, om, st, tk.t0, tk.t1));
         ktoc(s, tk, pro ? 8.5 : 8.0, sizeof(T));
         cur = 1 - cur;
         mode = kTilePlain;
@@ -377,14 +394,15 @@ tph_status vcycle_fused(tph_solver* s, int l, int* cur_out) {
     if (L.nu_pre == 0) {
         TPH_HIP(launch_zero_vel<T>(g, as<T>(L.ex[0]), as<T>(L.ey[0]), st));
     } else {
-        bool tk = ktic(s, l);
+        KTime tk = ktic(s, l);
         TPH_HIP(launch_smooth_tile<T>(g, nullptr, sm, 1, nullptr, nullptr, as<T>(L.ex[0]), as<T>(L.ey[0]), rx, ry, eb,
-                                      ep, nullptr, nullptr, om, st));
+                                      ep, nullptr, nullptr, om, st, tk.t0, tk.t1));
         ktoc(s, tk, 6.0, sizeof(T));
         for (int k = 1; k < L.nu_pre; ++k) {
             tk = ktic(s, l);
             TPH_HIP(launch_smooth_tile<T>(g, nullptr, sm, 0, as<T>(L.ex[cur]), as<T>(L.ey[cur]), as<T>(L.ex[1 - cur]),
-                                          as<T>(L.ey[1 - cur]), rx, ry, eb, ep, nullptr, nullptr, om, st));
+                                          as<T>(L.ey[1 - cur]), rx, ry, eb, ep, nullptr, nullptr, om, st,
+                                          tk.t0, tk.t1));
             ktoc(s, tk, 8.0, sizeof(T));
             cur = 1 - cur;
         }
@@ -398,16 +416,17 @@ tph_status vcycle_fused(tph_solver* s, int l, int* cur_out) {
         TPH_HIP(launch_prolong_add<T>(g, C.g, as<T>(C.ex[ccur]), as<T>(C.ey[ccur]), as<T>(L.ex[cur]),
                                       as<T>(L.ey[cur]), st));
     } else {
-        bool tk = ktic(s, l);
+        KTime tk = ktic(s, l);
         TPH_HIP(launch_smooth_tile<T>(g, &C.g, sm, 2, as<T>(L.ex[cur]), as<T>(L.ey[cur]), as<T>(L.ex[1 - cur]),
                                       as<T>(L.ey[1 - cur]), rx, ry, eb, ep, as<T>(C.ex[ccur]), as<T>(C.ey[ccur]), om,
-                                      st));
+                                      st, tk.t0, tk.t1));
         ktoc(s, tk, 8.5, sizeof(T));
         cur = 1 - cur;
         for (int k = 1; k < L.nu_post; ++k) {
             tk = ktic(s, l);
             TPH_HIP(launch_smooth_tile<T>(g, nullptr, sm, 0, as<T>(L.ex[cur]), as<T>(L.ey[cur]), as<T>(L.ex[1 - cur]),
-                                          as<T>(L.ey[1 - cur]), rx, ry, eb, ep, nullptr, nullptr, om, st));
+                                          as<T>(L.ey[1 - cur]), rx, ry, eb, ep, nullptr, nullptr, om, st,
+                                          tk.t0, tk.t1));
             ktoc(s, tk, 8.0, sizeof(T));
             cur = 1 - cur;
         }
@@ -722,20 +741,35 @@ tph_status create_impl(const tph_desc* desc, void* stream, tph_solver* s) {
             s->max_lds = lim;
     }
     s->lc = -1;
-    if (desc->fused && nlev >= 2 && s->ncoarse <= 2048) {
-        // highest level (smallest index) whose tail fits in one workgroup's LDS
-        // and whose per-sweep work suits one workgroup (<= 64 x 64 cells)
-        // leave room for the kernel's static LDS (per-level tables, a few KB)
+    if (desc->fused && nlev >= 2 && s->ncoarse <= 2048 && desc->coarse_level != -2) {
+        // a level qualifies when its tail fits in one workgroup's LDS (leaving
+        // room for the kernel's static tables) and its per-sweep work suits one
+        // workgroup (<= 64 x 64 cells); default: the finest such level
         const size_t budget = (size_t)std::min(s->max_lds, 160 * 1024) - 8 * 1024;
-        for (int l = 0; l < nlev - 1; ++l) {
+        auto fits = [&](int l, size_t* need_out) {
             Geom gs[kMaxLevels];
             for (int q = l; q < nlev; ++q) gs[q - l] = s->lev[q].g;
             const size_t need = s->mixed() ? coarse_cycle_lds_bytes<float>(gs, nlev - l, s->ncoarse)
                                            : coarse_cycle_lds_bytes<double>(gs, nlev - l, s->ncoarse);
-            if (s->lev[l].g.nx * s->lev[l].g.ny <= 64 * 64 && need <= budget) {
-                s->lc = l;
-                s->lc_lds = need;
-                break;
+            *need_out = need;
+            return s->lev[l].g.nx * s->lev[l].g.ny <= 64 * 64 && need <= budget;
+        };
+        size_t need = 0;
+        if (desc->coarse_level >= 0) {
+            const int l = desc->coarse_level;
+            if (l >= nlev - 1 || !fits(l, &need)) {
+                set_error("coarse_level " + std::to_string(l) + " does not fit the single-workgroup coarse tail");
+                return TPH_ERR_INVALID;
+            }
+            s->lc = l;
+            s->lc_lds = need;
+        } else {
+            for (int l = 0; l < nlev - 1; ++l) {
+                if (fits(l, &need)) {
+                    s->lc = l;
+                    s->lc_lds = need;
+                    break;
+                }
             }
         }
     }
@@ -918,6 +952,7 @@ void tph_desc_default(tph_desc* d, int32_t nx, int32_t ny) {
     d->fused = 1;
     d->msweep = -1;
     d->tile_shape = -1;
+    d->coarse_level = -1;
 }
 
 tph_status tph_create(const tph_desc* desc, void* hip_stream, tph_solver** out) {

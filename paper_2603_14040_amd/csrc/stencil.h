@@ -78,6 +78,30 @@ __device__ __forceinline__ T ly_diag(const T* __restrict__ eb, const T* __restri
     return -(T)2 * (ep[c + P] + ep[c]) * k.idy2 - (eb[c] * cr + eb[c - 1] * cl) * k.idx2;
 }
 
+// diag(L) at a node with no wall-adjacent shear term (1 < i < ny, resp.
+// 1 < j < nx): the general formulas with both boundary factors equal to 1
+template <typename T>
+__device__ __forceinline__ T lx_diag_inner(const T* __restrict__ eb, const T* __restrict__ ep, int c, int P,
+                                           const LevelC<T>& k) {
+    return -(T)2 * (ep[c + 1] + ep[c]) * k.idx2 - (eb[c] + eb[c - P]) * k.idy2;
+}
+
+template <typename T>
+__device__ __forceinline__ T ly_diag_inner(const T* __restrict__ eb, const T* __restrict__ ep, int c, int P,
+                                           const LevelC<T>& k) {
+    return -(T)2 * (ep[c + P] + ep[c]) * k.idy2 - (eb[c] + eb[c - 1]) * k.idx2;
+}
+
+// damped point update e + omega (r - (L e)) / diag.  FP32 (inside the
+// mixed-precision V-cycle) multiplies by the hardware reciprocal of the
+// diagonal (1 ulp) instead of the correctly rounded division; FP64 divides.
+__device__ __forceinline__ float relax(float e, float omega, float res, float d) {
+    return e + omega * res * __builtin_amdgcn_rcpf(d);
+}
+__device__ __forceinline__ double relax(double e, double omega, double res, double d) {
+    return e + omega * res / d;
+}
+
 // Energy weight of a continuity row: eta_p / (2/dx^2 + 2/dy^2)
 // (Sec. "Residual Norms", diagonal Schur surrogate).
 template <typename T>

@@ -41,9 +41,14 @@ def test_search_second_round_uses_interaction():
 
 def test_masks_and_solver_kwargs():
     assert at.plan_to_masks([(1, 0), (0, 1), (1, 1)], [0, 1, 3]) == (0b1001, 0b1010)
-    p = {"L0": (0, 0), "L1": (1, 1), "nu": 3, "uzawa_steps": 1, "restart": 30}
+    p = {"L0": (0, 0), "L1": (1, 1), "nu_pre": 3, "nu_post": 2, "nu_growth": 1.5, "uzawa_steps": 1, "restart": 30,
+         "coarse_level": 4}
     kw = at.solver_kwargs(p, [0, 1])
-    assert kw == dict(nu_pre=3, nu_post=3, uzawa_steps=1, restart=30, msweep=0b10, tile_shape=0b10)
+    assert kw == dict(nu_pre=3, nu_post=2, nu_growth=1.5, uzawa_steps=1, restart=30, msweep=0b10, tile_shape=0b10,
+                      coarse_level=4)
+    names = [k.name for k in at.knobs_for([0, 1, 2], [5])]
+    assert names[:5] == ["uzawa_steps", "nu_pre", "nu_post", "nu_growth", "restart"]
+    assert "coarse_level" in names and names[-3:] == ["L0", "L1", "L2"]
 
 
 def test_database_round_trip(tmp_path):

@@ -140,8 +140,9 @@ def test_preconditioner_matches_oracle_vcycle(case, prec, fused):
     assert np.array_equal(gy_[1:ny, nx + 1], (1 if bc[1] == 0 else -1) * gy_[1:ny, nx])
 
 
-# level plans of the fused V-cycle: (msweep mask, tile_shape mask); -1 = all
-PLANS = [(0, 0), (-1, -1), (0xFFFF, 0), (0xFFFF, 0xFFFF)]
+# level plans of the fused V-cycle: (msweep mask, tile_shape mask, coarse_level);
+# -1 = library default, coarse_level -2 = no single-workgroup coarse tail
+PLANS = [(0, 0, -1), (-1, -1, -1), (0xFFFF, 0, -2), (0xFFFF, 0xFFFF, -1), (0, 0xFFFF, -2)]
 
 
 @pytest.mark.parametrize("plan", PLANS)
@@ -155,10 +156,10 @@ def test_multisweep_plans_match_oracle_vcycle(case, prec, plan):
     nx, ny, bc, levels, sm, nu, growth, omega, alpha, steps = case
     eb, ep, rho = wl.random_fields(nx, ny, seed=nx * 5 + ny, eta_decades=2)
     rx, ry, rp = wl.random_state(nx, ny, seed=nx + 3)
-    msw, shp = plan
+    msw, shp, cl = plan
     s = solver_for(nx, ny, bc=bc, precision=prec, levels=levels, smoother=sm, nu_pre=nu, nu_post=nu,
                    nu_growth=growth, omega=omega, alpha=alpha, uzawa_steps=steps, fused=True, msweep=msw,
-                   tile_shape=shp)
+                   tile_shape=shp, coarse_level=cl)
     s.set_coefficients(T(eb), T(ep), T(rho))
     zx, zy, zp = s.precondition(T(rx), T(ry), T(rp))
     sched = [min(256, math.ceil(nu * growth ** l - 1e-9)) for l in range(levels)]
