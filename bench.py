@@ -117,8 +117,8 @@ def main():
         for _ in range(warmup):
             info = step()
         if precision == tph.MIXED:
-            # HIP events around every finest-level smoothing launch of the timed solves
-            s.kernel_timing(True)
+            # kernel time stamps of every 16th finest-level smoothing launch of the timed solves
+            s.kernel_timing(16)
             s.kernel_timing_read()
         torch.cuda.synchronize()
         infos = []
@@ -129,7 +129,7 @@ def main():
         dt = time.perf_counter() - t0
         if precision == tph.MIXED:
             live[:] = s.kernel_timing_read()
-            s.kernel_timing(False)
+            s.kernel_timing(0)
         for inf in infos:
             if inf.status != "TPH_OK":
                 raise RuntimeError(f"{tag} solve did not converge: {inf}")
@@ -291,8 +291,8 @@ def main():
                      "kernel": ("finest-level Gauss-Seidel on LDS tiles (FP32, " +
                                 ("multi-sweep passes with fused residual-restriction / prolongation"
                                  if plan0[0] == "multisweep" else "one sweep per launch") +
-                                f", tile shape {plan0[1]}), HIP events on the solver stream inside the "
-                                "timed solves"),
+                                f", tile shape {plan0[1]}), kernel time stamps (HIP events) of every 16th launch on "
+                                "the solver stream inside the timed solves"),
                      "launches": n_l, "dropped": drop_l, "us_per_launch": round(us_live, 3),
                      "algorithmic_bytes_per_launch": by_l / n_l},
         "kernels": kern,

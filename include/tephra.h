@@ -246,11 +246,13 @@ enum {
 tph_status tph_time_kernel(tph_solver* s, int32_t kind, int32_t reps, double* ms_per_launch,
                            double* bytes_per_launch);
 
-/* Measurement hook for the smoother inside real solves.  While enabled
- * (enable = 1), every finest-level smoothing launch of the fused V-cycle
+/* Measurement hook for the smoother inside real solves.  With enable = k
+ * >= 1, every k-th finest-level smoothing launch of the fused V-cycle
  * (desc.fused = 1) made by later solves on this handle is launched with a
  * pair of HIP events that take the kernel's own start and end time stamps
- * (hipExtLaunchKernel); up to 8192 launches are recorded between two reads,
+ * (hipExtLaunchKernel; a timed launch delays the stream by a few
+ * microseconds, hence the sampling); enable = 0 turns timing off.  Up to
+ * 8192 launches are recorded between two reads,
  * later ones are counted in *dropped.  The events are created on the first
  * enable and live as long as the handle.  tph_kernel_timing_read waits for
  * the stream, returns the number of timed launches, their summed duration in

@@ -221,9 +221,9 @@ class Solver:
                                                                 ctypes.byref(by)))
         return ms.value, by.value
 
-    def kernel_timing(self, enable: bool = True):
-        """Bracket every finest-level smoothing launch of later solves with HIP events."""
-        _lib.check("tph_kernel_timing", self._lib.tph_kernel_timing(self._h, 1 if enable else 0))
+    def kernel_timing(self, stride: int = 1):
+        """Time every stride-th finest-level smoothing launch of later solves (0: off)."""
+        _lib.check("tph_kernel_timing", self._lib.tph_kernel_timing(self._h, int(stride)))
 
     def kernel_timing_read(self):
         """(launches, total ms, total algorithmic bytes, dropped) since the last read; resets."""

@@ -92,15 +92,26 @@ hipError_t launch_res_restrict(const Geom& gf, const Geom& gc, const T* ex, cons
 
 template <typename T>
 hipError_t launch_coarse_cycle(const CoarseArgs<T>& a, size_t lds_bytes, int max_lds, hipStream_t st) {
-    if (lds_bytes > 64 * 1024) {
-        // request exactly what this launch needs (the kernel also has a few KB of static LDS)
-        (void)max_lds;
+    // raise the kernel's dynamic LDS limit when a launch needs more than 64 KB;
+    // the attribute is per function (and device), so it is set only when a
+    // launch needs more than any earlier one on this device
+    (void)max_lds;
+    static thread_local int dev_cached = -1;
+    static thread_local size_t granted = 64 * 1024;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return hipGetLastError();
+    if (dev != dev_cached) {
+        dev_cached = dev;
+        granted = 64 * 1024;
+    }
+    if (lds_bytes > granted) {
         hipError_t e = hipFuncSetAttribute((const void*)k_coarse_cycle<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds_bytes);
         if (e != hipSuccess) {
             (void)hipGetLastError();   // do not leave the error pending for unrelated later launches
             return e;
         }
+        granted = lds_bytes;
     }
     hipLaunchKernelGGL(k_coarse_cycle<T>, dim3(1), dim3(coarse_threads<T>()), lds_bytes, st, a);
     return hipGetLastError();

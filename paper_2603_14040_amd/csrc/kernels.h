@@ -91,9 +91,12 @@ hipError_t launch_axpy_dot(double* w, const double* V0, size_t vstride, int nv, 
                            hipStream_t st);
 // out[i] = sum_b partial[i * nblk + b], i < k  (fixed order: deterministic)
 // row sums of partial (k rows of nblk) into out; also into host_out (a device
-// pointer to mapped coherent host memory) when it is not null
+// pointer to mapped coherent host memory) when it is not null.  With k == 1
+// and host_seq not null, the kernel then writes seq to *host_seq (mapped host
+// memory) after a system-scope fence, so a host that sees seq there also sees
+// every value written to host memory by this and earlier kernels.
 hipError_t launch_reduce_rows(const double* partial, int nblk, int k, double* out, hipStream_t st,
-                              double* host_out = nullptr);
+                              double* host_out = nullptr, unsigned* host_seq = nullptr, unsigned seq = 0);
 // dst = src / sqrt(*nrm2)
 hipError_t launch_scale_by_rnorm(double* dst, const double* src, size_t n, const double* nrm2,
                                  hipStream_t st);

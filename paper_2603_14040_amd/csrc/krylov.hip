@@ -91,14 +91,19 @@ __global__ __launch_bounds__(256) void k_axpy_dot(double* __restrict__ w, const 
 }
 
 __global__ __launch_bounds__(256) void k_reduce_rows(const double* __restrict__ partial, int nblk,
-                                                    double* __restrict__ out, double* __restrict__ host_out) {
+                                                    double* __restrict__ out, double* __restrict__ host_out,
+                                                    unsigned* __restrict__ host_seq, unsigned seq) {
     const double* row = partial + (size_t)blockIdx.x * nblk;
     double s = 0.0;
     for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += row[b];
     s = block_sum(s);
     if (threadIdx.x == 0) {
         out[blockIdx.x] = s;
-        if (host_out) host_out[blockIdx.x] = s;   // visible to the host once the stream has synchronised
+        if (host_out) host_out[blockIdx.x] = s;
+        if (host_seq) {
+            __threadfence_system();               // the values above reach host memory first
+            *(volatile unsigned*)host_seq = seq;
+        }
     }
 }
 
@@ -179,8 +184,9 @@ hipError_t launch_axpy_dot(double* w, const double* V0, size_t vstride, int nv, 
 }
 
 hipError_t launch_reduce_rows(const double* partial, int nblk, int k, double* out, hipStream_t st,
-                              double* host_out) {
-    hipLaunchKernelGGL(k_reduce_rows, dim3(k), dim3(256), 0, st, partial, nblk, out, host_out);
+                              double* host_out, unsigned* host_seq, unsigned seq) {
+    if (host_seq && k != 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_reduce_rows, dim3(k), dim3(256), 0, st, partial, nblk, out, host_out, host_seq, seq);
     return hipGetLastError();
 }
 

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -105,6 +106,9 @@ struct tph_solver {
     double* dscal = nullptr;     // device scalars
     double* hscal = nullptr;     // pinned host mirror (mapped, coherent)
     double* hscal_dev = nullptr; // its device address: reductions write results there directly
+    unsigned* hseq = nullptr;    // mapped host word: sequence number written by the last reduction
+    unsigned* hseq_dev = nullptr;
+    unsigned seq = 0;
     double gx = 0, gy = 0;
     bool has_fx = false, has_fy = false;
     bool ready = false;
@@ -114,6 +118,8 @@ struct tph_solver {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // optional event timing of the finest-level smoother inside solves
     bool ktime = false;
+    int kstride = 1;              // time every kstride-th launch
+    long long kcount = 0;
     std::vector<hipEvent_t> kev;  // 2 per recorded launch
     int kev_used = 0;
     int kdropped = 0;
@@ -138,6 +144,7 @@ struct KTime {
 KTime ktic(tph_solver* s, int l) {
     KTime k;
     if (!s->ktime || l != 0) return k;
+    if (s->kcount++ % s->kstride != 0) return k;    // every kstride-th finest-level launch
     if (s->kev_used + 2 > (int)s->kev.size()) {
         ++s->kdropped;
         return k;
@@ -469,15 +476,34 @@ tph_status precondition(tph_solver* s, double* vraw, double* zraw, bool energy) 
 }
 
 // reduce partial rows into `k` device scalars at slot; with to_host the same
-// kernel also writes them into the mapped host mirror (no copy launch), read
-// by the host after wait()
-tph_status reduce_to(tph_solver* s, int nblk, int k, int slot, bool to_host = false) {
-    TPH_HIP(launch_reduce_rows(s->partial, nblk, k, s->dscal + slot, s->st, to_host ? s->hscal_dev + slot : nullptr));
+// kernel also writes them into the mapped host mirror (no copy launch).  A
+// reduction with `signal` (k == 1) ends the values the host is about to read:
+// it also posts the next sequence number, which wait_signal() polls.
+tph_status reduce_to(tph_solver* s, int nblk, int k, int slot, bool to_host = false, bool signal = false) {
+    TPH_HIP(launch_reduce_rows(s->partial, nblk, k, s->dscal + slot, s->st, to_host ? s->hscal_dev + slot : nullptr,
+                               signal ? s->hseq_dev : nullptr, signal ? ++s->seq : 0u));
     return TPH_OK;
 }
 
-tph_status wait(tph_solver* s) {
-    TPH_HIP(hipStreamSynchronize(s->st));
+// Wait until the last signalling reduction has posted its sequence number.
+// Polling the mapped word avoids the wake-up latency of a stream
+// synchronisation; past ~2 s of polling (a stalled device) it falls back to
+// hipStreamSynchronize, which also reports any device error.
+tph_status wait_signal(tph_solver* s) {
+    const volatile unsigned* flag = s->hseq;
+    const auto t0 = std::chrono::steady_clock::now();
+    for (unsigned spin = 0; *flag != s->seq; ++spin) {
+        if ((spin & 1023u) == 1023u &&
+            std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2000)) {
+            TPH_HIP(hipStreamSynchronize(s->st));
+            if (*flag != s->seq) {
+                set_error("reduction signal not observed after the stream completed");
+                return TPH_ERR_HIP;
+            }
+            break;
+        }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
     return TPH_OK;
 }
 
@@ -495,7 +521,7 @@ tph_status energy_residual_vec(tph_solver* s, double* xraw, double* braw, double
     Vec3 b = vec3(s, braw);
     TPH_HIP(launch_outer_residual(L.g, vec3(s, xraw), &b, L.eb64, L.ep64, vec3(s, outraw), ResMode::kResidual, true,
                                   s->partial, &nblk, s->st));
-    return reduce_to(s, nblk, 1, slot, to_host);
+    return reduce_to(s, nblk, 1, slot, to_host, to_host);
 }
 
 tph_status copy_in(tph_solver* s, const Geom& g, double* base, const double* user) {
@@ -555,7 +581,7 @@ tph_status fgmres(tph_solver* s, double* braw, tph_info* info) {
     {
         TPH_HIP(hipMemsetAsync(s->t2, 0, n3 * sizeof(double), s->st));
         TPH_TRY(energy_residual_vec(s, s->t2, braw, s->t1, kSlotMisc, true));
-        TPH_TRY(wait(s));
+        TPH_TRY(wait_signal(s));
     }
     const double bnorm = std::sqrt(s->hscal[kSlotMisc]);
     if (!std::isfinite(bnorm)) { set_error("right-hand side is not finite"); return TPH_ERR_NONFINITE; }
@@ -572,7 +598,7 @@ tph_status fgmres(tph_solver* s, double* braw, tph_info* info) {
     while (true) {
         // true residual r = W^(1/2) (b - A x) into V_0
         TPH_TRY(energy_residual_vec(s, s->x, braw, Vk(0), kSlotMisc, true));
-        TPH_TRY(wait(s));
+        TPH_TRY(wait_signal(s));
         const double beta = std::sqrt(s->hscal[kSlotMisc]);
         if (!std::isfinite(beta)) { set_error("non-finite residual during the solve"); return TPH_ERR_NONFINITE; }
         true_res = bnorm > 0 ? beta / bnorm : beta;
@@ -602,8 +628,8 @@ tph_status fgmres(tph_solver* s, double* braw, tph_info* info) {
             TPH_TRY(reduce_to(s, nblk_flat, j + 2, kSlotH1, true));  // h (j+1) and |w|^2 at kSlotH1 + j + 1
             TPH_HIP(launch_axpy_dot(w, Vk(0), n3, j + 1, s->dscal + kSlotH1, n3, false, 0, s->partial, nblk_flat,
                                     s->st));
-            TPH_TRY(reduce_to(s, nblk_flat, 1, kSlotNrm, true));
-            TPH_TRY(wait(s));
+            TPH_TRY(reduce_to(s, nblk_flat, 1, kSlotNrm, true, true));
+            TPH_TRY(wait_signal(s));
             double* col = &H[(size_t)j * (m + 1)];
             for (int i = 0; i <= j; ++i) col[i] = s->hscal[kSlotH1 + i];
             const double w2_before = s->hscal[kSlotH1 + j + 1];
@@ -612,8 +638,8 @@ tph_status fgmres(tph_solver* s, double* braw, tph_info* info) {
                 TPH_TRY(reduce_to(s, nblk_flat, j + 1, kSlotH2, true));
                 TPH_HIP(launch_axpy_dot(w, Vk(0), n3, j + 1, s->dscal + kSlotH2, n3, false, 0, s->partial, nblk_flat,
                                         s->st));
-                TPH_TRY(reduce_to(s, nblk_flat, 1, kSlotNrm, true));
-                TPH_TRY(wait(s));
+                TPH_TRY(reduce_to(s, nblk_flat, 1, kSlotNrm, true, true));
+                TPH_TRY(wait_signal(s));
                 for (int i = 0; i <= j; ++i) col[i] += s->hscal[kSlotH2 + i];
                 ++s->reorth_count;
             }
@@ -792,6 +818,10 @@ tph_status create_impl(const tph_desc* desc, void* stream, tph_solver* s) {
     TPH_TRY(dev_alloc(s, (void**)&s->Minv, (size_t)s->ncoarse * s->ncoarse * sizeof(double)));
     TPH_HIP(hipHostMalloc((void**)&s->hscal, kScalars * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent));
     TPH_HIP(hipHostGetDevicePointer((void**)&s->hscal_dev, s->hscal, 0));
+    TPH_HIP(hipHostMalloc((void**)&s->hseq, 64, hipHostMallocMapped | hipHostMallocCoherent));
+    TPH_HIP(hipHostGetDevicePointer((void**)&s->hseq_dev, s->hseq, 0));
+    *s->hseq = 0;
+    s->seq = 0;
     TPH_HIP(hipEventCreate(&s->ev0));
     TPH_HIP(hipEventCreate(&s->ev1));
     TPH_HIP(hipStreamSynchronize(s->st));
@@ -1195,7 +1225,7 @@ tph_status tph_time_kernel(tph_solver* s, int32_t kind, int32_t reps, double* ms
 tph_status tph_kernel_timing(tph_solver* s, int32_t enable) {
     g_last_error.clear();
     if (!s) { set_error("null handle"); return TPH_ERR_INVALID; }
-    if (enable != 0 && enable != 1) { set_error("enable must be 0 or 1"); return TPH_ERR_INVALID; }
+    if (enable < 0 || enable > 1024) { set_error("enable must be 0 (off) or a sampling stride in [1, 1024]"); return TPH_ERR_INVALID; }
     if (enable && s->kev.empty()) {
         s->kev.assign(2 * kMaxTimedLaunches, nullptr);
         for (auto& e : s->kev) {
@@ -1209,7 +1239,9 @@ tph_status tph_kernel_timing(tph_solver* s, int32_t enable) {
             }
         }
     }
-    s->ktime = enable == 1;
+    s->ktime = enable > 0;
+    s->kstride = enable > 0 ? enable : 1;
+    s->kcount = 0;
     return TPH_OK;
 }
 
@@ -1241,6 +1273,7 @@ void tph_destroy(tph_solver* s) {
     if (s->st || !s->dev_allocs.empty()) (void)hipStreamSynchronize(s->st);
     for (void* p : s->dev_allocs) (void)hipFree(p);
     if (s->hscal) (void)hipHostFree(s->hscal);
+    if (s->hseq) (void)hipHostFree(s->hseq);
     if (s->ev0) (void)hipEventDestroy(s->ev0);
     if (s->ev1) (void)hipEventDestroy(s->ev1);
     for (auto& e : s->kev)
