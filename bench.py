@@ -117,8 +117,9 @@ def main():
         for _ in range(warmup):
             info = step()
         if precision == tph.MIXED:
-            # kernel time stamps of every 16th finest-level smoothing launch of the timed solves
-            s.kernel_timing(16)
+            # kernel time stamps of every 17th finest-level smoothing launch of the timed solves
+            # (a stride prime to the launch pattern samples every sweep mode)
+            s.kernel_timing(17)
             s.kernel_timing_read()
         torch.cuda.synchronize()
         infos = []
@@ -158,6 +159,15 @@ def main():
         kern[name] = {"us": round(ms * 1e3, 3), "bytes": by, "GBps": round(by / (ms * 1e-3) / 1e9, 1)}
     # the roofline figure comes from the launches inside the timed solves
     n_l, ms_l, by_l, drop_l = live
+    # HBM traffic per launch from the committed counter runs, valid only for these exact kernel sources
+    traffic = None
+    tfile = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "smooth_l0_traffic.json")
+    if os.path.exists(tfile):
+        from paper_2603_14040_amd import profiling
+        with open(tfile) as fh:
+            tj = json.load(fh)
+        if tj.get("sources_sha256") == profiling.sources_hash():
+            traffic = tj["bytes_per_launch"]
     if n_l == 0:
         raise RuntimeError("no finest-level smoothing launch was timed")
     us_live = 1e3 * ms_l / n_l
@@ -287,11 +297,11 @@ def main():
         "mixed_speedup_vs_fp64": ms_64 / ms_mix if fp64_steps > 0 else None,
         "tuned": tuned,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": ("finest-level Gauss-Seidel on LDS tiles (FP32, " +
                                 ("multi-sweep passes with fused residual-restriction / prolongation"
                                  if plan0[0] == "multisweep" else "one sweep per launch") +
-                                f", tile shape {plan0[1]}), kernel time stamps (HIP events) of every 16th launch on "
+                                f", tile shape {plan0[1]}), kernel time stamps (HIP events) of every 17th launch on "
                                 "the solver stream inside the timed solves"),
                      "launches": n_l, "dropped": drop_l, "us_per_launch": round(us_live, 3),
                      "algorithmic_bytes_per_launch": by_l / n_l},

@@ -15,7 +15,8 @@ Knobs (all of them descriptor fields of tph_create):
   * the first level of the single-workgroup coarse tail (``coarse_level``);
   * pre- and post-smoothing sweeps and their growth per level (the paper's
     level-dependent schedule, nu_l = ceil(nu * growth^l));
-  * Uzawa sweeps per preconditioner application (``uzawa_steps``);
+  * Uzawa sweeps per preconditioner application (``uzawa_steps``) and the
+    Uzawa pressure relaxation ``alpha``; the smoother damping ``omega``;
   * FGMRES restart length.
 Parameter sets that resolve to the same kernel plan on every level are
 measured once.
@@ -151,14 +152,17 @@ def solver_kwargs(p: Params, tile_levels: Sequence[int]) -> dict:
     msw, shp = plan_to_masks(plan, tile_levels)
     return dict(nu_pre=int(p["nu_pre"]), nu_post=int(p["nu_post"]), nu_growth=float(p.get("nu_growth", 1.0)),
                 uzawa_steps=int(p["uzawa_steps"]), restart=int(p["restart"]), msweep=msw, tile_shape=shp,
-                coarse_level=int(p.get("coarse_level", -1)))
+                coarse_level=int(p.get("coarse_level", -1)), omega=float(p.get("omega", 1.0)),
+                alpha=float(p.get("alpha", 1.0)))
 
 
 def knobs_for(tile_levels: Sequence[int], coarse_levels: Sequence[int] = (), nus=(1, 2, 3),
-              growths=(1.0, 1.5, 2.0), uzawa=(1, 2, 3, 4, 5), restarts=(5, 8, 10, 15, 20, 30)) -> List[Knob]:
+              growths=(1.0, 1.5, 2.0), uzawa=(1, 2, 3, 4, 5), restarts=(5, 8, 10, 15, 20, 30),
+              alphas=(1.0, 1.5, 2.0, 3.0), omegas=(0.8, 1.0, 1.2)) -> List[Knob]:
     """Schedule knobs first (they move the iteration count), then the kernel plan."""
-    ks = [Knob("uzawa_steps", list(uzawa)), Knob("nu_pre", list(nus)), Knob("nu_post", list(nus)),
-          Knob("nu_growth", list(growths)), Knob("restart", list(restarts))]
+    ks = [Knob("alpha", list(alphas)), Knob("uzawa_steps", list(uzawa)), Knob("nu_pre", list(nus)),
+          Knob("nu_post", list(nus)), Knob("omega", list(omegas)), Knob("nu_growth", list(growths)),
+          Knob("restart", list(restarts))]
     if coarse_levels:
         ks.append(Knob("coarse_level", [-1] + list(coarse_levels)))
     ks += [Knob(f"L{l}", [(0, 0), (0, 1), (1, 0), (1, 1)]) for l in tile_levels]
@@ -195,7 +199,8 @@ def tune(eta_b, eta_p, rho_b, gx: float = 0.0, gy: float = -1.0, *, precision: O
     coarse_levels = [l for l in (lc0 + 1, lc0 + 2) if l < nlev - 1 and lc0 < nlev - 1]
     d = base.desc
     start: Params = {"nu_pre": int(d.nu_pre), "nu_post": int(d.nu_post), "nu_growth": float(d.nu_growth),
-                     "uzawa_steps": int(d.uzawa_steps), "restart": int(d.restart), "coarse_level": -1}
+                     "uzawa_steps": int(d.uzawa_steps), "restart": int(d.restart), "coarse_level": -1,
+                     "omega": float(d.omega), "alpha": float(d.alpha)}
     for l in tile_levels:
         k, s = plan0[l]
         start[f"L{l}"] = (1 if k == "multisweep" else 0, int(s))
@@ -215,7 +220,7 @@ def tune(eta_b, eta_p, rho_b, gx: float = 0.0, gy: float = -1.0, *, precision: O
         try:
             # the plan the solver actually runs: sets that differ only in ignored bits are one candidate
             eff = json.dumps([kw["nu_pre"], kw["nu_post"], kw["nu_growth"], kw["uzawa_steps"], kw["restart"],
-                              [s.level_plan(l) for l in range(s.levels)]])
+                              kw["omega"], kw["alpha"], [s.level_plan(l) for l in range(s.levels)]])
             eff_of[json.dumps(p, sort_keys=True)] = eff
             if eff in seen:
                 return seen[eff]
