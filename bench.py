@@ -191,13 +191,20 @@ def main():
         s64 = None
         probs = wl.batch_sinkers(args.batch, seed=4)
         log(f"[bench] batched workload: {len(probs)} problems, {sum(p.cells for p in probs)} cells")
-        t0 = time.perf_counter()
-        bat = tph.Batch([(p.nx, p.ny) for p in probs], device=dev, precision=tph.MIXED, restart=16)
-        t_create = time.perf_counter() - t0
         ebs = [to(p.eta_b) for p in probs]
         eps = [to(p.eta_p) for p in probs]
         rhs_ = [to(p.rho_b) for p in probs]
         gxy = [(p.gx, p.gy) for p in probs]
+        shapes = [(p.nx, p.ny) for p in probs]
+        btuned = {"params": {"restart": 16}, "ms": None, "default_ms": None, "trials": 0, "seconds": 0.0}
+        if not args.no_tune:
+            log("[bench] autotuning the batched schedule")
+            btuned = autotune.tune_batch(shapes, ebs, eps, rhs_, gxy, precision=tph.MIXED, device=dev)
+            log(f"[bench] batch: tuned {btuned['params']} {btuned['ms']:.1f} ms (defaults "
+                f"{btuned['default_ms']:.1f} ms, {btuned['trials']} trials, {btuned['seconds']:.1f} s)")
+        t0 = time.perf_counter()
+        bat = tph.Batch(shapes, device=dev, precision=tph.MIXED, **btuned["params"])
+        t_create = time.perf_counter() - t0
         outs = bat.zeros(), bat.zeros(), bat.zeros()
 
         def bstep():
@@ -218,7 +225,8 @@ def main():
         batch = {"workload": f"{len(probs)} centred sinkers, sizes 64..512 (seed 4), contrast 10^U(1,4), mixed",
                  "cells": bcells, "value": bcells / bdt, "unit": "cells/s", "ms_per_step": 1e3 * bdt,
                  "iters_max": max(its), "iters_mean": sum(its) / len(its),
-                 "converged": sum(1 for i in binf if i.res_energy <= 1e-8), "create_s": round(t_create, 2)}
+                 "converged": sum(1 for i in binf if i.res_energy <= 1e-8), "create_s": round(t_create, 2),
+                 "tuned": btuned}
         log(f"[bench] batch: {1e3 * bdt:.1f} ms, {bcells / bdt:.3e} cells/s, iterations max {max(its)}")
         bat.close()
         del bat, outs, ebs, eps, rhs_
@@ -228,7 +236,7 @@ def main():
     if not args.no_adjoint:
         base, m, m_true, cells_ = wl.adjoint_problem(n)
         eb_t, ep_t = wl.logvisc_to_eta(m_true, n, n)
-        sa = tph.Solver(n, n, precision=tph.MIXED, device=dev)
+        sa = tph.Solver(n, n, precision=tph.MIXED, device=dev, **tuned["mixed"]["params"])
         sa.set_coefficients(to(eb_t), to(ep_t), rho, pr.gx, pr.gy)
         vxt = sa.solve()[0]
         target = vxt[n, 1:n].clone()

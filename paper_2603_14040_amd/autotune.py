@@ -259,6 +259,56 @@ def tune(eta_b, eta_p, rho_b, gx: float = 0.0, gy: float = -1.0, *, precision: O
     return entry
 
 
+def tune_batch(shapes, eta_b, eta_p, rho_b, gxy, *, precision: Optional[int] = None, rtol: float = 1e-8,
+               reps: int = 1, rounds: int = 2, rel_gain: float = 0.02, device=None,
+               knobs: Optional[Sequence[Knob]] = None, log: Optional[Callable[[str], None]] = None) -> dict:
+    """Tune the schedule of a batched solve (lists of per-problem device arrays).
+
+    The batched kernels take no per-level plan, so the knobs are the
+    schedule ones: Uzawa relaxation and steps, sweeps and restart length.
+    The cost of a candidate is the median time of ``reps`` batched solves
+    (after one untimed solve, which also captures the iteration graph).
+    """
+    import torch
+    from . import MIXED, Batch
+
+    precision = MIXED if precision is None else precision
+    t_start = time.perf_counter()
+    start: Params = {"alpha": 1.0, "uzawa_steps": 2, "nu_pre": 2, "nu_post": 2, "restart": 16}
+    ks = knobs if knobs is not None else [Knob("alpha", [1.0, 1.5, 2.0]), Knob("uzawa_steps", [2, 3, 4]),
+                                          Knob("nu_pre", [1, 2]), Knob("nu_post", [1, 2]),
+                                          Knob("restart", [8, 16])]
+
+    def measure(p: Params) -> float:
+        b = Batch(shapes, device=device, precision=precision, rtol=rtol, **p)
+        try:
+            b.set_coefficients(eta_b, eta_p, rho_b, gxy)
+            outs = b.zeros(), b.zeros(), b.zeros()
+            ts = []
+            for r in range(reps + 1):
+                for o in outs:
+                    for t in o:
+                        t.zero_()
+                torch.cuda.synchronize(device)
+                t0 = time.perf_counter()
+                infos = b.solve(*outs)[3]
+                torch.cuda.synchronize(device)
+                if any(i.res_energy > rtol for i in infos):
+                    return math.inf
+                if r > 0:
+                    ts.append(time.perf_counter() - t0)
+            c = statistics.median(ts) * 1e3
+            if log:
+                log(f"[tune-batch] {p} -> {c:.1f} ms")
+            return c
+        finally:
+            b.close()
+
+    res = coordinate_search(measure, ks, start, rounds=rounds, rel_gain=rel_gain)
+    return {"params": dict(res.params), "ms": res.cost, "default_ms": res.trials[0][1], "trials": len(res.trials),
+            "seconds": round(time.perf_counter() - t_start, 2)}
+
+
 def device_name(device=None) -> str:
     """Architecture and compute-unit count of the device (stable across tools)."""
     import torch
