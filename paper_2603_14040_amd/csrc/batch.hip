@@ -332,6 +332,10 @@ struct tph_batch {
     int n_chunks = 0;
     hipGraphExec_t iter_exec = nullptr;
     hipGraph_t iter_graph = nullptr;
+    // batched coarsest factorisation: one workgroup per problem (null: some problem too large)
+    double** d_gj_mats = nullptr;
+    int* d_gj_n = nullptr;
+    int gj_nmax = 0;
     std::vector<void*> allocs;
     bool ready = false;
     bool mixed() const { return d.precision == TPH_MIXED; }
@@ -541,6 +545,25 @@ tph_status batch_create_impl(tph_batch* b, int count, const tph_desc* descs) {
             return TPH_ERR_UNSUPPORTED;
         }
         b->maxdepth = std::max(b->maxdepth, v.lc);
+    }
+    {
+        std::vector<double*> mats(count);
+        std::vector<int> ns(count);
+        bool small = true;
+        for (int p = 0; p < count; ++p) {
+            const TphSolverView v = tph_internal_view(b->s[p]);
+            mats[p] = const_cast<double*>(v.Minv);
+            ns[p] = v.ncoarse;
+            small = small && v.ncoarse <= kGJLds;
+            b->gj_nmax = std::max(b->gj_nmax, v.ncoarse);
+        }
+        if (small) {
+            B_TRY(b_alloc(b, (void**)&b->d_gj_mats, count * sizeof(double*)));
+            B_TRY(b_alloc(b, (void**)&b->d_gj_n, count * sizeof(int)));
+            B_HIP(hipMemcpyAsync(b->d_gj_mats, mats.data(), count * sizeof(double*), hipMemcpyHostToDevice, b->st));
+            B_HIP(hipMemcpyAsync(b->d_gj_n, ns.data(), count * sizeof(int), hipMemcpyHostToDevice, b->st));
+            B_HIP(hipStreamSynchronize(b->st));
+        }
     }
     // per-problem tables and work lists
     std::vector<BProb> pr(count);
@@ -823,12 +846,33 @@ tph_status tph_batch_set_coefficients(tph_batch* b, const double* const* eta_b, 
         tph_internal_set_error("could not order the batch stream after the caller's stream");
         return TPH_ERR_HIP;
     }
-    for (int p = 0; p < b->count; ++p) {
-        const tph_status s = tph_set_coefficients(b->s[p], eta_b[p], eta_p[p], rho_b[p], gxy[2 * p], gxy[2 * p + 1],
-                                                  nullptr, nullptr);
-        if (s != TPH_OK) {
-            tph_internal_set_error("problem " + std::to_string(p) + ": " + tph_last_error());
-            return s;
+    if (b->d_gj_mats) {
+        // every problem's setup enqueued on the batch stream, one launch factors all
+        // coarsest operators, one wait covers everything
+        for (int p = 0; p < b->count; ++p) {
+            const tph_status s = tph_internal_setup_enqueue(b->s[p], eta_b[p], eta_p[p], rho_b[p], gxy[2 * p],
+                                                            gxy[2 * p + 1]);
+            if (s != TPH_OK) {
+                tph_internal_set_error("problem " + std::to_string(p) + ": " + tph_last_error());
+                return s;
+            }
+        }
+        B_HIP(launch_gauss_jordan_batched(b->d_gj_mats, b->d_gj_n, b->count, b->gj_nmax, b->st));
+        for (int p = 0; p < b->count; ++p) {
+            const tph_status s = tph_internal_setup_finish(b->s[p]);
+            if (s != TPH_OK) {
+                tph_internal_set_error("problem " + std::to_string(p) + ": " + tph_last_error());
+                return s;
+            }
+        }
+    } else {
+        for (int p = 0; p < b->count; ++p) {
+            const tph_status s = tph_set_coefficients(b->s[p], eta_b[p], eta_p[p], rho_b[p], gxy[2 * p],
+                                                      gxy[2 * p + 1], nullptr, nullptr);
+            if (s != TPH_OK) {
+                tph_internal_set_error("problem " + std::to_string(p) + ": " + tph_last_error());
+                return s;
+            }
         }
     }
     b->ready = true;

@@ -113,6 +113,41 @@ __global__ __launch_bounds__(1024) void k_gauss_jordan(double* __restrict__ M, i
     }
 }
 
+// Gauss-Jordan inversion of an SPD matrix held entirely in LDS (n <= kGJLds):
+// the same elimination as k_gauss_jordan without the round trips to memory.
+// Blocks of a batched launch each invert their own matrix (mats[blockIdx.x],
+// sizes ns[blockIdx.x]).
+__device__ __forceinline__ void gauss_jordan_lds(double* __restrict__ Mg, int n, double* A, double* colk) {
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    for (int q = tid; q < n * n; q += nthr) A[q] = Mg[q];
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        for (int i = tid; i < n; i += nthr) colk[i] = A[i * n + k];
+        __syncthreads();
+        const double rd = 1.0 / colk[k];
+        for (int j = tid; j < n; j += nthr)
+            if (j != k) A[k * n + j] *= rd;
+        __syncthreads();
+        for (int q = tid; q < n * n; q += nthr) {
+            const int i = q / n, j = q - (q / n) * n;
+            if (i == k) continue;
+            if (j != k) A[q] -= colk[i] * A[k * n + j];
+            else A[q] = -colk[i] * rd;
+        }
+        __syncthreads();
+        if (tid == 0) A[k * n + k] = rd;
+        __syncthreads();
+    }
+    for (int q = tid; q < n * n; q += nthr) Mg[q] = A[q];
+}
+
+__global__ __launch_bounds__(1024) void k_gauss_jordan_lds(double* const* __restrict__ mats,
+                                                          const int* __restrict__ ns) {
+    extern __shared__ double lds[];
+    const int n = ns[blockIdx.x];
+    gauss_jordan_lds(mats[blockIdx.x], n, lds, lds + (size_t)n * n);
+}
+
 template <typename T>
 __global__ __launch_bounds__(1024) void k_coarse_solve(Geom g, const double* __restrict__ Minv,
                                                       const T* __restrict__ rx, const T* __restrict__ ry,
@@ -161,7 +196,37 @@ hipError_t launch_coarse_assemble(const Geom& g, const double* eb, const double*
     return hipGetLastError();
 }
 
-hipError_t launch_gauss_jordan(double* M, int n, hipStream_t st) {
+size_t gauss_jordan_lds_bytes(int n) { return ((size_t)n * n + n) * sizeof(double); }
+
+hipError_t launch_gauss_jordan_batched(double* const* mats, const int* ns, int count, int nmax, hipStream_t st) {
+    const size_t lds = gauss_jordan_lds_bytes(nmax);
+    if (nmax > kGJLds) return hipErrorInvalidValue;
+    static thread_local int dev_cached = -1;
+    static thread_local size_t granted = 64 * 1024;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return hipGetLastError();
+    if (dev != dev_cached) {
+        dev_cached = dev;
+        granted = 64 * 1024;
+    }
+    if (lds > granted) {
+        const hipError_t e = hipFuncSetAttribute((const void*)k_gauss_jordan_lds,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return e;
+        }
+        granted = lds;
+    }
+    hipLaunchKernelGGL(k_gauss_jordan_lds, dim3(count), dim3(1024), lds, st, mats, ns);
+    return hipGetLastError();
+}
+
+hipError_t launch_gauss_jordan(double* M, int n, hipStream_t st, double** table) {
+    if (n <= kGJLds && table) {
+        // table: device scratch of one pointer and one int (owned by the caller)
+        return launch_gauss_jordan_batched(table, (const int*)(table + 1), 1, n, st);
+    }
     hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), (size_t)n * sizeof(double), st, M, n);
     return hipGetLastError();
 }

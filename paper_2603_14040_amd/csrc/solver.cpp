@@ -81,6 +81,7 @@ struct tph_solver {
     int nlev = 0;
     LevelBuf lev[kMaxLevels];
     double* Minv = nullptr;
+    double** gj_table = nullptr; // device {Minv, ncoarse} for the LDS Gauss-Jordan (null: ncoarse too large)
     int ncoarse = 0;
     int lc = -1;                 // first level handled by the single-workgroup coarse kernel (-1: none)
     unsigned msw_mask = 0;       // levels smoothed in multi-sweep passes (resolved desc.msweep)
@@ -816,6 +817,12 @@ tph_status create_impl(const tph_desc* desc, void* stream, tph_solver* s) {
         }
     }
     TPH_TRY(dev_alloc(s, (void**)&s->Minv, (size_t)s->ncoarse * s->ncoarse * sizeof(double)));
+    if (s->ncoarse <= kGJLds) {
+        struct { double* m; int n; int pad; } tab{s->Minv, s->ncoarse, 0};
+        TPH_TRY(dev_alloc(s, (void**)&s->gj_table, sizeof(tab)));
+        TPH_HIP(hipMemcpyAsync(s->gj_table, &tab, sizeof(tab), hipMemcpyHostToDevice, s->st));
+        TPH_HIP(hipStreamSynchronize(s->st));
+    }
     TPH_HIP(hipHostMalloc((void**)&s->hscal, kScalars * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent));
     TPH_HIP(hipHostGetDevicePointer((void**)&s->hscal_dev, s->hscal, 0));
     TPH_HIP(hipHostMalloc((void**)&s->hseq, 64, hipHostMallocMapped | hipHostMallocCoherent));
@@ -908,9 +915,75 @@ tph_status time_kernel_t(tph_solver* s, int kind, int reps, double* ms, double* 
     return TPH_OK;
 }
 
+// Coefficient setup in two halves: enqueue every step on the solver's stream
+// (the coarsest factorisation only with `factor`; a batch factors all its
+// problems in one launch), then wait and check.  The validity counts are
+// written by the reduction straight into the mapped host block.
+tph_status setup_enqueue(tph_solver* s, const double* eta_b, const double* eta_p, const double* rho_b, double gx,
+                         double gy, const double* fx_extra, const double* fy_extra, bool factor) {
+    if (!s) { set_error("solver is NULL"); return TPH_ERR_INVALID; }
+    if (!eta_b || !eta_p || !rho_b) { set_error("eta_b, eta_p and rho_b are required"); return TPH_ERR_INVALID; }
+    if (!std::isfinite(gx) || !std::isfinite(gy)) { set_error("gravity must be finite"); return TPH_ERR_INVALID; }
+    s->ready = false;
+    const Geom& g0 = s->lev[0].g;
+    TPH_HIP(hipEventRecord(s->ev0, s->st));
+    TPH_TRY(copy_in(s, g0, s->lev[0].eb64, eta_b));
+    TPH_TRY(copy_in(s, g0, s->lev[0].ep64, eta_p));
+    TPH_TRY(copy_in(s, g0, s->rho, rho_b));
+    s->has_fx = fx_extra != nullptr;
+    s->has_fy = fy_extra != nullptr;
+    if (fx_extra) TPH_TRY(copy_in(s, g0, s->fxe, fx_extra));
+    if (fy_extra) TPH_TRY(copy_in(s, g0, s->fye, fy_extra));
+    int nblk = 0;
+    TPH_HIP(launch_check_coeffs(g0, s->lev[0].eb64, s->lev[0].ep64, s->rho, s->has_fx ? s->fxe : nullptr,
+                                s->has_fy ? s->fye : nullptr, s->partial, &nblk, s->st));
+    TPH_HIP(launch_reduce_rows(s->partial, nblk, 2, s->dscal + kSlotMisc + 2, s->st, s->hscal_dev + kSlotMisc + 2));
+    s->gx = gx;
+    s->gy = gy;
+    TPH_HIP(launch_rhs(g0, s->rho, gx, gy, s->has_fx ? s->fxe : nullptr, s->has_fy ? s->fye : nullptr,
+                       vec3(s, s->b), s->st));
+    for (int l = 1; l < s->nlev; ++l)
+        TPH_HIP(launch_restrict_eta(s->lev[l - 1].g, s->lev[l].g, s->lev[l - 1].eb64, s->lev[l - 1].ep64,
+                                    s->lev[l].eb64, s->lev[l].ep64, s->d.eta_mean == TPH_MEAN_GEOMETRIC, s->st));
+    if (s->mixed()) {
+        for (int l = 0; l < s->nlev; ++l) {
+            const size_t n = field_alloc(s->lev[l].g);
+            TPH_HIP(launch_cast_f64_f32(s->lev[l].eb64 - (kAlign - 1), (float*)s->lev[l].eb - (kAlign - 1), n, s->st));
+            TPH_HIP(launch_cast_f64_f32(s->lev[l].ep64 - (kAlign - 1), (float*)s->lev[l].ep - (kAlign - 1), n, s->st));
+        }
+    }
+    const LevelBuf& C = s->lev[s->nlev - 1];
+    TPH_HIP(launch_coarse_assemble(C.g, C.eb64, C.ep64, s->Minv, s->st));
+    if (factor) TPH_HIP(launch_gauss_jordan(s->Minv, s->ncoarse, s->st, s->gj_table));
+    TPH_HIP(hipEventRecord(s->ev1, s->st));
+    return TPH_OK;
+}
+
+tph_status setup_finish(tph_solver* s) {
+    TPH_HIP(hipStreamSynchronize(s->st));
+    float ms = 0.f;
+    TPH_HIP(hipEventElapsedTime(&ms, s->ev0, s->ev1));
+    s->t_setup_ms = ms;
+    if (s->hscal[kSlotMisc + 2] != 0.0) {
+        set_error("viscosity must be finite and positive (" + std::to_string((long long)s->hscal[kSlotMisc + 2]) +
+                  " bad entries)");
+        return TPH_ERR_INVALID;
+    }
+    if (s->hscal[kSlotMisc + 3] != 0.0) { set_error("density or extra force is not finite"); return TPH_ERR_NONFINITE; }
+    s->ready = true;
+    return TPH_OK;
+}
+
 }  // namespace
 
 // ============================================================ internal view
+tph_status tph_internal_setup_enqueue(tph_solver* s, const double* eta_b, const double* eta_p, const double* rho_b,
+                                      double gx, double gy) {
+    return setup_enqueue(s, eta_b, eta_p, rho_b, gx, gy, nullptr, nullptr, false);
+}
+
+tph_status tph_internal_setup_finish(tph_solver* s) { return setup_finish(s); }
+
 TphSolverView tph_internal_view(const tph_solver* s) {
     TphSolverView v{};
     v.nlev = s->nlev;
@@ -1006,53 +1079,8 @@ tph_status tph_create(const tph_desc* desc, void* hip_stream, tph_solver** out) 
 tph_status tph_set_coefficients(tph_solver* s, const double* eta_b, const double* eta_p, const double* rho_b,
                                 double gx, double gy, const double* fx_extra, const double* fy_extra) {
     g_last_error.clear();
-    if (!s) { set_error("solver is NULL"); return TPH_ERR_INVALID; }
-    if (!eta_b || !eta_p || !rho_b) { set_error("eta_b, eta_p and rho_b are required"); return TPH_ERR_INVALID; }
-    if (!std::isfinite(gx) || !std::isfinite(gy)) { set_error("gravity must be finite"); return TPH_ERR_INVALID; }
-    s->ready = false;
-    const Geom& g0 = s->lev[0].g;
-    TPH_HIP(hipEventRecord(s->ev0, s->st));
-    TPH_TRY(copy_in(s, g0, s->lev[0].eb64, eta_b));
-    TPH_TRY(copy_in(s, g0, s->lev[0].ep64, eta_p));
-    TPH_TRY(copy_in(s, g0, s->rho, rho_b));
-    s->has_fx = fx_extra != nullptr;
-    s->has_fy = fy_extra != nullptr;
-    if (fx_extra) TPH_TRY(copy_in(s, g0, s->fxe, fx_extra));
-    if (fy_extra) TPH_TRY(copy_in(s, g0, s->fye, fy_extra));
-    int nblk = 0;
-    TPH_HIP(launch_check_coeffs(g0, s->lev[0].eb64, s->lev[0].ep64, s->rho, s->has_fx ? s->fxe : nullptr,
-                                s->has_fy ? s->fye : nullptr, s->partial, &nblk, s->st));
-    TPH_HIP(launch_reduce_rows(s->partial, nblk, 2, s->dscal + kSlotMisc + 2, s->st));
-    s->gx = gx;
-    s->gy = gy;
-    TPH_HIP(launch_rhs(g0, s->rho, gx, gy, s->has_fx ? s->fxe : nullptr, s->has_fy ? s->fye : nullptr,
-                       vec3(s, s->b), s->st));
-    for (int l = 1; l < s->nlev; ++l)
-        TPH_HIP(launch_restrict_eta(s->lev[l - 1].g, s->lev[l].g, s->lev[l - 1].eb64, s->lev[l - 1].ep64,
-                                    s->lev[l].eb64, s->lev[l].ep64, s->d.eta_mean == TPH_MEAN_GEOMETRIC, s->st));
-    if (s->mixed()) {
-        for (int l = 0; l < s->nlev; ++l) {
-            const size_t n = field_alloc(s->lev[l].g);
-            TPH_HIP(launch_cast_f64_f32(s->lev[l].eb64 - (kAlign - 1), (float*)s->lev[l].eb - (kAlign - 1), n, s->st));
-            TPH_HIP(launch_cast_f64_f32(s->lev[l].ep64 - (kAlign - 1), (float*)s->lev[l].ep - (kAlign - 1), n, s->st));
-        }
-    }
-    const LevelBuf& C = s->lev[s->nlev - 1];
-    TPH_HIP(launch_coarse_assemble(C.g, C.eb64, C.ep64, s->Minv, s->st));
-    TPH_HIP(launch_gauss_jordan(s->Minv, s->ncoarse, s->st));
-    TPH_HIP(hipEventRecord(s->ev1, s->st));
-    TPH_TRY(fetch(s, kSlotMisc + 2, 2));
-    float ms = 0.f;
-    TPH_HIP(hipEventElapsedTime(&ms, s->ev0, s->ev1));
-    s->t_setup_ms = ms;
-    if (s->hscal[kSlotMisc + 2] != 0.0) {
-        set_error("viscosity must be finite and positive (" + std::to_string((long long)s->hscal[kSlotMisc + 2]) +
-                  " bad entries)");
-        return TPH_ERR_INVALID;
-    }
-    if (s->hscal[kSlotMisc + 3] != 0.0) { set_error("density or extra force is not finite"); return TPH_ERR_NONFINITE; }
-    s->ready = true;
-    return TPH_OK;
+    TPH_TRY(setup_enqueue(s, eta_b, eta_p, rho_b, gx, gy, fx_extra, fy_extra, true));
+    return setup_finish(s);
 }
 
 tph_status tph_solve(tph_solver* s, double* vx, double* vy, double* p, tph_info* info) {

@@ -36,5 +36,11 @@ TphSolverView tph_internal_view(const tph_solver* s);
 void tph_internal_set_error(const std::string& msg);
 // copy an initial guess in (walls zeroed, ghosts mirrored)
 tph_status tph_internal_load_solution(tph_solver* s, const double* vx, const double* vy, const double* p);
+// coefficient setup of one problem, enqueued on its stream without the
+// coarsest factorisation (the batch factors every problem in one launch),
+// and its completion (waits for the stream, checks the coefficients)
+tph_status tph_internal_setup_enqueue(tph_solver* s, const double* eta_b, const double* eta_p, const double* rho_b,
+                                      double gx, double gy);
+tph_status tph_internal_setup_finish(tph_solver* s);
 // remove the pressure mean of the solution and copy it out
 tph_status tph_internal_finish_solution(tph_solver* s, double* vx, double* vy, double* p);
