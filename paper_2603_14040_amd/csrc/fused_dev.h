@@ -619,9 +619,15 @@ struct LGeo {            // a level inside LDS: tight pitch nx + 2
     T idx, idy, idx2, idy2;
 };
 
-// Loops of the coarse tail map threads to rows: 64 consecutive threads
-// share a row (32 for the colour sweeps, which take every other node), so
-// node indices come from shifts instead of divisions by a runtime width.
+// Loops of the coarse tail map threads to rows: 2^s consecutive threads
+// share a row, with 2^s the smallest power of two covering the row (at most
+// 64), so every lane of a wave has work on small levels and node indices come
+// from shifts instead of divisions by a runtime width.
+__device__ __forceinline__ int lanes_log2(int width) {
+    int s = 0;
+    while ((1 << s) < width && s < 6) ++s;
+    return s;
+}
 
 // one Gauss-Seidel colour half-sweep of component comp, in place
 template <typename T>
@@ -630,10 +636,12 @@ __device__ void cc_gs_half(const LGeo<T>& L, const LevelC<T>& k, int comp, int c
     const int ncol = comp == 0 ? L.nx - 1 : L.nx;
     const int nrow = comp == 0 ? L.ny : L.ny - 1;
     const int tid = threadIdx.x;
-    for (int i = 1 + (tid >> 5); i <= nrow; i += blockDim.x >> 5) {
+    const int ls = lanes_log2((ncol + 1) >> 1);          // lanes per row: one node of the colour each
+    const int lm = (1 << ls) - 1;
+    for (int i = 1 + (tid >> ls); i <= nrow; i += blockDim.x >> ls) {
         // first column of colour col in row i: (i + j) & 1 == col
         const int j0 = 1 + (((i + 1) & 1) != col ? 1 : 0);
-        for (int j = j0 + 2 * (tid & 31); j <= ncol; j += 64) {
+        for (int j = j0 + 2 * (tid & lm); j <= ncol; j += 2 << ls) {
             const int c = i * L.P + j;
             if (comp == 0) {
                 const T d = lx_diag(eb, ep, c, L.P, i, L.ny, k);
@@ -706,7 +714,14 @@ __device__ __forceinline__ void coarse_cycle_body(const CoarseArgs<T>& A) {
     __shared__ int foff[kMaxLevels];
     __shared__ int s_top_off;
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const int rt = tid >> 6, rs_ = nthr >> 6, ct = tid & 63;   // row-parallel mapping
+    // row-parallel mapping for a row of `w` entries: (row, column, row stride, column stride)
+    auto rowmap = [&](int w, int& r0, int& rstep, int& c0, int& cstep) {
+        const int ls = lanes_log2(w);
+        r0 = tid >> ls;
+        rstep = nthr >> ls;
+        c0 = tid & ((1 << ls) - 1);
+        cstep = 1 << ls;
+    };
     if (tid == 0) {
         int off = 0;
         for (int l = 0; l < nl; ++l) {
@@ -735,8 +750,10 @@ __device__ __forceinline__ void coarse_cycle_body(const CoarseArgs<T>& A) {
         const T* geb = A.eb[l];
         const T* gep = A.ep[l];
         T *ex = F(l, 0), *ey = F(l, 1), *rx = F(l, 2), *ry = F(l, 3), *eb = F(l, 4), *ep = F(l, 5);
+        int rt, rs_, ct, cs_;
+        rowmap(P, rt, rs_, ct, cs_);
         for (int i = rt; i < L[l].ny + 2; i += rs_) {
-            for (int j = ct; j < P; j += 64) {
+            for (int j = ct; j < P; j += cs_) {
                 const int q = i * P + j, cg = i * Pg + j;
                 ex[q] = (T)0;
                 ey[q] = (T)0;
@@ -768,8 +785,10 @@ __device__ __forceinline__ void coarse_cycle_body(const CoarseArgs<T>& A) {
         smooth(l, A.nu_pre[l]);
         const LGeo<T>& G = L[l];
         T *ex = F(l, 0), *ey = F(l, 1), *rx = F(l, 2), *ry = F(l, 3), *eb = F(l, 4), *ep = F(l, 5);
+        int rt, rs_, ct, cs_;
+        rowmap(G.P, rt, rs_, ct, cs_);
         for (int i = rt; i < G.ny + 2; i += rs_) {
-            for (int j = ct; j < G.P; j += 64) {
+            for (int j = ct; j < G.P; j += cs_) {
                 const int q = i * G.P + j;
                 const bool vx = i >= 1 && i <= G.ny && j >= 1 && j < G.nx;
                 const bool vy = i >= 1 && i < G.ny && j >= 1 && j <= G.nx;
@@ -780,8 +799,9 @@ __device__ __forceinline__ void coarse_cycle_body(const CoarseArgs<T>& A) {
         __syncthreads();
         const LGeo<T>& C = L[l + 1];
         T *rcx = F(l + 1, 2), *rcy = F(l + 1, 3);
+        rowmap(C.nx, rt, rs_, ct, cs_);
         for (int I = 1 + rt; I <= C.ny; I += rs_) {
-            for (int J = 1 + ct; J <= C.nx; J += 64) {
+            for (int J = 1 + ct; J <= C.nx; J += cs_) {
                 const int Cc = I * C.P + J;
                 if (J < C.nx) {
                     T s = (T)0, wy = (T)0;
@@ -863,8 +883,10 @@ __device__ __forceinline__ void coarse_cycle_body(const CoarseArgs<T>& A) {
         const LGeo<T>& C = L[l + 1];
         T *ex = F(l, 0), *ey = F(l, 1);
         const T *ecx = F(l + 1, 0), *ecy = F(l + 1, 1);
+        int rt, rs_, ct, cs_;
+        rowmap(G.nx, rt, rs_, ct, cs_);
         for (int i = 1 + rt; i <= G.ny; i += rs_) {
-            for (int j = 1 + ct; j <= G.nx; j += 64) {
+            for (int j = 1 + ct; j <= G.nx; j += cs_) {
                 const int c = i * G.P + j;
                 if (j < G.nx) {
                     const T e = ex[c] + prolong_vx(ecx, C.P, i, j);
@@ -890,8 +912,10 @@ __device__ __forceinline__ void coarse_cycle_body(const CoarseArgs<T>& A) {
         const int Pg = A.g[0].pitch;
         const T* sx = F(0, 0);
         const T* sy = F(0, 1);
+        int rt, rs_, ct, cs_;
+        rowmap(P, rt, rs_, ct, cs_);
         for (int i = rt; i < L[0].ny + 2; i += rs_) {
-            for (int j = ct; j < P; j += 64) {
+            for (int j = ct; j < P; j += cs_) {
                 A.ex[i * Pg + j] = sx[i * P + j];
                 A.ey[i * Pg + j] = sy[i * P + j];
             }
