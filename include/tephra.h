@@ -191,6 +191,16 @@ tph_status tph_apply(tph_solver* s, const double* vx, const double* vy, const do
 tph_status tph_precondition(tph_solver* s, const double* rx, const double* ry, const double* rp,
                             double* zx, double* zy, double* zp);
 
+/* z = M^{-1} r exactly as tph_precondition, and w = A z, in one sequence:
+ * the exit of every Uzawa step is a single pass over the grid that also
+ * forms the next step's right-hand side, and the last one forms w, the
+ * product an outer Krylov method needs next (Sec. "Uzawa Iteration as a
+ * Fixed Point Method", Sec. "Comparison with FGMRES").  Arrays as in
+ * tph_precondition (inputs) and tph_apply (w: zero outside the equation
+ * rows). */
+tph_status tph_precondition_apply(tph_solver* s, const double* rx, const double* ry, const double* rp,
+                                  double* zx, double* zy, double* zp, double* wx, double* wy, double* wp);
+
 /* Relative energy residual of (vx, vy, p) for the right-hand side of
  * tph_set_coefficients (Sec. "Global Relative Energy Residual"). */
 tph_status tph_energy_residual(tph_solver* s, const double* vx, const double* vy,

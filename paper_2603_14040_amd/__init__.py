@@ -179,6 +179,16 @@ class Solver:
                                                     self._p(ax, "ax"), self._p(ay, "ay"), self._p(ap, "ap")))
         return ax, ay, ap
 
+    def precondition_apply(self, rx, ry, rp):
+        """(z, w) with z = M^{-1} r and w = A z (tph_precondition_apply)."""
+        z = (self.zeros(), self.zeros(), self.zeros())
+        w = (self.zeros(), self.zeros(), self.zeros())
+        self._sync_in()
+        _lib.check("tph_precondition_apply", self._lib.tph_precondition_apply(
+            self._h, self._p(rx, "rx"), self._p(ry, "ry"), self._p(rp, "rp"), *[self._p(t, "z") for t in z],
+            *[self._p(t, "w") for t in w]))
+        return z, w
+
     def precondition(self, rx, ry, rp):
         zx, zy, zp = self.zeros(), self.zeros(), self.zeros()
         self._sync_in()

@@ -76,6 +76,7 @@ def load(path: str = LIB_PATH):
         "tph_solve_rhs": (c_int32, [P, P, P, P, P, P, P, POINTER(Info)]),
         "tph_apply": (c_int32, [P, P, P, P, P, P, P]),
         "tph_precondition": (c_int32, [P, P, P, P, P, P, P]),
+        "tph_precondition_apply": (c_int32, [P, P, P, P, P, P, P, P, P, P]),
         "tph_energy_residual": (c_int32, [P, P, P, P, POINTER(c_double)]),
         "tph_level_viscosity": (c_int32, [P, c_int32, P, P]),
         "tph_level_shape": (c_int32, [P, c_int32, POINTER(c_int32), POINTER(c_int32)]),

@@ -39,6 +39,13 @@ hipError_t launch_precond_in(const Geom& g, Vec3 v, const double* eb, const doub
 // preconditioner exit: z_v = (double) e; z_p = alpha eta_p (r_p - D z_v)
 // (accumulate: z_v += e, z_p += alpha eta_p (r_p - D e))
 template <typename T>
+struct LinkArgs;
+// one pass linking two Uzawa steps (apply = false) or the last step and the
+// Krylov apply (apply = true); see uzawa_link_cell
+template <typename T>
+hipError_t launch_uzawa_link(const Geom& g, const LinkArgs<T>& a, bool apply, const double* eb, const double* ep,
+                             hipStream_t st);
+template <typename T>
 hipError_t launch_precond_out(const Geom& g, const T* ex, const T* ey, Vec3 v, const double* ep,
                               bool energy, double alpha, Vec3 z, hipStream_t st, bool accumulate = false);
 // right-hand side f = -rho g (+ extra) at velocity rows, 0 at continuity rows

@@ -26,6 +26,7 @@
 #include "common.h"
 #include "kernels.h"
 #include "solver_internal.h"
+#include "stencil_dev.h"
 
 using namespace tph;
 
@@ -445,13 +446,46 @@ tph_status vcycle_fused(tph_solver* s, int l, int* cur_out) {
 
 // z = M^{-1} v applied uzawa_steps times as a stationary iteration from z = 0:
 // step 1: z = M^{-1} r; step k: z += M^{-1} (r - A z).  `energy`: v holds
-// W^(1/2) r (a Krylov basis vector).
+// W^(1/2) r (a Krylov basis vector).  With wraw (the Krylov apply inside
+// FGMRES), each step's exit is one link pass: the last one also forms
+// w = W^(-1/2) A z into wraw, the others the next step's right-hand side;
+// z alternates between zraw and t1 (the last step writes zraw), the
+// pressure residual between t3 and t2.
 template <typename T>
-tph_status precondition_t(tph_solver* s, double* vraw, double* zraw, bool energy) {
+tph_status precondition_t(tph_solver* s, double* vraw, double* zraw, bool energy, double* wraw) {
     LevelBuf& L = s->lev[0];
     const Vec3 v = vec3(s, vraw), z = vec3(s, zraw);
     const bool fused = s->d.fused == 1;
-    for (int step = 0; step < s->d.uzawa_steps; ++step) {
+    const int S = s->d.uzawa_steps;
+    if (wraw) {
+        const Vec3 zb[2] = {z, vec3(s, s->t1)};
+        double* tpb[2] = {vec3(s, s->t3).p(), vec3(s, s->t2).p()};
+        TPH_HIP(launch_precond_in<T>(L.g, v, L.eb64, L.ep64, energy, as<T>(L.rx), as<T>(L.ry), s->st));
+        for (int q = 0; q < S; ++q) {
+            int cur = 0;
+            if (fused) TPH_TRY(vcycle_fused<T>(s, 0, &cur));
+            else TPH_TRY(vcycle<T>(s, 0, &cur));
+            LinkArgs<T> a{};
+            a.ex = as<T>(L.ex[cur]);
+            a.ey = as<T>(L.ey[cur]);
+            a.zold = zb[(S - q) & 1];
+            a.acc = q > 0 ? 1 : 0;
+            a.srcp = q == 0 ? v.p() : tpb[(q - 1) & 1];
+            a.src_scaled = (q == 0 && energy) ? 1 : 0;
+            a.alpha = s->d.alpha;
+            a.zout = zb[(S - 1 - q) & 1];
+            a.r = v;
+            a.r_scaled = energy ? 1 : 0;
+            a.rx = as<T>(L.rx);
+            a.ry = as<T>(L.ry);
+            a.tp = tpb[q & 1];
+            a.wout = vec3(s, wraw);
+            a.w_scaled = energy ? 1 : 0;
+            TPH_HIP(launch_uzawa_link<T>(L.g, a, q == S - 1, L.eb64, L.ep64, s->st));
+        }
+        return TPH_OK;
+    }
+    for (int step = 0; step < S; ++step) {
         Vec3 src = v;
         bool src_scaled = energy;
         if (step > 0) {
@@ -472,8 +506,9 @@ tph_status precondition_t(tph_solver* s, double* vraw, double* zraw, bool energy
     return TPH_OK;
 }
 
-tph_status precondition(tph_solver* s, double* vraw, double* zraw, bool energy) {
-    return s->mixed() ? precondition_t<float>(s, vraw, zraw, energy) : precondition_t<double>(s, vraw, zraw, energy);
+tph_status precondition(tph_solver* s, double* vraw, double* zraw, bool energy, double* wraw = nullptr) {
+    return s->mixed() ? precondition_t<float>(s, vraw, zraw, energy, wraw)
+                      : precondition_t<double>(s, vraw, zraw, energy, wraw);
 }
 
 // reduce partial rows into `k` device scalars at slot; with to_host the same
@@ -617,10 +652,8 @@ tph_status fgmres(tph_solver* s, double* braw, tph_info* info) {
         gv[0] = beta;
         int jdone = 0;
         for (int j = 0; j < m; ++j) {
-            TPH_TRY(precondition(s, Vk(j), Zk(j), true));
-            const LevelBuf& L = s->lev[0];
-            TPH_HIP(launch_outer_residual(L.g, vec3(s, Zk(j)), nullptr, L.eb64, L.ep64, vec3(s, Vk(j + 1)),
-                                          ResMode::kApply, true, nullptr, nullptr, s->st));
+            // z_j = M^{-1} v_j and w = W^(-1/2) A z_j (the apply fused into the last Uzawa step's exit)
+            TPH_TRY(precondition(s, Vk(j), Zk(j), true, Vk(j + 1)));
             double* w = Vk(j + 1);
             // classical Gram-Schmidt with selective re-orthogonalisation: one
             // projection pass, and a second only when the norm drops below
@@ -1119,6 +1152,30 @@ tph_status tph_apply(tph_solver* s, const double* vx, const double* vy, const do
     TPH_HIP(launch_outer_residual(L.g, vec3(s, s->t2), nullptr, L.eb64, L.ep64, vec3(s, s->t1), ResMode::kApply,
                                   false, nullptr, nullptr, s->st));
     TPH_TRY(store_solution(s, s->t1, ax, ay, ap));
+    TPH_HIP(hipStreamSynchronize(s->st));
+    return TPH_OK;
+}
+
+tph_status tph_precondition_apply(tph_solver* s, const double* rx, const double* ry, const double* rp, double* zx,
+                                  double* zy, double* zp, double* wx, double* wy, double* wp) {
+    g_last_error.clear();
+    TPH_TRY(require_ready(s));
+    if (!rx || !ry || !rp || !zx || !zy || !zp || !wx || !wy || !wp) {
+        set_error("all nine arrays are required");
+        return TPH_ERR_INVALID;
+    }
+    const Geom& g = s->lev[0].g;
+    Vec3 r = vec3(s, s->b2);
+    TPH_TRY(copy_in(s, g, r.vx(), rx));
+    TPH_TRY(copy_in(s, g, r.vy(), ry));
+    TPH_TRY(copy_in(s, g, r.p(), rp));
+    // z and w in the Krylov workspace, free outside a solve
+    double* zb = s->V;
+    double* wb = s->V + s->n3;
+    TPH_HIP(hipMemsetAsync(zb, 0, 2 * s->n3 * sizeof(double), s->st));
+    TPH_TRY(precondition(s, s->b2, zb, false, wb));
+    TPH_TRY(store_solution(s, zb, zx, zy, zp));
+    TPH_TRY(store_solution(s, wb, wx, wy, wp));
     TPH_HIP(hipStreamSynchronize(s->st));
     return TPH_OK;
 }

@@ -182,6 +182,14 @@ __global__ __launch_bounds__(256) void k_precond_out(Geom g, const T* __restrict
     precond_out_cell<T>(g, ex, ey, v, ep, energy, alpha, z, acc, i, j);
 }
 
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_uzawa_link(Geom g, LinkArgs<T> a, const double* __restrict__ eb,
+                                                   const double* __restrict__ ep) {
+    const int j = blockIdx.x * BX + threadIdx.x + 1;
+    const int i = blockIdx.y * BY + threadIdx.y + 1;
+    uzawa_link_cell<T, MODE>(g, a, eb, ep, i, j);
+}
+
 __global__ __launch_bounds__(256) void k_rhs(Geom g, const double* __restrict__ rho, double gx, double gy,
                                             const double* __restrict__ fxe, const double* __restrict__ fye,
                                             Vec3 b) {
@@ -367,6 +375,16 @@ hipError_t launch_precond_out(const Geom& g, const T* ex, const T* ey, Vec3 v, c
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_uzawa_link(const Geom& g, const LinkArgs<T>& a, bool apply, const double* eb, const double* ep,
+                             hipStream_t st) {
+    if (apply)
+        hipLaunchKernelGGL((k_uzawa_link<T, kLinkApply>), grid_cells(g), dim3(BX, BY), 0, st, g, a, eb, ep);
+    else
+        hipLaunchKernelGGL((k_uzawa_link<T, kLinkNext>), grid_cells(g), dim3(BX, BY), 0, st, g, a, eb, ep);
+    return hipGetLastError();
+}
+
 hipError_t launch_rhs(const Geom& g, const double* rho, double gx, double gy, const double* fxe,
                       const double* fye, Vec3 b, hipStream_t st) {
     hipLaunchKernelGGL(k_rhs, grid_cells(g), dim3(BX, BY), 0, st, g, rho, gx, gy, fxe, fye, b);
@@ -413,7 +431,9 @@ hipError_t launch_cast_f64_f32(const double* src, float* dst, size_t n, hipStrea
     template hipError_t launch_precond_in<T>(const Geom&, Vec3, const double*, const double*, bool, T*, T*,  \
                                              hipStream_t);                                                   \
     template hipError_t launch_precond_out<T>(const Geom&, const T*, const T*, Vec3, const double*, bool,    \
-                                              double, Vec3, hipStream_t, bool);
+                                              double, Vec3, hipStream_t, bool);                              \
+    template hipError_t launch_uzawa_link<T>(const Geom&, const LinkArgs<T>&, bool, const double*,           \
+                                             const double*, hipStream_t);
 TPH_INST(float)
 TPH_INST(double)
 #undef TPH_INST

@@ -105,4 +105,128 @@ __device__ __forceinline__ void precond_out_cell(const Geom& g, const T* __restr
     z.p()[c] = acc ? z.p()[c] + dp : dp;
 }
 
+// ---------------------------------------------------------------------------
+// Link between two Uzawa steps of the preconditioner (or its last step and
+// the Krylov apply), one pass per cell.  With e the V-cycle correction of
+// this step and s the step's source (the preconditioner input r at the first
+// step, energy-scaled or not; the residual t of the previous step after it):
+//   z_new = z_old + e,  z_new_p = z_old_p + alpha eta_p (s_p - D e)
+// (z_old = 0 at the first step), written to zout, then either
+//   kLinkNext:  t = r - A z_new  -> FP32/FP64 right-hand side of the next
+//               V-cycle (velocity) and tp (FP64 pressure part), or
+//   kLinkApply: w = A z_new (energy-scaled for a Krylov basis) into wout.
+// z_new at the neighbouring nodes the stencil needs is recomputed from e and
+// z_old there (both carry mirrored ghosts and zero walls), so no pass
+// waits for another; zout and zold must be different arrays.
+// ---------------------------------------------------------------------------
+enum { kLinkNext = 0, kLinkApply = 1 };
+
+template <typename T>
+struct LinkArgs {
+    const T* ex;            // V-cycle correction (FP32 or FP64)
+    const T* ey;
+    Vec3 zold;              // previous z (ignored at the first step)
+    int acc;                // 0 at the first step
+    const double* srcp;     // pressure part of the step's source
+    int src_scaled;         // source energy-scaled (first step inside FGMRES)
+    double alpha;
+    Vec3 zout;
+    Vec3 r;                 // preconditioner input (for kLinkNext)
+    int r_scaled;
+    T* rx;                  // kLinkNext: next right-hand side
+    T* ry;
+    double* tp;
+    Vec3 wout;              // kLinkApply
+    int w_scaled;           // kLinkApply: w = W^(-1/2) A z (Krylov basis scaling) instead of A z
+};
+
+template <typename T>
+__device__ __forceinline__ double link_zx(const LinkArgs<T>& a, int c) {
+    return (a.acc ? a.zold.vx()[c] : 0.0) + (double)a.ex[c];
+}
+template <typename T>
+__device__ __forceinline__ double link_zy(const LinkArgs<T>& a, int c) {
+    return (a.acc ? a.zold.vy()[c] : 0.0) + (double)a.ey[c];
+}
+template <typename T>
+__device__ __forceinline__ double link_zp(const LinkArgs<T>& a, const double* __restrict__ ep, int c, int P,
+                                          const LevelC<double>& k) {
+    const double div = ((double)a.ex[c] - (double)a.ex[c - 1]) * k.idx + ((double)a.ey[c] - (double)a.ey[c - P]) * k.idy;
+    double sp = a.srcp[c];
+    if (a.src_scaled) sp *= 1.0 / sqrt(wp_weight(ep[c], k));
+    return (a.acc ? a.zold.p()[c] : 0.0) + a.alpha * ep[c] * (sp - div);
+}
+
+template <typename T, int MODE>
+__device__ __forceinline__ void uzawa_link_cell(const Geom& g, const LinkArgs<T>& a, const double* __restrict__ eb,
+                                                const double* __restrict__ ep, int i, int j) {
+    if (i > g.ny || j > g.nx) return;
+    const LevelC<double> k = level_consts<double>(g);
+    const int P = g.pitch;
+    const int c = i * P + j;
+    // 3 x 3 patches of z_new velocities and of the viscosities around (i, j)
+    double zx[9], zy[9], pb[9], pe[9];
+#pragma unroll
+    for (int di = -1; di <= 1; ++di) {
+#pragma unroll
+        for (int dj = -1; dj <= 1; ++dj) {
+            const int q = (di + 1) * 3 + (dj + 1), cc = c + di * P + dj;
+            zx[q] = link_zx(a, cc);
+            zy[q] = link_zy(a, cc);
+            pb[q] = eb[cc];
+            pe[q] = ep[cc];
+        }
+    }
+    const double zpc = link_zp(a, ep, c, P, k);
+    // this cell's z_new (with ghost mirrors of wall-adjacent values)
+    if (j < g.nx) {
+        a.zout.vx()[c] = zx[4];
+        if (i == 1) a.zout.vx()[c - P] = (double)g.mir[2] * zx[4];
+        if (i == g.ny) a.zout.vx()[c + P] = (double)g.mir[3] * zx[4];
+    }
+    if (i < g.ny) {
+        a.zout.vy()[c] = zy[4];
+        if (j == 1) a.zout.vy()[c - 1] = (double)g.mir[0] * zy[4];
+        if (j == g.nx) a.zout.vy()[c + 1] = (double)g.mir[1] * zy[4];
+    }
+    a.zout.p()[c] = zpc;
+    const double* X = zx + 4;
+    const double* Y = zy + 4;
+    const double* B = pb + 4;
+    const double* E = pe + 4;
+    if (j < g.nx) {
+        const double av = lx_row(X, Y, B, E, 0, 3, k.idx, k.idy) - (link_zp(a, ep, c + 1, P, k) - zpc) * k.idx;
+        const double sq = sqrt(-lx_diag(B, E, 0, 3, i, g.ny, k));
+        if (MODE == kLinkNext) {
+            double rv = a.r.vx()[c];
+            if (a.r_scaled) rv *= sq;
+            a.rx[c] = (T)(rv - av);
+        } else {
+            a.wout.vx()[c] = a.w_scaled ? av / sq : av;
+        }
+    }
+    if (i < g.ny) {
+        const double av = ly_row(X, Y, B, E, 0, 3, k.idx, k.idy) - (link_zp(a, ep, c + P, P, k) - zpc) * k.idy;
+        const double sq = sqrt(-ly_diag(B, E, 0, 3, j, g.nx, k));
+        if (MODE == kLinkNext) {
+            double rv = a.r.vy()[c];
+            if (a.r_scaled) rv *= sq;
+            a.ry[c] = (T)(rv - av);
+        } else {
+            a.wout.vy()[c] = a.w_scaled ? av / sq : av;
+        }
+    }
+    {
+        const double av = (zx[4] - zx[3]) * k.idx + (zy[4] - zy[1]) * k.idy;
+        const double sw = sqrt(wp_weight(ep[c], k));
+        if (MODE == kLinkNext) {
+            double rv = a.r.p()[c];
+            if (a.r_scaled) rv /= sw;
+            a.tp[c] = rv - av;
+        } else {
+            a.wout.p()[c] = a.w_scaled ? av * sw : av;
+        }
+    }
+}
+
 }  // namespace tph

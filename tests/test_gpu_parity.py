@@ -183,6 +183,35 @@ def test_multisweep_plans_match_oracle_vcycle(case, prec, plan):
     assert np.array_equal(gy_[1:ny, nx + 1], (1 if bc[1] == 0 else -1) * gy_[1:ny, nx])
 
 
+@pytest.mark.parametrize("prec", [tph.FP64, tph.MIXED])
+@pytest.mark.parametrize("steps", [1, 2, 3, 4])
+def test_precondition_apply_matches_separate_kernels(prec, steps):
+    """The linked Uzawa exits (one pass per step, the last also forming A z)
+    give the preconditioner of the separate exit / residual / entry kernels,
+    and w = A z."""
+    nx, ny, bc = 200, 72, (1, 0, 1, 1)
+    eb, ep, rho = wl.random_fields(nx, ny, seed=91 + steps, eta_decades=2)
+    rx, ry, rp = wl.random_state(nx, ny, seed=17 + steps)
+    s = solver_for(nx, ny, bc=bc, precision=prec, uzawa_steps=steps, alpha=1.5)
+    s.set_coefficients(T(eb), T(ep), T(rho))
+    z_ref = [N(t) for t in s.precondition(T(rx), T(ry), T(rp))]
+    z, w = s.precondition_apply(T(rx), T(ry), T(rp))
+    z = [N(t) for t in z]
+    w = [N(t) for t in w]
+    w_ref = [N(t) for t in s.apply(*[T(t) for t in z])]
+    tol = 1e-12 if prec == tph.FP64 else 2e-5
+    sl = [np.s_[1:ny + 1, 1:nx], np.s_[1:ny, 1:nx + 1], np.s_[1:ny + 1, 1:nx + 1]]
+    for a, b_, q in zip(z, z_ref, sl):
+        err = relmax(a[q], b_[q])
+        print(f"[link] z rel max err {err:.2e}", flush=True)
+        assert err < tol
+    for a, b_, q in zip(w, w_ref, sl):
+        assert relmax(a[q], b_[q]) < 1e-12
+    # output contract of z: ghosts mirrored, walls zero
+    assert np.all(z[0][:, 0] == 0) and np.all(z[0][:, nx] == 0)
+    assert np.array_equal(z[0][0, 1:nx], (1 if bc[2] == 0 else -1) * z[0][1, 1:nx])
+
+
 def _check_solution_contract(nx, ny, bc, vx, vy, p):
     assert np.all(vx[:, 0] == 0) and np.all(vx[:, nx] == 0)
     assert np.all(vy[0, :] == 0) and np.all(vy[ny, :] == 0)
