@@ -58,6 +58,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=256, help="problems in the batched workload (0: skip)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-gradient workload")
+    ap.add_argument("--large", type=int, default=4096, help="cells per side of the multi-inclusion workload (0: skip)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -263,6 +264,47 @@ def main():
         log(f"[bench] adjoint gradient: {1e3 * adt:.1f} ms")
         sa.close()
 
+    # large multi-inclusion workload: 200 sharp discs, viscosity 10^U(-3,3); one mixed solve with the tuned
+    # schedule and a longer restart (the 1e6 contrast needs it), the finest-level sweep timed inside it
+    large = None
+    if args.large > 0:
+        nl_ = args.large
+        pl = wl.multi_inclusion(nl_)
+        log(f"[bench] multi-inclusion workload {nl_}x{nl_}")
+        ltuned = {"params": {"restart": 30}, "ms": None, "trials": 0, "seconds": 0.0}
+        if not args.no_tune:
+            # the schedule (not the per-level plan) tuned on the same recipe at 1024^2, untimed
+            ps = wl.multi_inclusion(1024)
+            ltuned = autotune.tune(to(ps.eta_b), to(ps.eta_p), to(ps.rho_b), ps.gx, ps.gy, precision=tph.MIXED,
+                                   reps=1, rounds=1, device=dev, knobs=autotune.schedule_knobs())
+            log(f"[bench] large: schedule tuned at 1024^2 {ltuned['params']} ({ltuned['trials']} trials, "
+                f"{ltuned['seconds']:.1f} s)")
+        kw = dict(ltuned["params"])
+        for key in ("msweep", "tile_shape", "coarse_level"):
+            kw.pop(key, None)                        # the per-level plan belongs to the tuning grid
+        sl = tph.Solver(nl_, nl_, precision=tph.MIXED, device=dev, max_iters=2000, **kw)
+        sl.set_coefficients(to(pl.eta_b), to(pl.eta_p), to(pl.rho_b), pl.gx, pl.gy)
+        sl.kernel_timing(17)
+        sl.kernel_timing_read()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        linf = sl.solve()[3]
+        torch.cuda.synchronize()
+        ldt = time.perf_counter() - t0
+        nk, msk, byk, _ = sl.kernel_timing_read()
+        large = {"workload": f"{nl_}x{nl_} cells, 200 discs (seed 3) radius U(0.005,0.03), eta 10^U(-3,3), rho "
+                             f"U(-1,1), mixed, schedule tuned on the 1024^2 instance", "cells": nl_ * nl_,
+                 "tuned": ltuned,
+                 "value": nl_ * nl_ / ldt, "unit": "cells/s", "ms": 1e3 * ldt, "iters": linf.iters,
+                 "res_energy": linf.res_energy, "status": linf.status,
+                 "smooth_l0": {"launches": nk, "us_per_launch": 1e3 * msk / max(nk, 1),
+                               "GBps": byk / max(msk * 1e-3, 1e-30) / 1e9,
+                               "frac": byk / max(msk * 1e-3, 1e-30) / 1e9 / HBM_PEAK_GBS}}
+        log(f"[bench] large: {1e3 * ldt:.0f} ms, {linf.iters} iterations, res {linf.res_energy:.1e}, finest sweep "
+            f"{large['smooth_l0']['GBps']:.0f} GB/s")
+        sl.close()
+        del sl
+
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import stokes as ost
@@ -317,6 +359,7 @@ def main():
         "copy_GBps": round(copy_gbs, 1),
         "batched": batch,
         "adjoint": adjoint,
+        "large": large,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

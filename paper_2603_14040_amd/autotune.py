@@ -15,7 +15,7 @@ Knobs (all of them descriptor fields of tph_create):
   * the first level of the single-workgroup coarse tail (``coarse_level``);
   * pre- and post-smoothing sweeps and their growth per level (the paper's
     level-dependent schedule, nu_l = ceil(nu * growth^l));
-  * Uzawa sweeps per preconditioner application (``uzawa_steps``) and the
+  * Uzawa sweeps per preconditioner application (``uzawa_steps``, 1..8) and the
     Uzawa pressure relaxation ``alpha``; the smoother damping ``omega``;
   * FGMRES restart length.
 Parameter sets that resolve to the same kernel plan on every level are
@@ -157,7 +157,7 @@ def solver_kwargs(p: Params, tile_levels: Sequence[int]) -> dict:
 
 
 def knobs_for(tile_levels: Sequence[int], coarse_levels: Sequence[int] = (), nus=(1, 2, 3),
-              growths=(1.0, 1.5, 2.0), uzawa=(1, 2, 3, 4, 5), restarts=(5, 8, 10, 15, 20, 30),
+              growths=(1.0, 1.5, 2.0), uzawa=(1, 2, 3, 4, 6, 8), restarts=(5, 8, 10, 15, 20, 30, 50, 64),
               alphas=(1.0, 1.5, 2.0, 3.0), omegas=(0.8, 1.0, 1.2)) -> List[Knob]:
     """Schedule knobs first (they move the iteration count), then the kernel plan."""
     ks = [Knob("alpha", list(alphas)), Knob("uzawa_steps", list(uzawa)), Knob("nu_pre", list(nus)),
@@ -172,10 +172,18 @@ def knobs_for(tile_levels: Sequence[int], coarse_levels: Sequence[int] = (), nus
 # ---------------------------------------------------------------------------
 # tuning a problem on the GPU
 # ---------------------------------------------------------------------------
+def schedule_knobs() -> List[Knob]:
+    """Knobs that carry over between grid sizes of one recipe (no per-level plan)."""
+    return [Knob("restart", [8, 16, 30, 50, 64]), Knob("alpha", [1.0, 1.5, 2.0, 3.0]),
+            Knob("uzawa_steps", [1, 2, 3, 4, 6, 8]), Knob("nu_pre", [1, 2, 3]), Knob("nu_post", [1, 2, 3]),
+            Knob("omega", [0.8, 1.0, 1.2])]
+
+
 def tune(eta_b, eta_p, rho_b, gx: float = 0.0, gy: float = -1.0, *, precision: Optional[int] = None,
          lx: float = 1.0, ly: float = 1.0, bc=(0, 0, 0, 0), rtol: float = 1e-8, reps: int = 3, rounds: int = 2,
          rel_gain: float = 0.02, db: Optional[TuningDB] = None, tag: str = "", device=None,
-         knobs: Optional[Sequence[Knob]] = None, log: Optional[Callable[[str], None]] = None) -> dict:
+         knobs: Optional[Sequence[Knob]] = None, log: Optional[Callable[[str], None]] = None,
+         max_iters: int = 2000) -> dict:
     """Tune the solve of one problem (device FP64 arrays of shape (ny+2, nx+2)).
 
     Returns the database entry: ``params`` (Solver keyword arguments),
@@ -214,7 +222,8 @@ def tune(eta_b, eta_p, rho_b, gx: float = 0.0, gy: float = -1.0, *, precision: O
     def measure(p: Params) -> float:
         kw = solver_kwargs(p, tile_levels)
         try:
-            s = Solver(nx, ny, lx, ly, bc=bc, precision=precision, rtol=rtol, device=device, **kw)
+            s = Solver(nx, ny, lx, ly, bc=bc, precision=precision, rtol=rtol, device=device, max_iters=max_iters,
+                       **kw)
         except _lib.TephraError:
             return math.inf            # e.g. a coarse tail that does not fit
         try:
