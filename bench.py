@@ -302,6 +302,17 @@ def main():
                                "frac": byk / max(msk * 1e-3, 1e-30) / 1e9 / HBM_PEAK_GBS}}
         log(f"[bench] large: {1e3 * ldt:.0f} ms, {linf.iters} iterations, res {linf.res_energy:.1e}, finest sweep "
             f"{large['smooth_l0']['GBps']:.0f} GB/s")
+        # the same solve as a viscosity-rescaling continuation from the lithostatic pressure
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cinf = sl.solve_continuation(to(pl.eta_b), to(pl.eta_p), to(pl.rho_b), pl.gx, pl.gy,
+                                     thetas=(0.0, 0.25, 0.5, 0.75, 1.0), stage_rtol=1e-3, lithostatic=True)[3]
+        torch.cuda.synchronize()
+        cdt = time.perf_counter() - t0
+        large["continuation"] = {"thetas": [0.0, 0.25, 0.5, 0.75, 1.0], "stage_rtol": 1e-3, "lithostatic": True,
+                                 "ms": 1e3 * cdt, "iters": cinf.iters, "res_energy": cinf.res_energy,
+                                 "status": cinf.status, "value": nl_ * nl_ / cdt}
+        log(f"[bench] large, continuation: {1e3 * cdt:.0f} ms, {cinf.iters} iterations, res {cinf.res_energy:.1e}")
         sl.close()
         del sl
 

@@ -170,6 +170,31 @@ tph_status tph_set_coefficients(tph_solver* s, const double* eta_b, const double
  * info may be NULL.  Returns TPH_OK or TPH_NOT_CONVERGED (or an error). */
 tph_status tph_solve(tph_solver* s, double* vx, double* vy, double* p, tph_info* info);
 
+/* Lithostatic pressure (Sec. "Viscosity Rescaling and Initial Guess"): the
+ * integral of rho g_y along y, discretely the hydrostatic balance of every
+ * y-momentum row for zero velocity, p(i+1, j) - p(i, j) = gy dy (rho_b(i, j-1)
+ * + rho_b(i, j)) / 2, with zero mean over the cells.  rho_b and p are device
+ * (ny+2) x (nx+2) FP64 arrays; p's ghost and wall entries are written 0.
+ * Needs only tph_create. */
+tph_status tph_lithostatic_pressure(tph_solver* s, const double* rho_b, double gy, double* p);
+
+/* Continuation solve (Sec. "Viscosity Rescaling and Initial Guess"): for
+ * theta in thetas[0..nthetas-1] (non-decreasing in [0, 1], the last equal to
+ * 1) the system with the computational viscosity (1 - theta) eta_min + theta
+ * eta (eta_min: the smallest of eta_b over the basic nodes and eta_p over the
+ * cells, both fields blended) is set up and solved from the previous stage's
+ * solution, to max(stage_rtol, desc.rtol) for the intermediate stages (a
+ * stage that stops short still hands its iterate on) and to desc.rtol for
+ * the last.  lithostatic = 1 starts from zero velocity and the lithostatic
+ * pressure (as tph_lithostatic_pressure), 0 from (vx, vy, p) as given.
+ * Afterwards the solver holds the original coefficients, as after
+ * tph_set_coefficients(eta_b, eta_p, rho_b, gx, gy).  info sums iterations,
+ * restarts and times over the stages; res_energy is the last stage's; the
+ * history (if given) is the concatenation of the stages'. */
+tph_status tph_solve_continuation(tph_solver* s, const double* eta_b, const double* eta_p, const double* rho_b,
+                                  double gx, double gy, const double* thetas, int32_t nthetas, double stage_rtol,
+                                  int32_t lithostatic, double* vx, double* vy, double* p, tph_info* info);
+
 /* Same with an explicit right-hand side (fx at vx rows, fy at vy rows, fp at
  * continuity rows), replacing the one from tph_set_coefficients for this call
  * only.  Used for the adjoint solve (A is symmetric, A = A^T). */

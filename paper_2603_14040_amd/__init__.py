@@ -160,6 +160,35 @@ class Solver:
         _lib.check("tph_solve", st, allow_not_converged=not raise_on_fail)
         return vx, vy, p, self._info(info, st, hist if history else [])
 
+    def lithostatic_pressure(self, rho_b, gy: float = -1.0):
+        """Zero-mean lithostatic pressure (tph_lithostatic_pressure)."""
+        p = self.zeros()
+        self._sync_in()
+        _lib.check("tph_lithostatic_pressure", self._lib.tph_lithostatic_pressure(
+            self._h, self._p(rho_b, "rho_b"), float(gy), self._p(p, "p")))
+        return p
+
+    def solve_continuation(self, eta_b, eta_p, rho_b, gx: float = 0.0, gy: float = -1.0,
+                           thetas=(0.0, 0.25, 0.5, 0.75, 1.0), stage_rtol: float = 1e-3, lithostatic: bool = True,
+                           vx=None, vy=None, p=None, history: int = 0):
+        """Viscosity-rescaling continuation solve (tph_solve_continuation); sets the coefficients."""
+        vx = self.zeros() if vx is None else vx
+        vy = self.zeros() if vy is None else vy
+        p = self.zeros() if p is None else p
+        th = (ctypes.c_double * len(thetas))(*[float(t) for t in thetas])
+        info = _lib.Info()
+        hist = (ctypes.c_double * max(history, 1))()
+        if history:
+            info.history = hist
+            info.history_len = history
+        self._sync_in()
+        st = self._lib.tph_solve_continuation(self._h, self._p(eta_b, "eta_b"), self._p(eta_p, "eta_p"),
+                                              self._p(rho_b, "rho_b"), float(gx), float(gy), th, len(thetas),
+                                              float(stage_rtol), 1 if lithostatic else 0, self._p(vx, "vx"),
+                                              self._p(vy, "vy"), self._p(p, "p"), ctypes.byref(info))
+        _lib.check("tph_solve_continuation", st, allow_not_converged=True)
+        return vx, vy, p, self._info(info, st, list(hist[:min(info.iters, history)]) if history else [])
+
     def solve_rhs(self, fx, fy, fp=None, vx=None, vy=None, p=None):
         vx = self.zeros() if vx is None else vx
         vy = self.zeros() if vy is None else vy

@@ -74,6 +74,9 @@ def load(path: str = LIB_PATH):
         "tph_set_coefficients": (c_int32, [P, P, P, P, c_double, c_double, P, P]),
         "tph_solve": (c_int32, [P, P, P, P, POINTER(Info)]),
         "tph_solve_rhs": (c_int32, [P, P, P, P, P, P, P, POINTER(Info)]),
+        "tph_lithostatic_pressure": (c_int32, [P, P, c_double, P]),
+        "tph_solve_continuation": (c_int32, [P, P, P, P, c_double, c_double, POINTER(c_double), c_int32, c_double,
+                                             c_int32, P, P, P, POINTER(Info)]),
         "tph_apply": (c_int32, [P, P, P, P, P, P, P]),
         "tph_precondition": (c_int32, [P, P, P, P, P, P, P]),
         "tph_precondition_apply": (c_int32, [P, P, P, P, P, P, P, P, P, P]),

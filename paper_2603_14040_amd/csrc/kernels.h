@@ -49,6 +49,13 @@ template <typename T>
 hipError_t launch_precond_out(const Geom& g, const T* ex, const T* ey, Vec3 v, const double* ep,
                               bool energy, double alpha, Vec3 z, hipStream_t st, bool accumulate = false);
 // right-hand side f = -rho g (+ extra) at velocity rows, 0 at continuity rows
+// lithostatic pressure at the cells (ghosts untouched), viscosity minimum
+// (partial: one slot per 64 x 4 block of the basic grid; out: 1 value), and
+// the continuation blend out = (1 - theta) m + theta in over n entries
+hipError_t launch_lithostatic(const Geom& g, const double* rho, double gy, double* p, hipStream_t st);
+hipError_t launch_eta_min(const Geom& g, const double* eb, const double* ep, double* partial, double* out,
+                          hipStream_t st);
+hipError_t launch_blend(const double* in, double* out, size_t n, double theta, double m, hipStream_t st);
 hipError_t launch_rhs(const Geom& g, const double* rho, double gx, double gy, const double* fxe,
                       const double* fye, Vec3 b, hipStream_t st);
 // per-block counts of invalid coefficients: [bad eta, nonfinite rho/force]

@@ -83,6 +83,8 @@ struct tph_solver {
     LevelBuf lev[kMaxLevels];
     double* Minv = nullptr;
     double** gj_table = nullptr; // device {Minv, ncoarse} for the LDS Gauss-Jordan (null: ncoarse too large)
+    double* cont_eb = nullptr;   // continuation: blended viscosities in the caller's dense layout (lazy)
+    double* cont_ep = nullptr;
     int ncoarse = 0;
     int lc = -1;                 // first level handled by the single-workgroup coarse kernel (-1: none)
     unsigned msw_mask = 0;       // levels smoothed in multi-sweep passes (resolved desc.msweep)
@@ -1007,6 +1009,17 @@ tph_status setup_finish(tph_solver* s) {
     return TPH_OK;
 }
 
+// Viscosity minimum of the caller's dense (ny+2) x (nx+2) fields (basic
+// nodes and cells), returned on the host.
+tph_status eta_min_dense(tph_solver* s, const double* eta_b, const double* eta_p, double* m) {
+    Geom gd = s->lev[0].g;
+    gd.pitch = gd.nx + 2;
+    TPH_HIP(launch_eta_min(gd, eta_b, eta_p, s->partial, s->dscal + kSlotMisc + 4, s->st));
+    TPH_TRY(fetch(s, kSlotMisc + 4, 1));
+    *m = s->hscal[kSlotMisc + 4];
+    return TPH_OK;
+}
+
 }  // namespace
 
 // ============================================================ internal view
@@ -1125,6 +1138,96 @@ tph_status tph_solve(tph_solver* s, double* vx, double* vy, double* p, tph_info*
     if (r < 0) return r;
     TPH_TRY(store_solution(s, s->x, vx, vy, p));
     TPH_HIP(hipStreamSynchronize(s->st));
+    return r;
+}
+
+tph_status tph_lithostatic_pressure(tph_solver* s, const double* rho_b, double gy, double* p) {
+    g_last_error.clear();
+    if (!s) { set_error("solver is NULL"); return TPH_ERR_INVALID; }
+    if (!rho_b || !p) { set_error("rho_b and p are required"); return TPH_ERR_INVALID; }
+    if (!std::isfinite(gy)) { set_error("gravity must be finite"); return TPH_ERR_INVALID; }
+    const Geom& g = s->lev[0].g;
+    TPH_TRY(copy_in(s, g, s->gtmp[2], rho_b));
+    const Vec3 t = vec3(s, s->t3);
+    TPH_HIP(hipMemsetAsync(s->t3, 0, s->n3 * sizeof(double), s->st));
+    TPH_HIP(launch_lithostatic(g, s->gtmp[2], gy, t.p(), s->st));
+    TPH_TRY(remove_pressure_mean(s, s->t3));
+    TPH_TRY(copy_out(s, g, p, t.p()));
+    TPH_HIP(hipStreamSynchronize(s->st));
+    return TPH_OK;
+}
+
+tph_status tph_solve_continuation(tph_solver* s, const double* eta_b, const double* eta_p, const double* rho_b,
+                                  double gx, double gy, const double* thetas, int32_t nthetas, double stage_rtol,
+                                  int32_t lithostatic, double* vx, double* vy, double* p, tph_info* info) {
+    g_last_error.clear();
+    if (!s) { set_error("solver is NULL"); return TPH_ERR_INVALID; }
+    if (!eta_b || !eta_p || !rho_b || !vx || !vy || !p) {
+        set_error("eta_b, eta_p, rho_b, vx, vy and p are required");
+        return TPH_ERR_INVALID;
+    }
+    if (!thetas || nthetas < 1 || nthetas > 64) { set_error("thetas must hold 1..64 values"); return TPH_ERR_INVALID; }
+    for (int k = 0; k < nthetas; ++k) {
+        if (!(thetas[k] >= 0.0 && thetas[k] <= 1.0) || (k > 0 && thetas[k] < thetas[k - 1])) {
+            set_error("thetas must be non-decreasing values in [0, 1]");
+            return TPH_ERR_INVALID;
+        }
+    }
+    if (thetas[nthetas - 1] != 1.0) { set_error("the last theta must be 1 (the original viscosity)"); return TPH_ERR_INVALID; }
+    if (!(stage_rtol > 0.0 && stage_rtol < 1.0)) { set_error("stage_rtol must be in (0, 1)"); return TPH_ERR_INVALID; }
+    if (lithostatic != 0 && lithostatic != 1) { set_error("lithostatic must be 0 or 1"); return TPH_ERR_INVALID; }
+    const Geom& g = s->lev[0].g;
+    const size_t nd = (size_t)(g.ny + 2) * (g.nx + 2);
+    if (!s->cont_eb) {
+        TPH_TRY(dev_alloc(s, (void**)&s->cont_eb, nd * sizeof(double)));
+        TPH_TRY(dev_alloc(s, (void**)&s->cont_ep, nd * sizeof(double)));
+    }
+    double m = 0.0;
+    TPH_TRY(eta_min_dense(s, eta_b, eta_p, &m));
+    if (!(m > 0.0) || !std::isfinite(m)) { set_error("viscosity must be finite and positive"); return TPH_ERR_INVALID; }
+    // initial guess: the lithostatic pressure with zero velocity, or the caller's fields
+    if (lithostatic) {
+        TPH_HIP(hipMemsetAsync(s->x, 0, s->n3 * sizeof(double), s->st));
+        TPH_TRY(copy_in(s, g, s->gtmp[2], rho_b));
+        TPH_HIP(launch_lithostatic(g, s->gtmp[2], gy, vec3(s, s->x).p(), s->st));
+    } else {
+        TPH_TRY(load_solution(s, s->x, vx, vy, p));
+    }
+    const double rtol = s->d.rtol;
+    tph_info tot{};
+    tph_status r = TPH_OK;
+    for (int k = 0; k < nthetas && r >= 0; ++k) {
+        TPH_HIP(launch_blend(eta_b, s->cont_eb, nd, thetas[k], m, s->st));
+        TPH_HIP(launch_blend(eta_p, s->cont_ep, nd, thetas[k], m, s->st));
+        TPH_TRY(setup_enqueue(s, s->cont_eb, s->cont_ep, rho_b, gx, gy, nullptr, nullptr, true));
+        TPH_TRY(setup_finish(s));
+        tph_info st{};
+        if (info && info->history && tot.iters < info->history_len) {
+            st.history = info->history + tot.iters;
+            st.history_len = info->history_len - tot.iters;
+        }
+        s->d.rtol = k == nthetas - 1 ? rtol : std::max(stage_rtol, rtol);
+        r = fgmres(s, s->b, &st);
+        s->d.rtol = rtol;
+        tot.iters += st.iters;
+        tot.restarts += st.restarts;
+        tot.res_energy = st.res_energy;
+        tot.res_estimate = st.res_estimate;
+        tot.t_setup_ms += s->t_setup_ms;
+        tot.t_solve_ms += st.t_solve_ms;
+        // an intermediate stage that stops short of stage_rtol still gives the next one its start
+        if (r == TPH_NOT_CONVERGED && k < nthetas - 1) r = TPH_OK;
+    }
+    if (r < 0) return r;
+    TPH_TRY(store_solution(s, s->x, vx, vy, p));
+    TPH_HIP(hipStreamSynchronize(s->st));
+    if (info) {
+        double* h = info->history;
+        const int32_t hl = info->history_len;
+        *info = tot;
+        info->history = h;
+        info->history_len = hl;
+    }
     return r;
 }
 

@@ -190,6 +190,50 @@ __global__ __launch_bounds__(256) void k_uzawa_link(Geom g, LinkArgs<T> a, const
     uzawa_link_cell<T, MODE>(g, a, eb, ep, i, j);
 }
 
+// Lithostatic pressure, one thread per column marching up the rows: the
+// hydrostatic balance of each y-momentum row for zero velocity,
+// p(i+1, j) - p(i, j) = gy dy (rho_b(i, j-1) + rho_b(i, j)) / 2, p(1, j) = 0.
+__global__ __launch_bounds__(256) void k_lithostatic(Geom g, const double* __restrict__ rho, double gy,
+                                                    double* __restrict__ p) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x + 1;
+    if (j > g.nx) return;
+    const int P = g.pitch;
+    double acc = 0.0;
+    for (int i = 1; i <= g.ny; ++i) {
+        p[i * P + j] = acc;
+        if (i < g.ny) acc += gy * g.dy * 0.5 * (rho[i * P + j - 1] + rho[i * P + j]);
+    }
+}
+
+// block minima of eta_b over the basic nodes (0..ny, 0..nx) and of eta_p over the cells
+__global__ __launch_bounds__(256) void k_eta_min(Geom g, const double* __restrict__ eb,
+                                                const double* __restrict__ ep, double* __restrict__ partial) {
+    const int j = blockIdx.x * BX + threadIdx.x;
+    const int i = blockIdx.y * BY + threadIdx.y;
+    double v = HUGE_VAL;
+    if (i <= g.ny && j <= g.nx) {
+        v = eb[i * g.pitch + j];
+        if (i >= 1 && j >= 1) v = fmin(v, ep[i * g.pitch + j]);
+    }
+    const double m = block_min(v);
+    if (threadIdx.x == 0 && threadIdx.y == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = m;
+}
+
+__global__ __launch_bounds__(256) void k_min_rows(const double* __restrict__ partial, int n,
+                                                 double* __restrict__ out) {
+    double v = HUGE_VAL;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) v = fmin(v, partial[t]);
+    const double m = block_min(v);
+    if (threadIdx.x == 0) out[0] = m;
+}
+
+// out = (1 - theta) m + theta in over n entries
+__global__ __launch_bounds__(256) void k_blend(const double* __restrict__ in, double* __restrict__ out, size_t n,
+                                              double theta, double m) {
+    for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
+        out[t] = (1.0 - theta) * m + theta * in[t];
+}
+
 __global__ __launch_bounds__(256) void k_rhs(Geom g, const double* __restrict__ rho, double gx, double gy,
                                             const double* __restrict__ fxe, const double* __restrict__ fye,
                                             Vec3 b) {
@@ -382,6 +426,27 @@ hipError_t launch_uzawa_link(const Geom& g, const LinkArgs<T>& a, bool apply, co
         hipLaunchKernelGGL((k_uzawa_link<T, kLinkApply>), grid_cells(g), dim3(BX, BY), 0, st, g, a, eb, ep);
     else
         hipLaunchKernelGGL((k_uzawa_link<T, kLinkNext>), grid_cells(g), dim3(BX, BY), 0, st, g, a, eb, ep);
+    return hipGetLastError();
+}
+
+hipError_t launch_lithostatic(const Geom& g, const double* rho, double gy, double* p, hipStream_t st) {
+    hipLaunchKernelGGL(k_lithostatic, dim3((g.nx + 255) / 256), dim3(256), 0, st, g, rho, gy, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_eta_min(const Geom& g, const double* eb, const double* ep, double* partial, double* out,
+                          hipStream_t st) {
+    const dim3 grid((g.nx + 1 + BX - 1) / BX, (g.ny + 1 + BY - 1) / BY);
+    hipLaunchKernelGGL(k_eta_min, grid, dim3(BX, BY), 0, st, g, eb, ep, partial);
+    hipLaunchKernelGGL(k_min_rows, dim3(1), dim3(256), 0, st, partial, (int)(grid.x * grid.y), out);
+    return hipGetLastError();
+}
+
+hipError_t launch_blend(const double* in, double* out, size_t n, double theta, double m, hipStream_t st) {
+    size_t b = (n + 2047) / 2048;
+    if (b < 1) b = 1;
+    if (b > 4096) b = 4096;
+    hipLaunchKernelGGL(k_blend, dim3((unsigned)b), dim3(256), 0, st, in, out, n, theta, m);
     return hipGetLastError();
 }
 
