@@ -743,25 +743,72 @@ __device__ __forceinline__ void coarse_cycle_body(const CoarseArgs<T>& A) {
     const size_t off_end = (size_t)s_top_off + 2 * (size_t)ntop;
     double* rs = (double*)(sm + ((off_end * sizeof(T) + 7) / 8) * 8 / sizeof(T));
 
-    // load viscosities of every level and the right-hand side of the top level; zero the rest
-    for (int l = 0; l < nl; ++l) {
-        const int P = L[l].P;
-        const int Pg = A.g[l].pitch;
-        const T* geb = A.eb[l];
-        const T* gep = A.ep[l];
-        T *ex = F(l, 0), *ey = F(l, 1), *rx = F(l, 2), *ry = F(l, 3), *eb = F(l, 4), *ep = F(l, 5);
-        int rt, rs_, ct, cs_;
-        rowmap(P, rt, rs_, ct, cs_);
-        for (int i = rt; i < L[l].ny + 2; i += rs_) {
-            for (int j = ct; j < P; j += cs_) {
-                const int q = i * P + j, cg = i * Pg + j;
-                ex[q] = (T)0;
-                ey[q] = (T)0;
-                rx[q] = l == 0 ? A.rx[cg] : (T)0;
-                ry[q] = l == 0 ? A.ry[cg] : (T)0;
-                eb[q] = geb[cg];
-                ep[q] = gep[cg];
+    // load viscosities of every level and the right-hand side of the top level; zero the rest.
+    // One flat index over all levels; the first KL entries of every thread are
+    // loaded into registers together (all loads in flight) before any store.
+    __shared__ int qoff[kMaxLevels + 1];
+    if (tid == 0) {
+        int q = 0;
+        for (int l = 0; l < nl; ++l) {
+            qoff[l] = q;
+            q += (L[l].ny + 2) * L[l].P;
+        }
+        qoff[nl] = q;
+    }
+    __syncthreads();
+    {
+        constexpr int KL = sizeof(T) == 4 ? 8 : 16;
+        const int ntot = qoff[nl];
+        auto locate = [&](int q, int& l, int& i, int& j) {
+            l = 0;
+            while (q >= qoff[l + 1]) ++l;
+            const int r = q - qoff[l];
+            i = r / L[l].P;
+            j = r - i * L[l].P;
+        };
+        T vb[KL], vp[KL], vx[KL], vy[KL];
+#pragma unroll
+        for (int k = 0; k < KL; ++k) {
+            const int q = tid + k * nthr;
+            vb[k] = vp[k] = vx[k] = vy[k] = (T)0;
+            if (q < ntot) {
+                int l, i, j;
+                locate(q, l, i, j);
+                const int cg = i * A.g[l].pitch + j;
+                vb[k] = A.eb[l][cg];
+                vp[k] = A.ep[l][cg];
+                if (l == 0) {
+                    vx[k] = A.rx[cg];
+                    vy[k] = A.ry[cg];
+                }
             }
+        }
+#pragma unroll
+        for (int k = 0; k < KL; ++k) {
+            const int q = tid + k * nthr;
+            if (q < ntot) {
+                int l, i, j;
+                locate(q, l, i, j);
+                const int r = i * L[l].P + j;
+                F(l, 0)[r] = (T)0;
+                F(l, 1)[r] = (T)0;
+                F(l, 2)[r] = vx[k];
+                F(l, 3)[r] = vy[k];
+                F(l, 4)[r] = vb[k];
+                F(l, 5)[r] = vp[k];
+            }
+        }
+        // remaining entries (only for very elongated tails)
+        for (int q = tid + KL * nthr; q < ntot; q += nthr) {
+            int l, i, j;
+            locate(q, l, i, j);
+            const int r = i * L[l].P + j, cg = i * A.g[l].pitch + j;
+            F(l, 0)[r] = (T)0;
+            F(l, 1)[r] = (T)0;
+            F(l, 2)[r] = l == 0 ? A.rx[cg] : (T)0;
+            F(l, 3)[r] = l == 0 ? A.ry[cg] : (T)0;
+            F(l, 4)[r] = A.eb[l][cg];
+            F(l, 5)[r] = A.ep[l][cg];
         }
     }
     __syncthreads();
@@ -848,30 +895,43 @@ __device__ __forceinline__ void coarse_cycle_body(const CoarseArgs<T>& A) {
         }
         __syncthreads();
         const int sub = tid & 15, grp = tid >> 4, ngrp = nthr >> 4;
-        for (int m = grp; m < n; m += ngrp) {
-            const double* row = A.Minv + (size_t)m * n;
-            double s = 0.0;
+        auto put = [&](int m, double sv) {
+            const T e = (T)(-sv);
+            if (m < nvx) {
+                const int i = 1 + m / (G.nx - 1), j = 1 + m % (G.nx - 1);
+                const int c = i * G.P + j;
+                ex[c] = e;
+                if (i == 1) ex[c - G.P] = K[l].mirS * e;
+                if (i == G.ny) ex[c + G.P] = K[l].mirN * e;
+            } else {
+                const int mm = m - nvx;
+                const int i = 1 + mm / G.nx, j = 1 + mm % G.nx;
+                const int c = i * G.P + j;
+                ey[c] = e;
+                if (j == 1) ey[c - 1] = K[l].mirW * e;
+                if (j == G.nx) ey[c + 1] = K[l].mirE * e;
+            }
+        };
+        // two rows per 16-lane group at a time, column loop unrolled: the loads
+        // of both rows are in flight together
+        for (int m0 = grp; m0 < n; m0 += 2 * ngrp) {
+            const int m1 = m0 + ngrp;
+            const double* row0 = A.Minv + (size_t)m0 * n;
+            const double* row1 = A.Minv + (size_t)(m1 < n ? m1 : m0) * n;
+            double s0 = 0.0, s1 = 0.0;
 #pragma unroll 8
-            for (int q = sub; q < n; q += 16) s += row[q] * rs[q];
-            // sum over the 16 lanes of the group (aligned groups inside a wave)
-            for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
+            for (int q = sub; q < n; q += 16) {
+                const double x = rs[q];
+                s0 += row0[q] * x;
+                s1 += row1[q] * x;
+            }
+            for (int o = 8; o > 0; o >>= 1) {
+                s0 += __shfl_xor(s0, o, 16);
+                s1 += __shfl_xor(s1, o, 16);
+            }
             if (sub == 0) {
-                const T e = (T)(-s);
-                int i, j;
-                if (m < nvx) {
-                    i = 1 + m / (G.nx - 1); j = 1 + m % (G.nx - 1);
-                    const int c = i * G.P + j;
-                    ex[c] = e;
-                    if (i == 1) ex[c - G.P] = K[l].mirS * e;
-                    if (i == G.ny) ex[c + G.P] = K[l].mirN * e;
-                } else {
-                    const int mm = m - nvx;
-                    i = 1 + mm / G.nx; j = 1 + mm % G.nx;
-                    const int c = i * G.P + j;
-                    ey[c] = e;
-                    if (j == 1) ey[c - 1] = K[l].mirW * e;
-                    if (j == G.nx) ey[c + 1] = K[l].mirE * e;
-                }
+                put(m0, s0);
+                if (m1 < n) put(m1, s1);
             }
         }
         __syncthreads();
