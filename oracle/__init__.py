@@ -19,5 +19,8 @@ Contents
 ``adjoint``   surface-velocity misfit, adjoint solve and the gradient with
               respect to the viscosity and density fields obtained by
               differentiating the assembled operator term by term.
+``continuation`` viscosity-rescaling blend and lithostatic pressure.
+``accelerators`` flexible GCR(m) and Anderson acceleration AA(m, beta)
+              around the Uzawa fixed-point map.
 """
-from . import stokes, multigrid, adjoint  # noqa: F401
+from . import stokes, multigrid, adjoint, continuation, accelerators  # noqa: F401
