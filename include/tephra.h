@@ -10,12 +10,12 @@
  *     [ D  0 ] [p] = [0],     G p = -grad_h p,  D v = div_h v,
  *
  * with f = -rho g (gravity moved to the right-hand side) plus an optional
- * extra body force.  The solver is flexible GMRES(m) in FP64 (Ch. 4
- * "Accelerators", "Comparison with FGMRES") preconditioned by one Uzawa step
- * (Sec. "Uzawa Iteration as a Fixed Point Method"): a geometric multigrid
- * V-cycle on L (Sec. "Multigrid Cycles") followed by the viscosity-scaled
- * pressure update.  The stopping test is the relative energy residual of
- * Sec. "Residual Norms".
+ * extra body force.  The solver is an FP64 accelerator (Ch. 4
+ * "Accelerators": flexible GMRES(m), flexible GCR(m) or Anderson
+ * acceleration AA(m, beta)) around the Uzawa step (Sec. "Uzawa Iteration as
+ * a Fixed Point Method"): a geometric multigrid V-cycle on L (Sec.
+ * "Multigrid Cycles") followed by the viscosity-scaled pressure update.  The
+ * stopping test is the relative energy residual of Sec. "Residual Norms".
  *
  * ARRAY CONVENTION (all field arguments).  A problem of nx x ny cells uses
  * dense row-major FP64 arrays of (ny + 2) x (nx + 2) entries, row index i
@@ -85,6 +85,18 @@ enum { TPH_SMOOTH_JACOBI = 0, TPH_SMOOTH_GS = 1 };
 /* Coarse-level viscosity: normalised bilinear restriction of eta
  * (arithmetic) or of log(eta) (geometric). */
 enum { TPH_MEAN_ARITHMETIC = 0, TPH_MEAN_GEOMETRIC = 1 };
+/* Accelerator around the Uzawa fixed-point map (Ch. 4 "Accelerators"):
+ *   TPH_ACCEL_FGMRES    flexible GMRES(m) in the energy inner product, the
+ *                       Uzawa step as right preconditioner (Sec. "Comparison
+ *                       with FGMRES");
+ *   TPH_ACCEL_GCR       restarted flexible GCR(m) (Alg. "Flexible GCR(m)")
+ *                       in the same inner product: residual-minimising over
+ *                       the preconditioned directions of a cycle;
+ *   TPH_ACCEL_ANDERSON  Anderson acceleration with depth m and mixing beta
+ *                       (Alg. "Anderson Acceleration(m) with Mixing") on
+ *                       G(x) = x + M^{-1}(b - A x); its least-squares norm is
+ *                       the Euclidean norm over the unknowns (vx, vy, p). */
+enum { TPH_ACCEL_FGMRES = 0, TPH_ACCEL_GCR = 1, TPH_ACCEL_ANDERSON = 2 };
 
 typedef struct tph_desc {
     int32_t nx, ny;        /* cells; each must be divisible by 2^(levels-1)  */
@@ -100,8 +112,10 @@ typedef struct tph_desc {
     double alpha;          /* Uzawa pressure relaxation                       */
     int32_t eta_mean;      /* TPH_MEAN_*                                      */
     double rtol;           /* relative energy residual target                 */
-    int32_t restart;       /* FGMRES restart length m (1..64)                 */
-    int32_t max_iters;     /* total FGMRES iterations                         */
+    int32_t restart;       /* m of the accelerator: FGMRES / GCR restart length
+                              (1..64), Anderson depth (0..64)                 */
+    int32_t max_iters;     /* total iterations (applications of the Uzawa
+                              preconditioner)                                 */
     int32_t uzawa_steps;   /* Uzawa sweeps per preconditioner application (1..8):
                               z <- z + M^{-1}(r - A z), the fixed-point map of the
                               splitting A = M - N applied this many times         */
@@ -123,14 +137,17 @@ typedef struct tph_desc {
                               64 x 64 cells whose tail fits in LDS; -2 = none (one
                               launch per level down to the coarsest); l >= 0 =
                               level l (rejected when it does not fit)          */
-    int32_t reserved[3];   /* must be zero                                    */
+    int32_t accel;         /* TPH_ACCEL_*                                     */
+    double beta;           /* Anderson mixing in (0, 1]; ignored otherwise    */
 } tph_desc;
 
 typedef struct tph_info {
-    int32_t iters;         /* FGMRES iterations (= preconditioner applications) */
-    int32_t restarts;      /* restart cycles started                          */
+    int32_t iters;         /* iterations (= preconditioner applications whose
+                              result entered the returned iterate)           */
+    int32_t restarts;      /* FGMRES / GCR restart cycles started (Anderson: 0) */
     double res_energy;     /* true relative energy residual of the result     */
-    double res_estimate;   /* FGMRES least-squares estimate at exit           */
+    double res_estimate;   /* FGMRES / GCR recurrence estimate at exit
+                              (Anderson: the true residual)                   */
     double t_setup_ms;     /* last tph_set_coefficients, device time          */
     double t_solve_ms;     /* this solve, host wall time                      */
     double* history;       /* optional caller-owned HOST buffer: estimate per iteration */
@@ -144,7 +161,7 @@ typedef struct tph_solver tph_solver;
  * pre- and 2 post-sweeps on every level, alpha 1, arithmetic coarse
  * viscosity, two Uzawa sweeps per preconditioner application, fused
  * kernels with the default multi-sweep levels and tile shapes (-1), rtol
- * 1e-8, restart 20, max_iters 500. */
+ * 1e-8, FGMRES with restart 20, max_iters 500, beta 1. */
 void tph_desc_default(tph_desc* d, int32_t nx, int32_t ny);
 
 /* Create a solver for the grid in *desc; hip_stream is a hipStream_t (NULL:

@@ -14,12 +14,12 @@ from typing import Optional, Sequence, Tuple
 import torch
 
 from . import _lib
-from ._lib import (FP64, FREE_SLIP, MEAN_ARITHMETIC, MEAN_GEOMETRIC, MIXED, NO_SLIP,
-                   SMOOTH_GS, SMOOTH_JACOBI, TephraError)
+from ._lib import (ACCEL_ANDERSON, ACCEL_FGMRES, ACCEL_GCR, FP64, FREE_SLIP, MEAN_ARITHMETIC,
+                   MEAN_GEOMETRIC, MIXED, NO_SLIP, SMOOTH_GS, SMOOTH_JACOBI, TephraError)
 
 __all__ = ["Solver", "Batch", "SolveInfo", "StokesFunction", "solve", "FP64", "MIXED", "FREE_SLIP",
            "NO_SLIP", "SMOOTH_GS", "SMOOTH_JACOBI", "MEAN_ARITHMETIC", "MEAN_GEOMETRIC",
-           "TephraError", "library"]
+           "ACCEL_FGMRES", "ACCEL_GCR", "ACCEL_ANDERSON", "TephraError", "library"]
 
 
 def library():
@@ -60,13 +60,15 @@ class Solver:
                  eta_mean: int = MEAN_ARITHMETIC, rtol: float = 1e-8, restart: int = 20,
                  max_iters: int = 500, uzawa_steps: int = 2, fused: bool = True,
                  msweep: int = -1, tile_shape: int = -1, coarse_level: int = -1,
+                 accel="fgmres", beta: float = 1.0,
                  device: Optional[torch.device] = None,
                  stream: Optional[torch.cuda.Stream] = None):
         lib = _lib.load()
         d = _desc(lib, nx, ny, lx=lx, ly=ly, bc=bc, precision=precision, levels=levels, smoother=smoother,
                   nu_pre=nu_pre, nu_post=nu_post, nu_growth=nu_growth, omega=omega, alpha=alpha,
                   eta_mean=eta_mean, rtol=rtol, restart=restart, max_iters=max_iters, uzawa_steps=uzawa_steps,
-                  fused=fused, msweep=msweep, tile_shape=tile_shape, coarse_level=coarse_level)
+                  fused=fused, msweep=msweep, tile_shape=tile_shape, coarse_level=coarse_level,
+                  accel=accel, beta=beta)
         self.desc = d
         self.nx, self.ny = nx, ny
         self.shape = (ny + 2, nx + 2)
@@ -283,7 +285,8 @@ class Solver:
 
 def _desc(lib, nx, ny, lx=1.0, ly=1.0, bc=(FREE_SLIP,) * 4, precision=MIXED, levels=0, smoother=SMOOTH_GS,
           nu_pre=2, nu_post=2, nu_growth=1.0, omega=1.0, alpha=1.0, eta_mean=MEAN_ARITHMETIC, rtol=1e-8,
-          restart=20, max_iters=500, uzawa_steps=2, fused=True, msweep=-1, tile_shape=-1, coarse_level=-1):
+          restart=20, max_iters=500, uzawa_steps=2, fused=True, msweep=-1, tile_shape=-1, coarse_level=-1,
+          accel="fgmres", beta=1.0):
     d = _lib.Desc()
     lib.tph_desc_default(ctypes.byref(d), nx, ny)
     d.lx, d.ly = float(lx), float(ly)
@@ -294,6 +297,8 @@ def _desc(lib, nx, ny, lx=1.0, ly=1.0, bc=(FREE_SLIP,) * 4, precision=MIXED, lev
     d.omega, d.alpha, d.eta_mean, d.rtol = float(omega), float(alpha), int(eta_mean), float(rtol)
     d.restart, d.max_iters, d.uzawa_steps, d.fused = int(restart), int(max_iters), int(uzawa_steps), int(bool(fused))
     d.msweep, d.tile_shape, d.coarse_level = int(msweep), int(tile_shape), int(coarse_level)
+    d.accel = _lib.ACCEL_NAMES[accel.lower()] if isinstance(accel, str) else int(accel)
+    d.beta = float(beta)
     return d
 
 

@@ -21,6 +21,8 @@ FREE_SLIP, NO_SLIP = 0, 1
 FP64, MIXED = 0, 1
 SMOOTH_JACOBI, SMOOTH_GS = 0, 1
 MEAN_ARITHMETIC, MEAN_GEOMETRIC = 0, 1
+ACCEL_FGMRES, ACCEL_GCR, ACCEL_ANDERSON = 0, 1, 2
+ACCEL_NAMES = {"fgmres": ACCEL_FGMRES, "gcr": ACCEL_GCR, "anderson": ACCEL_ANDERSON}
 KERNEL_SMOOTH, KERNEL_APPLY, KERNEL_RESIDUAL, KERNEL_RESTRICT, KERNEL_PROLONG = 0, 1, 2, 3, 4
 
 
@@ -32,7 +34,7 @@ class Desc(ctypes.Structure):
                 ("eta_mean", c_int32), ("rtol", c_double), ("restart", c_int32),
                 ("max_iters", c_int32), ("uzawa_steps", c_int32), ("fused", c_int32),
                 ("msweep", c_int32), ("tile_shape", c_int32), ("coarse_level", c_int32),
-                ("reserved", c_int32 * 3)]
+                ("accel", c_int32), ("beta", c_double)]
 
 
 class Info(ctypes.Structure):

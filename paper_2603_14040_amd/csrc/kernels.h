@@ -40,10 +40,11 @@ hipError_t launch_precond_in(const Geom& g, Vec3 v, const double* eb, const doub
 // (accumulate: z_v += e, z_p += alpha eta_p (r_p - D e))
 template <typename T>
 struct LinkArgs;
-// one pass linking two Uzawa steps (apply = false) or the last step and the
-// Krylov apply (apply = true); see uzawa_link_cell
+// one pass linking two Uzawa steps (mode kLinkNext), the last step and the
+// Krylov apply (kLinkApply) or ending the last step (kLinkStore); see
+// uzawa_link_cell
 template <typename T>
-hipError_t launch_uzawa_link(const Geom& g, const LinkArgs<T>& a, bool apply, const double* eb, const double* ep,
+hipError_t launch_uzawa_link(const Geom& g, const LinkArgs<T>& a, int mode, const double* eb, const double* ep,
                              hipStream_t st);
 template <typename T>
 hipError_t launch_precond_out(const Geom& g, const T* ex, const T* ey, Vec3 v, const double* ep,
@@ -129,6 +130,44 @@ hipError_t launch_scale_by_rbeta(double* dst, const double* src, size_t n, const
 // x += sum_j y[j] Z_j  (k <= 8 per launch)
 hipError_t launch_update_x(double* x, const double* Z0, size_t zstride, int k, const double* y,
                            size_t n, hipStream_t st);
+// flexible GCR step (see k_gcr_step): coefficients by value, i <= kMaxRestart
+struct GcrStepArgs {
+    double* w;               // in: new direction A z (energy-scaled); out: w^ (normalised)
+    const double* W0;        // earlier w^_0 .. w^_{i-1}, stride apart
+    double* z;               // in: preconditioned z; out: z' (same combination as w)
+    const double* Z0;        // earlier z'_0 .. z'_{i-1}
+    double* x;
+    double* r;               // energy-scaled residual
+    size_t stride, n;
+    int i, orth_w;
+    double inv_nu, alpha;
+    double hw[kMaxRestart];
+    double hz[kMaxRestart];
+};
+hipError_t launch_gcr_step(const GcrStepArgs& a, hipStream_t st);
+// Anderson: dot products over the unknowns of three-field solution vectors
+// (vecs[i] and f are raw vector pointers, fields fstride apart), in chunks of
+// 8; partial rows as launch_multidot.  nblk = unknown_dot_blocks(g).
+constexpr int kVecSetMax = 8;
+struct VecSet { const double* v[kVecSetMax]; };
+int unknown_dot_blocks(const Geom& g);
+hipError_t launch_multidot_unknowns(const Geom& g, size_t fstride, const double* const* vecs, int nv,
+                                    const double* f, double* partial, int nblk, hipStream_t st, int norm_slot);
+// out = sum_v cx[v] X[v] + cf[v] F[v] over n entries; out may alias X[0] (and
+// no other input)
+struct MixArgs {
+    double* out;
+    size_t n;
+    int nv, acc;
+    const double* X[kVecSetMax];
+    const double* F[kVecSetMax];
+    double cx[kVecSetMax];
+    double cf[kVecSetMax];
+};
+hipError_t launch_mix(double* out, const double* const* X, const double* cx, const double* const* F,
+                      const double* cf, int nv, size_t n, hipStream_t st);
+// writes seq to mapped host memory after every earlier kernel of the stream
+hipError_t launch_post_seq(unsigned* host_seq, unsigned seq, hipStream_t st);
 // sum of p over cells -> partial; then p -= mean
 hipError_t launch_p_sum(const Geom& g, const double* p, double* partial, int* nblk_out, hipStream_t st);
 hipError_t launch_p_shift(const Geom& g, double* p, const double* sum, hipStream_t st);

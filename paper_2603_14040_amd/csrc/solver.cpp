@@ -207,7 +207,17 @@ tph_status validate_desc(const tph_desc* d, int* nlev_out) {
     if (!(d->omega > 0.0) || d->omega > 2.0) { set_error("omega must be in (0, 2]"); return TPH_ERR_INVALID; }
     if (!(d->alpha > 0.0) || !std::isfinite(d->alpha)) { set_error("alpha must be positive"); return TPH_ERR_INVALID; }
     if (!(d->rtol > 0.0) || !(d->rtol < 1.0)) { set_error("rtol must be in (0, 1)"); return TPH_ERR_INVALID; }
-    if (d->restart < 1 || d->restart > kMaxRestart) { set_error("restart must be in [1, 64]"); return TPH_ERR_INVALID; }
+    if (d->accel != TPH_ACCEL_FGMRES && d->accel != TPH_ACCEL_GCR && d->accel != TPH_ACCEL_ANDERSON) {
+        set_error("accel must be TPH_ACCEL_FGMRES, TPH_ACCEL_GCR or TPH_ACCEL_ANDERSON");
+        return TPH_ERR_INVALID;
+    }
+    if (d->accel == TPH_ACCEL_ANDERSON) {
+        if (d->restart < 0 || d->restart > kMaxRestart) { set_error("Anderson depth (restart) must be in [0, 64]"); return TPH_ERR_INVALID; }
+        if (!(d->beta > 0.0) || d->beta > 1.0) { set_error("beta must be in (0, 1]"); return TPH_ERR_INVALID; }
+    } else if (d->restart < 1 || d->restart > kMaxRestart) {
+        set_error("restart must be in [1, 64]");
+        return TPH_ERR_INVALID;
+    }
     if (d->max_iters < 1) { set_error("max_iters must be >= 1"); return TPH_ERR_INVALID; }
     if (d->uzawa_steps < 1 || d->uzawa_steps > 8) { set_error("uzawa_steps must be in [1, 8]"); return TPH_ERR_INVALID; }
     if (d->fused != 0 && d->fused != 1) { set_error("fused must be 0 or 1"); return TPH_ERR_INVALID; }
@@ -449,17 +459,19 @@ tph_status vcycle_fused(tph_solver* s, int l, int* cur_out) {
 // z = M^{-1} v applied uzawa_steps times as a stationary iteration from z = 0:
 // step 1: z = M^{-1} r; step k: z += M^{-1} (r - A z).  `energy`: v holds
 // W^(1/2) r (a Krylov basis vector).  With wraw (the Krylov apply inside
-// FGMRES), each step's exit is one link pass: the last one also forms
-// w = W^(-1/2) A z into wraw, the others the next step's right-hand side;
-// z alternates between zraw and t1 (the last step writes zraw), the
-// pressure residual between t3 and t2.
+// FGMRES and GCR) or `link`, each step's exit is one link pass: the last one
+// ends the step and, with wraw, also forms w = W^(1/2) A z there; the others
+// form the next step's right-hand side.  z alternates between zraw and t1
+// (the last step writes zraw), the pressure residual between t3 and t2.
+// Without either, each step runs as separate residual / entry / V-cycle /
+// exit kernels.
 template <typename T>
-tph_status precondition_t(tph_solver* s, double* vraw, double* zraw, bool energy, double* wraw) {
+tph_status precondition_t(tph_solver* s, double* vraw, double* zraw, bool energy, double* wraw, bool link) {
     LevelBuf& L = s->lev[0];
     const Vec3 v = vec3(s, vraw), z = vec3(s, zraw);
     const bool fused = s->d.fused == 1;
     const int S = s->d.uzawa_steps;
-    if (wraw) {
+    if (wraw || link) {
         const Vec3 zb[2] = {z, vec3(s, s->t1)};
         double* tpb[2] = {vec3(s, s->t3).p(), vec3(s, s->t2).p()};
         TPH_HIP(launch_precond_in<T>(L.g, v, L.eb64, L.ep64, energy, as<T>(L.rx), as<T>(L.ry), s->st));
@@ -481,9 +493,10 @@ tph_status precondition_t(tph_solver* s, double* vraw, double* zraw, bool energy
             a.rx = as<T>(L.rx);
             a.ry = as<T>(L.ry);
             a.tp = tpb[q & 1];
-            a.wout = vec3(s, wraw);
+            a.wout = wraw ? vec3(s, wraw) : Vec3{nullptr, 0};
             a.w_scaled = energy ? 1 : 0;
-            TPH_HIP(launch_uzawa_link<T>(L.g, a, q == S - 1, L.eb64, L.ep64, s->st));
+            const int mode = q < S - 1 ? kLinkNext : (wraw ? kLinkApply : kLinkStore);
+            TPH_HIP(launch_uzawa_link<T>(L.g, a, mode, L.eb64, L.ep64, s->st));
         }
         return TPH_OK;
     }
@@ -508,9 +521,10 @@ tph_status precondition_t(tph_solver* s, double* vraw, double* zraw, bool energy
     return TPH_OK;
 }
 
-tph_status precondition(tph_solver* s, double* vraw, double* zraw, bool energy, double* wraw = nullptr) {
-    return s->mixed() ? precondition_t<float>(s, vraw, zraw, energy, wraw)
-                      : precondition_t<double>(s, vraw, zraw, energy, wraw);
+tph_status precondition(tph_solver* s, double* vraw, double* zraw, bool energy, double* wraw = nullptr,
+                        bool link = false) {
+    return s->mixed() ? precondition_t<float>(s, vraw, zraw, energy, wraw, link)
+                      : precondition_t<double>(s, vraw, zraw, energy, wraw, link);
 }
 
 // reduce partial rows into `k` device scalars at slot; with to_host the same
@@ -654,7 +668,7 @@ tph_status fgmres(tph_solver* s, double* braw, tph_info* info) {
         gv[0] = beta;
         int jdone = 0;
         for (int j = 0; j < m; ++j) {
-            // z_j = M^{-1} v_j and w = W^(-1/2) A z_j (the apply fused into the last Uzawa step's exit)
+            // z_j = M^{-1} v_j and w = W^(1/2) A z_j (the apply fused into the last Uzawa step's exit)
             TPH_TRY(precondition(s, Vk(j), Zk(j), true, Vk(j + 1)));
             double* w = Vk(j + 1);
             // classical Gram-Schmidt with selective re-orthogonalisation: one
@@ -727,6 +741,348 @@ tph_status fgmres(tph_solver* s, double* braw, tph_info* info) {
     return result;
 }
 
+// ------------------------------------------------------------------ GCR
+// Restarted flexible GCR(m) (Alg. "Flexible GCR(m)") in the energy inner
+// product: r and the directions w = A z are stored scaled by W^(1/2), as the
+// FGMRES basis.  V_0 holds r, V_{i+1} the normalised w_i, Z_i the matching
+// z_i.  The Gram-Schmidt projection against the earlier w's is one classical
+// pass whose coefficients come from one multi-dot, with the norm of the
+// projected vector from Pythagoras; when that cancels (|w_perp|^2 < |w|^2 / 2)
+// the projection is carried out explicitly and repeated once, as for the
+// FGMRES basis.  Normalising the pair, x += alpha z and r -= alpha w are one
+// kernel.  alpha = <r, w_i> is taken from the same multi-dot, before the
+// projection: r is orthogonal to the earlier w's, so both agree up to
+// rounding.  |r|^2 then drops by alpha^2, which gives the convergence
+// estimate without another reduction; each restart recomputes the true
+// residual.
+tph_status gcr(tph_solver* s, double* braw, tph_info* info) {
+    const int m = s->d.restart;
+    const size_t n3 = s->n3;
+    const int nblk = flat_blocks(n3);
+    auto Vk = [&](int k) { return s->V + (size_t)k * n3; };
+    auto Zk = [&](int k) { return s->Z + (size_t)k * n3; };
+    const auto t0 = std::chrono::steady_clock::now();
+    {
+        TPH_HIP(hipMemsetAsync(s->t2, 0, n3 * sizeof(double), s->st));
+        TPH_TRY(energy_residual_vec(s, s->t2, braw, s->t1, kSlotMisc, true));
+        TPH_TRY(wait_signal(s));
+    }
+    const double bnorm = std::sqrt(s->hscal[kSlotMisc]);
+    if (!std::isfinite(bnorm)) { set_error("right-hand side is not finite"); return TPH_ERR_NONFINITE; }
+
+    int its = 0, restarts = 0;
+    double est = 0.0, true_res = 0.0;
+    tph_status result = TPH_NOT_CONVERGED;
+    double best_true = HUGE_VAL;
+    int stalled = 0;
+    bool stagnated = false;
+    GcrStepArgs a{};
+    while (true) {
+        TPH_TRY(energy_residual_vec(s, s->x, braw, Vk(0), kSlotMisc, true));
+        TPH_TRY(wait_signal(s));
+        const double beta = std::sqrt(s->hscal[kSlotMisc]);
+        if (!std::isfinite(beta)) { set_error("non-finite residual during the solve"); return TPH_ERR_NONFINITE; }
+        true_res = bnorm > 0 ? beta / bnorm : beta;
+        if (bnorm == 0.0 || true_res <= s->d.rtol) { result = TPH_OK; break; }
+        if (its >= s->d.max_iters) break;
+        if (true_res > 0.9 * best_true) {
+            if (++stalled >= 3) { stagnated = true; break; }
+        } else {
+            stalled = 0;
+        }
+        best_true = std::min(best_true, true_res);
+        ++restarts;
+        double rho2 = beta * beta;
+        for (int i = 0; i < m; ++i) {
+            double* w = Vk(i + 1);
+            double* z = Zk(i);
+            // z = M^{-1} r and w = W^(1/2) A z (the apply fused into the last Uzawa step's exit)
+            TPH_TRY(precondition(s, Vk(0), z, true, w));
+            // <r, w>, <w_j, w> (j < i) and |w|^2 in one pass
+            TPH_HIP(launch_multidot(Vk(0), n3, i + 1, w, n3, s->partial, nblk, s->st, i + 1));
+            TPH_TRY(reduce_to(s, nblk, i + 2, kSlotH1, true));
+            TPH_HIP(launch_post_seq(s->hseq_dev, ++s->seq, s->st));
+            TPH_TRY(wait_signal(s));
+            const double c = s->hscal[kSlotH1];
+            const double w2 = s->hscal[kSlotH1 + i + 1];
+            double h2 = 0.0;
+            for (int j = 0; j < i; ++j) {
+                a.hw[j] = a.hz[j] = s->hscal[kSlotH1 + 1 + j];
+                h2 += a.hz[j] * a.hz[j];
+            }
+            double nu2 = w2 - h2;
+            a.orth_w = 1;
+            if (i > 0 && !(nu2 >= 0.5 * w2)) {
+                TPH_HIP(launch_axpy_dot(w, Vk(1), n3, i, s->dscal + kSlotH1 + 1, n3, false, 0, s->partial, nblk,
+                                        s->st));
+                TPH_TRY(reduce_to(s, nblk, 1, kSlotNrm, true, true));
+                TPH_TRY(wait_signal(s));
+                nu2 = s->hscal[kSlotNrm];
+                if (nu2 < 0.5 * w2) {
+                    TPH_HIP(launch_multidot(Vk(1), n3, i, w, n3, s->partial, nblk, s->st));
+                    TPH_TRY(reduce_to(s, nblk, i, kSlotH2, true));
+                    TPH_HIP(launch_axpy_dot(w, Vk(1), n3, i, s->dscal + kSlotH2, n3, false, 0, s->partial, nblk,
+                                            s->st));
+                    TPH_TRY(reduce_to(s, nblk, 1, kSlotNrm, true, true));
+                    TPH_TRY(wait_signal(s));
+                    for (int j = 0; j < i; ++j) a.hz[j] += s->hscal[kSlotH2 + j];
+                    nu2 = s->hscal[kSlotNrm];
+                    ++s->reorth_count;
+                }
+                a.orth_w = 0;   // w already projected; z takes the accumulated coefficients
+            }
+            if (!std::isfinite(nu2) || !std::isfinite(c)) {
+                set_error("non-finite value in the GCR directions");
+                return TPH_ERR_NONFINITE;
+            }
+            if (!(nu2 > 0.0)) break;   // the new direction adds nothing: restart
+            const double nu = std::sqrt(nu2);
+            a.w = w;
+            a.W0 = Vk(1);
+            a.z = z;
+            a.Z0 = Zk(0);
+            a.x = s->x;
+            a.r = Vk(0);
+            a.stride = n3;
+            a.n = n3;
+            a.i = i;
+            a.inv_nu = 1.0 / nu;
+            a.alpha = c / nu;
+            TPH_HIP(launch_gcr_step(a, s->st));
+            rho2 = std::max(rho2 - a.alpha * a.alpha, 0.0);
+            est = std::sqrt(rho2) / bnorm;
+            if (info && info->history && its < info->history_len) info->history[its] = est;
+            ++its;
+            if (est <= s->d.rtol || its >= s->d.max_iters) break;
+        }
+    }
+    TPH_TRY(remove_pressure_mean(s, s->x));
+    TPH_HIP(hipStreamSynchronize(s->st));
+    const auto t1 = std::chrono::steady_clock::now();
+    if (info) {
+        info->iters = its;
+        info->restarts = restarts;
+        info->res_energy = true_res;
+        info->res_estimate = its ? est : true_res;
+        info->t_setup_ms = s->t_setup_ms;
+        info->t_solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    }
+    if (result == TPH_NOT_CONVERGED)
+        set_error(std::string(stagnated ? "GCR stagnated (rounding floor of the residual)" : "GCR reached max_iters") +
+                  " with relative energy residual " + std::to_string(true_res));
+    return result;
+}
+
+// ------------------------------------------------------------- Anderson
+// alpha minimising |sum_i alpha_i f_i|_2 subject to sum_i alpha_i = 1, from
+// the Gram matrix G (n x n, row-major) of the window f_0 .. f_{n-1}.
+// Eliminating the constraint (alpha_{n-1} = 1 - sum of the others) leaves the
+// normal equations N g = -q, N_ij = (f_i - f_l).(f_j - f_l),
+// q_i = (f_i - f_l).f_l (l = n - 1), which are solved by Cholesky with
+// diagonal pivoting; directions whose pivot falls below 1e-13 of the largest
+// diagonal entry are dropped (a rank-deficient window), their coefficients
+// left at zero.
+void aa_coefficients(const std::vector<double>& G, int n, std::vector<double>& alpha) {
+    alpha.assign(n, 0.0);
+    alpha[n - 1] = 1.0;
+    const int k = n - 1;
+    if (k == 0) return;
+    const int l = n - 1;
+    std::vector<double> N((size_t)k * k), rhs(k);
+    std::vector<int> perm(k);
+    double dmax = 0.0;
+    for (int i = 0; i < k; ++i) {
+        for (int j = 0; j < k; ++j)
+            N[(size_t)i * k + j] = G[(size_t)i * n + j] - G[(size_t)i * n + l] - G[(size_t)l * n + j] + G[(size_t)l * n + l];
+        rhs[i] = -(G[(size_t)i * n + l] - G[(size_t)l * n + l]);
+        perm[i] = i;
+        dmax = std::max(dmax, N[(size_t)i * k + i]);
+    }
+    if (!(dmax > 0.0)) return;
+    int r = 0;
+    for (; r < k; ++r) {
+        int p = r;
+        for (int t = r + 1; t < k; ++t)
+            if (N[(size_t)t * k + t] > N[(size_t)p * k + p]) p = t;
+        if (!(N[(size_t)p * k + p] > 1e-13 * dmax)) break;
+        if (p != r) {
+            for (int t = 0; t < k; ++t) std::swap(N[(size_t)r * k + t], N[(size_t)p * k + t]);
+            for (int t = 0; t < k; ++t) std::swap(N[(size_t)t * k + r], N[(size_t)t * k + p]);
+            std::swap(rhs[r], rhs[p]);
+            std::swap(perm[r], perm[p]);
+        }
+        const double d = std::sqrt(N[(size_t)r * k + r]);
+        N[(size_t)r * k + r] = d;
+        for (int t = r + 1; t < k; ++t) N[(size_t)t * k + r] /= d;
+        for (int t = r + 1; t < k; ++t)
+            for (int u = r + 1; u <= t; ++u) {
+                N[(size_t)t * k + u] -= N[(size_t)t * k + r] * N[(size_t)u * k + r];
+                N[(size_t)u * k + t] = N[(size_t)t * k + u];
+            }
+    }
+    // L y = rhs, L^T g = y on the leading r x r block
+    std::vector<double> y(r);
+    for (int i = 0; i < r; ++i) {
+        double t = rhs[i];
+        for (int j = 0; j < i; ++j) t -= N[(size_t)i * k + j] * y[j];
+        y[i] = t / N[(size_t)i * k + i];
+    }
+    double sum = 0.0;
+    for (int i = r - 1; i >= 0; --i) {
+        double t = y[i];
+        for (int j = i + 1; j < r; ++j) t -= N[(size_t)j * k + i] * y[j];
+        y[i] = t / N[(size_t)i * k + i];
+    }
+    for (int i = 0; i < r; ++i) {
+        alpha[perm[i]] = y[i];
+        sum += y[i];
+    }
+    alpha[l] = 1.0 - sum;
+}
+
+// AA(m) with mixing beta (Alg. "Anderson Acceleration(m) with Mixing") on the
+// Uzawa fixed-point map G(x) = x + M^{-1}(b - A x).  A ring of m + 1 slots
+// holds the iterates x_i (V_0 .. V_m) and their corrections f_i = G(x_i) - x_i
+// (Z_0 .. Z_m); iterate k lives in slot k mod (m + 1) and V_{m+1} takes the
+// residual.  Per iteration, behind one host wait: the energy residual of x_k
+// and its norm, f_k = M^{-1}(b - A x_k) through the link path, and the new
+// row of the Gram matrix of the window (dot products over the unknowns).  The
+// host then solves the constrained least-squares problem and one kernel
+// forms x_{k+1} = sum_i alpha_i (x_i + beta f_i), which is the paper's
+// (1 - beta) sum alpha_i x_i + beta sum alpha_i G(x_i).  The first step is
+// x_1 = G(x_0).  When x_k has converged, the f_k computed alongside its
+// residual is not used.
+tph_status anderson(tph_solver* s, double* braw, tph_info* info) {
+    const int m = s->d.restart;
+    const int ns = m + 1;
+    const double beta_mix = s->d.beta;
+    const size_t n3 = s->n3;
+    const Geom& g0 = s->lev[0].g;
+    const int nblk_u = unknown_dot_blocks(g0);
+    auto Xk = [&](long long k) { return s->V + (size_t)(k % ns) * n3; };
+    auto Fk = [&](long long k) { return s->Z + (size_t)(k % ns) * n3; };
+    double* R = s->V + (size_t)ns * n3;
+    const auto t0 = std::chrono::steady_clock::now();
+    {
+        TPH_HIP(hipMemsetAsync(s->t2, 0, n3 * sizeof(double), s->st));
+        TPH_TRY(energy_residual_vec(s, s->t2, braw, s->t1, kSlotMisc, true));
+        TPH_TRY(wait_signal(s));
+    }
+    const double bnorm = std::sqrt(s->hscal[kSlotMisc]);
+    if (!std::isfinite(bnorm)) { set_error("right-hand side is not finite"); return TPH_ERR_NONFINITE; }
+    TPH_HIP(hipMemcpyAsync(Xk(0), s->x, n3 * sizeof(double), hipMemcpyDeviceToDevice, s->st));
+
+    std::vector<double> gram((size_t)ns * ns, 0.0), Gw, alpha, cx, cf;
+    std::vector<const double*> xs, fs;
+    long long k = 0;
+    double true_res = 0.0, best = HUGE_VAL;
+    int stalled = 0;
+    const int stall_limit = std::max(30, 3 * ns);
+    bool stagnated = false;
+    tph_status result = TPH_NOT_CONVERGED;
+    while (true) {
+        const int mk = (int)std::min<long long>(m, k);
+        // residual of x_k and its norm
+        {
+            const LevelBuf& L = s->lev[0];
+            int nblk = 0;
+            Vec3 b = vec3(s, braw);
+            TPH_HIP(launch_outer_residual(L.g, vec3(s, Xk(k)), &b, L.eb64, L.ep64, vec3(s, R), ResMode::kResidual,
+                                          true, s->partial, &nblk, s->st));
+            TPH_TRY(reduce_to(s, nblk, 1, kSlotMisc, true));
+        }
+        const bool more = k < s->d.max_iters;
+        if (more) {
+            TPH_TRY(precondition(s, R, Fk(k), true, nullptr, true));
+            // f_k . f_i over the window (oldest first) and |f_k|^2
+            fs.clear();
+            for (long long i = k - mk; i < k; ++i) fs.push_back(Fk(i));
+            TPH_HIP(launch_multidot_unknowns(g0, s->F, fs.data(), mk, Fk(k), s->partial, nblk_u, s->st, mk));
+            TPH_TRY(reduce_to(s, nblk_u, mk + 1, kSlotH1, true));
+        }
+        TPH_HIP(launch_post_seq(s->hseq_dev, ++s->seq, s->st));
+        TPH_TRY(wait_signal(s));
+        const double rn = std::sqrt(s->hscal[kSlotMisc]);
+        if (!std::isfinite(rn)) { set_error("non-finite residual during the solve"); return TPH_ERR_NONFINITE; }
+        true_res = bnorm > 0 ? rn / bnorm : rn;
+        if (k > 0 && info && info->history && k - 1 < info->history_len) info->history[k - 1] = true_res;
+        if (bnorm == 0.0 || true_res <= s->d.rtol) { result = TPH_OK; break; }
+        if (!more) break;
+        if (true_res <= 0.9 * best) {
+            best = true_res;
+            stalled = 0;
+        } else if (++stalled >= stall_limit) {
+            stagnated = true;
+            break;
+        }
+        // Gram row of f_k, then the window's Gram matrix (oldest first)
+        const int sk = (int)(k % ns);
+        for (int c = 0; c < mk; ++c) {
+            const int sc = (int)((k - mk + c) % ns);
+            const double v = s->hscal[kSlotH1 + c];
+            gram[(size_t)sk * ns + sc] = v;
+            gram[(size_t)sc * ns + sk] = v;
+        }
+        gram[(size_t)sk * ns + sk] = s->hscal[kSlotH1 + mk];
+        if (!std::isfinite(gram[(size_t)sk * ns + sk])) {
+            set_error("non-finite value in the Anderson corrections");
+            return TPH_ERR_NONFINITE;
+        }
+        const int n = mk + 1;
+        if (k == 0) {
+            alpha.assign(1, 1.0);
+        } else {
+            Gw.assign((size_t)n * n, 0.0);
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j)
+                    Gw[(size_t)i * n + j] = gram[(size_t)((k - mk + i) % ns) * ns + (size_t)((k - mk + j) % ns)];
+            aa_coefficients(Gw, n, alpha);
+        }
+        xs.clear();
+        fs.clear();
+        cx.assign(n, 0.0);
+        cf.assign(n, 0.0);
+        const double bm = k == 0 ? 1.0 : beta_mix;   // x_1 = G(x_0)
+        for (int i = 0; i < n; ++i) {
+            xs.push_back(Xk(k - mk + i));
+            fs.push_back(Fk(k - mk + i));
+            cx[i] = alpha[i];
+            cf[i] = bm * alpha[i];
+            if (!std::isfinite(alpha[i])) {
+                set_error("non-finite Anderson coefficients");
+                return TPH_ERR_NONFINITE;
+            }
+        }
+        // the output slot is the oldest iterate's when the window is full: it comes first
+        TPH_HIP(launch_mix(Xk(k + 1), xs.data(), cx.data(), fs.data(), cf.data(), n, n3, s->st));
+        ++k;
+    }
+    TPH_HIP(hipMemcpyAsync(s->x, Xk(k), n3 * sizeof(double), hipMemcpyDeviceToDevice, s->st));
+    TPH_TRY(remove_pressure_mean(s, s->x));
+    TPH_HIP(hipStreamSynchronize(s->st));
+    const auto t1 = std::chrono::steady_clock::now();
+    if (info) {
+        info->iters = (int32_t)k;
+        info->restarts = 0;
+        info->res_energy = true_res;
+        info->res_estimate = true_res;
+        info->t_setup_ms = s->t_setup_ms;
+        info->t_solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    }
+    if (result == TPH_NOT_CONVERGED)
+        set_error(std::string(stagnated ? "Anderson acceleration stagnated" : "Anderson acceleration reached max_iters") +
+                  " with relative energy residual " + std::to_string(true_res));
+    return result;
+}
+
+tph_status accelerate(tph_solver* s, double* braw, tph_info* info) {
+    switch (s->d.accel) {
+        case TPH_ACCEL_GCR: return gcr(s, braw, info);
+        case TPH_ACCEL_ANDERSON: return anderson(s, braw, info);
+        default: return fgmres(s, braw, info);
+    }
+}
+
 tph_status require_ready(tph_solver* s) {
     if (!s) { set_error("solver is NULL"); return TPH_ERR_INVALID; }
     if (!s->ready) { set_error("tph_set_coefficients has not succeeded on this solver"); return TPH_ERR_INVALID; }
@@ -784,8 +1140,11 @@ tph_status create_impl(const tph_desc* desc, void* stream, tph_solver* s) {
     TPH_TRY(dev_alloc(s, (void**)&s->t1, vb));
     TPH_TRY(dev_alloc(s, (void**)&s->t2, vb));
     TPH_TRY(dev_alloc(s, (void**)&s->t3, vb));
-    TPH_TRY(dev_alloc(s, (void**)&s->V, vb * (desc->restart + 1)));
-    TPH_TRY(dev_alloc(s, (void**)&s->Z, vb * desc->restart));
+    // FGMRES: m + 1 basis vectors, m preconditioned ones; GCR: r and m
+    // directions w, m directions z; Anderson: m + 1 iterates and the residual,
+    // m + 1 corrections
+    TPH_TRY(dev_alloc(s, (void**)&s->V, vb * (desc->restart + 2)));
+    TPH_TRY(dev_alloc(s, (void**)&s->Z, vb * (desc->restart + 1)));
     void* p = nullptr;
     TPH_TRY(alloc_field(s, g0, sizeof(double), &p)); s->rho = (double*)p;
     TPH_TRY(alloc_field(s, g0, sizeof(double), &p)); s->fxe = (double*)p;
@@ -1096,6 +1455,8 @@ void tph_desc_default(tph_desc* d, int32_t nx, int32_t ny) {
     d->eta_mean = TPH_MEAN_ARITHMETIC;
     d->rtol = 1e-8;
     d->restart = 20;
+    d->accel = TPH_ACCEL_FGMRES;
+    d->beta = 1.0;
     d->max_iters = 500;
     d->uzawa_steps = 2;
     d->fused = 1;
@@ -1134,7 +1495,7 @@ tph_status tph_solve(tph_solver* s, double* vx, double* vy, double* p, tph_info*
     TPH_TRY(require_ready(s));
     if (!vx || !vy || !p) { set_error("vx, vy and p are required"); return TPH_ERR_INVALID; }
     TPH_TRY(load_solution(s, s->x, vx, vy, p));
-    const tph_status r = fgmres(s, s->b, info);
+    const tph_status r = accelerate(s, s->b, info);
     if (r < 0) return r;
     TPH_TRY(store_solution(s, s->x, vx, vy, p));
     TPH_HIP(hipStreamSynchronize(s->st));
@@ -1207,7 +1568,7 @@ tph_status tph_solve_continuation(tph_solver* s, const double* eta_b, const doub
             st.history_len = info->history_len - tot.iters;
         }
         s->d.rtol = k == nthetas - 1 ? rtol : std::max(stage_rtol, rtol);
-        r = fgmres(s, s->b, &st);
+        r = accelerate(s, s->b, &st);
         s->d.rtol = rtol;
         tot.iters += st.iters;
         tot.restarts += st.restarts;
@@ -1238,7 +1599,7 @@ tph_status tph_solve_rhs(tph_solver* s, const double* fx, const double* fy, cons
     if (!vx || !vy || !p) { set_error("vx, vy and p are required"); return TPH_ERR_INVALID; }
     TPH_TRY(load_solution(s, s->b2, fx, fy, fp));
     TPH_TRY(load_solution(s, s->x, vx, vy, p));
-    const tph_status r = fgmres(s, s->b2, info);
+    const tph_status r = accelerate(s, s->b2, info);
     if (r < 0) return r;
     TPH_TRY(store_solution(s, s->x, vx, vy, p));
     TPH_HIP(hipStreamSynchronize(s->st));
@@ -1367,7 +1728,7 @@ tph_status tph_solve_adjoint(tph_solver* s, const double* gvx, const double* gvy
     TPH_HIP(launch_fold_ghost_grad(g, r, s->st));
     TPH_TRY(remove_pressure_mean(s, s->b2));
     TPH_HIP(hipMemsetAsync(s->x, 0, s->n3 * sizeof(double), s->st));
-    const tph_status st = fgmres(s, s->b2, info);
+    const tph_status st = accelerate(s, s->b2, info);
     if (st < 0) return st;
     TPH_TRY(store_solution(s, s->x, lvx, lvy, lp));
     TPH_HIP(hipStreamSynchronize(s->st));

@@ -420,12 +420,16 @@ hipError_t launch_precond_out(const Geom& g, const T* ex, const T* ey, Vec3 v, c
 }
 
 template <typename T>
-hipError_t launch_uzawa_link(const Geom& g, const LinkArgs<T>& a, bool apply, const double* eb, const double* ep,
+hipError_t launch_uzawa_link(const Geom& g, const LinkArgs<T>& a, int mode, const double* eb, const double* ep,
                              hipStream_t st) {
-    if (apply)
+    if (mode == kLinkApply)
         hipLaunchKernelGGL((k_uzawa_link<T, kLinkApply>), grid_cells(g), dim3(BX, BY), 0, st, g, a, eb, ep);
-    else
+    else if (mode == kLinkStore)
+        hipLaunchKernelGGL((k_uzawa_link<T, kLinkStore>), grid_cells(g), dim3(BX, BY), 0, st, g, a, eb, ep);
+    else if (mode == kLinkNext)
         hipLaunchKernelGGL((k_uzawa_link<T, kLinkNext>), grid_cells(g), dim3(BX, BY), 0, st, g, a, eb, ep);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -497,7 +501,7 @@ hipError_t launch_cast_f64_f32(const double* src, float* dst, size_t n, hipStrea
                                              hipStream_t);                                                   \
     template hipError_t launch_precond_out<T>(const Geom&, const T*, const T*, Vec3, const double*, bool,    \
                                               double, Vec3, hipStream_t, bool);                              \
-    template hipError_t launch_uzawa_link<T>(const Geom&, const LinkArgs<T>&, bool, const double*,           \
+    template hipError_t launch_uzawa_link<T>(const Geom&, const LinkArgs<T>&, int, const double*,           \
                                              const double*, hipStream_t);
 TPH_INST(float)
 TPH_INST(double)

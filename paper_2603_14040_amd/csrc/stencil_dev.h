@@ -114,12 +114,13 @@ __device__ __forceinline__ void precond_out_cell(const Geom& g, const T* __restr
 // (z_old = 0 at the first step), written to zout, then either
 //   kLinkNext:  t = r - A z_new  -> FP32/FP64 right-hand side of the next
 //               V-cycle (velocity) and tp (FP64 pressure part), or
-//   kLinkApply: w = A z_new (energy-scaled for a Krylov basis) into wout.
+//   kLinkApply: w = A z_new (energy-scaled for a Krylov basis) into wout, or
+//   kLinkStore: nothing more (the last step when no apply is wanted).
 // z_new at the neighbouring nodes the stencil needs is recomputed from e and
 // z_old there (both carry mirrored ghosts and zero walls), so no pass
 // waits for another; zout and zold must be different arrays.
 // ---------------------------------------------------------------------------
-enum { kLinkNext = 0, kLinkApply = 1 };
+enum { kLinkNext = 0, kLinkApply = 1, kLinkStore = 2 };
 
 template <typename T>
 struct LinkArgs {
@@ -137,7 +138,7 @@ struct LinkArgs {
     T* ry;
     double* tp;
     Vec3 wout;              // kLinkApply
-    int w_scaled;           // kLinkApply: w = W^(-1/2) A z (Krylov basis scaling) instead of A z
+    int w_scaled;           // kLinkApply: w = W^(1/2) A z (Krylov basis scaling) instead of A z
 };
 
 template <typename T>
@@ -190,6 +191,7 @@ __device__ __forceinline__ void uzawa_link_cell(const Geom& g, const LinkArgs<T>
         if (j == g.nx) a.zout.vy()[c + 1] = (double)g.mir[1] * zy[4];
     }
     a.zout.p()[c] = zpc;
+    if (MODE == kLinkStore) return;
     const double* X = zx + 4;
     const double* Y = zy + 4;
     const double* B = pb + 4;

@@ -31,7 +31,9 @@ def test_struct_layout_matches_header(lib):
     lib.tph_desc_default(ctypes.byref(d), 64, 32)
     assert (d.nx, d.ny, d.lx, d.precision, d.restart) == (64, 32, 1.0, _lib.MIXED, 20)
     assert d.rtol == 1e-8 and d.nu_growth == 1.0 and d.uzawa_steps == 2 and d.fused == 1
-    assert d.msweep == -1 and d.tile_shape == -1 and d.coarse_level == -1 and list(d.reserved) == [0] * 3
+    assert d.msweep == -1 and d.tile_shape == -1 and d.coarse_level == -1
+    assert d.accel == _lib.ACCEL_FGMRES and d.beta == 1.0
+    assert _lib.Desc.accel.offset == 132 and _lib.Desc.beta.offset == 136
 
 
 def _create(lib, **kw):
@@ -61,6 +63,12 @@ def _create(lib, **kw):
     (dict(tile_shape=-5), "tile_shape"),
     (dict(coarse_level=-3), "coarse_level"),
     (dict(coarse_level=0, nx=256, ny=256), "coarse_level"),
+    (dict(accel=3), "accel"),
+    (dict(accel=1, restart=0), "restart"),
+    (dict(accel=2, restart=-1), "Anderson depth"),
+    (dict(accel=2, restart=65), "Anderson depth"),
+    (dict(accel=2, beta=0.0), "beta"),
+    (dict(accel=2, beta=1.5), "beta"),
 ])
 def test_invalid_descriptor_rejected_on_host(lib, kw, needle):
     st, h, msg = _create(lib, **kw)
