@@ -59,6 +59,8 @@ def main():
     ap.add_argument("--batch", type=int, default=256, help="problems in the batched workload (0: skip)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-gradient workload")
     ap.add_argument("--large", type=int, default=4096, help="cells per side of the multi-inclusion workload (0: skip)")
+    ap.add_argument("--accel-steps", type=int, default=5,
+                    help="timed steps of the GCR and Anderson solves of the main workload (0: skip)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -147,6 +149,57 @@ def main():
     if fp64_steps > 0:
         s64, ms_64, inf_64 = run(tph.FP64, fp64_steps, 1, "fp64")
     plan0 = s_mix.level_plan(0)
+
+    # the accelerators of Sec. "Accelerators" on the same workload, mixed precision, with the tuned schedule
+    # and kernel plan: flexible GCR(m) (restart tuned) and Anderson AA(m, beta) (depth and mixing tuned);
+    # the tuning is untimed, each timed step is set_coefficients + solve as above
+    accels = {}
+    if args.accel_steps > 0:
+        from paper_2603_14040_amd.autotune import Knob
+        base = dict(tuned["mixed"]["params"])
+        space = {"gcr": [Knob("restart", [5, 8, 10, 15, 20, 30])],
+                 "anderson": [Knob("restart", [3, 5, 8, 10, 15, 20]), Knob("beta", [0.5, 0.7, 0.85, 1.0])]}
+        first = {"gcr": {"restart": int(base.get("restart", 20))}, "anderson": {"restart": 10, "beta": 1.0}}
+        for name in ("gcr", "anderson"):
+            params = dict(base, accel=name, **first[name])
+            at_ = None
+            if not args.no_tune:
+                at_ = autotune.tune(eb, ep, rho, pr.gx, pr.gy, precision=tph.MIXED, reps=1, rounds=1, device=dev,
+                                    knobs=space[name], start=params)
+                params = at_["params"]
+                log(f"[bench] {name}: tuned restart {params['restart']} beta {params['beta']} ({at_['trials']} trials)")
+            sa_ = tph.Solver(n, n, precision=tph.MIXED, device=dev, **params)
+            ax_, ay_, ap_ = sa_.zeros(), sa_.zeros(), sa_.zeros()
+
+            def astep_():
+                ax_.zero_(); ay_.zero_(); ap_.zero_()
+                sa_.set_coefficients(eb, ep, rho, pr.gx, pr.gy)
+                return sa_.solve(ax_, ay_, ap_)[3]
+
+            astep_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ainf = [astep_() for _ in range(args.accel_steps)]
+            torch.cuda.synchronize()
+            ams = 1e3 * (time.perf_counter() - t0) / args.accel_steps
+            if any(i.status != "TPH_OK" for i in ainf):
+                raise RuntimeError(f"{name} solve did not converge: {ainf[-1]}")
+            kind = tph._lib.KERNEL_GCR_STEP if name == "gcr" else tph._lib.KERNEL_AA_MIX
+            kms, kby = sa_.time_kernel(kind, 100)
+            kgbs = kby / (kms * 1e-3) / 1e9
+            accels[name] = {"ms_per_step": ams, "value": cells / (ams * 1e-3), "unit": "cells/s",
+                            "iters": ainf[-1].iters, "res_energy": ainf[-1].res_energy,
+                            "restart": params["restart"], "beta": params["beta"] if name == "anderson" else None,
+                            "tuning_trials": at_["trials"] if at_ else 0,
+                            "kernel": {"name": "k_gcr_step" if name == "gcr" else "k_mix",
+                                       "what": ("GCR step update with restart/2 earlier pairs" if name == "gcr"
+                                                else "Anderson mixing over restart + 1 stored pairs"),
+                                       "us": round(kms * 1e3, 2), "bytes": kby, "GBps": round(kgbs, 1),
+                                       "frac": round(kgbs / HBM_PEAK_GBS, 4)}}
+            log(f"[bench] {name}: {ams:.2f} ms/step, iters {ainf[-1].iters}, res {ainf[-1].res_energy:.2e}; "
+                f"{accels[name]['kernel']['name']} {kgbs:.0f} GB/s")
+            sa_.close()
+            del sa_
 
     # dominant kernel: finest-level smoother of the mixed path, HIP events on the solver stream
     kern = {}
@@ -346,7 +399,8 @@ def main():
         "dtype": "f32 V-cycle + f64 Krylov/residual (mixed)",
         "data": "synthetic",
         "config": {"workload": f"random-viscosity {n}x{n} cells, log10 eta Gaussian random field "
-                               f"(corr. length 0.05, contrast 1e4), free slip, FGMRES({s_mix.desc.restart}) + "
+                               f"(corr. length 0.05, contrast 1e4), free slip, "
+                               f"{['FGMRES', 'GCR', 'Anderson'][s_mix.desc.accel]}({s_mix.desc.restart}) + "
                                f"{s_mix.levels}-level V-cycle, relative energy residual 1e-8",
                    "cells": cells, "levels": s_mix.levels, "precision": "mixed", "global_batch": 1},
         "iters": inf_mix[-1].iters,
@@ -356,6 +410,7 @@ def main():
         "fp64": ({"value": cells / (ms_64 * 1e-3), "ms_per_step": ms_64, "iters": inf_64[-1].iters,
                   "res_energy": inf_64[-1].res_energy} if fp64_steps > 0 else None),
         "mixed_speedup_vs_fp64": ms_64 / ms_mix if fp64_steps > 0 else None,
+        "accelerators": accels or None,
         "tuned": tuned,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,

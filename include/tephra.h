@@ -286,7 +286,12 @@ enum {
     TPH_KERNEL_APPLY = 1,    /* FP64 matrix-free operator apply with energy scaling (Krylov step) */
     TPH_KERNEL_RESIDUAL = 2, /* finest-level velocity residual r - L e in the V-cycle type */
     TPH_KERNEL_RESTRICT = 3, /* finest -> second level residual restriction */
-    TPH_KERNEL_PROLONG = 4   /* second -> finest level prolongation and correction */
+    TPH_KERNEL_PROLONG = 4,  /* second -> finest level prolongation and correction */
+    TPH_KERNEL_GCR_STEP = 5, /* flexible GCR step update (Alg. "Flexible GCR(m)"): project and
+                                normalise the new (w, z) pair against i = restart / 2 earlier
+                                pairs, update x and r (FP64, every entry of the vectors) */
+    TPH_KERNEL_AA_MIX = 6    /* Anderson mixing x = sum_i alpha_i (x_i + beta f_i) over
+                                restart + 1 stored pairs (FP64, every entry of the vectors) */
 };
 
 /* Measurement hook: run `reps` back-to-back launches of one hot-path kernel
@@ -294,7 +299,8 @@ enum {
  * duration per launch (*ms_per_launch) and the algorithmic bytes one launch
  * must move (*bytes_per_launch: each field word the operation reads or
  * writes, counted once).  Requires tph_set_coefficients; the kernels operate
- * on the solver's own workspace (the correction arrays are modified). */
+ * on the solver's own workspace (the correction arrays, Krylov vectors and
+ * the solution held between solves are modified; caller arrays are not). */
 tph_status tph_time_kernel(tph_solver* s, int32_t kind, int32_t reps, double* ms_per_launch,
                            double* bytes_per_launch);
 

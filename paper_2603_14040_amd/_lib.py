@@ -24,6 +24,7 @@ MEAN_ARITHMETIC, MEAN_GEOMETRIC = 0, 1
 ACCEL_FGMRES, ACCEL_GCR, ACCEL_ANDERSON = 0, 1, 2
 ACCEL_NAMES = {"fgmres": ACCEL_FGMRES, "gcr": ACCEL_GCR, "anderson": ACCEL_ANDERSON}
 KERNEL_SMOOTH, KERNEL_APPLY, KERNEL_RESIDUAL, KERNEL_RESTRICT, KERNEL_PROLONG = 0, 1, 2, 3, 4
+KERNEL_GCR_STEP, KERNEL_AA_MIX = 5, 6
 
 
 class Desc(ctypes.Structure):

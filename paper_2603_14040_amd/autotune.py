@@ -1,9 +1,9 @@
 """Autotuner of the solver's kernel plan and sweep schedule.
 
 The converged answer of a solve does not depend on any parameter tuned
-here: the V-cycle/Uzawa step is only the preconditioner of the flexible
-Krylov iteration, which converges to the same discrete solution (the
-paper's Sec. "Comparison with FGMRES" and its multigrid sections).  The
+here: the V-cycle/Uzawa step is only the preconditioner of the accelerator
+(flexible GMRES, GCR or Anderson), which converges to the same discrete
+solution (the paper's Sec. "Accelerators" and its multigrid sections).  The
 parameters trade work per iteration against the number of iterations and
 map the work onto the chip differently, so the fastest choice depends on
 the grid, the viscosity structure and the device.  The tuner measures
@@ -17,7 +17,9 @@ Knobs (all of them descriptor fields of tph_create):
     level-dependent schedule, nu_l = ceil(nu * growth^l));
   * Uzawa sweeps per preconditioner application (``uzawa_steps``, 1..8) and the
     Uzawa pressure relaxation ``alpha``; the smoother damping ``omega``;
-  * FGMRES restart length.
+  * the Krylov accelerator (flexible GMRES or GCR) and its restart length;
+    for Anderson acceleration (tuned from an explicit knob list) the depth
+    (``restart``) and the mixing ``beta``.
 Parameter sets that resolve to the same kernel plan on every level are
 measured once.
 
@@ -153,16 +155,23 @@ def solver_kwargs(p: Params, tile_levels: Sequence[int]) -> dict:
     return dict(nu_pre=int(p["nu_pre"]), nu_post=int(p["nu_post"]), nu_growth=float(p.get("nu_growth", 1.0)),
                 uzawa_steps=int(p["uzawa_steps"]), restart=int(p["restart"]), msweep=msw, tile_shape=shp,
                 coarse_level=int(p.get("coarse_level", -1)), omega=float(p.get("omega", 1.0)),
-                alpha=float(p.get("alpha", 1.0)))
+                alpha=float(p.get("alpha", 1.0)), accel=str(p.get("accel", "fgmres")),
+                beta=float(p.get("beta", 1.0)))
 
 
 def knobs_for(tile_levels: Sequence[int], coarse_levels: Sequence[int] = (), nus=(1, 2, 3),
               growths=(1.0, 1.5, 2.0), uzawa=(1, 2, 3, 4, 6, 8), restarts=(5, 8, 10, 15, 20, 30, 50, 64),
-              alphas=(1.0, 1.5, 2.0, 3.0), omegas=(0.8, 1.0, 1.2)) -> List[Knob]:
-    """Schedule knobs first (they move the iteration count), then the kernel plan."""
+              alphas=(1.0, 1.5, 2.0, 3.0), omegas=(0.8, 1.0, 1.2),
+              accels=("fgmres", "gcr")) -> List[Knob]:
+    """Schedule knobs first (they move the iteration count), then the kernel plan.
+
+    The Krylov accelerator (flexible GMRES or GCR, both residual-minimising
+    over the preconditioned directions) is a knob beside its restart length."""
     ks = [Knob("alpha", list(alphas)), Knob("uzawa_steps", list(uzawa)), Knob("nu_pre", list(nus)),
           Knob("nu_post", list(nus)), Knob("omega", list(omegas)), Knob("nu_growth", list(growths)),
           Knob("restart", list(restarts))]
+    if len(accels) > 1:
+        ks.append(Knob("accel", list(accels)))
     if coarse_levels:
         ks.append(Knob("coarse_level", [-1] + list(coarse_levels)))
     ks += [Knob(f"L{l}", [(0, 0), (0, 1), (1, 0), (1, 1)]) for l in tile_levels]
@@ -183,12 +192,14 @@ def tune(eta_b, eta_p, rho_b, gx: float = 0.0, gy: float = -1.0, *, precision: O
          lx: float = 1.0, ly: float = 1.0, bc=(0, 0, 0, 0), rtol: float = 1e-8, reps: int = 3, rounds: int = 2,
          rel_gain: float = 0.02, db: Optional[TuningDB] = None, tag: str = "", device=None,
          knobs: Optional[Sequence[Knob]] = None, log: Optional[Callable[[str], None]] = None,
-         max_iters: int = 2000) -> dict:
+         max_iters: int = 2000, start: Optional[dict] = None) -> dict:
     """Tune the solve of one problem (device FP64 arrays of shape (ny+2, nx+2)).
 
     Returns the database entry: ``params`` (Solver keyword arguments),
     ``ms`` (median solve time), ``iters``, ``trials`` and ``seconds``
     spent.  With ``db`` the entry is stored under the problem's key.
+    ``start`` overrides entries of the starting point (schedule keys of
+    ``solver_kwargs``, ``accel``, ``beta``).
     """
     import torch
     from . import MIXED, Solver, _lib
@@ -206,12 +217,21 @@ def tune(eta_b, eta_p, rho_b, gx: float = 0.0, gy: float = -1.0, *, precision: O
     tile_levels = [l for l in range(min(lc0 + 2, nlev - 1))]
     coarse_levels = [l for l in (lc0 + 1, lc0 + 2) if l < nlev - 1 and lc0 < nlev - 1]
     d = base.desc
-    start: Params = {"nu_pre": int(d.nu_pre), "nu_post": int(d.nu_post), "nu_growth": float(d.nu_growth),
-                     "uzawa_steps": int(d.uzawa_steps), "restart": int(d.restart), "coarse_level": -1,
-                     "omega": float(d.omega), "alpha": float(d.alpha)}
+    init: Params = {"nu_pre": int(d.nu_pre), "nu_post": int(d.nu_post), "nu_growth": float(d.nu_growth),
+                    "uzawa_steps": int(d.uzawa_steps), "restart": int(d.restart), "coarse_level": -1,
+                    "omega": float(d.omega), "alpha": float(d.alpha), "accel": "fgmres", "beta": 1.0}
     for l in tile_levels:
         k, s = plan0[l]
-        start[f"L{l}"] = (1 if k == "multisweep" else 0, int(s))
+        init[f"L{l}"] = (1 if k == "multisweep" else 0, int(s))
+    for key, v in (start or {}).items():
+        if key in init and not key.startswith("L"):
+            init[key] = v
+    if start and ("msweep" in start or "tile_shape" in start):
+        # a per-level plan given as descriptor masks (-1: that level's default)
+        for l in tile_levels:
+            m0, s0 = init[f"L{l}"]
+            msw, shp = int(start.get("msweep", -1)), int(start.get("tile_shape", -1))
+            init[f"L{l}"] = ((msw >> l) & 1 if msw >= 0 else m0, (shp >> l) & 1 if shp >= 0 else s0)
     base.close()
     del base
 
@@ -228,7 +248,8 @@ def tune(eta_b, eta_p, rho_b, gx: float = 0.0, gy: float = -1.0, *, precision: O
             return math.inf            # e.g. a coarse tail that does not fit
         try:
             # the plan the solver actually runs: sets that differ only in ignored bits are one candidate
-            eff = json.dumps([kw["nu_pre"], kw["nu_post"], kw["nu_growth"], kw["uzawa_steps"], kw["restart"],
+            eff = json.dumps([kw["accel"], kw["beta"], kw["nu_pre"], kw["nu_post"], kw["nu_growth"],
+                              kw["uzawa_steps"], kw["restart"],
                               kw["omega"], kw["alpha"], [s.level_plan(l) for l in range(s.levels)]])
             eff_of[json.dumps(p, sort_keys=True)] = eff
             if eff in seen:
@@ -256,7 +277,7 @@ def tune(eta_b, eta_p, rho_b, gx: float = 0.0, gy: float = -1.0, *, precision: O
         finally:
             s.close()
 
-    res = coordinate_search(measure, knobs if knobs is not None else knobs_for(tile_levels, coarse_levels), start,
+    res = coordinate_search(measure, knobs if knobs is not None else knobs_for(tile_levels, coarse_levels), init,
                             rounds=rounds, rel_gain=rel_gain)
     best_kw = solver_kwargs(res.params, tile_levels)
     entry = {"params": best_kw, "ms": res.cost, "iters": iters.get(eff_of.get(json.dumps(res.params, sort_keys=True))),

@@ -1241,6 +1241,16 @@ tph_status time_kernel_t(tph_solver* s, int kind, int reps, double* ms, double* 
     T* ep = as<T>(L.ep);
     const T om = (T)s->d.omega;
     double words = 0.0;
+    // Krylov / Anderson vector kernels: i = restart / 2 earlier GCR pairs; restart + 1 Anderson slots
+    // (zero coefficients: the launches stream the same bytes whatever the values)
+    const int gcr_i = std::min(s->d.restart / 2, s->d.restart - 1 < 0 ? 0 : s->d.restart - 1);
+    const int mix_n = s->d.restart + 1;
+    std::vector<const double*> mix_x(mix_n), mix_f(mix_n);
+    std::vector<double> mix_c(mix_n, 0.0);
+    for (int v = 0; v < mix_n; ++v) {
+        mix_x[v] = s->V + (size_t)v * s->n3;
+        mix_f[v] = s->Z + (size_t)v * s->n3;
+    }
     auto one = [&](int r) -> tph_status {
         switch (kind) {
             case TPH_KERNEL_SMOOTH:
@@ -1266,6 +1276,29 @@ tph_status time_kernel_t(tph_solver* s, int kind, int reps, double* ms, double* 
                 TPH_HIP(launch_vel_residual<T>(g, as<T>(L.ex[0]), as<T>(L.ey[0]), as<T>(L.rx), as<T>(L.ry), eb, ep,
                                                as<T>(L.tx), as<T>(L.ty), st));
                 break;
+            case TPH_KERNEL_GCR_STEP: {
+                GcrStepArgs a{};
+                const int i = gcr_i;
+                a.w = s->V + (size_t)(i + 1) * s->n3;
+                a.W0 = s->V + s->n3;
+                a.z = s->Z + (size_t)i * s->n3;
+                a.Z0 = s->Z;
+                a.x = s->x;
+                a.r = s->V;
+                a.stride = s->n3;
+                a.n = s->n3;
+                a.i = i;
+                a.orth_w = 1;
+                a.inv_nu = 1.0;
+                a.alpha = 0.0;
+                TPH_HIP(launch_gcr_step(a, st));
+                break;
+            }
+            case TPH_KERNEL_AA_MIX: {
+                TPH_HIP(launch_mix(s->V + (size_t)(mix_n) * s->n3, mix_x.data(), mix_c.data(), mix_f.data(),
+                                   mix_c.data(), mix_n, s->n3, st));
+                break;
+            }
             case TPH_KERNEL_RESTRICT:
                 if (s->d.fused)
                     TPH_HIP(launch_res_restrict<T>(g, s->lev[1].g, as<T>(L.ex[0]), as<T>(L.ey[0]), as<T>(L.rx),
@@ -1294,9 +1327,16 @@ tph_status time_kernel_t(tph_solver* s, int kind, int reps, double* ms, double* 
         case TPH_KERNEL_RESTRICT:                           // fused: read e, r, eta_b, eta_p, write 2 coarse (1/4)
             words = s->d.fused ? 6.5 : 2.5;                 // separate: read t (2), write 2 coarse
             break;
+        case TPH_KERNEL_GCR_STEP:                           // read 2i earlier vectors; w, z, x, r read + written
+            words = (2.0 * gcr_i + 8.0) * (double)s->n3 / cells;
+            break;
+        case TPH_KERNEL_AA_MIX:                             // read 2n vectors, write 1 (+ re-read/write per chunk)
+            words = (2.0 * mix_n + 1.0 + 2.0 * ((mix_n + kVecSetMax - 1) / kVecSetMax - 1)) * (double)s->n3 / cells;
+            break;
         default: words = 5.0; break;                        // read 2 coarse (1/4), e (2); write e (2)
     }
-    const double wbytes = kind == TPH_KERNEL_APPLY ? 8.0 : W;
+    const bool fp64_kernel = kind == TPH_KERNEL_APPLY || kind == TPH_KERNEL_GCR_STEP || kind == TPH_KERNEL_AA_MIX;
+    const double wbytes = fp64_kernel ? 8.0 : W;
     TPH_TRY(one(0));                                     // warm
     TPH_HIP(hipEventRecord(s->ev0, st));
     for (int r = 0; r < reps; ++r) TPH_TRY(one(r));
@@ -1758,7 +1798,7 @@ tph_status tph_time_kernel(tph_solver* s, int32_t kind, int32_t reps, double* ms
                            double* bytes_per_launch) {
     g_last_error.clear();
     TPH_TRY(require_ready(s));
-    if (reps < 1 || kind < TPH_KERNEL_SMOOTH || kind > TPH_KERNEL_PROLONG) {
+    if (reps < 1 || kind < TPH_KERNEL_SMOOTH || kind > TPH_KERNEL_AA_MIX) {
         set_error("bad kernel kind or repetition count");
         return TPH_ERR_INVALID;
     }

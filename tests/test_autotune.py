@@ -45,10 +45,15 @@ def test_masks_and_solver_kwargs():
          "coarse_level": 4}
     kw = at.solver_kwargs(p, [0, 1])
     assert kw == dict(nu_pre=3, nu_post=2, nu_growth=1.5, uzawa_steps=1, restart=30, msweep=0b10, tile_shape=0b10,
-                      coarse_level=4, omega=1.0, alpha=1.0)
-    names = [k.name for k in at.knobs_for([0, 1, 2], [5])]
-    assert names[:7] == ["alpha", "uzawa_steps", "nu_pre", "nu_post", "omega", "nu_growth", "restart"]
+                      coarse_level=4, omega=1.0, alpha=1.0, accel="fgmres", beta=1.0)
+    kw = at.solver_kwargs(dict(p, accel="anderson", beta=0.7), [0, 1])
+    assert kw["accel"] == "anderson" and kw["beta"] == 0.7
+    ks = at.knobs_for([0, 1, 2], [5])
+    names = [k.name for k in ks]
+    assert names[:8] == ["alpha", "uzawa_steps", "nu_pre", "nu_post", "omega", "nu_growth", "restart", "accel"]
+    assert list(ks[7].candidates) == ["fgmres", "gcr"]
     assert "coarse_level" in names and names[-3:] == ["L0", "L1", "L2"]
+    assert "accel" not in [k.name for k in at.knobs_for([0], accels=("fgmres",))]
 
 
 def test_database_round_trip(tmp_path):

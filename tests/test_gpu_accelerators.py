@@ -161,3 +161,25 @@ def test_batch_rejects_other_accelerators():
     with pytest.raises(tph.TephraError) as e:
         tph.Batch([(32, 32), (64, 64)], device=DEV, accel="gcr")
     assert "TPH_ERR_UNSUPPORTED" in str(e.value)
+
+
+@pytest.mark.parametrize("m", [1, 10, 20])
+def test_vector_kernel_timing(m):
+    """The GCR step and Anderson mixing kernels time without touching the
+    caller's arrays; the bytes follow from the vector length (every entry of
+    the padded three-field vectors)."""
+    pr = wl.random_viscosity(128)
+    s = solver_for(pr, precision=tph.MIXED, accel="anderson", restart=m)
+    s.set_coefficients(T(pr.eta_b), T(pr.eta_p), T(pr.rho_b))
+    pitch = (pr.nx + 2 + 63) // 64 * 64
+    n3 = 3 * ((pr.ny + 2) * pitch + 64)
+    ms, by = s.time_kernel(tph._lib.KERNEL_GCR_STEP, 20)
+    i = min(m // 2, m - 1)
+    assert ms > 0 and by == pytest.approx((2 * i + 8) * n3 * 8, rel=1e-12)
+    ms, by = s.time_kernel(tph._lib.KERNEL_AA_MIX, 20)
+    nv = m + 1
+    chunks = (nv + 7) // 8
+    assert ms > 0 and by == pytest.approx((2 * nv + 1 + 2 * (chunks - 1)) * n3 * 8, rel=1e-12)
+    # the handle still solves afterwards
+    vx, vy, p, info = s.solve()
+    assert info.status == "TPH_OK"

@@ -52,3 +52,13 @@ def test_traffic_calibrated_by_copy(tmp_path):
     assert abs(r["fetch"]["bytes"] - 400 * 1024) < 1e-6 and abs(r["write"]["bytes"] - 100 * 1024) < 1e-6
     assert abs(r["bytes_per_launch"] - 500 * 1024) < 1e-6
     assert len(r["sources_sha256"]) == 64
+
+
+def test_sources_hash_covers_the_smoother_files():
+    import os
+    csrc = os.path.join(os.path.dirname(pf.__file__), "csrc")
+    for fn in pf.SMOOTHER_SOURCES:
+        assert os.path.exists(os.path.join(csrc, fn))
+    h = pf.sources_hash()
+    assert len(h) == 64 and h == pf.sources_hash()
+    assert pf.sources_hash(("common.h",)) != h
