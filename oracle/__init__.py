@@ -22,5 +22,7 @@ Contents
 ``continuation`` viscosity-rescaling blend and lithostatic pressure.
 ``accelerators`` flexible GCR(m) and Anderson acceleration AA(m, beta)
               around the Uzawa fixed-point map.
+``ras``       RAS-type temporal-blocking Jacobi smoother and its SplitMix64
+              tile shifts.
 """
-from . import stokes, multigrid, adjoint, continuation, accelerators  # noqa: F401
+from . import stokes, multigrid, adjoint, continuation, accelerators, ras  # noqa: F401

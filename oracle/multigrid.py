@@ -13,8 +13,10 @@ Everything here follows Ch. 4 "The Multigrid Method" and "Accelerators":
   coarse field with its boundary ghosts mirrored first.
 * coarse levels: the same stencil rediscretised with restricted viscosities
   (geometric multigrid, Sec. "Geometric vs Algebraic Multigrid").
-* damped Jacobi (eq. damped_jacobi) and damped Gauss-Seidel with a parallel
-  colouring (eq. sor_update); the colouring is vx-red, vx-black, vy-red,
+* damped Jacobi (eq. damped_jacobi), the RAS-type temporal-blocking Jacobi
+  of Alg. "RAS-Type Temporal Blocking" (module ``ras``; on every level or,
+  as the paper's "Mixed" configuration, below the finest) and damped
+  Gauss-Seidel with a parallel colouring (eq. sor_update); the colouring is vx-red, vx-black, vy-red,
   vy-black with red = (i + j) even, since the vx/vy cross terms couple the
   two velocity components at nodes of either parity.
 * V-cycle (eq. multigrid_levels), exact coarsest solve.
@@ -209,9 +211,12 @@ class MGParams:
     nu_pre: Sequence[int]
     nu_post: Sequence[int]
     omega: float = 0.6
-    smoother: str = "jacobi"        # or "gs"
+    smoother: str = "jacobi"        # "gs", "ras" (every level) or "ras_mixed" (Jacobi on the finest)
     alpha: float = 2.0
     eta_mean: str = "arithmetic"
+    ras_tile: int = 32              # RAS tile side (T_I = T_J)
+    ras_inner: int = 4              # RAS local sweeps per outer iteration
+    seed: int = 0                   # RAS shift generator seed
 
 
 def build_hierarchy(g: Grid, eta_b, eta_p, prm: MGParams) -> List[Level]:
@@ -223,14 +228,31 @@ def build_hierarchy(g: Grid, eta_b, eta_p, prm: MGParams) -> List[Level]:
     return levs
 
 
-def vcycle(levs: List[Level], prm: MGParams, l: int, r: np.ndarray) -> np.ndarray:
-    """Approximate L_l^{-1} r by one V-cycle from zero initial guess."""
+def _smoother(prm: MGParams, l: int, cycle: int):
+    """The smoothing routine of level l: fn(lev, e, r, omega, sweeps, leg)."""
+    ras_here = prm.smoother == "ras" or (prm.smoother == "ras_mixed" and l > 0)
+    if ras_here:
+        from .ras import ras_jacobi, ras_shifts
+        T = (prm.ras_tile, prm.ras_tile)
+
+        def fn(lev, e, r, omega, sweeps, leg):
+            n_outer = -(-sweeps // prm.ras_inner) if sweeps > 0 else 0
+            sh = ras_shifts(prm.seed, cycle, l, leg, n_outer, T)
+            return ras_jacobi(lev, e, r, omega, sweeps, T, prm.ras_inner, sh)
+        return fn
+    base = colored_gs if prm.smoother == "gs" else jacobi
+    return lambda lev, e, r, omega, sweeps, leg: base(lev, e, r, omega, sweeps)
+
+
+def vcycle(levs: List[Level], prm: MGParams, l: int, r: np.ndarray, cycle: int = 0) -> np.ndarray:
+    """Approximate L_l^{-1} r by one V-cycle from zero initial guess (`cycle`
+    numbers the V-cycles of one preconditioner call: the RAS shifts depend on it)."""
     lev = levs[l]
     if l == len(levs) - 1:
         return spla.spsolve(lev.L.tocsc(), r)
-    smooth = jacobi if prm.smoother == "jacobi" else colored_gs
+    smooth = _smoother(prm, l, cycle)
     e = np.zeros_like(r)
-    e = smooth(lev, e, r, prm.omega, prm.nu_pre[l])
+    e = smooth(lev, e, r, prm.omega, prm.nu_pre[l], 0)
     res = r - lev.L @ e
     g, gc = lev.g, levs[l + 1].g
     rx, ry = vec_to_vel(g, res)
@@ -241,12 +263,12 @@ def vcycle(levs: List[Level], prm: MGParams, l: int, r: np.ndarray) -> np.ndarra
     ry[:, g.nx + 1] = 0.0
     rcx = restrict(g, "vx", rx)
     rcy = restrict(g, "vy", ry)
-    ec = vcycle(levs, prm, l + 1, vel_to_vec(gc, rcx, rcy))
+    ec = vcycle(levs, prm, l + 1, vel_to_vec(gc, rcx, rcy), cycle)
     ecx, ecy = vec_to_vel(gc, ec)
     fx = prolong(gc, "vx", ecx, g)
     fy = prolong(gc, "vy", ecy, g)
     e = e + vel_to_vec(g, fx, fy)
-    e = smooth(lev, e, r, prm.omega, prm.nu_post[l])
+    e = smooth(lev, e, r, prm.omega, prm.nu_post[l], 1)
     return e
 
 
@@ -258,10 +280,10 @@ def divergence(g: Grid, vx: np.ndarray, vy: np.ndarray) -> np.ndarray:
     return out
 
 
-def precondition(levs: List[Level], prm: MGParams, rx, ry, rp):
+def precondition(levs: List[Level], prm: MGParams, rx, ry, rp, cycle: int = 0):
     """One application of the Uzawa preconditioner M^{-1} to (r_v, r_p)."""
     g = levs[0].g
-    zv = vcycle(levs, prm, 0, vel_to_vec(g, rx, ry))
+    zv = vcycle(levs, prm, 0, vel_to_vec(g, rx, ry), cycle)
     zx, zy = vec_to_vel(g, zv)
     dz = divergence(g, zx, zy)
     zp = np.zeros_like(rp)
@@ -277,9 +299,9 @@ def uzawa_preconditioner(levs: List[Level], prm: MGParams, A, rx, ry, rp, steps:
     g = levs[0].g
     r = st_to_vector(g, rx, ry, rp)
     z = np.zeros_like(r)
-    for _ in range(steps):
+    for step in range(steps):
         tx, ty, tp = st_to_arrays_res(g, r - A @ z)
-        dx_, dy_, dp_ = precondition(levs, prm, tx, ty, tp)
+        dx_, dy_, dp_ = precondition(levs, prm, tx, ty, tp, step)
         z = z + st_to_vector(g, dx_, dy_, dp_)
     return st_to_arrays_sol(g, z)
 
