@@ -78,10 +78,24 @@ enum { TPH_WEST = 0, TPH_EAST = 1, TPH_SOUTH = 2, TPH_NORTH = 3 };
  * FP32; outer residual, Krylov orthogonalisation, coarsest solve and the
  * pressure step stay FP64. */
 enum { TPH_FP64 = 0, TPH_MIXED = 1 };
-/* Smoother on L (Sec. "Smoothers"): damped Jacobi (eq. damped_jacobi) or
+/* Smoother on L (Sec. "Smoothers"): damped Jacobi (eq. damped_jacobi),
  * damped Gauss-Seidel (eq. sor_update) in four colour half-sweeps
- * (vx red, vx black, vy red, vy black; red = (i + j) even). */
-enum { TPH_SMOOTH_JACOBI = 0, TPH_SMOOTH_GS = 1 };
+ * (vx red, vx black, vy red, vy black; red = (i + j) even), or the RAS-type
+ * temporal-blocking Jacobi of Alg. "RAS-Type Temporal Blocking" on every
+ * level (TPH_SMOOTH_RAS) or below the finest level, which takes damped
+ * Jacobi (TPH_SMOOTH_RAS_MIXED, the paper's "Mixed" configuration).  RAS:
+ * each outer iteration (one launch) splits the velocity unknowns into
+ * ras_tile x ras_tile tiles with boundaries at rows 1 + s_i + k ras_tile and
+ * columns 1 + s_j + k ras_tile, and every tile runs ras_inner damped Jacobi
+ * sweeps on its unknowns with the values outside it held at the state the
+ * outer iteration started from; ceil(nu / ras_inner) outer iterations make
+ * up a smoothing call of nu sweeps.  The shifts are SplitMix64 draws from
+ * desc.seed at the counter ((((cycle * 16 + level) * 2 + leg) * 256 + outer)
+ * * 2 + axis) modulo ras_tile, where cycle numbers the V-cycles of one
+ * preconditioner application (0 .. uzawa_steps - 1) and leg is 0 (pre) or
+ * 1 (post).  The RAS smoothers run without the single-workgroup coarse tail
+ * and are not available to the batched solver. */
+enum { TPH_SMOOTH_JACOBI = 0, TPH_SMOOTH_GS = 1, TPH_SMOOTH_RAS = 2, TPH_SMOOTH_RAS_MIXED = 3 };
 /* Coarse-level viscosity: normalised bilinear restriction of eta
  * (arithmetic) or of log(eta) (geometric). */
 enum { TPH_MEAN_ARITHMETIC = 0, TPH_MEAN_GEOMETRIC = 1 };
@@ -139,6 +153,9 @@ typedef struct tph_desc {
                               level l (rejected when it does not fit)          */
     int32_t accel;         /* TPH_ACCEL_*                                     */
     double beta;           /* Anderson mixing in (0, 1]; ignored otherwise    */
+    int32_t ras_tile;      /* RAS tile side: 8, 16 or 32                      */
+    int32_t ras_inner;     /* RAS local sweeps per outer iteration (1..16)    */
+    uint64_t seed;         /* seed of the RAS tile shifts                     */
 } tph_desc;
 
 typedef struct tph_info {
@@ -161,7 +178,8 @@ typedef struct tph_solver tph_solver;
  * pre- and 2 post-sweeps on every level, alpha 1, arithmetic coarse
  * viscosity, two Uzawa sweeps per preconditioner application, fused
  * kernels with the default multi-sweep levels and tile shapes (-1), rtol
- * 1e-8, FGMRES with restart 20, max_iters 500, beta 1. */
+ * 1e-8, FGMRES with restart 20, max_iters 500, beta 1, RAS tiles 32 x 32
+ * with 4 inner sweeps and seed 0. */
 void tph_desc_default(tph_desc* d, int32_t nx, int32_t ny);
 
 /* Create a solver for the grid in *desc; hip_stream is a hipStream_t (NULL:
@@ -258,7 +276,8 @@ tph_status tph_level_shape(tph_solver* s, int32_t level, int32_t* nx, int32_t* n
 /* How level l is processed by the fused V-cycle (desc.fused = 1):
  * *kind = 0: one-sweep LDS tile launches (plus the fused residual-restriction),
  *         1: multi-sweep LDS passes, 2: inside the single-workgroup coarse
- *         tail, 3: coarsest level without the coarse tail (dense solve);
+ *         tail, 3: coarsest level without the coarse tail (dense solve),
+ *         4: RAS tile launches;
  * *shape = 1 if its tiles use the small shape.  With desc.fused = 0 every
  * level reports kind 0.  Either output may be NULL. */
 tph_status tph_level_plan(tph_solver* s, int32_t level, int32_t* kind, int32_t* shape);
@@ -282,7 +301,8 @@ tph_status tph_coeff_gradient(tph_solver* s, const double* vx, const double* vy,
 /* Kernels that tph_time_kernel can time. */
 enum {
     TPH_KERNEL_SMOOTH = 0,   /* one finest-level smoother launch (fused: one full sweep on LDS tiles;
-                                otherwise a Jacobi sweep or one GS colour half-sweep) */
+                                otherwise a Jacobi sweep or one GS colour half-sweep; RAS: one
+                                outer iteration of ras_inner sweeps) */
     TPH_KERNEL_APPLY = 1,    /* FP64 matrix-free operator apply with energy scaling (Krylov step) */
     TPH_KERNEL_RESIDUAL = 2, /* finest-level velocity residual r - L e in the V-cycle type */
     TPH_KERNEL_RESTRICT = 3, /* finest -> second level residual restriction */

@@ -8,7 +8,7 @@ from __future__ import annotations
 import ctypes
 import os
 import re
-from ctypes import POINTER, c_char_p, c_double, c_int32, c_void_p
+from ctypes import POINTER, c_char_p, c_double, c_int32, c_uint64, c_void_p
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtephra.so")
@@ -19,7 +19,7 @@ STATUS_NAMES = {0: "TPH_OK", 1: "TPH_NOT_CONVERGED", -1: "TPH_ERR_INVALID", -2: 
                 -3: "TPH_ERR_HIP", -4: "TPH_ERR_NONFINITE", -5: "TPH_ERR_UNSUPPORTED"}
 FREE_SLIP, NO_SLIP = 0, 1
 FP64, MIXED = 0, 1
-SMOOTH_JACOBI, SMOOTH_GS = 0, 1
+SMOOTH_JACOBI, SMOOTH_GS, SMOOTH_RAS, SMOOTH_RAS_MIXED = 0, 1, 2, 3
 MEAN_ARITHMETIC, MEAN_GEOMETRIC = 0, 1
 ACCEL_FGMRES, ACCEL_GCR, ACCEL_ANDERSON = 0, 1, 2
 ACCEL_NAMES = {"fgmres": ACCEL_FGMRES, "gcr": ACCEL_GCR, "anderson": ACCEL_ANDERSON}
@@ -35,7 +35,8 @@ class Desc(ctypes.Structure):
                 ("eta_mean", c_int32), ("rtol", c_double), ("restart", c_int32),
                 ("max_iters", c_int32), ("uzawa_steps", c_int32), ("fused", c_int32),
                 ("msweep", c_int32), ("tile_shape", c_int32), ("coarse_level", c_int32),
-                ("accel", c_int32), ("beta", c_double)]
+                ("accel", c_int32), ("beta", c_double), ("ras_tile", c_int32), ("ras_inner", c_int32),
+                ("seed", c_uint64)]
 
 
 class Info(ctypes.Structure):

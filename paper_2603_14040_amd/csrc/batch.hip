@@ -531,6 +531,10 @@ tph_status batch_create_impl(tph_batch* b, int count, const tph_desc* descs) {
                                    "omega, alpha, restart, max_iters, uzawa_steps and rtol, with fused kernels");
             return TPH_ERR_INVALID;
         }
+        if (q.smoother != TPH_SMOOTH_JACOBI && q.smoother != TPH_SMOOTH_GS) {
+            tph_internal_set_error("the batched solver smooths with Jacobi or Gauss-Seidel only");
+            return TPH_ERR_UNSUPPORTED;
+        }
         if (q.accel != TPH_ACCEL_FGMRES) {
             tph_internal_set_error("the batched solver runs flexible GMRES only (accel = TPH_ACCEL_FGMRES)");
             return TPH_ERR_UNSUPPORTED;

@@ -102,6 +102,17 @@ template <typename T>
 hipError_t launch_coarse_solve(const Geom& g, const double* Minv, const T* rx, const T* ry, T* ex, T* ey,
                                hipStream_t st);
 
+// -------------------------------------------------------------------- ras.hip
+// one outer iteration of the RAS-type temporal-blocking Jacobi smoother:
+// tile x tile tiles (8, 16 or 32) with boundaries at rows 1 + si + k tile and
+// columns 1 + sj + k tile, `inner` damped Jacobi sweeps per tile with the
+// outside held at the input state; zero: the input is zero (exi, eyi unused).
+// The output buffers must differ from the inputs.
+template <typename T>
+hipError_t launch_ras_tile(const Geom& g, int tile, int si, int sj, int inner, bool zero, const T* exi, const T* eyi,
+                           T* exo, T* eyo, const T* rx, const T* ry, const T* eb, const T* ep, T omega,
+                           hipStream_t st);
+
 // ----------------------------------------------------------------- krylov.hip
 int flat_blocks(size_t n);
 // partial[i * nblk + b] = sum over block b of V_i . w (any nv, in chunks of 8); when

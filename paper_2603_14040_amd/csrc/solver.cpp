@@ -129,7 +129,9 @@ struct tph_solver {
     int kdropped = 0;
     double kbytes = 0.0;
     std::vector<void*> dev_allocs;
+    int vc_cycle = 0;             // V-cycle index inside the current preconditioner application (RAS shifts)
     bool mixed() const { return d.precision == TPH_MIXED; }
+    bool ras() const { return d.smoother == TPH_SMOOTH_RAS || d.smoother == TPH_SMOOTH_RAS_MIXED; }
 };
 
 namespace {
@@ -200,7 +202,15 @@ tph_status validate_desc(const tph_desc* d, int* nlev_out) {
     for (int w = 0; w < 4; ++w)
         if (d->bc[w] != TPH_FREE_SLIP && d->bc[w] != TPH_NO_SLIP) { set_error("bad boundary condition"); return TPH_ERR_INVALID; }
     if (d->precision != TPH_FP64 && d->precision != TPH_MIXED) { set_error("bad precision"); return TPH_ERR_INVALID; }
-    if (d->smoother != TPH_SMOOTH_JACOBI && d->smoother != TPH_SMOOTH_GS) { set_error("bad smoother"); return TPH_ERR_INVALID; }
+    if (d->smoother != TPH_SMOOTH_JACOBI && d->smoother != TPH_SMOOTH_GS && d->smoother != TPH_SMOOTH_RAS &&
+        d->smoother != TPH_SMOOTH_RAS_MIXED) {
+        set_error("bad smoother");
+        return TPH_ERR_INVALID;
+    }
+    if (d->smoother == TPH_SMOOTH_RAS || d->smoother == TPH_SMOOTH_RAS_MIXED) {
+        if (d->ras_tile != 8 && d->ras_tile != 16 && d->ras_tile != 32) { set_error("ras_tile must be 8, 16 or 32"); return TPH_ERR_INVALID; }
+        if (d->ras_inner < 1 || d->ras_inner > 16) { set_error("ras_inner must be in [1, 16]"); return TPH_ERR_INVALID; }
+    }
     if (d->eta_mean != TPH_MEAN_ARITHMETIC && d->eta_mean != TPH_MEAN_GEOMETRIC) { set_error("bad eta_mean"); return TPH_ERR_INVALID; }
     if (d->nu_pre < 0 || d->nu_post < 0 || d->nu_pre > 256 || d->nu_post > 256) { set_error("bad sweep counts"); return TPH_ERR_INVALID; }
     if (!(d->nu_growth >= 1.0) || d->nu_growth > 4.0) { set_error("nu_growth must be in [1, 4]"); return TPH_ERR_INVALID; }
@@ -254,6 +264,48 @@ tph_status validate_desc(const tph_desc* d, int* nlev_out) {
 template <typename T>
 T* as(void* p) { return (T*)p; }
 
+// ------------------------------------------------------- RAS smoothing
+// Output k (0-based) of SplitMix64 started from `state` (Steele, Lea and
+// Flood, 2014): the RAS tile shifts are draws of it.
+uint64_t splitmix64(uint64_t state, uint64_t k) {
+    uint64_t z = state + (k + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+constexpr uint64_t kRasMaxOuter = 256;
+
+bool ras_level(const tph_solver* s, int l) {
+    return s->d.smoother == TPH_SMOOTH_RAS || (s->d.smoother == TPH_SMOOTH_RAS_MIXED && l > 0);
+}
+
+// nu sweeps of the RAS-type temporal-blocking smoother on level l:
+// ceil(nu / ras_inner) outer iterations, one launch each, with shifts drawn
+// for (V-cycle of this preconditioner application, level, leg, outer, axis);
+// from_zero: the first launch starts from e = 0 and writes buffer 0.
+template <typename T>
+tph_status ras_smooth(tph_solver* s, int l, int nu, bool from_zero, int leg, int* cur) {
+    LevelBuf& L = s->lev[l];
+    const int TT = s->d.ras_tile, inner = s->d.ras_inner;
+    const int nout = (nu + inner - 1) / inner;
+    for (int t = 0; t < nout; ++t) {
+        const uint64_t key = ((((uint64_t)s->vc_cycle * kMaxLevels + (uint64_t)l) * 2 + (uint64_t)leg) * kRasMaxOuter +
+                              (uint64_t)t) * 2;
+        const int si = (int)(splitmix64(s->d.seed, key) % (uint64_t)TT);
+        const int sj = (int)(splitmix64(s->d.seed, key + 1) % (uint64_t)TT);
+        const bool z = from_zero && t == 0;
+        const int out = z ? 0 : 1 - *cur;
+        const KTime tk = ktic(s, l);
+        TPH_HIP(launch_ras_tile<T>(L.g, TT, si, sj, inner, z, z ? nullptr : as<T>(L.ex[*cur]),
+                                   z ? nullptr : as<T>(L.ey[*cur]), as<T>(L.ex[out]), as<T>(L.ey[out]), as<T>(L.rx),
+                                   as<T>(L.ry), as<T>(L.eb), as<T>(L.ep), (T)s->d.omega, s->st));
+        ktoc(s, tk, z ? 6.0 : 8.0, sizeof(T));
+        *cur = out;
+    }
+    return TPH_OK;
+}
+
 // ----------------------------------------------------------------- V-cycle
 template <typename T>
 tph_status vcycle(tph_solver* s, int l, int* cur_out) {
@@ -271,8 +323,10 @@ tph_status vcycle(tph_solver* s, int l, int* cur_out) {
         return TPH_OK;
     }
     int cur = 0;
-    const bool jac = s->d.smoother == TPH_SMOOTH_JACOBI;
+    const bool jac = s->d.smoother != TPH_SMOOTH_GS;     // RAS_MIXED: Jacobi on the finest level
+    const bool ras = ras_level(s, l);
     auto sweeps = [&](int nu, bool from_zero) -> tph_status {
+        if (ras) return ras_smooth<T>(s, l, nu, from_zero, from_zero ? 0 : 1, &cur);
         for (int k = 0; k < nu; ++k) {
             const bool z = from_zero && k == 0;
             if (jac) {
@@ -412,6 +466,21 @@ tph_status vcycle_fused(tph_solver* s, int l, int* cur_out) {
     }
     int cur = 0;
     if (((s->msw_mask >> l) & 1u) && L.nu_pre > 0 && L.nu_post > 0) return vcycle_msweep<T>(s, l, cur_out);
+    if (ras_level(s, l)) {
+        // RAS launches, fused residual + restriction, separate prolongation
+        LevelBuf& C = s->lev[l + 1];
+        if (L.nu_pre == 0) TPH_HIP(launch_zero_vel<T>(g, as<T>(L.ex[0]), as<T>(L.ey[0]), st));
+        else TPH_TRY(ras_smooth<T>(s, l, L.nu_pre, true, 0, &cur));
+        TPH_HIP(launch_res_restrict<T>(g, C.g, as<T>(L.ex[cur]), as<T>(L.ey[cur]), rx, ry, eb, ep, as<T>(C.rx),
+                                       as<T>(C.ry), st));
+        int ccur = 0;
+        TPH_TRY(vcycle_fused<T>(s, l + 1, &ccur));
+        TPH_HIP(launch_prolong_add<T>(g, C.g, as<T>(C.ex[ccur]), as<T>(C.ey[ccur]), as<T>(L.ex[cur]),
+                                      as<T>(L.ey[cur]), st));
+        TPH_TRY(ras_smooth<T>(s, l, L.nu_post, false, 1, &cur));
+        *cur_out = cur;
+        return TPH_OK;
+    }
     if (L.nu_pre == 0) {
         TPH_HIP(launch_zero_vel<T>(g, as<T>(L.ex[0]), as<T>(L.ey[0]), st));
     } else {
@@ -476,6 +545,7 @@ tph_status precondition_t(tph_solver* s, double* vraw, double* zraw, bool energy
         double* tpb[2] = {vec3(s, s->t3).p(), vec3(s, s->t2).p()};
         TPH_HIP(launch_precond_in<T>(L.g, v, L.eb64, L.ep64, energy, as<T>(L.rx), as<T>(L.ry), s->st));
         for (int q = 0; q < S; ++q) {
+            s->vc_cycle = q;
             int cur = 0;
             if (fused) TPH_TRY(vcycle_fused<T>(s, 0, &cur));
             else TPH_TRY(vcycle<T>(s, 0, &cur));
@@ -501,6 +571,7 @@ tph_status precondition_t(tph_solver* s, double* vraw, double* zraw, bool energy
         return TPH_OK;
     }
     for (int step = 0; step < S; ++step) {
+        s->vc_cycle = step;
         Vec3 src = v;
         bool src_scaled = energy;
         if (step > 0) {
@@ -1162,7 +1233,8 @@ tph_status create_impl(const tph_desc* desc, void* stream, tph_solver* s) {
             s->max_lds = lim;
     }
     s->lc = -1;
-    if (desc->fused && nlev >= 2 && s->ncoarse <= 2048 && desc->coarse_level != -2) {
+    // the coarse tail smooths with Jacobi or Gauss-Seidel only: the RAS smoothers run level by level
+    if (desc->fused && nlev >= 2 && s->ncoarse <= 2048 && desc->coarse_level != -2 && !s->ras()) {
         // a level qualifies when its tail fits in one workgroup's LDS (leaving
         // room for the kernel's static tables) and its per-sweep work suits one
         // workgroup (<= 64 x 64 cells); default: the finest such level
@@ -1254,7 +1326,12 @@ tph_status time_kernel_t(tph_solver* s, int kind, int reps, double* ms, double* 
     auto one = [&](int r) -> tph_status {
         switch (kind) {
             case TPH_KERNEL_SMOOTH:
-                if (s->d.fused) {
+                if (ras_level(s, 0)) {
+                    const int a = r & 1;
+                    TPH_HIP(launch_ras_tile<T>(g, s->d.ras_tile, 0, 0, s->d.ras_inner, false, as<T>(L.ex[a]),
+                                               as<T>(L.ey[a]), as<T>(L.ex[1 - a]), as<T>(L.ey[1 - a]), as<T>(L.rx),
+                                               as<T>(L.ry), eb, ep, om, st));
+                } else if (s->d.fused) {
                     const int a = r & 1;
                     TPH_HIP(launch_smooth_tile<T>(g, nullptr, s->d.smoother, 0, as<T>(L.ex[a]), as<T>(L.ey[a]),
                                                   as<T>(L.ex[1 - a]), as<T>(L.ey[1 - a]), as<T>(L.rx), as<T>(L.ry), eb,
@@ -1320,7 +1397,8 @@ tph_status time_kernel_t(tph_solver* s, int kind, int reps, double* ms, double* 
             // half-sweep: read both velocities, eta_b, eta_p and half of one r;
             // write half of one component.
             // a fused sweep (either smoother) reads e, r, eta_b, eta_p and writes e
-            words = (s->d.fused || s->d.smoother == TPH_SMOOTH_JACOBI) ? 8.0 : 5.0;
+            // a RAS launch: read e, r, eta_b, eta_p once for ras_inner sweeps, write e
+            words = (s->d.fused || s->d.smoother != TPH_SMOOTH_GS) ? 8.0 : 5.0;
             break;
         case TPH_KERNEL_APPLY: words = 8.0; break;          // read vx, vy, p, eta_b, eta_p; write 3
         case TPH_KERNEL_RESIDUAL: words = 8.0; break;       // read e (2), r (2), eta_b, eta_p; write t (2)
@@ -1497,6 +1575,9 @@ void tph_desc_default(tph_desc* d, int32_t nx, int32_t ny) {
     d->restart = 20;
     d->accel = TPH_ACCEL_FGMRES;
     d->beta = 1.0;
+    d->ras_tile = 32;
+    d->ras_inner = 4;
+    d->seed = 0;
     d->max_iters = 500;
     d->uzawa_steps = 2;
     d->fused = 1;
@@ -1733,6 +1814,7 @@ tph_status tph_level_plan(tph_solver* s, int32_t level, int32_t* kind, int32_t* 
         const LevelBuf& L = s->lev[level];
         if (s->lc >= 0 && level >= s->lc) k = 2;
         else if (level == s->nlev - 1) k = 3;
+        else if (ras_level(s, level)) k = 4;
         else if (((s->msw_mask >> level) & 1u) && L.nu_pre > 0 && L.nu_post > 0) k = 1;
     }
     if (kind) *kind = k;
