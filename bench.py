@@ -61,6 +61,8 @@ def main():
     ap.add_argument("--large", type=int, default=4096, help="cells per side of the multi-inclusion workload (0: skip)")
     ap.add_argument("--accel-steps", type=int, default=5,
                     help="timed steps of the GCR and Anderson solves of the main workload (0: skip)")
+    ap.add_argument("--ras-steps", type=int, default=5,
+                    help="timed steps of the RAS-smoother solve of the main workload (0: skip)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -200,6 +202,60 @@ def main():
                 f"{accels[name]['kernel']['name']} {kgbs:.0f} GB/s")
             sa_.close()
             del sa_
+
+    # the RAS-type temporal-blocking smoother (every level, or below a Jacobi finest level) on the same
+    # workload: smoother variant, tile side, inner sweeps, sweeps and damping tuned (untimed) around the
+    # tuned accelerator schedule; the RAS kernel is timed on the finest level
+    ras_out = None
+    if args.ras_steps > 0:
+        from paper_2603_14040_amd.autotune import Knob
+        base = {k: v for k, v in tuned["mixed"]["params"].items() if k not in ("msweep", "tile_shape", "coarse_level")}
+        params = dict(base, smoother=tph.SMOOTH_RAS, ras_tile=16, ras_inner=4, nu_pre=4, nu_post=4, omega=0.6)
+        rt_ = None
+        if not args.no_tune:
+            rt_ = autotune.tune(eb, ep, rho, pr.gx, pr.gy, precision=tph.MIXED, reps=1, rounds=2, device=dev,
+                                knobs=[Knob("smoother", [tph.SMOOTH_RAS, tph.SMOOTH_RAS_MIXED]),
+                                       Knob("ras_tile", [8, 16, 32]), Knob("ras_inner", [1, 2, 4, 8]),
+                                       Knob("nu_pre", [2, 4, 8]), Knob("nu_post", [2, 4, 8]),
+                                       Knob("omega", [0.5, 0.6, 0.7])], start=params)
+            params = {k: v for k, v in rt_["params"].items() if k not in ("msweep", "tile_shape", "coarse_level")}
+            log(f"[bench] ras: tuned {params} ({rt_['trials']} trials, {rt_['seconds']:.1f} s)")
+        sr_ = tph.Solver(n, n, precision=tph.MIXED, device=dev, **params)
+        rx_, ry_, rp_ = sr_.zeros(), sr_.zeros(), sr_.zeros()
+
+        def rstep_():
+            rx_.zero_(); ry_.zero_(); rp_.zero_()
+            sr_.set_coefficients(eb, ep, rho, pr.gx, pr.gy)
+            return sr_.solve(rx_, ry_, rp_)[3]
+
+        rstep_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rinf = [rstep_() for _ in range(args.ras_steps)]
+        torch.cuda.synchronize()
+        rms = 1e3 * (time.perf_counter() - t0) / args.ras_steps
+        if any(i.status != "TPH_OK" for i in rinf):
+            raise RuntimeError(f"RAS solve did not converge: {rinf[-1]}")
+        sr_.close()
+        # the RAS kernel on the finest level (one outer iteration of ras_inner sweeps)
+        kr_ = tph.Solver(n, n, precision=tph.MIXED, device=dev, smoother=tph.SMOOTH_RAS,
+                         ras_tile=params["ras_tile"], ras_inner=params["ras_inner"], omega=params["omega"])
+        kr_.set_coefficients(eb, ep, rho, pr.gx, pr.gy)
+        kms, kby = kr_.time_kernel(tph._lib.KERNEL_SMOOTH, 100)
+        kr_.close()
+        kgbs = kby / (kms * 1e-3) / 1e9
+        ras_out = {"ms_per_step": rms, "value": cells / (rms * 1e-3), "unit": "cells/s", "iters": rinf[-1].iters,
+                   "res_energy": rinf[-1].res_energy,
+                   "params": {k: params[k] for k in ("smoother", "ras_tile", "ras_inner", "nu_pre", "nu_post",
+                                                     "omega", "accel", "restart", "uzawa_steps", "alpha")},
+                   "tuning_trials": rt_["trials"] if rt_ else 0,
+                   "kernel": {"name": "k_ras_tile", "what": (f"one outer iteration ({params['ras_inner']} Jacobi "
+                                                             f"sweeps) on {params['ras_tile']}^2 tiles, finest level"),
+                              "us": round(kms * 1e3, 2), "bytes": kby, "GBps": round(kgbs, 1),
+                              "frac": round(kgbs / HBM_PEAK_GBS, 4),
+                              "sweeps_per_s": params["ras_inner"] / (kms * 1e-3)}}
+        log(f"[bench] ras: {rms:.2f} ms/step, iters {rinf[-1].iters}, res {rinf[-1].res_energy:.2e}; k_ras_tile "
+            f"{kms * 1e3:.1f} us per launch, {kgbs:.0f} GB/s")
 
     # dominant kernel: finest-level smoother of the mixed path, HIP events on the solver stream
     kern = {}
@@ -411,6 +467,7 @@ def main():
                   "res_energy": inf_64[-1].res_energy} if fp64_steps > 0 else None),
         "mixed_speedup_vs_fp64": ms_64 / ms_mix if fp64_steps > 0 else None,
         "accelerators": accels or None,
+        "ras": ras_out,
         "tuned": tuned,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,

@@ -156,6 +156,17 @@ typedef struct tph_desc {
     int32_t ras_tile;      /* RAS tile side: 8, 16 or 32                      */
     int32_t ras_inner;     /* RAS local sweeps per outer iteration (1..16)    */
     uint64_t seed;         /* seed of the RAS tile shifts                     */
+    int32_t graph;         /* 1: each preconditioner application inside a solve
+                              (the Uzawa steps with their V-cycles and linked
+                              exits) is captured once per distinct set of
+                              vectors as a HIP graph and replayed; 0: every
+                              kernel is launched on its own.  Same kernels and
+                              results either way; while kernel timing is on
+                              (tph_kernel_timing) applications run uncaptured.
+                              Off by default: on MI355X the replays (launched
+                              into a library stream joined by events) ran the
+                              benchmark solve no faster than direct launches */
+    int32_t pad_;          /* must be zero                                    */
 } tph_desc;
 
 typedef struct tph_info {
@@ -179,7 +190,7 @@ typedef struct tph_solver tph_solver;
  * viscosity, two Uzawa sweeps per preconditioner application, fused
  * kernels with the default multi-sweep levels and tile shapes (-1), rtol
  * 1e-8, FGMRES with restart 20, max_iters 500, beta 1, RAS tiles 32 x 32
- * with 4 inner sweeps and seed 0. */
+ * with 4 inner sweeps and seed 0, no graph capture. */
 void tph_desc_default(tph_desc* d, int32_t nx, int32_t ny);
 
 /* Create a solver for the grid in *desc; hip_stream is a hipStream_t (NULL:

@@ -63,6 +63,7 @@ class Solver:
                  max_iters: int = 500, uzawa_steps: int = 2, fused: bool = True,
                  msweep: int = -1, tile_shape: int = -1, coarse_level: int = -1,
                  accel="fgmres", beta: float = 1.0, ras_tile: int = 32, ras_inner: int = 4, seed: int = 0,
+                 graph: bool = False,
                  device: Optional[torch.device] = None,
                  stream: Optional[torch.cuda.Stream] = None):
         lib = _lib.load()
@@ -70,7 +71,7 @@ class Solver:
                   nu_pre=nu_pre, nu_post=nu_post, nu_growth=nu_growth, omega=omega, alpha=alpha,
                   eta_mean=eta_mean, rtol=rtol, restart=restart, max_iters=max_iters, uzawa_steps=uzawa_steps,
                   fused=fused, msweep=msweep, tile_shape=tile_shape, coarse_level=coarse_level,
-                  accel=accel, beta=beta, ras_tile=ras_tile, ras_inner=ras_inner, seed=seed)
+                  accel=accel, beta=beta, ras_tile=ras_tile, ras_inner=ras_inner, seed=seed, graph=graph)
         self.desc = d
         self.nx, self.ny = nx, ny
         self.shape = (ny + 2, nx + 2)
@@ -288,7 +289,7 @@ class Solver:
 def _desc(lib, nx, ny, lx=1.0, ly=1.0, bc=(FREE_SLIP,) * 4, precision=MIXED, levels=0, smoother=SMOOTH_GS,
           nu_pre=2, nu_post=2, nu_growth=1.0, omega=1.0, alpha=1.0, eta_mean=MEAN_ARITHMETIC, rtol=1e-8,
           restart=20, max_iters=500, uzawa_steps=2, fused=True, msweep=-1, tile_shape=-1, coarse_level=-1,
-          accel="fgmres", beta=1.0, ras_tile=32, ras_inner=4, seed=0):
+          accel="fgmres", beta=1.0, ras_tile=32, ras_inner=4, seed=0, graph=False):
     d = _lib.Desc()
     lib.tph_desc_default(ctypes.byref(d), nx, ny)
     d.lx, d.ly = float(lx), float(ly)
@@ -302,6 +303,7 @@ def _desc(lib, nx, ny, lx=1.0, ly=1.0, bc=(FREE_SLIP,) * 4, precision=MIXED, lev
     d.accel = _lib.ACCEL_NAMES[accel.lower()] if isinstance(accel, str) else int(accel)
     d.beta = float(beta)
     d.ras_tile, d.ras_inner, d.seed = int(ras_tile), int(ras_inner), int(seed)
+    d.graph = int(bool(graph))
     return d
 
 

@@ -36,7 +36,7 @@ class Desc(ctypes.Structure):
                 ("max_iters", c_int32), ("uzawa_steps", c_int32), ("fused", c_int32),
                 ("msweep", c_int32), ("tile_shape", c_int32), ("coarse_level", c_int32),
                 ("accel", c_int32), ("beta", c_double), ("ras_tile", c_int32), ("ras_inner", c_int32),
-                ("seed", c_uint64)]
+                ("seed", c_uint64), ("graph", c_int32), ("pad_", c_int32)]
 
 
 class Info(ctypes.Structure):

@@ -19,7 +19,8 @@ Knobs (all of them descriptor fields of tph_create):
     Uzawa pressure relaxation ``alpha``; the smoother damping ``omega``;
   * the Krylov accelerator (flexible GMRES or GCR) and its restart length;
     for Anderson acceleration (tuned from an explicit knob list) the depth
-    (``restart``) and the mixing ``beta``.
+    (``restart``) and the mixing ``beta``; for the RAS smoothers (also from
+    an explicit list) the tile side and the inner sweeps.
 Parameter sets that resolve to the same kernel plan on every level are
 measured once.
 
@@ -156,7 +157,8 @@ def solver_kwargs(p: Params, tile_levels: Sequence[int]) -> dict:
                 uzawa_steps=int(p["uzawa_steps"]), restart=int(p["restart"]), msweep=msw, tile_shape=shp,
                 coarse_level=int(p.get("coarse_level", -1)), omega=float(p.get("omega", 1.0)),
                 alpha=float(p.get("alpha", 1.0)), accel=str(p.get("accel", "fgmres")),
-                beta=float(p.get("beta", 1.0)))
+                beta=float(p.get("beta", 1.0)), smoother=int(p.get("smoother", 1)),
+                ras_tile=int(p.get("ras_tile", 32)), ras_inner=int(p.get("ras_inner", 4)))
 
 
 def knobs_for(tile_levels: Sequence[int], coarse_levels: Sequence[int] = (), nus=(1, 2, 3),
@@ -219,7 +221,8 @@ def tune(eta_b, eta_p, rho_b, gx: float = 0.0, gy: float = -1.0, *, precision: O
     d = base.desc
     init: Params = {"nu_pre": int(d.nu_pre), "nu_post": int(d.nu_post), "nu_growth": float(d.nu_growth),
                     "uzawa_steps": int(d.uzawa_steps), "restart": int(d.restart), "coarse_level": -1,
-                    "omega": float(d.omega), "alpha": float(d.alpha), "accel": "fgmres", "beta": 1.0}
+                    "omega": float(d.omega), "alpha": float(d.alpha), "accel": "fgmres", "beta": 1.0,
+                    "smoother": int(d.smoother), "ras_tile": int(d.ras_tile), "ras_inner": int(d.ras_inner)}
     for l in tile_levels:
         k, s = plan0[l]
         init[f"L{l}"] = (1 if k == "multisweep" else 0, int(s))
@@ -248,7 +251,8 @@ def tune(eta_b, eta_p, rho_b, gx: float = 0.0, gy: float = -1.0, *, precision: O
             return math.inf            # e.g. a coarse tail that does not fit
         try:
             # the plan the solver actually runs: sets that differ only in ignored bits are one candidate
-            eff = json.dumps([kw["accel"], kw["beta"], kw["nu_pre"], kw["nu_post"], kw["nu_growth"],
+            eff = json.dumps([kw["accel"], kw["beta"], kw["smoother"], kw["ras_tile"], kw["ras_inner"],
+                              kw["nu_pre"], kw["nu_post"], kw["nu_growth"],
                               kw["uzawa_steps"], kw["restart"],
                               kw["omega"], kw["alpha"], [s.level_plan(l) for l in range(s.levels)]])
             eff_of[json.dumps(p, sort_keys=True)] = eff

@@ -20,10 +20,13 @@
 namespace tph {
 namespace {
 
-constexpr int kRasThreads = 256;
+// one thread per tile node (both components): the sweeps' dependency chain is
+// one update long per thread
+template <int TT>
+constexpr int ras_threads() { return TT * TT < 1024 ? TT * TT : 1024; }
 
 template <typename T, int TT>
-__global__ __launch_bounds__(kRasThreads) void k_ras_tile(Geom g, int si, int sj, int inner, int zero,
+__global__ __launch_bounds__(ras_threads<TT>()) void k_ras_tile(Geom g, int si, int sj, int inner, int zero,
                                                          const T* __restrict__ exi, const T* __restrict__ eyi,
                                                          T* __restrict__ exo, T* __restrict__ eyo,
                                                          const T* __restrict__ rx, const T* __restrict__ ry,
@@ -31,7 +34,8 @@ __global__ __launch_bounds__(kRasThreads) void k_ras_tile(Geom g, int si, int sj
                                                          T omega) {
     constexpr int W = TT + 2;                 // LDS window side: the tile and a halo of one node
     constexpr int NQ = TT * TT;
-    constexpr int K = (NQ + kRasThreads - 1) / kRasThreads;
+    constexpr int NT = ras_threads<TT>();
+    constexpr int K = (NQ + NT - 1) / NT;
     __shared__ T sx[2][W * W];
     __shared__ T sy[2][W * W];
     __shared__ T sb[W * W];
@@ -45,7 +49,7 @@ __global__ __launch_bounds__(kRasThreads) void k_ras_tile(Geom g, int si, int sj
     const int P = g.pitch;
     const size_t base = (size_t)(R0 - 1) * P + (C0 - 1);
 
-    for (int q = threadIdx.x; q < W * W; q += kRasThreads) {
+    for (int q = threadIdx.x; q < W * W; q += NT) {
         const int a = q / W, b = q - a * W;
         T vx = (T)0, vy = (T)0, vb = (T)1, vp = (T)1;
         if (a < nr && b < nc) {
@@ -71,7 +75,7 @@ __global__ __launch_bounds__(kRasThreads) void k_ras_tile(Geom g, int si, int sj
     T rvx[K], rvy[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const int q = threadIdx.x + k * kRasThreads;
+        const int q = threadIdx.x + k * NT;
         const int a = q / TT + 1, b = q % TT + 1;
         const int i = R0 - 1 + a, j = C0 - 1 + b;
         const bool in = q < NQ && i < R1 && j < C1;
@@ -142,7 +146,7 @@ hipError_t launch_ras_t(const Geom& g, int si, int sj, int inner, bool zero, con
                         T* eyo, const T* rx, const T* ry, const T* eb, const T* ep, T omega, hipStream_t st) {
     const int oi = si ? si - TT : 0, oj = sj ? sj - TT : 0;
     const dim3 grid((g.nx - oj + TT - 1) / TT, (g.ny - oi + TT - 1) / TT);
-    hipLaunchKernelGGL((k_ras_tile<T, TT>), grid, dim3(kRasThreads), 0, st, g, si, sj, inner, zero ? 1 : 0, exi, eyi,
+    hipLaunchKernelGGL((k_ras_tile<T, TT>), grid, dim3(ras_threads<TT>()), 0, st, g, si, sj, inner, zero ? 1 : 0, exi, eyi,
                        exo, eyo, rx, ry, eb, ep, omega);
     return hipGetLastError();
 }

@@ -130,6 +130,22 @@ struct tph_solver {
     double kbytes = 0.0;
     std::vector<void*> dev_allocs;
     int vc_cycle = 0;             // V-cycle index inside the current preconditioner application (RAS shifts)
+    // captured preconditioner applications, one per (v, z, w, energy, link) set
+    struct PGraph {
+        const double* v;
+        const double* z;
+        const double* w;
+        bool energy, link;
+        hipGraph_t graph;
+        hipGraphExec_t exec;
+    };
+    std::vector<PGraph> pgraphs;
+    bool graph_broken = false;    // capture failed once: launch eagerly from then on
+    // graphs are captured on and launched into a stream of the library's own
+    // (the caller's stream may be the legacy default stream, which cannot be
+    // captured), joined to the caller's stream by events before and after
+    hipStream_t gst = nullptr;
+    hipEvent_t gev0 = nullptr, gev1 = nullptr;
     bool mixed() const { return d.precision == TPH_MIXED; }
     bool ras() const { return d.smoother == TPH_SMOOTH_RAS || d.smoother == TPH_SMOOTH_RAS_MIXED; }
 };
@@ -232,6 +248,7 @@ tph_status validate_desc(const tph_desc* d, int* nlev_out) {
     if (d->uzawa_steps < 1 || d->uzawa_steps > 8) { set_error("uzawa_steps must be in [1, 8]"); return TPH_ERR_INVALID; }
     if (d->fused != 0 && d->fused != 1) { set_error("fused must be 0 or 1"); return TPH_ERR_INVALID; }
     if (d->msweep < -1 || d->tile_shape < -1) { set_error("msweep and tile_shape must be -1 or a level mask"); return TPH_ERR_INVALID; }
+    if (d->graph != 0 && d->graph != 1) { set_error("graph must be 0 or 1"); return TPH_ERR_INVALID; }
     if (d->coarse_level < -2) { set_error("coarse_level must be -2, -1 or a level index"); return TPH_ERR_INVALID; }
     int nlev = d->levels;
     if (nlev == 0) {
@@ -592,10 +609,63 @@ tph_status precondition_t(tph_solver* s, double* vraw, double* zraw, bool energy
     return TPH_OK;
 }
 
-tph_status precondition(tph_solver* s, double* vraw, double* zraw, bool energy, double* wraw = nullptr,
-                        bool link = false) {
+tph_status precondition_eager(tph_solver* s, double* vraw, double* zraw, bool energy, double* wraw, bool link) {
     return s->mixed() ? precondition_t<float>(s, vraw, zraw, energy, wraw, link)
                       : precondition_t<double>(s, vraw, zraw, energy, wraw, link);
+}
+
+// One preconditioner application.  On the linked path (inside the
+// accelerators) with desc.graph set, the ~10 launches per Uzawa step are
+// captured on first use for each distinct (v, z, w) and replayed as one
+// graph launch afterwards: every kernel argument is fixed per solver (the
+// level buffers, the RAS shifts of step q, the coefficients live in device
+// memory), so a replay launches exactly the kernels of the eager path.
+// Kernel time stamps need per-launch events, so timed solves run eagerly.
+tph_status precondition(tph_solver* s, double* vraw, double* zraw, bool energy, double* wraw = nullptr,
+                        bool link = false) {
+    if (!s->d.graph || s->graph_broken || s->ktime || !(wraw || link))
+        return precondition_eager(s, vraw, zraw, energy, wraw, link);
+    const tph_solver::PGraph* hit = nullptr;
+    for (const auto& pg : s->pgraphs)
+        if (pg.v == vraw && pg.z == zraw && pg.w == wraw && pg.energy == energy && pg.link == link) hit = &pg;
+    if (!hit) {
+        if (!s->gst) {
+            if (hipStreamCreateWithFlags(&s->gst, hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&s->gev0, hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&s->gev1, hipEventDisableTiming) != hipSuccess) {
+                (void)hipGetLastError();
+                s->graph_broken = true;
+                return precondition_eager(s, vraw, zraw, energy, wraw, link);
+            }
+        }
+        tph_solver::PGraph pg{vraw, zraw, wraw, energy, link, nullptr, nullptr};
+        if (hipStreamBeginCapture(s->gst, hipStreamCaptureModeRelaxed) != hipSuccess) {
+            (void)hipGetLastError();
+            s->graph_broken = true;
+            return precondition_eager(s, vraw, zraw, energy, wraw, link);
+        }
+        hipStream_t user = s->st;
+        s->st = s->gst;                          // every launcher enqueues on s->st
+        const tph_status st = precondition_eager(s, vraw, zraw, energy, wraw, link);
+        s->st = user;
+        const hipError_t e = hipStreamEndCapture(s->gst, &pg.graph);
+        if (st != TPH_OK || e != hipSuccess || !pg.graph ||
+            hipGraphInstantiate(&pg.exec, pg.graph, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            if (pg.graph) (void)hipGraphDestroy(pg.graph);
+            s->graph_broken = true;
+            if (st != TPH_OK) return st;
+            return precondition_eager(s, vraw, zraw, energy, wraw, link);
+        }
+        s->pgraphs.push_back(pg);
+        hit = &s->pgraphs.back();
+    }
+    TPH_HIP(hipEventRecord(s->gev0, s->st));
+    TPH_HIP(hipStreamWaitEvent(s->gst, s->gev0, 0));
+    TPH_HIP(hipGraphLaunch(hit->exec, s->gst));
+    TPH_HIP(hipEventRecord(s->gev1, s->gst));
+    TPH_HIP(hipStreamWaitEvent(s->st, s->gev1, 0));
+    return TPH_OK;
 }
 
 // reduce partial rows into `k` device scalars at slot; with to_host the same
@@ -1578,6 +1648,8 @@ void tph_desc_default(tph_desc* d, int32_t nx, int32_t ny) {
     d->ras_tile = 32;
     d->ras_inner = 4;
     d->seed = 0;
+    d->graph = 0;
+    d->pad_ = 0;
     d->max_iters = 500;
     d->uzawa_steps = 2;
     d->fused = 1;
@@ -1754,10 +1826,15 @@ tph_status tph_precondition_apply(tph_solver* s, const double* rx, const double*
     TPH_TRY(copy_in(s, g, r.vx(), rx));
     TPH_TRY(copy_in(s, g, r.vy(), ry));
     TPH_TRY(copy_in(s, g, r.p(), rp));
-    // z and w in the Krylov workspace, free outside a solve
-    double* zb = s->V;
+    // z and w in the accelerator workspace, free outside a solve: z (a
+    // solution-type vector, mirrored ghosts) in the first preconditioned
+    // slot, w (residual-type) in the second basis slot.  Basis vectors must
+    // stay zero outside the equation rows (the Krylov kernels stream every
+    // entry), so z must not go there.
+    double* zb = s->Z;
     double* wb = s->V + s->n3;
-    TPH_HIP(hipMemsetAsync(zb, 0, 2 * s->n3 * sizeof(double), s->st));
+    TPH_HIP(hipMemsetAsync(zb, 0, s->n3 * sizeof(double), s->st));
+    TPH_HIP(hipMemsetAsync(wb, 0, s->n3 * sizeof(double), s->st));
     TPH_TRY(precondition(s, s->b2, zb, false, wb));
     TPH_TRY(store_solution(s, zb, zx, zy, zp));
     TPH_TRY(store_solution(s, wb, wx, wy, wp));
@@ -1949,6 +2026,16 @@ void tph_destroy(tph_solver* s) {
     if (s->ev1) (void)hipEventDestroy(s->ev1);
     for (auto& e : s->kev)
         if (e) (void)hipEventDestroy(e);
+    for (auto& pg : s->pgraphs) {
+        if (pg.exec) (void)hipGraphExecDestroy(pg.exec);
+        if (pg.graph) (void)hipGraphDestroy(pg.graph);
+    }
+    if (s->gst) {
+        (void)hipStreamSynchronize(s->gst);
+        (void)hipStreamDestroy(s->gst);
+    }
+    if (s->gev0) (void)hipEventDestroy(s->gev0);
+    if (s->gev1) (void)hipEventDestroy(s->gev1);
     delete s;
 }
 

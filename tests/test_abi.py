@@ -26,7 +26,7 @@ def test_struct_layout_matches_header(lib):
     # tph_desc: offsets follow the C layout (doubles 8-aligned)
     assert _lib.Desc.lx.offset == 8 and _lib.Desc.bc.offset == 24
     assert _lib.Desc.nu_growth.offset == 64 and _lib.Desc.rtol.offset == 96
-    assert ctypes.sizeof(_lib.Desc) == 160
+    assert ctypes.sizeof(_lib.Desc) == 168
     d = _lib.Desc()
     lib.tph_desc_default(ctypes.byref(d), 64, 32)
     assert (d.nx, d.ny, d.lx, d.precision, d.restart) == (64, 32, 1.0, _lib.MIXED, 20)
@@ -36,6 +36,7 @@ def test_struct_layout_matches_header(lib):
     assert _lib.Desc.accel.offset == 132 and _lib.Desc.beta.offset == 136
     assert _lib.Desc.ras_tile.offset == 144 and _lib.Desc.ras_inner.offset == 148 and _lib.Desc.seed.offset == 152
     assert (d.ras_tile, d.ras_inner, d.seed) == (32, 4, 0)
+    assert _lib.Desc.graph.offset == 160 and d.graph == 0
 
 
 def _create(lib, **kw):
@@ -72,6 +73,7 @@ def _create(lib, **kw):
     (dict(accel=2, beta=0.0), "beta"),
     (dict(accel=2, beta=1.5), "beta"),
     (dict(smoother=4), "smoother"),
+    (dict(graph=2), "graph"),
     (dict(smoother=2, ras_tile=12), "ras_tile"),
     (dict(smoother=3, ras_inner=0), "ras_inner"),
     (dict(smoother=2, ras_inner=17), "ras_inner"),

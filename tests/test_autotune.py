@@ -45,7 +45,8 @@ def test_masks_and_solver_kwargs():
          "coarse_level": 4}
     kw = at.solver_kwargs(p, [0, 1])
     assert kw == dict(nu_pre=3, nu_post=2, nu_growth=1.5, uzawa_steps=1, restart=30, msweep=0b10, tile_shape=0b10,
-                      coarse_level=4, omega=1.0, alpha=1.0, accel="fgmres", beta=1.0)
+                      coarse_level=4, omega=1.0, alpha=1.0, accel="fgmres", beta=1.0, smoother=1, ras_tile=32,
+                      ras_inner=4)
     kw = at.solver_kwargs(dict(p, accel="anderson", beta=0.7), [0, 1])
     assert kw["accel"] == "anderson" and kw["beta"] == 0.7
     ks = at.knobs_for([0, 1, 2], [5])
