@@ -24,5 +24,6 @@ Contents
               around the Uzawa fixed-point map.
 ``ras``       RAS-type temporal-blocking Jacobi smoother and its SplitMix64
               tile shifts.
+``markers``   marker <-> grid bilinear interpolation and RK4 marker advection.
 """
-from . import stokes, multigrid, adjoint, continuation, accelerators, ras  # noqa: F401
+from . import stokes, multigrid, adjoint, continuation, accelerators, ras, markers  # noqa: F401
