@@ -63,6 +63,9 @@ def main():
                     help="timed steps of the GCR and Anderson solves of the main workload (0: skip)")
     ap.add_argument("--ras-steps", type=int, default=5,
                     help="timed steps of the RAS-smoother solve of the main workload (0: skip)")
+    ap.add_argument("--mic-steps", type=int, default=3,
+                    help="timed marker-in-cell steps on the main grid (0: skip)")
+    ap.add_argument("--markers-per-cell", type=int, default=16)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -425,6 +428,73 @@ def main():
         sl.close()
         del sl
 
+    # marker-in-cell step (Sec. "The Marker-in-Cell Method"): markers carry viscosity and density; one step =
+    # marker -> grid (eta_b, rho_b on basic nodes, eta_p on cells), the Stokes solve with the tuned schedule
+    # (mixed), grid -> marker RK4 advection with dt = half a cell at the largest speed
+    mic = None
+    if args.mic_steps > 0:
+        xm_, ym_, meta_, mrho_ = wl.markers(pr, per_cell=args.markers_per_cell, seed=13)
+        nm = xm_.size
+        X_, Y_, E_, R_ = to(xm_), to(ym_), to(meta_), to(mrho_)
+        mk_ = tph.Markers(n, n, capacity=nm, device=dev)
+        sm_ = tph.Solver(n, n, precision=tph.MIXED, device=dev, **tuned["mixed"]["params"])
+        mvx, mvy, mp = sm_.zeros(), sm_.zeros(), sm_.zeros()
+        stages = {"to_grid": 0.0, "solve": 0.0, "advect": 0.0}
+
+        def mic_step(timed):
+            t0 = time.perf_counter()
+            eb_, rb_ = mk_.to_grid("basic", X_, Y_, [E_, R_])
+            ep_ = mk_.to_grid("cell", X_, Y_, [E_])[0]
+            ep_[0, :] = 1.0; ep_[-1, :] = 1.0; ep_[:, 0] = 1.0; ep_[:, -1] = 1.0   # unused entries
+            eb_[-1, :] = 1.0; eb_[:, -1] = 1.0
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            mvx.zero_(); mvy.zero_(); mp.zero_()
+            sm_.set_coefficients(eb_, ep_, rb_, pr.gx, pr.gy)
+            inf_ = sm_.solve(mvx, mvy, mp)[3]
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            vmax = max(mvx.abs().max().item(), mvy.abs().max().item())
+            mk_.advect_rk4(X_, Y_, mvx, mvy, 0.5 / n / max(vmax, 1e-300))
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            if timed:
+                stages["to_grid"] += t1 - t0
+                stages["solve"] += t2 - t1
+                stages["advect"] += t3 - t2
+            return inf_
+
+        mic_step(False)
+        t0 = time.perf_counter()
+        minf = [mic_step(True) for _ in range(args.mic_steps)]
+        mdt = (time.perf_counter() - t0) / args.mic_steps
+        if any(i.status != "TPH_OK" for i in minf):
+            raise RuntimeError(f"marker-in-cell solve did not converge: {minf[-1]}")
+        # the RK4 kernel alone: positions read and written once (32 B per marker), grids through the caches
+        Xa, Ya = X_.clone(), Y_.clone()
+        mk_.advect_rk4(Xa, Ya, mvx, mvy, 1e-9)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(20):
+            mk_.advect_rk4(Xa, Ya, mvx, mvy, 1e-9)
+        torch.cuda.synchronize()
+        rk_ms = 1e3 * (time.perf_counter() - t0) / 20
+        rk_gbs = 32.0 * nm / (rk_ms * 1e-3) / 1e9
+        per = {k: 1e3 * v / args.mic_steps for k, v in stages.items()}
+        mic = {"workload": f"{nm} markers ({args.markers_per_cell} per cell, seed 13) on the {n}x{n} random-viscosity "
+                           f"grid, eta and rho per marker; step = marker -> grid (3 fields, 2 binnings) + mixed "
+                           f"solve + RK4", "markers": nm, "ms_per_step": 1e3 * mdt,
+               "stages_ms": per, "iters": minf[-1].iters, "res_energy": minf[-1].res_energy,
+               "markers_to_grid_per_s": 3 * nm / (per["to_grid"] * 1e-3),
+               "rk4": {"ms": rk_ms, "markers_per_s": nm / (rk_ms * 1e-3), "GBps": round(rk_gbs, 1),
+                       "frac": round(rk_gbs / HBM_PEAK_GBS, 4),
+                       "what": "positions 2 x 8 B read + written per marker; 64 grid reads per marker from cache"}}
+        log(f"[bench] marker-in-cell: {1e3 * mdt:.1f} ms/step (to_grid {per['to_grid']:.1f}, solve "
+            f"{per['solve']:.1f}, advect {per['advect']:.2f} ms), RK4 kernel {rk_ms:.2f} ms = {rk_gbs:.0f} GB/s")
+        mk_.close()
+        sm_.close()
+        del mk_, sm_, X_, Y_, E_, R_
+
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import stokes as ost
@@ -468,6 +538,7 @@ def main():
         "mixed_speedup_vs_fp64": ms_64 / ms_mix if fp64_steps > 0 else None,
         "accelerators": accels or None,
         "ras": ras_out,
+        "marker_in_cell": mic,
         "tuned": tuned,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,

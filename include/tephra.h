@@ -385,6 +385,68 @@ const char* tph_last_error(void);
 /* Library version string. */
 const char* tph_version(void);
 
+/* ------------------------------------------------------------------------
+ * Markers (Ch. 4, Sec. "The Marker-in-Cell Method", Sec. "Interpolation
+ * Between Markers and Grid", Sec. "Advection of Lagrangian Markers").
+ *
+ * Marker positions and values are DEVICE arrays of n FP64 entries (caller
+ * owned); positions lie in [0, lx] x [0, ly].  Grid arrays use the dense
+ * (ny + 2) x (nx + 2) convention of this header.  Node grids:
+ *   TPH_NODES_BASIC (j dx, i dy),                i in [0, ny],     j in [0, nx]
+ *   TPH_NODES_CELL  ((j - 1/2) dx, (i - 1/2) dy), i in [1, ny],     j in [1, nx]
+ *   TPH_NODES_VX    (j dx, (i - 1/2) dy),         i in [0, ny + 1], j in [0, nx]
+ *   TPH_NODES_VY    ((j - 1/2) dx, i dy),         i in [0, ny],     j in [0, nx + 1]
+ * (vx and vy include the walls and the mirrored ghosts of a solver output).
+ * Bilinear weights of a marker at (x, y) in the cell whose lower-left node
+ * is (i, j): (1 - rx)(1 - ry), rx (1 - ry), (1 - rx) ry, rx ry on (i, j),
+ * (i, j+1), (i+1, j), (i+1, j+1), with rx = (x - x_j) / dx, ry = (y - y_i) / dy.
+ * All work is enqueued on the stream given at creation; tph_markers_sync
+ * waits for it.
+ * ------------------------------------------------------------------------ */
+enum { TPH_NODES_BASIC = 0, TPH_NODES_CELL = 1, TPH_NODES_VX = 2, TPH_NODES_VY = 3 };
+
+typedef struct tph_markers tph_markers;
+
+/* Workspace for an nx x ny grid of size lx x ly and up to `capacity`
+ * markers (sort buffers, per-cell ranges and partial sums).  Errors:
+ * TPH_ERR_INVALID for bad sizes, TPH_ERR_OOM. */
+tph_status tph_markers_create(int32_t nx, int32_t ny, double lx, double ly, int32_t capacity, void* hip_stream,
+                              tph_markers** out);
+void tph_markers_destroy(tph_markers* h);
+
+/* Marker -> grid, step 1: bin the n markers by the cell of the `kind` node
+ * grid (TPH_NODES_BASIC or TPH_NODES_CELL) that contains them, with a stable
+ * sort of (cell, marker index).  xm and ym must stay valid and unchanged
+ * until the last tph_markers_to_grid of this binning. */
+tph_status tph_markers_bin(tph_markers* h, int32_t kind, int32_t n, const double* xm, const double* ym);
+
+/* Marker -> grid, step 2 (any number of fields per binning): grid(i, j) =
+ * sum_m w_m(i, j) phi_m / sum_m w_m(i, j) over the binned markers that reach
+ * node (i, j) of the binned kind (normalised bilinear average), `fill` where
+ * none does; entries outside the kind's node range are not written.
+ * Weights that fall on nodes outside the range are dropped (the
+ * normalisation absorbs them).  Without atomics: per-cell partial sums in
+ * sorted order, then per-node sums of its four cells in a fixed order, so the
+ * result is bitwise reproducible. */
+tph_status tph_markers_to_grid(tph_markers* h, const double* phi_m, double fill, double* grid);
+
+/* Grid -> marker: phi_m = the bilinear interpolation of the `kind` node
+ * grid at each marker (the weights sum to one).  The cell is taken within
+ * the kind's node range and rx, ry are clamped to [0, 1] (no
+ * extrapolation). */
+tph_status tph_markers_from_grid(tph_markers* h, int32_t kind, int32_t n, const double* xm, const double* ym,
+                                 const double* grid, double* phi_m);
+
+/* One classical RK4 step (eq. rk4_method) of dx/dt = v(x) for n markers, in
+ * place, with v interpolated from the staggered velocity arrays vx, vy (a
+ * solver output: walls and ghosts set) as in tph_markers_from_grid; every
+ * stage position and the result are clamped to [0, lx] x [0, ly]. */
+tph_status tph_markers_advect_rk4(tph_markers* h, int32_t n, double* xm, double* ym, const double* vx,
+                                  const double* vy, double dt);
+
+/* Wait for the marker stream (reports any device error). */
+tph_status tph_markers_sync(tph_markers* h);
+
 #ifdef __cplusplus
 }
 #endif

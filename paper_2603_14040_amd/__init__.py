@@ -21,7 +21,7 @@ from ._lib import (ACCEL_ANDERSON, ACCEL_FGMRES, ACCEL_GCR, FP64, FREE_SLIP, MEA
 __all__ = ["Solver", "Batch", "SolveInfo", "StokesFunction", "solve", "FP64", "MIXED", "FREE_SLIP",
            "NO_SLIP", "SMOOTH_GS", "SMOOTH_JACOBI", "SMOOTH_RAS", "SMOOTH_RAS_MIXED", "MEAN_ARITHMETIC",
            "MEAN_GEOMETRIC",
-           "ACCEL_FGMRES", "ACCEL_GCR", "ACCEL_ANDERSON", "TephraError", "library"]
+           "ACCEL_FGMRES", "ACCEL_GCR", "ACCEL_ANDERSON", "Markers", "TephraError", "library"]
 
 
 def library():
@@ -387,6 +387,94 @@ class Batch:
                          infos[k].t_solve_ms)
                for k in range(self.count)]
         return vx, vy, p, out
+
+
+def _mptr(t, n, name):
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() \
+            or t.dim() != 1 or t.numel() != n:
+        raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of {n} entries")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Markers:
+    """Marker <-> grid transfers and RK4 advection (tph_markers_*).
+
+    Marker positions and values are 1D float64 CUDA tensors of n entries;
+    grids are (ny + 2, nx + 2) float64 tensors.  Node kinds: "basic",
+    "cell", "vx", "vy" (see the header).
+    """
+
+    def __init__(self, nx: int, ny: int, lx: float = 1.0, ly: float = 1.0, capacity: int = 1 << 20,
+                 device: Optional[torch.device] = None, stream: Optional[torch.cuda.Stream] = None):
+        lib = _lib.load()
+        self._lib = lib
+        self.nx, self.ny = nx, ny
+        self.shape = (ny + 2, nx + 2)
+        self.capacity = int(capacity)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            h = ctypes.c_void_p()
+            _lib.check("tph_markers_create", lib.tph_markers_create(nx, ny, float(lx), float(ly), self.capacity,
+                                                                    ctypes.c_void_p(self.stream.cuda_stream),
+                                                                    ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.tph_markers_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_in(self):
+        if self.stream != torch.cuda.current_stream(self.device):
+            self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def _sync_out(self):
+        if self.stream != torch.cuda.current_stream(self.device):
+            torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
+    def to_grid(self, kind: str, xm, ym, fields, fill: float = 0.0):
+        """Normalised bilinear averages of each marker field on the `kind` nodes (one binning)."""
+        n = xm.numel()
+        self._sync_in()
+        _lib.check("tph_markers_bin", self._lib.tph_markers_bin(self._h, _lib.NODE_KINDS[kind], n,
+                                                                _mptr(xm, n, "xm"), _mptr(ym, n, "ym")))
+        outs = []
+        for k, f in enumerate(fields):
+            g = torch.zeros(self.shape, dtype=torch.float64, device=self.device)
+            _lib.check("tph_markers_to_grid", self._lib.tph_markers_to_grid(self._h, _mptr(f, n, f"fields[{k}]"),
+                                                                            float(fill), _ptr(g, self.shape, "grid")))
+            outs.append(g)
+        self._sync_out()
+        return outs
+
+    def from_grid(self, kind: str, xm, ym, grid):
+        n = xm.numel()
+        out = torch.empty(n, dtype=torch.float64, device=self.device)
+        self._sync_in()
+        _lib.check("tph_markers_from_grid", self._lib.tph_markers_from_grid(
+            self._h, _lib.NODE_KINDS[kind], n, _mptr(xm, n, "xm"), _mptr(ym, n, "ym"), _ptr(grid, self.shape, "grid"),
+            _mptr(out, n, "out")))
+        self._sync_out()
+        return out
+
+    def advect_rk4(self, xm, ym, vx, vy, dt: float):
+        """One RK4 step in place."""
+        n = xm.numel()
+        self._sync_in()
+        _lib.check("tph_markers_advect_rk4", self._lib.tph_markers_advect_rk4(
+            self._h, n, _mptr(xm, n, "xm"), _mptr(ym, n, "ym"), _ptr(vx, self.shape, "vx"), _ptr(vy, self.shape, "vy"),
+            float(dt)))
+        self._sync_out()
+
+    def sync(self):
+        _lib.check("tph_markers_sync", self._lib.tph_markers_sync(self._h))
 
 
 def solve(eta_b, eta_p, rho_b, gx: float = 0.0, gy: float = -1.0, lx: float = 1.0, ly: float = 1.0,

@@ -22,6 +22,8 @@ FP64, MIXED = 0, 1
 SMOOTH_JACOBI, SMOOTH_GS, SMOOTH_RAS, SMOOTH_RAS_MIXED = 0, 1, 2, 3
 MEAN_ARITHMETIC, MEAN_GEOMETRIC = 0, 1
 ACCEL_FGMRES, ACCEL_GCR, ACCEL_ANDERSON = 0, 1, 2
+NODES_BASIC, NODES_CELL, NODES_VX, NODES_VY = 0, 1, 2, 3
+NODE_KINDS = {"basic": NODES_BASIC, "cell": NODES_CELL, "vx": NODES_VX, "vy": NODES_VY}
 ACCEL_NAMES = {"fgmres": ACCEL_FGMRES, "gcr": ACCEL_GCR, "anderson": ACCEL_ANDERSON}
 KERNEL_SMOOTH, KERNEL_APPLY, KERNEL_RESIDUAL, KERNEL_RESTRICT, KERNEL_PROLONG = 0, 1, 2, 3, 4
 KERNEL_GCR_STEP, KERNEL_AA_MIX = 5, 6
@@ -99,6 +101,13 @@ def load(path: str = LIB_PATH):
         "tph_batch_set_coefficients": (c_int32, [P, POINTER(P), POINTER(P), POINTER(P), POINTER(c_double)]),
         "tph_batch_solve": (c_int32, [P, POINTER(P), POINTER(P), POINTER(P), POINTER(Info)]),
         "tph_batch_destroy": (None, [P]),
+        "tph_markers_create": (c_int32, [c_int32, c_int32, c_double, c_double, c_int32, P, POINTER(P)]),
+        "tph_markers_destroy": (None, [P]),
+        "tph_markers_bin": (c_int32, [P, c_int32, c_int32, P, P]),
+        "tph_markers_to_grid": (c_int32, [P, P, c_double, P]),
+        "tph_markers_from_grid": (c_int32, [P, c_int32, c_int32, P, P, P, P]),
+        "tph_markers_advect_rk4": (c_int32, [P, c_int32, P, P, P, P, c_double]),
+        "tph_markers_sync": (c_int32, [P]),
         "tph_last_error": (c_char_p, []),
         "tph_version": (c_char_p, []),
     }

@@ -1,0 +1,381 @@
+// Marker <-> grid transfers and RK4 marker advection (Sec. "Interpolation
+// Between Markers and Grid", Sec. "Advection of Lagrangian Markers",
+// eq. rk4_method), behind the tph_markers_* entry points of tephra.h.
+//
+// Marker -> grid without atomics: markers are binned by the node-grid cell
+// that contains them (the cell whose four corners are the nodes they weight)
+// with a stable radix sort of (cell, marker) pairs; each cell then sums, in
+// sorted order, the weighted values and weights its markers give to its four
+// corners, and each node adds the partial sums of its (up to) four cells in
+// a fixed order.  Every sum has one writer and a fixed order, so results are
+// bitwise reproducible.  Grid -> marker and RK4 are one thread per marker;
+// all four RK4 stages run in registers, the velocity grids are read through
+// the caches.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <cmath>
+#include <cstdint>
+#include <string>
+
+#include "../../include/tephra.h"
+#include "solver_internal.h"
+
+struct tph_markers {
+    int nx = 0, ny = 0;
+    double lx = 0, ly = 0, dx = 0, dy = 0;
+    int capacity = 0;
+    hipStream_t st = nullptr;
+    uint32_t* keys[2] = {nullptr, nullptr};
+    int32_t* vals[2] = {nullptr, nullptr};
+    void* temp = nullptr;
+    size_t temp_bytes = 0;
+    int32_t* cstart = nullptr;     // per cell: first sorted position
+    int32_t* cend = nullptr;       // one past the last
+    double* partial = nullptr;     // per cell: 4 corners x (sum w phi, sum w)
+    int sorted = 0;                // which key/value buffer holds the sorted pairs
+    // the current binning
+    int kind = -1;
+    int n = 0;
+    const double* xm = nullptr;
+    const double* ym = nullptr;
+};
+
+namespace {
+
+void tph_internal_set_error_m(const std::string& m) { tph_internal_set_error(m); }
+
+// node grid of a kind: node (i, j) at (x0 + j dx, y0 + i dy), i in [imin, imax], j in [jmin, jmax]
+struct NodeGrid {
+    double x0, y0, dx, dy;
+    int imin, imax, jmin, jmax;
+    int pitch;                     // nx + 2: the caller's dense array layout
+    double idx, idy;               // 1 / dx, 1 / dy (interpolation multiplies instead of dividing)
+};
+
+NodeGrid node_grid(const tph_markers* h, int kind) {
+    NodeGrid q{};
+    q.dx = h->dx;
+    q.dy = h->dy;
+    q.pitch = h->nx + 2;
+    switch (kind) {
+        case TPH_NODES_BASIC: q = {0.0, 0.0, h->dx, h->dy, 0, h->ny, 0, h->nx, h->nx + 2}; break;
+        case TPH_NODES_CELL: q = {-0.5 * h->dx, -0.5 * h->dy, h->dx, h->dy, 1, h->ny, 1, h->nx, h->nx + 2}; break;
+        case TPH_NODES_VX: q = {0.0, -0.5 * h->dy, h->dx, h->dy, 0, h->ny + 1, 0, h->nx, h->nx + 2}; break;
+        default: q = {-0.5 * h->dx, 0.0, h->dx, h->dy, 0, h->ny, 0, h->nx + 1, h->nx + 2}; break;
+    }
+    q.idx = 1.0 / h->dx;
+    q.idy = 1.0 / h->dy;
+    return q;
+}
+
+// cells of the binning: lower-left node index (i, j) in [0, ny] x [0, nx] for both scatter kinds
+__device__ __forceinline__ uint32_t cell_key(const NodeGrid& q, int nx, int ny, double x, double y) {
+    int j = (int)floor((x - q.x0) / q.dx);
+    int i = (int)floor((y - q.y0) / q.dy);
+    j = j < 0 ? 0 : (j > nx ? nx : j);
+    i = i < 0 ? 0 : (i > ny ? ny : i);
+    return (uint32_t)(i * (nx + 1) + j);
+}
+
+__global__ __launch_bounds__(256) void k_bin(NodeGrid q, int nx, int ny, int n, const double* __restrict__ xm,
+                                             const double* __restrict__ ym, uint32_t* __restrict__ keys,
+                                             int32_t* __restrict__ vals) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    keys[m] = cell_key(q, nx, ny, xm[m], ym[m]);
+    vals[m] = m;
+}
+
+__global__ __launch_bounds__(256) void k_ranges(int n, const uint32_t* __restrict__ keys, int32_t* __restrict__ cstart,
+                                                int32_t* __restrict__ cend) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const uint32_t k = keys[p];
+    if (p == 0 || keys[p - 1] != k) cstart[k] = p;
+    if (p == n - 1 || keys[p + 1] != k) cend[k] = p + 1;
+}
+
+// per cell, in sorted (stable: marker index) order: sums of w phi and w for its four corners
+__global__ __launch_bounds__(256) void k_cell_partials(NodeGrid q, int nx, int ny, const int32_t* __restrict__ cstart,
+                                                       const int32_t* __restrict__ cend,
+                                                       const int32_t* __restrict__ order,
+                                                       const double* __restrict__ xm, const double* __restrict__ ym,
+                                                       const double* __restrict__ phi, double* __restrict__ partial) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ncell = (nx + 1) * (ny + 1);
+    if (c >= ncell) return;
+    const int i = c / (nx + 1), j = c - i * (nx + 1);
+    const double xj = q.x0 + j * q.dx, yi = q.y0 + i * q.dy;
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int p = cstart[c]; p < cend[c]; ++p) {
+        const int m = order[p];
+        const double rx = (xm[m] - xj) / q.dx, ry = (ym[m] - yi) / q.dy;
+        const double f = phi[m];
+        const double w00 = (1.0 - rx) * (1.0 - ry), w01 = rx * (1.0 - ry), w10 = (1.0 - rx) * ry, w11 = rx * ry;
+        s[0] += w00 * f;
+        s[1] += w00;
+        s[2] += w01 * f;
+        s[3] += w01;
+        s[4] += w10 * f;
+        s[5] += w10;
+        s[6] += w11 * f;
+        s[7] += w11;
+    }
+    double* out = partial + (size_t)c * 8;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) out[k] = s[k];
+}
+
+// node (i, j) = corner (1,1) of cell (i-1, j-1), (1,0) of (i-1, j), (0,1) of (i, j-1), (0,0) of (i, j)
+__global__ __launch_bounds__(256) void k_nodes(NodeGrid q, int nx, int ny, const double* __restrict__ partial,
+                                               double fill, double* __restrict__ grid) {
+    const int j = q.jmin + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const int i = q.imin + (int)blockIdx.y;
+    if (j > q.jmax || i > q.imax) return;
+    double num = 0.0, den = 0.0;
+    const int ci[4] = {i - 1, i - 1, i, i};
+    const int cj[4] = {j - 1, j, j - 1, j};
+    const int corner[4] = {3, 2, 1, 0};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (ci[k] < 0 || ci[k] > ny || cj[k] < 0 || cj[k] > nx) continue;
+        const double* pp = partial + ((size_t)ci[k] * (nx + 1) + cj[k]) * 8 + 2 * corner[k];
+        num += pp[0];
+        den += pp[1];
+    }
+    grid[(size_t)i * q.pitch + j] = den > 0.0 ? num / den : fill;
+}
+
+// (the cell found by a multiplication may differ from the divided one for a
+// marker on a cell edge; both cells give the same value there)
+__device__ __forceinline__ double interp(const NodeGrid& q, const double* __restrict__ grid, double x, double y) {
+    const double tx = (x - q.x0) * q.idx, ty = (y - q.y0) * q.idy;
+    int j = (int)floor(tx);
+    int i = (int)floor(ty);
+    j = j < q.jmin ? q.jmin : (j > q.jmax - 1 ? q.jmax - 1 : j);
+    i = i < q.imin ? q.imin : (i > q.imax - 1 ? q.imax - 1 : i);
+    double rx = tx - j, ry = ty - i;
+    rx = rx < 0.0 ? 0.0 : (rx > 1.0 ? 1.0 : rx);
+    ry = ry < 0.0 ? 0.0 : (ry > 1.0 ? 1.0 : ry);
+    const double* g0 = grid + (size_t)i * q.pitch + j;
+    const double* g1 = g0 + q.pitch;
+    return (1.0 - rx) * (1.0 - ry) * g0[0] + rx * (1.0 - ry) * g0[1] + (1.0 - rx) * ry * g1[0] + rx * ry * g1[1];
+}
+
+__global__ __launch_bounds__(256) void k_from_grid(NodeGrid q, int n, const double* __restrict__ xm,
+                                                   const double* __restrict__ ym, const double* __restrict__ grid,
+                                                   double* __restrict__ out) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    out[m] = interp(q, grid, xm[m], ym[m]);
+}
+
+__global__ __launch_bounds__(256) void k_rk4(NodeGrid qx, NodeGrid qy, double lx, double ly, int n,
+                                             double* __restrict__ xm, double* __restrict__ ym,
+                                             const double* __restrict__ vx, const double* __restrict__ vy, double dt) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    auto clampx = [&](double v) { return v < 0.0 ? 0.0 : (v > lx ? lx : v); };
+    auto clampy = [&](double v) { return v < 0.0 ? 0.0 : (v > ly ? ly : v); };
+    const double x = xm[m], y = ym[m];
+    const double k1x = interp(qx, vx, x, y), k1y = interp(qy, vy, x, y);
+    double sx = clampx(x + 0.5 * dt * k1x), sy = clampy(y + 0.5 * dt * k1y);
+    const double k2x = interp(qx, vx, sx, sy), k2y = interp(qy, vy, sx, sy);
+    sx = clampx(x + 0.5 * dt * k2x);
+    sy = clampy(y + 0.5 * dt * k2y);
+    const double k3x = interp(qx, vx, sx, sy), k3y = interp(qy, vy, sx, sy);
+    sx = clampx(x + dt * k3x);
+    sy = clampy(y + dt * k3y);
+    const double k4x = interp(qx, vx, sx, sy), k4y = interp(qy, vy, sx, sy);
+    xm[m] = clampx(x + dt / 6.0 * (k1x + 2.0 * k2x + 2.0 * k3x + k4x));
+    ym[m] = clampy(y + dt / 6.0 * (k1y + 2.0 * k2y + 2.0 * k3y + k4y));
+}
+
+inline unsigned blocks(long long n) { return (unsigned)((n + 255) / 256); }
+
+#define M_HIP(call)                                                                                  \
+    do {                                                                                             \
+        hipError_t e_ = (call);                                                                      \
+        if (e_ != hipSuccess) {                                                                      \
+            tph_internal_set_error_m(std::string("HIP error in ") + #call + ": " + hipGetErrorString(e_)); \
+            return TPH_ERR_HIP;                                                                      \
+        }                                                                                            \
+    } while (0)
+
+int key_bits(const tph_markers* h) {
+    const uint64_t ncell = (uint64_t)(h->nx + 1) * (uint64_t)(h->ny + 1);
+    int b = 1;
+    while (b < 32 && (1ull << b) < ncell) ++b;
+    return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+tph_status tph_markers_create(int32_t nx, int32_t ny, double lx, double ly, int32_t capacity, void* hip_stream,
+                              tph_markers** out) {
+    tph_internal_set_error_m("");
+    if (!out) {
+        tph_internal_set_error_m("out is NULL");
+        return TPH_ERR_INVALID;
+    }
+    *out = nullptr;
+    if (nx < 1 || ny < 1 || (int64_t)(nx + 2) * (ny + 2) > (int64_t)1 << 30 || !(lx > 0) || !(ly > 0) ||
+        !std::isfinite(lx) || !std::isfinite(ly) || capacity < 1) {
+        tph_internal_set_error_m("need nx, ny >= 1 (grid at most 2^30 entries), positive finite lx, ly and capacity >= 1");
+        return TPH_ERR_INVALID;
+    }
+    tph_markers* h = new tph_markers();
+    h->nx = nx;
+    h->ny = ny;
+    h->lx = lx;
+    h->ly = ly;
+    h->dx = lx / nx;
+    h->dy = ly / ny;
+    h->capacity = capacity;
+    h->st = (hipStream_t)hip_stream;
+    const size_t ncell = (size_t)(nx + 1) * (ny + 1);
+    bool ok = true;
+    for (int k = 0; k < 2 && ok; ++k) {
+        ok = hipMalloc(&h->keys[k], (size_t)capacity * sizeof(uint32_t)) == hipSuccess &&
+             hipMalloc(&h->vals[k], (size_t)capacity * sizeof(int32_t)) == hipSuccess;
+    }
+    ok = ok && hipMalloc(&h->cstart, ncell * sizeof(int32_t)) == hipSuccess &&
+         hipMalloc(&h->cend, ncell * sizeof(int32_t)) == hipSuccess &&
+         hipMalloc(&h->partial, ncell * 8 * sizeof(double)) == hipSuccess;
+    if (ok) {
+        hipcub::DoubleBuffer<uint32_t> kb(h->keys[0], h->keys[1]);
+        hipcub::DoubleBuffer<int32_t> vb(h->vals[0], h->vals[1]);
+        ok = hipcub::DeviceRadixSort::SortPairs(nullptr, h->temp_bytes, kb, vb, capacity, 0, 32, h->st) == hipSuccess &&
+             hipMalloc(&h->temp, h->temp_bytes > 0 ? h->temp_bytes : 1) == hipSuccess;
+    }
+    if (!ok) {
+        (void)hipGetLastError();
+        tph_markers_destroy(h);
+        tph_internal_set_error_m("out of device memory for the marker workspace");
+        return TPH_ERR_OOM;
+    }
+    *out = h;
+    return TPH_OK;
+}
+
+void tph_markers_destroy(tph_markers* h) {
+    if (!h) return;
+    if (h->st) (void)hipStreamSynchronize(h->st);
+    for (int k = 0; k < 2; ++k) {
+        if (h->keys[k]) (void)hipFree(h->keys[k]);
+        if (h->vals[k]) (void)hipFree(h->vals[k]);
+    }
+    if (h->cstart) (void)hipFree(h->cstart);
+    if (h->cend) (void)hipFree(h->cend);
+    if (h->partial) (void)hipFree(h->partial);
+    if (h->temp) (void)hipFree(h->temp);
+    delete h;
+}
+
+tph_status tph_markers_bin(tph_markers* h, int32_t kind, int32_t n, const double* xm, const double* ym) {
+    tph_internal_set_error_m("");
+    if (!h || (n > 0 && (!xm || !ym))) {
+        tph_internal_set_error_m("handle, xm and ym are required");
+        return TPH_ERR_INVALID;
+    }
+    if (kind != TPH_NODES_BASIC && kind != TPH_NODES_CELL) {
+        tph_internal_set_error_m("marker -> grid transfers go to TPH_NODES_BASIC or TPH_NODES_CELL");
+        return TPH_ERR_INVALID;
+    }
+    if (n < 0 || n > h->capacity) {
+        tph_internal_set_error_m("n must be in [0, capacity]");
+        return TPH_ERR_INVALID;
+    }
+    const NodeGrid q = node_grid(h, kind);
+    const size_t ncell = (size_t)(h->nx + 1) * (h->ny + 1);
+    M_HIP(hipMemsetAsync(h->cstart, 0, ncell * sizeof(int32_t), h->st));
+    M_HIP(hipMemsetAsync(h->cend, 0, ncell * sizeof(int32_t), h->st));
+    h->kind = kind;
+    h->n = n;
+    h->xm = xm;
+    h->ym = ym;
+    h->sorted = 0;
+    if (n == 0) return TPH_OK;
+    hipLaunchKernelGGL(k_bin, dim3(blocks(n)), dim3(256), 0, h->st, q, h->nx, h->ny, n, xm, ym, h->keys[0],
+                       h->vals[0]);
+    M_HIP(hipGetLastError());
+    hipcub::DoubleBuffer<uint32_t> kb(h->keys[0], h->keys[1]);
+    hipcub::DoubleBuffer<int32_t> vb(h->vals[0], h->vals[1]);
+    size_t tb = h->temp_bytes;
+    M_HIP(hipcub::DeviceRadixSort::SortPairs(h->temp, tb, kb, vb, n, 0, key_bits(h), h->st));
+    h->sorted = kb.selector;
+    hipLaunchKernelGGL(k_ranges, dim3(blocks(n)), dim3(256), 0, h->st, n, h->keys[h->sorted], h->cstart, h->cend);
+    M_HIP(hipGetLastError());
+    return TPH_OK;
+}
+
+tph_status tph_markers_to_grid(tph_markers* h, const double* phi_m, double fill, double* grid) {
+    tph_internal_set_error_m("");
+    if (!h || !grid || (h->n > 0 && !phi_m)) {
+        tph_internal_set_error_m("handle, phi_m and grid are required");
+        return TPH_ERR_INVALID;
+    }
+    if (h->kind < 0) {
+        tph_internal_set_error_m("no binning: call tph_markers_bin first");
+        return TPH_ERR_INVALID;
+    }
+    const NodeGrid q = node_grid(h, h->kind);
+    const int ncell = (h->nx + 1) * (h->ny + 1);
+    hipLaunchKernelGGL(k_cell_partials, dim3(blocks(ncell)), dim3(256), 0, h->st, q, h->nx, h->ny, h->cstart, h->cend,
+                       h->vals[h->sorted], h->xm, h->ym, phi_m, h->partial);
+    M_HIP(hipGetLastError());
+    const dim3 grid_((unsigned)((q.jmax - q.jmin + 1 + 255) / 256), (unsigned)(q.imax - q.imin + 1));
+    hipLaunchKernelGGL(k_nodes, grid_, dim3(256), 0, h->st, q, h->nx, h->ny, h->partial, fill, grid);
+    M_HIP(hipGetLastError());
+    return TPH_OK;
+}
+
+tph_status tph_markers_from_grid(tph_markers* h, int32_t kind, int32_t n, const double* xm, const double* ym,
+                                 const double* grid, double* phi_m) {
+    tph_internal_set_error_m("");
+    if (!h || (n > 0 && (!xm || !ym || !grid || !phi_m))) {
+        tph_internal_set_error_m("handle, xm, ym, grid and phi_m are required");
+        return TPH_ERR_INVALID;
+    }
+    if (kind < TPH_NODES_BASIC || kind > TPH_NODES_VY || n < 0) {
+        tph_internal_set_error_m("bad node kind or marker count");
+        return TPH_ERR_INVALID;
+    }
+    if (n == 0) return TPH_OK;
+    hipLaunchKernelGGL(k_from_grid, dim3(blocks(n)), dim3(256), 0, h->st, node_grid(h, kind), n, xm, ym, grid, phi_m);
+    M_HIP(hipGetLastError());
+    return TPH_OK;
+}
+
+tph_status tph_markers_advect_rk4(tph_markers* h, int32_t n, double* xm, double* ym, const double* vx,
+                                  const double* vy, double dt) {
+    tph_internal_set_error_m("");
+    if (!h || (n > 0 && (!xm || !ym || !vx || !vy))) {
+        tph_internal_set_error_m("handle, xm, ym, vx and vy are required");
+        return TPH_ERR_INVALID;
+    }
+    if (n < 0 || !std::isfinite(dt)) {
+        tph_internal_set_error_m("n must be >= 0 and dt finite");
+        return TPH_ERR_INVALID;
+    }
+    if (n == 0) return TPH_OK;
+    hipLaunchKernelGGL(k_rk4, dim3(blocks(n)), dim3(256), 0, h->st, node_grid(h, TPH_NODES_VX),
+                       node_grid(h, TPH_NODES_VY), h->lx, h->ly, n, xm, ym, vx, vy, dt);
+    M_HIP(hipGetLastError());
+    return TPH_OK;
+}
+
+tph_status tph_markers_sync(tph_markers* h) {
+    tph_internal_set_error_m("");
+    if (!h) {
+        tph_internal_set_error_m("handle is NULL");
+        return TPH_ERR_INVALID;
+    }
+    M_HIP(hipStreamSynchronize(h->st));
+    return TPH_OK;
+}
+
+}  // extern "C"

@@ -29,6 +29,10 @@ Recipes (all FP64, ``numpy.random.default_rng`` / PCG64):
 * ``multi_inclusion``: discs painted in draw order over a background
   (eta = 1, rho = 0); later discs overwrite earlier ones.
 * ``batch_sinkers``: independent sinkers of uneven square sizes.
+* ``markers``: ``per_cell`` markers in every cell of a problem's grid at
+  uniform random positions inside the cell (one seed), each carrying the
+  viscosity eta_p of its cell and the density rho_b of the basic node
+  nearest to it.
 """
 from __future__ import annotations
 
@@ -270,3 +274,17 @@ def random_state(nx: int, ny: int, seed: int):
     vy = rng.standard_normal((ny + 2, nx + 2))
     p = rng.standard_normal((ny + 2, nx + 2))
     return vx, vy, p
+
+
+def markers(pr: "Problem", per_cell: int = 16, seed: int = 7):
+    """Marker positions (x, y) and properties (eta, rho) for a problem; see the module recipes."""
+    rng = np.random.default_rng(seed)
+    nx, ny = pr.nx, pr.ny
+    dx, dy = pr.lx / nx, pr.ly / ny
+    ci = np.repeat(np.arange(ny), nx * per_cell)
+    cj = np.tile(np.repeat(np.arange(nx), per_cell), ny)
+    x = (cj + rng.random(ci.size)) * dx
+    y = (ci + rng.random(ci.size)) * dy
+    eta = pr.eta_p[ci + 1, cj + 1]
+    rho = pr.rho_b[np.clip(np.rint(y / dy).astype(np.int64), 0, ny), np.clip(np.rint(x / dx).astype(np.int64), 0, nx)]
+    return x, y, eta.astype(np.float64), rho.astype(np.float64)
