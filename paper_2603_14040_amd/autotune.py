@@ -185,7 +185,7 @@ def knobs_for(tile_levels: Sequence[int], coarse_levels: Sequence[int] = (), nus
 # ---------------------------------------------------------------------------
 def schedule_knobs() -> List[Knob]:
     """Knobs that carry over between grid sizes of one recipe (no per-level plan)."""
-    return [Knob("restart", [8, 16, 30, 50, 64]), Knob("alpha", [1.0, 1.5, 2.0, 3.0]),
+    return [Knob("restart", [8, 16, 30, 50, 64]), Knob("accel", ["fgmres", "gcr"]), Knob("alpha", [1.0, 1.5, 2.0, 3.0]),
             Knob("uzawa_steps", [1, 2, 3, 4, 6, 8]), Knob("nu_pre", [1, 2, 3]), Knob("nu_post", [1, 2, 3]),
             Knob("omega", [0.8, 1.0, 1.2])]
 

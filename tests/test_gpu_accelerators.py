@@ -183,3 +183,34 @@ def test_vector_kernel_timing(m):
     # the handle still solves afterwards
     vx, vy, p, info = s.solve()
     assert info.status == "TPH_OK"
+
+
+@pytest.mark.parametrize("accel,m,beta", [("gcr", 12, 1.0), ("anderson", 8, 0.8)])
+def test_accelerators_drive_continuation_and_adjoint(accel, m, beta):
+    """The continuation stages and the adjoint solve run through the chosen
+    accelerator and still meet the oracle."""
+    from oracle import adjoint as adj
+    pr = wl.sinker(64, eta_in=1e3, radius=0.15)
+    g = st.Grid(64, 64)
+    ref = st.solve(g, pr.eta_b, pr.eta_p, pr.rho_b, pr.gx, pr.gy)
+    s = solver_for(pr, precision=tph.FP64, rtol=1e-12, max_iters=3000, accel=accel, restart=m, beta=beta)
+    vx, vy, p, info = s.solve_continuation(T(pr.eta_b), T(pr.eta_p), T(pr.rho_b), pr.gx, pr.gy,
+                                           thetas=(0.0, 0.5, 1.0), stage_rtol=1e-3, lithostatic=True)
+    assert info.status == "TPH_OK" or info.res_energy < 1e-10
+    ev, ep_ = st.parity_errors(g, ref, N(vx), N(vy), N(p))
+    assert ev < 1e-7 and ep_ < 1e-7
+    # adjoint gradient of a surface misfit on a small random field
+    n = 32
+    base = wl.random_viscosity(n, ell=0.15, contrast=100.0)
+    g2 = st.Grid(n, n)
+    target = 0.01 * np.random.default_rng(9).standard_normal(n - 1)
+    gref = adj.gradient(g2, base.eta_b, base.eta_p, base.rho_b, 0.2, -1.0, target)
+    s2 = solver_for(base, precision=tph.FP64, rtol=1e-12, max_iters=3000, accel=accel, restart=m, beta=beta)
+    eb = T(base.eta_b).requires_grad_(True)
+    ep = T(base.eta_p).requires_grad_(True)
+    rho = T(base.rho_b).requires_grad_(True)
+    vx2, vy2, p2 = tph.StokesFunction.apply(eb, ep, rho, s2, 0.2, -1.0)
+    J = 0.5 * g2.dx * torch.sum((vx2[n, 1:n] - T(target)) ** 2)
+    J.backward()
+    a, b = N(ep.grad)[1:n + 1, 1:n + 1], gref["g_eta_p"][1:n + 1, 1:n + 1]
+    assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-6
