@@ -197,7 +197,7 @@ def main():
                             "restart": params["restart"], "beta": params["beta"] if name == "anderson" else None,
                             "tuning_trials": at_["trials"] if at_ else 0,
                             "kernel": {"name": "k_gcr_step" if name == "gcr" else "k_mix",
-                                       "what": ("GCR step update with restart/2 earlier pairs" if name == "gcr"
+                                       "what": ("GCR step update with restart/2 earlier directions" if name == "gcr"
                                                 else "Anderson mixing over restart + 1 stored pairs"),
                                        "us": round(kms * 1e3, 2), "bytes": kby, "GBps": round(kgbs, 1),
                                        "frac": round(kgbs / HBM_PEAK_GBS, 4)}}

@@ -319,8 +319,9 @@ enum {
     TPH_KERNEL_RESTRICT = 3, /* finest -> second level residual restriction */
     TPH_KERNEL_PROLONG = 4,  /* second -> finest level prolongation and correction */
     TPH_KERNEL_GCR_STEP = 5, /* flexible GCR step update (Alg. "Flexible GCR(m)"): project and
-                                normalise the new (w, z) pair against i = restart / 2 earlier
-                                pairs, update x and r (FP64, every entry of the vectors) */
+                                normalise the new direction w against i = restart / 2 earlier
+                                ones and update r (FP64, every entry of the vectors; x is
+                                updated once per cycle) */
     TPH_KERNEL_AA_MIX = 6    /* Anderson mixing x = sum_i alpha_i (x_i + beta f_i) over
                                 restart + 1 stored pairs (FP64, every entry of the vectors) */
 };

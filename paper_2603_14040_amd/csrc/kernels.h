@@ -145,7 +145,7 @@ hipError_t launch_update_x(double* x, const double* Z0, size_t zstride, int k, c
 struct GcrStepArgs {
     double* w;               // in: new direction A z (energy-scaled); out: w^ (normalised)
     const double* W0;        // earlier w^_0 .. w^_{i-1}, stride apart
-    double* z;               // in: preconditioned z; out: z' (same combination as w)
+    double* z;               // in: preconditioned z; out: z' (same combination as w); null: skip z, x
     const double* Z0;        // earlier z'_0 .. z'_{i-1}
     double* x;
     double* r;               // energy-scaled residual

@@ -145,8 +145,8 @@ __global__ __launch_bounds__(256) void k_update_x(double* __restrict__ x, const 
 
 // One step of flexible GCR after the Gram-Schmidt coefficients are known:
 //   w^ = (w - sum_j hw_j W_j) / nu   (orth_w = 0: w is already orthogonal)
-//   z' = (z - sum_j hz_j Z_j) / nu
-//   x += alpha z',  r -= alpha w^
+//   r -= alpha w^
+// and, when z is given, z' = (z - sum_j hz_j Z_j) / nu, x += alpha z'.
 // The coefficients travel in the kernel arguments (uniform scalar loads).
 __global__ __launch_bounds__(256) void k_gcr_step(const GcrStepArgs a) {
     for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < a.n; t += (size_t)gridDim.x * blockDim.x) {
@@ -155,15 +155,17 @@ __global__ __launch_bounds__(256) void k_gcr_step(const GcrStepArgs a) {
 #pragma unroll 4
             for (int j = 0; j < a.i; ++j) wv -= a.hw[j] * a.W0[j * a.stride + t];
         }
-        double zv = a.z[t];
-#pragma unroll 4
-        for (int j = 0; j < a.i; ++j) zv -= a.hz[j] * a.Z0[j * a.stride + t];
         wv *= a.inv_nu;
-        zv *= a.inv_nu;
         a.w[t] = wv;
-        a.z[t] = zv;
-        a.x[t] += a.alpha * zv;
         a.r[t] -= a.alpha * wv;
+        if (a.z) {
+            double zv = a.z[t];
+#pragma unroll 4
+            for (int j = 0; j < a.i; ++j) zv -= a.hz[j] * a.Z0[j * a.stride + t];
+            zv *= a.inv_nu;
+            a.z[t] = zv;
+            a.x[t] += a.alpha * zv;
+        }
     }
 }
 

@@ -885,8 +885,11 @@ tph_status fgmres(tph_solver* s, double* braw, tph_info* info) {
 // ------------------------------------------------------------------ GCR
 // Restarted flexible GCR(m) (Alg. "Flexible GCR(m)") in the energy inner
 // product: r and the directions w = A z are stored scaled by W^(1/2), as the
-// FGMRES basis.  V_0 holds r, V_{i+1} the normalised w_i, Z_i the matching
-// z_i.  The Gram-Schmidt projection against the earlier w's is one classical
+// FGMRES basis.  V_0 holds r, V_{i+1} the normalised w_i, Z_i the raw
+// preconditioned z_i.  The projected, normalised z'_i of the algorithm are
+// the combinations z' = Z C with C upper triangular (C e_i = (e_i - sum_j
+// h_j C e_j) / nu_i), so x += sum_i alpha_i z'_i is applied once per cycle as
+// x += Z (C alpha): the same iterate, without rewriting z and x every step.  The Gram-Schmidt projection against the earlier w's is one classical
 // pass whose coefficients come from one multi-dot, with the norm of the
 // projected vector from Pythagoras; when that cancels (|w_perp|^2 < |w|^2 / 2)
 // the projection is carried out explicitly and repeated once, as for the
@@ -918,6 +921,7 @@ tph_status gcr(tph_solver* s, double* braw, tph_info* info) {
     int stalled = 0;
     bool stagnated = false;
     GcrStepArgs a{};
+    std::vector<double> C((size_t)m * m), alph(m), ycoef(m);
     while (true) {
         TPH_TRY(energy_residual_vec(s, s->x, braw, Vk(0), kSlotMisc, true));
         TPH_TRY(wait_signal(s));
@@ -934,6 +938,7 @@ tph_status gcr(tph_solver* s, double* braw, tph_info* info) {
         best_true = std::min(best_true, true_res);
         ++restarts;
         double rho2 = beta * beta;
+        int done = 0;
         for (int i = 0; i < m; ++i) {
             double* w = Vk(i + 1);
             double* z = Zk(i);
@@ -978,11 +983,17 @@ tph_status gcr(tph_solver* s, double* braw, tph_info* info) {
             }
             if (!(nu2 > 0.0)) break;   // the new direction adds nothing: restart
             const double nu = std::sqrt(nu2);
+            // column i of C: (e_i - sum_j hz_j C e_j) / nu
+            for (int k = 0; k <= i; ++k) {
+                double t = k == i ? 1.0 : 0.0;
+                for (int j = k; j < i; ++j) t -= a.hz[j] * C[(size_t)j * m + k];
+                C[(size_t)i * m + k] = t / nu;
+            }
             a.w = w;
             a.W0 = Vk(1);
-            a.z = z;
-            a.Z0 = Zk(0);
-            a.x = s->x;
+            a.z = nullptr;             // z and x: once per cycle below
+            a.Z0 = nullptr;
+            a.x = nullptr;
             a.r = Vk(0);
             a.stride = n3;
             a.n = n3;
@@ -990,11 +1001,24 @@ tph_status gcr(tph_solver* s, double* braw, tph_info* info) {
             a.inv_nu = 1.0 / nu;
             a.alpha = c / nu;
             TPH_HIP(launch_gcr_step(a, s->st));
+            alph[i] = a.alpha;
+            done = i + 1;
             rho2 = std::max(rho2 - a.alpha * a.alpha, 0.0);
             est = std::sqrt(rho2) / bnorm;
             if (info && info->history && its < info->history_len) info->history[its] = est;
             ++its;
             if (est <= s->d.rtol || its >= s->d.max_iters) break;
+        }
+        // x += Z (C alpha) over the directions of this cycle
+        if (done > 0) {
+            for (int k = 0; k < done; ++k) {
+                double t = 0.0;
+                for (int i = k; i < done; ++i) t += C[(size_t)i * m + k] * alph[i];
+                ycoef[k] = t;
+            }
+            TPH_HIP(hipMemcpyAsync(s->dscal + kSlotY, ycoef.data(), done * sizeof(double), hipMemcpyHostToDevice,
+                                   s->st));
+            TPH_HIP(launch_update_x(s->x, s->Z, n3, done, s->dscal + kSlotY, n3, s->st));
         }
     }
     TPH_TRY(remove_pressure_mean(s, s->x));
@@ -1428,9 +1452,9 @@ tph_status time_kernel_t(tph_solver* s, int kind, int reps, double* ms, double* 
                 const int i = gcr_i;
                 a.w = s->V + (size_t)(i + 1) * s->n3;
                 a.W0 = s->V + s->n3;
-                a.z = s->Z + (size_t)i * s->n3;
-                a.Z0 = s->Z;
-                a.x = s->x;
+                a.z = nullptr;             // the step as the solve runs it: w and r
+                a.Z0 = nullptr;
+                a.x = nullptr;
                 a.r = s->V;
                 a.stride = s->n3;
                 a.n = s->n3;
@@ -1475,8 +1499,8 @@ tph_status time_kernel_t(tph_solver* s, int kind, int reps, double* ms, double* 
         case TPH_KERNEL_RESTRICT:                           // fused: read e, r, eta_b, eta_p, write 2 coarse (1/4)
             words = s->d.fused ? 6.5 : 2.5;                 // separate: read t (2), write 2 coarse
             break;
-        case TPH_KERNEL_GCR_STEP:                           // read 2i earlier vectors; w, z, x, r read + written
-            words = (2.0 * gcr_i + 8.0) * (double)s->n3 / cells;
+        case TPH_KERNEL_GCR_STEP:                           // read i earlier vectors; w, r read + written
+            words = (gcr_i + 4.0) * (double)s->n3 / cells;
             break;
         case TPH_KERNEL_AA_MIX:                             // read 2n vectors, write 1 (+ re-read/write per chunk)
             words = (2.0 * mix_n + 1.0 + 2.0 * ((mix_n + kVecSetMax - 1) / kVecSetMax - 1)) * (double)s->n3 / cells;

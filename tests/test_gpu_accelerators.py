@@ -175,7 +175,7 @@ def test_vector_kernel_timing(m):
     n3 = 3 * ((pr.ny + 2) * pitch + 64)
     ms, by = s.time_kernel(tph._lib.KERNEL_GCR_STEP, 20)
     i = min(m // 2, m - 1)
-    assert ms > 0 and by == pytest.approx((2 * i + 8) * n3 * 8, rel=1e-12)
+    assert ms > 0 and by == pytest.approx((i + 4) * n3 * 8, rel=1e-12)
     ms, by = s.time_kernel(tph._lib.KERNEL_AA_MIX, 20)
     nv = m + 1
     chunks = (nv + 7) // 8
