@@ -722,6 +722,26 @@ __device__ __forceinline__ void coarse_cycle_body(const CoarseArgs<T>& A) {
         c0 = tid & ((1 << ls) - 1);
         cstep = 1 << ls;
     };
+    // Small coarsest systems (at most 128 unknowns, RM rows per 16-lane
+    // group): each lane's entries of the inverse are loaded into registers
+    // first, so their memory latency hides behind the load phase below
+    // instead of stalling the coarsest solve.  Same products and sums in the
+    // same order as the loop over memory.
+    constexpr int KM = 8, RM = sizeof(T) == 4 ? 2 : 4;
+    const int sub = tid & 15, grp = tid >> 4, ngrp = nthr >> 4;
+    const bool minv_regs = A.nc <= 16 * KM && A.nc <= RM * ngrp;
+    double mv[RM][KM];
+    if (minv_regs) {
+#pragma unroll
+        for (int r = 0; r < RM; ++r) {
+            const int m = grp + r * ngrp;
+#pragma unroll
+            for (int k = 0; k < KM; ++k) {
+                const int q = sub + 16 * k;
+                mv[r][k] = (m < A.nc && q < A.nc) ? A.Minv[(size_t)m * A.nc + q] : 0.0;
+            }
+        }
+    }
     if (tid == 0) {
         int off = 0;
         for (int l = 0; l < nl; ++l) {
@@ -894,7 +914,6 @@ __device__ __forceinline__ void coarse_cycle_body(const CoarseArgs<T>& A) {
             else { const int mm = m - nvx; i = 1 + mm / G.nx; j = 1 + mm % G.nx; rs[m] = (double)ry[i * G.P + j]; }
         }
         __syncthreads();
-        const int sub = tid & 15, grp = tid >> 4, ngrp = nthr >> 4;
         auto put = [&](int m, double sv) {
             const T e = (T)(-sv);
             if (m < nvx) {
@@ -912,9 +931,23 @@ __device__ __forceinline__ void coarse_cycle_body(const CoarseArgs<T>& A) {
                 if (j == G.nx) ey[c + 1] = K[l].mirE * e;
             }
         };
-        // two rows per 16-lane group at a time, column loop unrolled: the loads
-        // of both rows are in flight together
-        for (int m0 = grp; m0 < n; m0 += 2 * ngrp) {
+        if (minv_regs) {
+#pragma unroll
+            for (int r = 0; r < RM; ++r) {
+                const int m = grp + r * ngrp;
+                double sv = 0.0;
+#pragma unroll
+                for (int k = 0; k < KM; ++k) {
+                    const int q = sub + 16 * k;
+                    if (q < n) sv += mv[r][k] * rs[q];
+                }
+                for (int o = 8; o > 0; o >>= 1) sv += __shfl_xor(sv, o, 16);
+                if (sub == 0 && m < n) put(m, sv);
+            }
+        }
+        // otherwise two rows per 16-lane group at a time, column loop unrolled:
+        // the loads of both rows are in flight together
+        for (int m0 = minv_regs ? n : grp; m0 < n; m0 += 2 * ngrp) {
             const int m1 = m0 + ngrp;
             const double* row0 = A.Minv + (size_t)m0 * n;
             const double* row1 = A.Minv + (size_t)(m1 < n ? m1 : m0) * n;
