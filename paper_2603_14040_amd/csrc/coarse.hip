@@ -82,35 +82,34 @@ __global__ void k_coarse_assemble(Geom g, const double* __restrict__ eb, const d
     }
 }
 
-// In-place Gauss-Jordan inverse of an SPD matrix (no pivoting needed), one
-// workgroup of 1024 threads; column k is staged in LDS before each step.
-__global__ __launch_bounds__(1024) void k_gauss_jordan(double* __restrict__ M, int n) {
-    extern __shared__ double colk[];
-    const int tid = threadIdx.x;
-    const int nthr = blockDim.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int nwave = nthr >> 6;
-    for (int k = 0; k < n; ++k) {
-        for (int i = tid; i < n; i += nthr) colk[i] = M[(size_t)i * n + k];
-        __syncthreads();
-        const double rd = 1.0 / colk[k];
-        for (int j = tid; j < n; j += nthr)
-            if (j != k) M[(size_t)k * n + j] *= rd;
-        __syncthreads();
-        for (int i = wave; i < n; i += nwave) {
-            if (i == k) continue;
-            const double f = colk[i];
-            double* ri = M + (size_t)i * n;
-            const double* rk = M + (size_t)k * n;
-            for (int j = lane; j < n; j += 64) {
-                if (j != k) ri[j] -= f * rk[j];
-                else ri[j] = -f * rd;
-            }
-        }
-        if (tid == 0) M[(size_t)k * n + k] = rd;
-        __syncthreads();
+// In-place Gauss-Jordan inverse of an SPD matrix (no pivoting needed) in
+// memory, one step k per pair of launches over the whole device: the pivot
+// launch copies row k (scaled by 1 / M[k][k]) and column k into separate
+// vectors, so the elimination launch can overwrite both while every row
+// reads the values of the previous step.
+__global__ __launch_bounds__(256) void k_gj_pivot(const double* __restrict__ M, int n, int k,
+                                                  double* __restrict__ prow, double* __restrict__ pcol) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const double rd = 1.0 / M[(size_t)k * n + k];
+    prow[t] = t == k ? rd : M[(size_t)k * n + t] * rd;
+    pcol[t] = M[(size_t)t * n + k];
+}
+
+__global__ __launch_bounds__(256) void k_gj_eliminate(double* __restrict__ M, int n, int k,
+                                                      const double* __restrict__ prow,
+                                                      const double* __restrict__ pcol) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (j >= n) return;
+    double* ri = M + (size_t)i * n;
+    if (i == k) {
+        ri[j] = prow[j];
+        return;
     }
+    const double f = pcol[i];
+    if (j != k) ri[j] -= f * prow[j];
+    else ri[j] = -f * prow[k];
 }
 
 // Gauss-Jordan inversion of an SPD matrix held entirely in LDS (n <= kGJLds):
@@ -222,12 +221,19 @@ hipError_t launch_gauss_jordan_batched(double* const* mats, const int* ns, int c
     return hipGetLastError();
 }
 
-hipError_t launch_gauss_jordan(double* M, int n, hipStream_t st, double** table) {
+hipError_t launch_gauss_jordan(double* M, int n, hipStream_t st, double** table, double* work) {
     if (n <= kGJLds && table) {
         // table: device scratch of one pointer and one int (owned by the caller)
         return launch_gauss_jordan_batched(table, (const int*)(table + 1), 1, n, st);
     }
-    hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), (size_t)n * sizeof(double), st, M, n);
+    if (!work) return hipErrorInvalidValue;
+    double* prow = work;
+    double* pcol = work + n;
+    const dim3 g1((n + 255) / 256), g2((n + 255) / 256, n);
+    for (int k = 0; k < n; ++k) {
+        hipLaunchKernelGGL(k_gj_pivot, g1, dim3(256), 0, st, M, n, k, prow, pcol);
+        hipLaunchKernelGGL(k_gj_eliminate, g2, dim3(256), 0, st, M, n, k, prow, pcol);
+    }
     return hipGetLastError();
 }
 

@@ -83,6 +83,7 @@ struct tph_solver {
     LevelBuf lev[kMaxLevels];
     double* Minv = nullptr;
     double** gj_table = nullptr; // device {Minv, ncoarse} for the LDS Gauss-Jordan (null: ncoarse too large)
+    double* gj_work = nullptr;   // pivot row and column of the device-wide Gauss-Jordan (larger ncoarse)
     double* cont_eb = nullptr;   // continuation: blended viscosities in the caller's dense layout (lazy)
     double* cont_ep = nullptr;
     int ncoarse = 0;
@@ -1382,6 +1383,8 @@ tph_status create_impl(const tph_desc* desc, void* stream, tph_solver* s) {
         TPH_TRY(dev_alloc(s, (void**)&s->gj_table, sizeof(tab)));
         TPH_HIP(hipMemcpyAsync(s->gj_table, &tab, sizeof(tab), hipMemcpyHostToDevice, s->st));
         TPH_HIP(hipStreamSynchronize(s->st));
+    } else {
+        TPH_TRY(dev_alloc(s, (void**)&s->gj_work, 2 * (size_t)s->ncoarse * sizeof(double)));
     }
     TPH_HIP(hipHostMalloc((void**)&s->hscal, kScalars * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent));
     TPH_HIP(hipHostGetDevicePointer((void**)&s->hscal_dev, s->hscal, 0));
@@ -1560,7 +1563,7 @@ tph_status setup_enqueue(tph_solver* s, const double* eta_b, const double* eta_p
     }
     const LevelBuf& C = s->lev[s->nlev - 1];
     TPH_HIP(launch_coarse_assemble(C.g, C.eb64, C.ep64, s->Minv, s->st));
-    if (factor) TPH_HIP(launch_gauss_jordan(s->Minv, s->ncoarse, s->st, s->gj_table));
+    if (factor) TPH_HIP(launch_gauss_jordan(s->Minv, s->ncoarse, s->st, s->gj_table, s->gj_work));
     TPH_HIP(hipEventRecord(s->ev1, s->st));
     return TPH_OK;
 }
