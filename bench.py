@@ -66,6 +66,8 @@ def main():
     ap.add_argument("--mic-steps", type=int, default=3,
                     help="timed marker-in-cell steps on the main grid (0: skip)")
     ap.add_argument("--markers-per-cell", type=int, default=16)
+    ap.add_argument("--robust-iters", type=int, default=1000,
+                    help="Uzawa iterations of the 1e8-contrast sinker robustness runs (0: skip)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -428,6 +430,52 @@ def main():
         sl.close()
         del sl
 
+    # robustness runs after the paper's sinker test (Ch. "Robustness" set-up): a centred inclusion of radius
+    # 0.2 with viscosity contrast 1e8 and density 33 in a host of density 32 (the 3300 / 3200 kg/m^3 of the
+    # test, scaled), free-slip walls (zero normal velocity on every wall), g = (0, -1), 512 x 608 cells on
+    # the unit square (the test's 501 x 601 nodes; factor-2 coarsening over 5 levels gives the coarsest
+    # 32 x 38 grid that 4 levels coarsened by 2.5 give there); unaccelerated Uzawa iterations (Anderson depth
+    # 0, beta 1), one V-cycle each, 5 + 5 sweeps growing by 2.5 per level, omega_v = 0.3, alpha = 0.6,
+    # continuation theta = 0, 0.25, ..., 1 switched every 25 iterations from the lithostatic pressure, then
+    # theta = 1 up to --robust-iters iterations or until the residual stops falling; the four smoother
+    # configurations of the test, FP64
+    robust = None
+    if args.robust_iters > 125:
+        ps_ = wl.sinker(512, ny=608, radius=0.2, eta_in=1e8, rho_in=33.0, eta_out=1.0, rho_out=32.0)
+        ebs_, eps_, rhos_ = to(ps_.eta_b), to(ps_.eta_p), to(ps_.rho_b)
+        robust = {"workload": ("sinker 512x608 cells, contrast 1e8, densities 33 / 32, free slip, unaccelerated "
+                               "Uzawa (one V-cycle per iteration, 5 levels, 5+5 sweeps x2.5 per level, omega 0.3, "
+                               "alpha 0.6), continuation theta 0..1 in steps of 0.25 every 25 iterations from the "
+                               "lithostatic pressure, FP64"), "smoothers": {}}
+        for name_, sm_ in (("rbgs", tph.SMOOTH_GS), ("jacobi", tph.SMOOTH_JACOBI), ("ras", tph.SMOOTH_RAS),
+                           ("mixed", tph.SMOOTH_RAS_MIXED)):
+            kw_ = dict(precision=tph.FP64, levels=5, smoother=sm_, nu_pre=5, nu_post=5, nu_growth=2.5, omega=0.3,
+                       alpha=0.6, accel="anderson", restart=0, beta=1.0, uzawa_steps=1, rtol=1e-14, ras_tile=32,
+                       ras_inner=4)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s1_ = tph.Solver(512, 608, device=dev, max_iters=25, **kw_)
+            vxs, vys, pps, i1_ = s1_.solve_continuation(ebs_, eps_, rhos_, ps_.gx, ps_.gy,
+                                                        thetas=(0.0, 0.25, 0.5, 0.75, 1.0), stage_rtol=1e-14,
+                                                        lithostatic=True, history=125)
+            s2_ = tph.Solver(512, 608, device=dev, max_iters=args.robust_iters - i1_.iters, **kw_)
+            s2_.set_coefficients(ebs_, eps_, rhos_, ps_.gx, ps_.gy)
+            vxs, vys, pps, i2_ = s2_.solve(vxs, vys, pps, history=args.robust_iters)
+            torch.cuda.synchronize()
+            rdt = time.perf_counter() - t0
+            h_ = list(i1_.history) + list(i2_.history)
+            first = {f"{t:.0e}": next((k + 1 for k, v in enumerate(h_) if k >= 100 and v <= t), None)
+                     for t in (1e-6, 1e-8, 1e-10)}
+            robust["smoothers"][name_] = {
+                "iters": i1_.iters + i2_.iters, "seconds": round(rdt, 3), "res_final": i2_.res_energy,
+                "res_at": {str(k): h_[k - 1] for k in (1, 25, 50, 75, 100, 125, 150, 200, 250) if k <= len(h_)},
+                "first_iter_below": first}
+            log(f"[bench] robustness {name_}: {i1_.iters + i2_.iters} iterations in {rdt:.2f} s, final residual "
+                f"{i2_.res_energy:.2e}, first below 1e-8 at {first['1e-08']}")
+            s1_.close()
+            s2_.close()
+        del ebs_, eps_, rhos_
+
     # marker-in-cell step (Sec. "The Marker-in-Cell Method"): markers carry viscosity and density; one step =
     # marker -> grid (eta_b, rho_b on basic nodes, eta_p on cells), the Stokes solve with the tuned schedule
     # (mixed), grid -> marker RK4 advection with dt = half a cell at the largest speed
@@ -539,6 +587,7 @@ def main():
         "accelerators": accels or None,
         "ras": ras_out,
         "marker_in_cell": mic,
+        "robustness": robust,
         "tuned": tuned,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
