@@ -148,7 +148,7 @@ __global__ __launch_bounds__(1024) void k_gauss_jordan_lds(double* const* __rest
 }
 
 template <typename T>
-__global__ __launch_bounds__(1024) void k_coarse_solve(Geom g, const double* __restrict__ Minv,
+__global__ __launch_bounds__(256) void k_coarse_solve(Geom g, const double* __restrict__ Minv,
                                                       const T* __restrict__ rx, const T* __restrict__ ry,
                                                       T* __restrict__ ex, T* __restrict__ ey, int n) {
     extern __shared__ double rs[];
@@ -163,7 +163,8 @@ __global__ __launch_bounds__(1024) void k_coarse_solve(Geom g, const double* __r
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int nwave = blockDim.x >> 6;
-    for (int m = wave; m < n; m += nwave) {
+    // one wave per row of the inverse; every workgroup holds the whole right-hand side
+    for (int m = blockIdx.x * nwave + wave; m < n; m += gridDim.x * nwave) {
         const double* row = Minv + (size_t)m * n;
         double s = 0.0;
         for (int q = lane; q < n; q += 64) s += row[q] * rs[q];
@@ -241,8 +242,9 @@ template <typename T>
 hipError_t launch_coarse_solve(const Geom& g, const double* Minv, const T* rx, const T* ry, T* ex, T* ey,
                                hipStream_t st) {
     const int n = coarse_unknowns(g);
-    hipLaunchKernelGGL(k_coarse_solve<T>, dim3(1), dim3(1024), (size_t)n * sizeof(double), st, g, Minv, rx, ry,
-                       ex, ey, n);
+    // 4 rows per workgroup: the n^2 inverse streams through the whole device
+    hipLaunchKernelGGL(k_coarse_solve<T>, dim3((n + 3) / 4), dim3(256), (size_t)n * sizeof(double), st, g, Minv, rx,
+                       ry, ex, ey, n);
     return hipGetLastError();
 }
 

@@ -88,18 +88,18 @@ int coarse_unknowns(const Geom& g);
 hipError_t launch_coarse_assemble(const Geom& g, const double* eb, const double* ep, double* M,
                                   hipStream_t st);
 // In-place inverse of the n x n SPD matrix M (row-major) by Gauss-Jordan
-// elimination in one workgroup; matrices with n <= kGJLds are inverted in
-// LDS, which needs `table`: device memory holding {M, (int)n} as written by
-// the caller (a pointer followed by an int).
+// elimination.  n <= kGJLds: one workgroup in LDS, which needs `table`:
+// device memory holding {M, (int)n} as written by the caller (a pointer
+// followed by an int).  Larger n: 2 n launches over the device with `work`
+// = 2 n doubles of device scratch.
 constexpr int kGJLds = 136;    // (136^2 + 136) doubles = 149 KB of LDS
-// n <= kGJLds with table: one workgroup in LDS; otherwise 2 n launches over
-// the device with work = 2 n doubles of device scratch
 hipError_t launch_gauss_jordan(double* M, int n, hipStream_t st, double** table, double* work);
 // one workgroup per matrix: mats[i] (device array of device pointers), sizes
 // ns[i] <= kGJLds, nmax = max ns[i]
 hipError_t launch_gauss_jordan_batched(double* const* mats, const int* ns, int count, int nmax, hipStream_t st);
 size_t gauss_jordan_lds_bytes(int n);
-// e = L^{-1} r = -M^{-1} r with M^{-1} stored; r, e level fields (ghosts of e written)
+// e = L^{-1} r = -M^{-1} r with M^{-1} stored; r, e level fields (ghosts of e
+// written); one wave per row, 4 rows per workgroup
 template <typename T>
 hipError_t launch_coarse_solve(const Geom& g, const double* Minv, const T* rx, const T* ry, T* ex, T* ey,
                                hipStream_t st);
