@@ -273,8 +273,12 @@ __device__ __forceinline__ void stage_rhs(const Geom& g, int gi0, int gj0, const
 // reads the ghost, so a later sweep (or the residual) in the same pass sees
 // the mirror of the latest value, as a sweep over the whole grid with
 // ghosts refilled between sweeps does.  A single sweep without residual
-// never re-reads a ghost, and the store writes the ghosts.
-template <typename T, int TW, int TH, int H, int NSTAGE, bool IN, bool GHOSTS>
+// never re-reads a ghost, and the store writes the ghosts.  With ZERO the
+// pass starts from a zero iterate, so in the first sweep the vx-red stage
+// reads only zeros (L e = 0) and the vx-black and vy-red stages read no
+// non-zero vy: their stencils skip those terms (fewer loads; the same values
+// up to rounding).
+template <typename T, int TW, int TH, int H, int NSTAGE, bool IN, bool GHOSTS, bool ZERO>
 __device__ __forceinline__ void gs_stages(const Geom& g, int gi0, int gj0, T* sx, T* sy, const T* sb, const T* sp,
                                           const T* rr, T omega, const LevelC<T>& k) {
     using S = Stages<TW, TH, H, NSTAGE>;
@@ -295,7 +299,10 @@ __device__ __forceinline__ void gs_stages(const Geom& g, int gi0, int gj0, T* sx
             if (comp == 0) {
                 if (!ux_at<IN>(g, gi, gj)) continue;
                 const T d = dx_at<IN>(sb, sp, c, RW, gi, g, k);
-                const T e = relax(sx[c], omega, r - lx_row(sx, sy, sb, sp, c, RW, k.idx, k.idy), d);
+                T e;
+                if (ZERO && s == 0) e = relax((T)0, omega, r, d);
+                else if (ZERO && s == 1) e = relax(sx[c], omega, r - lx_row_novy(sx, sb, sp, c, RW, k.idx, k.idy), d);
+                else e = relax(sx[c], omega, r - lx_row(sx, sy, sb, sp, c, RW, k.idx, k.idy), d);
                 sx[c] = e;
                 if (GHOSTS && !IN) {
                     if (gi == 1 && a >= 1) sx[c - RW] = k.mirS * e;
@@ -304,7 +311,8 @@ __device__ __forceinline__ void gs_stages(const Geom& g, int gi0, int gj0, T* sx
             } else {
                 if (!uy_at<IN>(g, gi, gj)) continue;
                 const T d = dy_at<IN>(sb, sp, c, RW, gj, g, k);
-                const T e = relax(sy[c], omega, r - ly_row(sx, sy, sb, sp, c, RW, k.idx, k.idy), d);
+                const T e = (ZERO && s == 2) ? relax((T)0, omega, r - ly_row_novy(sx, sb, c, RW, k.idx, k.idy), d)
+                                             : relax(sy[c], omega, r - ly_row(sx, sy, sb, sp, c, RW, k.idx, k.idy), d);
                 sy[c] = e;
                 if (GHOSTS && !IN) {
                     if (gj == 1 && b >= 1) sy[c - 1] = k.mirW * e;
@@ -421,7 +429,8 @@ __device__ __forceinline__ void gs_tile_run(const Geom& g, const Geom& gc, const
         }
     }
     tile_load<T, RW, RH, MODE, IN>(g, gc, gi0, gj0, exi, eyi, eb, ep, ecx, ecy, sx, sy, sb, sp, scx, scy, k);
-    gs_stages<T, TW, TH, H, 4 * NS, IN, (NS > 1 || RR)>(g, gi0, gj0, sx, sy, sb, sp, rr, omega, k);
+    gs_stages<T, TW, TH, H, 4 * NS, IN, (NS > 1 || RR), MODE == kModeZero>(g, gi0, gj0, sx, sy, sb, sp, rr, omega,
+                                                                          k);
     tile_store<T, TW, TH, H, IN>(g, gi0, gj0, sx, sy, exo, eyo, k);
     if (RR) {
 #pragma unroll

@@ -46,6 +46,19 @@ __device__ __forceinline__ T lx_row(const T* __restrict__ vx, const T* __restric
     return (sxx_r - sxx_l) * idx + (sxy_t - sxy_b) * idy;
 }
 
+// lx_row where every vy the stencil reads is zero (the vy differences drop
+// out; equal to lx_row up to how the fused multiply-adds round)
+template <typename T>
+__device__ __forceinline__ T lx_row_novy(const T* __restrict__ vx, const T* __restrict__ eb,
+                                         const T* __restrict__ ep, int c, int P, T idx, T idy) {
+    const T v = vx[c];
+    const T sxx_r = (T)2 * ep[c + 1] * ((vx[c + 1] - v) * idx);
+    const T sxx_l = (T)2 * ep[c] * ((v - vx[c - 1]) * idx);
+    const T sxy_t = eb[c] * ((vx[c + P] - v) * idy);
+    const T sxy_b = eb[c - P] * ((v - vx[c - P]) * idy);
+    return (sxx_r - sxx_l) * idx + (sxy_t - sxy_b) * idy;
+}
+
 // (L v)_y at vy(i, j): d(syx)/dx + d(syy)/dy.
 template <typename T>
 __device__ __forceinline__ T ly_row(const T* __restrict__ vx, const T* __restrict__ vy,
@@ -57,6 +70,16 @@ __device__ __forceinline__ T ly_row(const T* __restrict__ vx, const T* __restric
     const T syx_r = eb[c] * ((vx[c + P] - vx[c]) * idy + (vy[c + 1] - v) * idx);
     const T syx_l = eb[c - 1] * ((vx[c + P - 1] - vx[c - 1]) * idy + (v - vy[c - 1]) * idx);
     return (syy_t - syy_b) * idy + (syx_r - syx_l) * idx;
+}
+
+// ly_row where every vy the stencil reads is zero (syy vanishes, syx keeps its
+// vx differences)
+template <typename T>
+__device__ __forceinline__ T ly_row_novy(const T* __restrict__ vx, const T* __restrict__ eb, int c, int P, T idx,
+                                         T idy) {
+    const T syx_r = eb[c] * ((vx[c + P] - vx[c]) * idy);
+    const T syx_l = eb[c - 1] * ((vx[c + P - 1] - vx[c - 1]) * idy);
+    return (syx_r - syx_l) * idx;
 }
 
 // diag(L) at vx(i, j) and vy(i, j).  At a wall-adjacent node the shear term
