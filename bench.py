@@ -72,8 +72,9 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs (--gpus > 1) are not "
-                                   "supported (see DESIGN.md for how the solve would shard)"}))
+        print(json.dumps({"error": "the solver runs on one GPU; multi-GPU runs (--gpus > 1) are not supported "
+                                   "(a sharded solve would split the grid into row bands, one per GPU, with "
+                                   "halo exchanges per sweep and all-reduces for the Krylov dot products)"}))
         sys.exit(2)
 
     import numpy as np
