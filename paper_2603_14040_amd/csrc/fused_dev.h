@@ -638,13 +638,10 @@ __device__ __forceinline__ int lanes_log2(int width) {
     return s;
 }
 
-// one Gauss-Seidel colour half-sweep of component comp, in place.  zs = 0,
-// 1, 2: this is that half-sweep of a sweep from a zero iterate, whose
-// stencil then skips the terms that are still zero (as in gs_stages); -1:
-// the general update.
+// one Gauss-Seidel colour half-sweep of component comp, in place
 template <typename T>
 __device__ void cc_gs_half(const LGeo<T>& L, const LevelC<T>& k, int comp, int col, T* ex, T* ey, const T* rx,
-                           const T* ry, const T* eb, const T* ep, T omega, int zs) {
+                           const T* ry, const T* eb, const T* ep, T omega) {
     const int ncol = comp == 0 ? L.nx - 1 : L.nx;
     const int nrow = comp == 0 ? L.ny : L.ny - 1;
     const int tid = threadIdx.x;
@@ -657,17 +654,13 @@ __device__ void cc_gs_half(const LGeo<T>& L, const LevelC<T>& k, int comp, int c
             const int c = i * L.P + j;
             if (comp == 0) {
                 const T d = lx_diag(eb, ep, c, L.P, i, L.ny, k);
-                T e;
-                if (zs == 0) e = relax((T)0, omega, rx[c], d);
-                else if (zs == 1) e = relax(ex[c], omega, rx[c] - lx_row_novy(ex, eb, ep, c, L.P, k.idx, k.idy), d);
-                else e = relax(ex[c], omega, rx[c] - lx_row(ex, ey, eb, ep, c, L.P, k.idx, k.idy), d);
+                const T e = relax(ex[c], omega, rx[c] - lx_row(ex, ey, eb, ep, c, L.P, k.idx, k.idy), d);
                 ex[c] = e;
                 if (i == 1) ex[c - L.P] = k.mirS * e;
                 if (i == L.ny) ex[c + L.P] = k.mirN * e;
             } else {
                 const T d = ly_diag(eb, ep, c, L.P, j, L.nx, k);
-                const T e = zs == 2 ? relax((T)0, omega, ry[c] - ly_row_novy(ex, eb, c, L.P, k.idx, k.idy), d)
-                                    : relax(ey[c], omega, ry[c] - ly_row(ex, ey, eb, ep, c, L.P, k.idx, k.idy), d);
+                const T e = relax(ey[c], omega, ry[c] - ly_row(ex, ey, eb, ep, c, L.P, k.idx, k.idy), d);
                 ey[c] = e;
                 if (j == 1) ey[c - 1] = k.mirW * e;
                 if (j == L.nx) ey[c + 1] = k.mirE * e;
@@ -849,14 +842,12 @@ __device__ __forceinline__ void coarse_cycle_body(const CoarseArgs<T>& A) {
     }
     __syncthreads();
 
-    // zero_start: the level's correction is still zero (the down leg)
-    auto smooth = [&](int l, int nu, bool zero_start) {
+    auto smooth = [&](int l, int nu) {
         T *ex = F(l, 0), *ey = F(l, 1), *rx = F(l, 2), *ry = F(l, 3), *eb = F(l, 4), *ep = F(l, 5);
         for (int s = 0; s < nu; ++s) {
             if (A.smoother == kSmGS) {
                 for (int h = 0; h < 4; ++h) {
-                    cc_gs_half(L[l], K[l], h >> 1, h & 1, ex, ey, rx, ry, eb, ep, A.omega,
-                               zero_start && s == 0 && h < 3 ? h : -1);
+                    cc_gs_half(L[l], K[l], h >> 1, h & 1, ex, ey, rx, ry, eb, ep, A.omega);
                     __syncthreads();
                 }
             } else {
@@ -867,7 +858,7 @@ __device__ __forceinline__ void coarse_cycle_body(const CoarseArgs<T>& A) {
 
     // ---- down: smooth, residual, restrict
     for (int l = 0; l < nl - 1; ++l) {
-        smooth(l, A.nu_pre[l], true);
+        smooth(l, A.nu_pre[l]);
         const LGeo<T>& G = L[l];
         T *ex = F(l, 0), *ey = F(l, 1), *rx = F(l, 2), *ry = F(l, 3), *eb = F(l, 4), *ep = F(l, 5);
         int rt, rs_, ct, cs_;
@@ -1014,7 +1005,7 @@ __device__ __forceinline__ void coarse_cycle_body(const CoarseArgs<T>& A) {
             }
         }
         __syncthreads();
-        smooth(l, A.nu_post[l], false);
+        smooth(l, A.nu_post[l]);
     }
 
     // ---- write the top-level correction (every entry: walls zero, ghosts mirrored)
