@@ -112,39 +112,52 @@ __global__ __launch_bounds__(256) void k_gj_eliminate(double* __restrict__ M, in
     else ri[j] = -f * prow[k];
 }
 
-// Gauss-Jordan inversion of an SPD matrix held entirely in LDS (n <= kGJLds):
-// the same elimination as k_gauss_jordan without the round trips to memory.
-// Blocks of a batched launch each invert their own matrix (mats[blockIdx.x],
-// sizes ns[blockIdx.x]).
-__device__ __forceinline__ void gauss_jordan_lds(double* __restrict__ Mg, int n, double* A, double* colk) {
-    const int tid = threadIdx.x, nthr = blockDim.x;
-    for (int q = tid; q < n * n; q += nthr) A[q] = Mg[q];
-    __syncthreads();
-    for (int k = 0; k < n; ++k) {
-        for (int i = tid; i < n; i += nthr) colk[i] = A[i * n + k];
-        __syncthreads();
-        const double rd = 1.0 / colk[k];
-        for (int j = tid; j < n; j += nthr)
-            if (j != k) A[k * n + j] *= rd;
-        __syncthreads();
-        for (int q = tid; q < n * n; q += nthr) {
-            const int i = q / n, j = q - (q / n) * n;
-            if (i == k) continue;
-            if (j != k) A[q] -= colk[i] * A[k * n + j];
-            else A[q] = -colk[i] * rd;
-        }
-        __syncthreads();
-        if (tid == 0) A[k * n + k] = rd;
-        __syncthreads();
-    }
-    for (int q = tid; q < n * n; q += nthr) Mg[q] = A[q];
-}
+// Gauss-Jordan inversion of a small SPD matrix (n <= kGJLds) held in LDS by
+// one workgroup of kGJThreads threads (>= 2 n); thread t owns entries t, t +
+// kGJThreads, ..., whose rows and columns it steps through without integer
+// division.  Each step k copies the old row k and column k aside, then every
+// thread updates its own entries (the same operations as the device-wide
+// form: row k scaled by 1 / M[k][k], the others reduced by the scaled row),
+// two barriers per step.  Blocks of a batched launch each invert their own
+// matrix (mats[blockIdx.x], sizes ns[blockIdx.x]).
+constexpr int kGJThreads = 1024;
+static_assert(kGJThreads >= 2 * kGJLds, "row and column copies take one thread per entry");
 
-__global__ __launch_bounds__(1024) void k_gauss_jordan_lds(double* const* __restrict__ mats,
-                                                          const int* __restrict__ ns) {
+__global__ __launch_bounds__(kGJThreads) void k_gauss_jordan_lds(double* const* __restrict__ mats,
+                                                                const int* __restrict__ ns) {
     extern __shared__ double lds[];
     const int n = ns[blockIdx.x];
-    gauss_jordan_lds(mats[blockIdx.x], n, lds, lds + (size_t)n * n);
+    double* __restrict__ Mg = mats[blockIdx.x];
+    double* A = lds;
+    double* prow = lds + (size_t)n * n;
+    double* pcol = prow + n;
+    const int tid = threadIdx.x, nn = n * n;
+    // (row, column) of entry tid and the step between owned entries
+    const int i0 = tid / n, j0 = tid - (tid / n) * n;
+    const int di = kGJThreads / n, dj = kGJThreads - (kGJThreads / n) * n;
+    for (int e = tid; e < nn; e += kGJThreads) A[e] = Mg[e];
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        if (tid < n) prow[tid] = A[k * n + tid];
+        else if (tid < 2 * n) pcol[tid - n] = A[(tid - n) * n + k];
+        __syncthreads();
+        const double rd = 1.0 / pcol[k];
+#pragma unroll 4
+        for (int e = tid, i = i0, j = j0; e < nn; e += kGJThreads) {
+            if (i == k) {
+                A[e] = j == k ? rd : A[e] * rd;
+            } else {
+                const double f = pcol[i];
+                if (j == k) A[e] = -f * rd;
+                else A[e] -= f * (prow[j] * rd);
+            }
+            i += di;
+            j += dj;
+            if (j >= n) { j -= n; ++i; }
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < nn; e += kGJThreads) Mg[e] = A[e];
 }
 
 template <typename T>
@@ -196,7 +209,7 @@ hipError_t launch_coarse_assemble(const Geom& g, const double* eb, const double*
     return hipGetLastError();
 }
 
-size_t gauss_jordan_lds_bytes(int n) { return ((size_t)n * n + n) * sizeof(double); }
+size_t gauss_jordan_lds_bytes(int n) { return ((size_t)n * n + 2 * (size_t)n) * sizeof(double); }
 
 hipError_t launch_gauss_jordan_batched(double* const* mats, const int* ns, int count, int nmax, hipStream_t st) {
     const size_t lds = gauss_jordan_lds_bytes(nmax);
@@ -218,7 +231,7 @@ hipError_t launch_gauss_jordan_batched(double* const* mats, const int* ns, int c
         }
         granted = lds;
     }
-    hipLaunchKernelGGL(k_gauss_jordan_lds, dim3(count), dim3(1024), lds, st, mats, ns);
+    hipLaunchKernelGGL(k_gauss_jordan_lds, dim3(count), dim3(kGJThreads), lds, st, mats, ns);
     return hipGetLastError();
 }
 
