@@ -112,52 +112,58 @@ __global__ __launch_bounds__(256) void k_gj_eliminate(double* __restrict__ M, in
     else ri[j] = -f * prow[k];
 }
 
-// Gauss-Jordan inversion of a small SPD matrix (n <= kGJLds) held in LDS by
-// one workgroup of kGJThreads threads (>= 2 n); thread t owns entries t, t +
-// kGJThreads, ..., whose rows and columns it steps through without integer
-// division.  Each step k copies the old row k and column k aside, then every
-// thread updates its own entries (the same operations as the device-wide
-// form: row k scaled by 1 / M[k][k], the others reduced by the scaled row),
-// two barriers per step.  Blocks of a batched launch each invert their own
-// matrix (mats[blockIdx.x], sizes ns[blockIdx.x]).
+// Gauss-Jordan inversion of a small SPD matrix (n <= kGJLds) by one
+// workgroup of kGJThreads threads, the matrix held in registers: R =
+// kGJThreads / n threads share a row, each owning a run of at most kGJRun
+// consecutive entries.  Each step k copies the old row k and column k to
+// LDS, then every thread updates its own entries (the same operations as
+// the device-wide form: row k scaled by 1 / M[k][k], the others reduced by
+// the scaled row), two barriers per step.  Blocks of a batched launch each
+// invert their own matrix (mats[blockIdx.x], sizes ns[blockIdx.x]).
 constexpr int kGJThreads = 1024;
-static_assert(kGJThreads >= 2 * kGJLds, "row and column copies take one thread per entry");
+constexpr int kGJRun = 20;   // max over n <= 136 of ceil(n / floor(1024 / n))
+static_assert(kGJThreads >= kGJLds, "one row per thread at least");
 
 __global__ __launch_bounds__(kGJThreads) void k_gauss_jordan_lds(double* const* __restrict__ mats,
                                                                 const int* __restrict__ ns) {
     extern __shared__ double lds[];
     const int n = ns[blockIdx.x];
     double* __restrict__ Mg = mats[blockIdx.x];
-    double* A = lds;
-    double* prow = lds + (size_t)n * n;
-    double* pcol = prow + n;
-    const int tid = threadIdx.x, nn = n * n;
-    // (row, column) of entry tid and the step between owned entries
-    const int i0 = tid / n, j0 = tid - (tid / n) * n;
-    const int di = kGJThreads / n, dj = kGJThreads - (kGJThreads / n) * n;
-    for (int e = tid; e < nn; e += kGJThreads) A[e] = Mg[e];
-    __syncthreads();
+    double* prow = lds;
+    double* pcol = lds + n;
+    const int tid = threadIdx.x;
+    const int R = kGJThreads / n;                   // threads per row
+    const int ch = (n + R - 1) / R;                 // run length
+    const int i = tid / R, p = tid - (tid / R) * R;
+    const int j0 = p * ch;
+    const int cnt = i < n ? (j0 + ch <= n ? ch : (j0 < n ? n - j0 : 0)) : 0;
+    double a[kGJRun];
+#pragma unroll
+    for (int c = 0; c < kGJRun; ++c) a[c] = c < cnt ? Mg[(size_t)i * n + j0 + c] : 0.0;
     for (int k = 0; k < n; ++k) {
-        if (tid < n) prow[tid] = A[k * n + tid];
-        else if (tid < 2 * n) pcol[tid - n] = A[(tid - n) * n + k];
+#pragma unroll
+        for (int c = 0; c < kGJRun; ++c) {
+            if (c < cnt) {
+                if (i == k) prow[j0 + c] = a[c];
+                if (j0 + c == k) pcol[i] = a[c];
+            }
+        }
         __syncthreads();
         const double rd = 1.0 / pcol[k];
-#pragma unroll 4
-        for (int e = tid, i = i0, j = j0; e < nn; e += kGJThreads) {
-            if (i == k) {
-                A[e] = j == k ? rd : A[e] * rd;
-            } else {
-                const double f = pcol[i];
-                if (j == k) A[e] = -f * rd;
-                else A[e] -= f * (prow[j] * rd);
+        const double f = cnt > 0 ? pcol[i] : 0.0;
+#pragma unroll
+        for (int c = 0; c < kGJRun; ++c) {
+            if (c < cnt) {
+                const int j = j0 + c;
+                if (i == k) a[c] = j == k ? rd : a[c] * rd;
+                else a[c] = j == k ? -f * rd : a[c] - f * (prow[j] * rd);
             }
-            i += di;
-            j += dj;
-            if (j >= n) { j -= n; ++i; }
         }
         __syncthreads();
     }
-    for (int e = tid; e < nn; e += kGJThreads) Mg[e] = A[e];
+#pragma unroll
+    for (int c = 0; c < kGJRun; ++c)
+        if (c < cnt) Mg[(size_t)i * n + j0 + c] = a[c];
 }
 
 template <typename T>
@@ -209,7 +215,7 @@ hipError_t launch_coarse_assemble(const Geom& g, const double* eb, const double*
     return hipGetLastError();
 }
 
-size_t gauss_jordan_lds_bytes(int n) { return ((size_t)n * n + 2 * (size_t)n) * sizeof(double); }
+size_t gauss_jordan_lds_bytes(int n) { return 2 * (size_t)n * sizeof(double); }
 
 hipError_t launch_gauss_jordan_batched(double* const* mats, const int* ns, int count, int nmax, hipStream_t st) {
     const size_t lds = gauss_jordan_lds_bytes(nmax);

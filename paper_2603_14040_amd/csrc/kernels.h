@@ -92,7 +92,7 @@ hipError_t launch_coarse_assemble(const Geom& g, const double* eb, const double*
 // device memory holding {M, (int)n} as written by the caller (a pointer
 // followed by an int).  Larger n: 2 n launches over the device with `work`
 // = 2 n doubles of device scratch.
-constexpr int kGJLds = 136;    // (136^2 + 2 136) doubles = 150 KB of LDS
+constexpr int kGJLds = 136;    // largest n inverted by one workgroup (registers, 2 n doubles of LDS)
 hipError_t launch_gauss_jordan(double* M, int n, hipStream_t st, double** table, double* work);
 // one workgroup per matrix: mats[i] (device array of device pointers), sizes
 // ns[i] <= kGJLds, nmax = max ns[i]
