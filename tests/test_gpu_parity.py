@@ -140,6 +140,32 @@ def test_preconditioner_matches_oracle_vcycle(case, prec, fused):
     assert np.array_equal(gy_[1:ny, nx + 1], (1 if bc[1] == 0 else -1) * gy_[1:ny, nx])
 
 
+@pytest.mark.parametrize("prec", [tph.FP64, tph.MIXED])
+def test_large_coarsest_system_matches_oracle_vcycle(prec):
+    """A hierarchy whose coarsest level (32 x 38 cells, 2362 unknowns) is too
+    large for the one-workgroup inverse and for the coarse tail: the
+    device-wide Gauss-Jordan and the row-parallel dense solve give the
+    oracle's V-cycle (exact coarsest solve)."""
+    nx, ny, levels = 512, 608, 5
+    eb, ep, rho = wl.random_fields(nx, ny, seed=71, eta_decades=2)
+    rx, ry, rp = wl.random_state(nx, ny, seed=72)
+    s = solver_for(nx, ny, bc=(1, 0, 0, 1), precision=prec, levels=levels, nu_pre=1, nu_post=1, omega=1.0,
+                   alpha=1.0, uzawa_steps=1)
+    s.set_coefficients(T(eb), T(ep), T(rho))
+    zx, zy, zp = (N(t) for t in s.precondition(T(rx), T(ry), T(rp)))
+    prm = mg.MGParams(levels=levels, nu_pre=[1] * levels, nu_post=[1] * levels, omega=1.0, smoother="gs",
+                      alpha=1.0)
+    g = st.Grid(nx, ny, 1.0, 1.0, (1, 0, 0, 1))
+    ox, oy, op = mg.precondition(mg.build_hierarchy(g, eb, ep, prm), prm, rx, ry, rp)
+    v_ref = np.concatenate([ox[1:ny + 1, 1:nx].ravel(), oy[1:ny, 1:nx + 1].ravel()])
+    v_got = np.concatenate([zx[1:ny + 1, 1:nx].ravel(), zy[1:ny, 1:nx + 1].ravel()])
+    ev = np.linalg.norm(v_got - v_ref) / np.linalg.norm(v_ref)
+    epr = np.linalg.norm(zp[1:ny + 1, 1:nx + 1] - op[1:ny + 1, 1:nx + 1]) / np.linalg.norm(op[1:ny + 1, 1:nx + 1])
+    print(f"[large coarsest] prec={prec} rel err v {ev:.2e} p {epr:.2e}", flush=True)
+    tol = 1e-11 if prec == tph.FP64 else 5e-5
+    assert ev < tol and epr < tol
+
+
 # level plans of the fused V-cycle: (msweep mask, tile_shape mask, coarse_level);
 # -1 = library default, coarse_level -2 = no single-workgroup coarse tail
 PLANS = [(0, 0, -1), (-1, -1, -1), (0xFFFF, 0, -2), (0xFFFF, 0xFFFF, -1), (0, 0xFFFF, -2)]
