@@ -1,0 +1,26 @@
+"""Host-side contract of bench.py that needs no GPU: more than one GPU is
+refused with one JSON line and exit status 2, and the options that skip the
+side workloads exist (the profiling commands in profiles/ use them)."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_multi_gpu_is_refused_with_a_json_line():
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                         text=True, cwd=ROOT, timeout=120)
+    assert res.returncode == 2
+    line = res.stdout.strip().splitlines()[-1]
+    assert "one GPU" in json.loads(line)["error"]
+
+
+def test_side_workload_switches_exist():
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"], capture_output=True, text=True,
+                         cwd=ROOT, timeout=120)
+    assert res.returncode == 0
+    for opt in ("--steps", "--warmup", "--fp64-steps", "--batch", "--large", "--accel-steps", "--ras-steps",
+                "--mic-steps", "--robust-iters", "--no-cpu-baseline", "--tuning-db", "--reuse-tuning"):
+        assert opt in res.stdout, opt
