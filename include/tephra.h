@@ -180,6 +180,14 @@ typedef struct tph_info {
     double t_solve_ms;     /* this solve, host wall time                      */
     double* history;       /* optional caller-owned HOST buffer: estimate per iteration */
     int32_t history_len;   /* its capacity (entries)                          */
+    int32_t vcycles;       /* V-cycles run by this solve: uzawa_steps per
+                              preconditioner application, counting every
+                              application (also one whose result the accelerator
+                              did not keep)                                   */
+    double res_l2;         /* plain relative residual ||b - A x||_2 / ||b||_2
+                              over every equation row, no energy weights
+                              (Sec. "Residual Norms" reports it beside the
+                              energy residual)                                */
 } tph_info;
 
 typedef struct tph_solver tph_solver;
@@ -194,10 +202,31 @@ typedef struct tph_solver tph_solver;
 void tph_desc_default(tph_desc* d, int32_t nx, int32_t ny);
 
 /* Create a solver for the grid in *desc; hip_stream is a hipStream_t (NULL:
- * the null stream).  Allocates all device workspace (levels, Krylov basis).
- * Errors: TPH_ERR_INVALID (sizes, levels, parameters), TPH_ERR_OOM,
- * TPH_ERR_HIP.  *out is NULL on failure. */
+ * the null stream).  Allocates all device workspace (levels, Krylov basis)
+ * through the process-wide allocator (tph_set_allocator).  Errors:
+ * TPH_ERR_INVALID (sizes, levels, parameters), TPH_ERR_OOM (an allocation
+ * failed; everything allocated before it has been freed again), TPH_ERR_HIP.
+ * *out is NULL on failure. */
 tph_status tph_create(const tph_desc* desc, void* hip_stream, tph_solver** out);
+
+/* Device memory of the library's workspace (the shared simulation state of
+ * Ch. 5 "Simulation State": the caller's memory manager, e.g. a framework's
+ * caching allocator, can own it).  alloc(bytes, ctx) returns `bytes` of
+ * device memory on the device current at the call, 256-byte aligned, or NULL
+ * when it cannot (the library then returns TPH_ERR_OOM after freeing what it
+ * had obtained); free(ptr, ctx) releases a block alloc returned.  Both NULL:
+ * hipMalloc / hipFree (the initial state).  Exactly one NULL: TPH_ERR_INVALID.
+ *   s == NULL: the process-wide default, read by every later tph_create,
+ *              tph_batch_create and tph_markers_create (thread-safe).
+ *   s != NULL: that solver's allocator for blocks it allocates from now on
+ *              (workspace made on demand, e.g. by tph_solve_continuation);
+ *              blocks it already holds stay where they are.
+ * Every block is freed with the free function of the allocator that made it,
+ * after the handle's stream has drained (tph_destroy and the other destroy
+ * calls).  Pinned host memory (for scalars the host reads) is not device
+ * workspace and is always taken from hipHostMalloc.  Returns TPH_OK. */
+tph_status tph_set_allocator(tph_solver* s, void* (*alloc)(size_t bytes, void* ctx),
+                             void (*free)(void* ptr, void* ctx), void* ctx);
 
 /* Coefficient setup (hot-path step "coefficient setup"): copies eta_b,
  * eta_p (basic nodes, cell centres) and builds f = -rho_b g averaged to the

@@ -7,7 +7,10 @@ the staggered-grid convention documented in the header.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
+import os
+import weakref
 from dataclasses import dataclass, field
 from typing import Optional, Sequence, Tuple
 
@@ -21,12 +24,72 @@ from ._lib import (ACCEL_ANDERSON, ACCEL_FGMRES, ACCEL_GCR, FP64, FREE_SLIP, MEA
 __all__ = ["Solver", "Batch", "SolveInfo", "StokesFunction", "solve", "FP64", "MIXED", "FREE_SLIP",
            "NO_SLIP", "SMOOTH_GS", "SMOOTH_JACOBI", "SMOOTH_RAS", "SMOOTH_RAS_MIXED", "MEAN_ARITHMETIC",
            "MEAN_GEOMETRIC",
-           "ACCEL_FGMRES", "ACCEL_GCR", "ACCEL_ANDERSON", "Markers", "TephraError", "library"]
+           "ACCEL_FGMRES", "ACCEL_GCR", "ACCEL_ANDERSON", "Markers", "TephraError", "library", "set_allocator"]
 
 
 def library():
     """The loaded libtephra.so (raises if it has not been built)."""
     return _lib.load()
+
+
+# ---------------------------------------------------------------- allocator
+# The library's device workspace is taken from torch's caching allocator
+# (tph_set_allocator with the process-wide default), so that torch accounts
+# for it and reuses its blocks; TEPHRA_ALLOCATOR=hip keeps hipMalloc.
+def _torch_alloc(nbytes, ctx):
+    try:
+        dev = torch.cuda.current_device()
+        return torch.cuda.caching_allocator_alloc(int(nbytes), device=dev, stream=torch.cuda.current_stream(dev))
+    except Exception:
+        return None                      # NULL: the library reports TPH_ERR_OOM
+
+
+def _torch_free(ptr, ctx):
+    try:
+        torch.cuda.caching_allocator_delete(ptr)
+    except Exception:
+        pass
+
+
+_ALLOC_CB = _lib.ALLOC_FN(_torch_alloc)
+_FREE_CB = _lib.FREE_FN(_torch_free)
+_allocator = None
+_live = weakref.WeakSet()                # handles closed before the interpreter tears torch down
+
+
+def set_allocator(kind: str = "torch", alloc=None, free=None):
+    """Process-wide device allocator of handles created from now on.
+
+    kind "torch": torch's caching allocator; "hip": hipMalloc / hipFree;
+    "custom": the ctypes callbacks ``alloc`` (_lib.ALLOC_FN) and ``free``
+    (_lib.FREE_FN), which the caller keeps alive.
+    """
+    global _allocator
+    lib = _lib.load()
+    if kind == "torch":
+        a, f = _ALLOC_CB, _FREE_CB
+    elif kind == "hip":
+        a, f = _lib.ALLOC_FN(), _lib.FREE_FN()
+    elif kind == "custom":
+        a, f = alloc, free
+    else:
+        raise ValueError("kind must be 'torch', 'hip' or 'custom'")
+    _lib.check("tph_set_allocator", lib.tph_set_allocator(None, a, f, None))
+    _allocator = kind
+
+
+def _ensure_allocator():
+    if _allocator is None:
+        set_allocator("hip" if os.environ.get("TEPHRA_ALLOCATOR", "torch") == "hip" else "torch")
+
+
+@atexit.register
+def _close_live_handles():
+    for h in list(_live):
+        try:
+            h.close()
+        except Exception:
+            pass
 
 
 @dataclass
@@ -39,6 +102,8 @@ class SolveInfo:
     t_setup_ms: float
     t_solve_ms: float
     history: list = field(default_factory=list)
+    vcycles: int = 0
+    res_l2: float = float("nan")
 
 
 def _ptr(t: Optional[torch.Tensor], shape, name: str):
@@ -67,6 +132,7 @@ class Solver:
                  device: Optional[torch.device] = None,
                  stream: Optional[torch.cuda.Stream] = None):
         lib = _lib.load()
+        _ensure_allocator()
         d = _desc(lib, nx, ny, lx=lx, ly=ly, bc=bc, precision=precision, levels=levels, smoother=smoother,
                   nu_pre=nu_pre, nu_post=nu_post, nu_growth=nu_growth, omega=omega, alpha=alpha,
                   eta_mean=eta_mean, rtol=rtol, restart=restart, max_iters=max_iters, uzawa_steps=uzawa_steps,
@@ -83,6 +149,8 @@ class Solver:
                                                     ctypes.byref(h)))
         self._h = h
         self._lib = lib
+        self.generation = 0           # bumped whenever the solver's coefficients change
+        _live.add(self)
 
     # -- lifetime -----------------------------------------------------------
     def close(self):
@@ -118,7 +186,7 @@ class Solver:
         n = min(info.iters, len(hist))
         return SolveInfo(_lib.STATUS_NAMES.get(status, str(status)), info.iters, info.restarts,
                          info.res_energy, info.res_estimate, info.t_setup_ms, info.t_solve_ms,
-                         [hist[k] for k in range(n)])
+                         [hist[k] for k in range(n)], vcycles=info.vcycles, res_l2=info.res_l2)
 
     # -- entry points ---------------------------------------------------------
     @property
@@ -146,6 +214,7 @@ class Solver:
 
     def set_coefficients(self, eta_b, eta_p, rho_b, gx: float = 0.0, gy: float = -1.0,
                          fx_extra=None, fy_extra=None):
+        self.generation += 1
         self._sync_in()
         _lib.check("tph_set_coefficients", self._lib.tph_set_coefficients(
             self._h, self._p(eta_b, "eta_b"), self._p(eta_p, "eta_p"), self._p(rho_b, "rho_b"),
@@ -180,6 +249,7 @@ class Solver:
         vx = self.zeros() if vx is None else vx
         vy = self.zeros() if vy is None else vy
         p = self.zeros() if p is None else p
+        self.generation += 1           # the stages load blended coefficients
         th = (ctypes.c_double * len(thetas))(*[float(t) for t in thetas])
         info = _lib.Info()
         hist = (ctypes.c_double * max(history, 1))()
@@ -318,6 +388,7 @@ class Batch:
     def __init__(self, shapes, device: Optional[torch.device] = None,
                  stream: Optional[torch.cuda.Stream] = None, **params):
         lib = _lib.load()
+        _ensure_allocator()
         self._lib = lib
         self.count = len(shapes)
         self.rtol = float(params.get("rtol", 1e-8))
@@ -339,6 +410,7 @@ class Batch:
                                                                 ctypes.c_void_p(self.stream.cuda_stream),
                                                                 ctypes.byref(h)))
         self._h = h
+        _live.add(self)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -384,7 +456,7 @@ class Batch:
         _lib.check("tph_batch_solve", st, allow_not_converged=True)
         out = [SolveInfo("TPH_OK" if infos[k].res_energy <= self.rtol else "TPH_NOT_CONVERGED", infos[k].iters,
                          infos[k].restarts, infos[k].res_energy, infos[k].res_estimate, infos[k].t_setup_ms,
-                         infos[k].t_solve_ms)
+                         infos[k].t_solve_ms, vcycles=infos[k].vcycles, res_l2=infos[k].res_l2)
                for k in range(self.count)]
         return vx, vy, p, out
 
@@ -407,6 +479,7 @@ class Markers:
     def __init__(self, nx: int, ny: int, lx: float = 1.0, ly: float = 1.0, capacity: int = 1 << 20,
                  device: Optional[torch.device] = None, stream: Optional[torch.cuda.Stream] = None):
         lib = _lib.load()
+        _ensure_allocator()
         self._lib = lib
         self.nx, self.ny = nx, ny
         self.shape = (ny + 2, nx + 2)
@@ -419,6 +492,7 @@ class Markers:
                                                                     ctypes.c_void_p(self.stream.cuda_stream),
                                                                     ctypes.byref(h)))
         self._h = h
+        _live.add(self)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -491,24 +565,42 @@ class StokesFunction(torch.autograd.Function):
 
     Forward: tph_set_coefficients + tph_solve on the given solver.  Backward:
     the adjoint solve (A is symmetric) with right-hand side (dJ/dvx, dJ/dvy,
-    dJ/dp), then the coefficient-gradient kernel.
+    dJ/dp), then the coefficient-gradient kernel.  The adjoint needs the
+    operator of the forward solve: when the solver's coefficients have
+    changed in between (another forward on the same solver, a continuation),
+    backward loads the saved forward coefficients again.  A forward or
+    adjoint solve that does not reach the solver's rtol raises TephraError
+    (a gradient of an unconverged state is not the gradient of J).
     """
 
     @staticmethod
     def forward(ctx, eta_b, eta_p, rho_b, solver: Solver, gx: float = 0.0, gy: float = -1.0):
-        solver.set_coefficients(eta_b.detach().contiguous(), eta_p.detach().contiguous(),
-                                rho_b.detach().contiguous(), gx, gy)
+        eb, ep, rb = eta_b.detach().contiguous(), eta_p.detach().contiguous(), rho_b.detach().contiguous()
+        solver.set_coefficients(eb, ep, rb, gx, gy)
         vx, vy, p, info = solver.solve()
+        if info.status != "TPH_OK":
+            raise TephraError("tph_solve", _lib.TPH_NOT_CONVERGED,
+                              f"forward solve of StokesFunction did not converge: relative energy residual "
+                              f"{info.res_energy:.3e} after {info.iters} iterations (rtol {solver.desc.rtol:g})")
         ctx.solver = solver
         ctx.info = info
-        ctx.save_for_backward(vx, vy, p)
+        ctx.generation = solver.generation
+        ctx.gravity = (float(gx), float(gy))
+        ctx.save_for_backward(vx, vy, p, eb, ep, rb)
         return vx, vy, p
 
     @staticmethod
     def backward(ctx, gvx, gvy, gp):
         s: Solver = ctx.solver
-        vx, vy, p = ctx.saved_tensors
+        vx, vy, p, eb, ep, rb = ctx.saved_tensors
+        if s.generation != ctx.generation:
+            s.set_coefficients(eb, ep, rb, *ctx.gravity)     # the forward operator again
+            ctx.generation = s.generation
         z = lambda g: s.zeros() if g is None else g.contiguous()
-        lx, ly, lp, _ = s.solve_adjoint(z(gvx), z(gvy), z(gp))
+        lx, ly, lp, info = s.solve_adjoint(z(gvx), z(gvy), z(gp))
+        if info.status != "TPH_OK":
+            raise TephraError("tph_solve_adjoint", _lib.TPH_NOT_CONVERGED,
+                              f"adjoint solve of StokesFunction did not converge: relative energy residual "
+                              f"{info.res_energy:.3e} after {info.iters} iterations (rtol {s.desc.rtol:g})")
         gb, gpp, gr = s.coeff_gradient(vx, vy, p, lx, ly, lp)
         return gb, gpp, gr, None, None, None

@@ -8,7 +8,7 @@ from __future__ import annotations
 import ctypes
 import os
 import re
-from ctypes import POINTER, c_char_p, c_double, c_int32, c_uint64, c_void_p
+from ctypes import POINTER, c_char_p, c_double, c_int32, c_size_t, c_uint64, c_void_p
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtephra.so")
@@ -44,7 +44,13 @@ class Desc(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [("iters", c_int32), ("restarts", c_int32), ("res_energy", c_double),
                 ("res_estimate", c_double), ("t_setup_ms", c_double), ("t_solve_ms", c_double),
-                ("history", POINTER(c_double)), ("history_len", c_int32)]
+                ("history", POINTER(c_double)), ("history_len", c_int32), ("vcycles", c_int32),
+                ("res_l2", c_double)]
+
+
+# device allocator callbacks of tph_set_allocator
+ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, c_size_t, c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, c_void_p)
 
 
 class TephraError(RuntimeError):
@@ -77,6 +83,7 @@ def load(path: str = LIB_PATH):
     sig = {
         "tph_desc_default": (None, [POINTER(Desc), c_int32, c_int32]),
         "tph_create": (c_int32, [POINTER(Desc), P, POINTER(P)]),
+        "tph_set_allocator": (c_int32, [P, ALLOC_FN, FREE_FN, P]),
         "tph_set_coefficients": (c_int32, [P, P, P, P, c_double, c_double, P, P]),
         "tph_solve": (c_int32, [P, P, P, P, POINTER(Info)]),
         "tph_solve_rhs": (c_int32, [P, P, P, P, P, P, P, POINTER(Info)]),

@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "../../include/tephra.h"
+#include "devmem.h"
 #include "fused_dev.h"
 #include "solver_internal.h"
 #include "stencil_dev.h"
@@ -336,7 +337,7 @@ struct tph_batch {
     double** d_gj_mats = nullptr;
     int* d_gj_n = nullptr;
     int gj_nmax = 0;
-    std::vector<void*> allocs;
+    tph::DeviceArena mem;        // device workspace (through the allocator current at creation)
     bool ready = false;
     bool mixed() const { return d.precision == TPH_MIXED; }
 };
@@ -351,13 +352,12 @@ constexpr int kSlotMisc = kSlotY + tph::kMaxRestart;
 constexpr int kScal = kSlotMisc + 8;
 
 tph_status b_alloc(tph_batch* b, void** p, size_t bytes) {
-    hipError_t e = hipMalloc(p, bytes);
+    std::string what;
+    const hipError_t e = b->mem.alloc(p, bytes, &what);
     if (e != hipSuccess) {
-        *p = nullptr;
-        tph_internal_set_error("batch allocation failed: " + std::string(hipGetErrorString(e)));
+        tph_internal_set_error("batch workspace: " + what);
         return e == hipErrorOutOfMemory ? TPH_ERR_OOM : TPH_ERR_HIP;
     }
-    b->allocs.push_back(*p);
     return TPH_OK;
 }
 
@@ -717,7 +717,14 @@ tph_status batch_solve_impl(tph_batch* b, tph_info* infos) {
             if (bnorm[p] == 0.0 || true_res[p] <= b->d.rtol) { h_unf[p] = 0; status[p] = TPH_OK; continue; }
             if (its[p] >= b->d.max_iters) { h_unf[p] = 0; continue; }
             if (true_res[p] > 0.9 * best[p]) {
-                if (++stall[p] >= 3) { h_unf[p] = 0; continue; }
+                if (++stall[p] >= 3) {
+                    // stagnation only near the rounding floor (see the single solver); the
+                    // problem's x and b live in its solver, the stream is idle here
+                    double floor_ = 0.0;
+                    B_TRY(tph_internal_rounding_floor(b->s[p], bnorm[p], &floor_));
+                    if (true_res[p] <= 100.0 * floor_) { h_unf[p] = 0; continue; }
+                    stall[p] = 0;
+                }
             } else {
                 stall[p] = 0;
             }
@@ -795,10 +802,16 @@ tph_status batch_solve_impl(tph_batch* b, tph_info* infos) {
         B_HIP(hipStreamSynchronize(st));
     }
     const auto t1 = std::chrono::steady_clock::now();
+    if (infos) {
+        for (int p = 0; p < P; ++p) B_TRY(tph_internal_plain_residual_enqueue(b->s[p]));
+        B_HIP(hipStreamSynchronize(st));
+    }
     tph_status worst = TPH_OK;
     for (int p = 0; p < P; ++p) {
         if (infos) {
             infos[p].iters = its[p];
+            infos[p].vcycles = its[p] * b->d.uzawa_steps;
+            infos[p].res_l2 = tph_internal_plain_residual_read(b->s[p]);
             infos[p].restarts = restarts[p];
             infos[p].res_energy = true_res[p];
             infos[p].res_estimate = its[p] ? est[p] : true_res[p];
@@ -823,6 +836,7 @@ tph_status tph_batch_create(int32_t count, const tph_desc* descs, void* hip_stre
     }
     *out = nullptr;
     tph_batch* b = new tph_batch();
+    b->mem.a = tph::default_allocator();
     b->user_st = (hipStream_t)hip_stream;
     tph_status s = TPH_OK;
     if (hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking) != hipSuccess ||
@@ -925,7 +939,7 @@ void tph_batch_destroy(tph_batch* b) {
     if (b->iter_exec) (void)hipGraphExecDestroy(b->iter_exec);
     if (b->iter_graph) (void)hipGraphDestroy(b->iter_graph);
     for (tph_solver* s : b->s) tph_destroy(s);
-    for (void* p : b->allocs) (void)hipFree(p);
+    b->mem.release_all();
     if (b->h_scal) (void)hipHostFree(b->h_scal);
     if (b->h_j) (void)hipHostFree(b->h_j);
     if (b->h_int) (void)hipHostFree(b->h_int);

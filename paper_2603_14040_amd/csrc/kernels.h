@@ -14,6 +14,9 @@ enum class ResMode { kResidual = 0, kApply = 1 };
 hipError_t launch_outer_residual(const Geom& g, Vec3 x, const Vec3* b, const double* eb, const double* ep,
                                  Vec3 out, ResMode mode, bool energy, double* partial, int* nblk_out,
                                  hipStream_t st, bool b_scaled = false);
+// per-block sums of the squared energy-weighted row magnitudes |b| + |A| |x|
+hipError_t launch_residual_magnitude(const Geom& g, Vec3 x, Vec3 b, const double* eb, const double* ep,
+                                    double* partial, int* nblk_out, hipStream_t st);
 // walls to zero, ghosts mirrored, for a solution-type vx / vy pair
 template <typename T>
 hipError_t launch_fill_bc(const Geom& g, T* vx, T* vy, hipStream_t st);

@@ -19,6 +19,7 @@
 #include <string>
 
 #include "../../include/tephra.h"
+#include "devmem.h"
 #include "solver_internal.h"
 
 struct tph_markers {
@@ -39,6 +40,7 @@ struct tph_markers {
     int n = 0;
     const double* xm = nullptr;
     const double* ym = nullptr;
+    tph::DeviceArena mem;          // device workspace (through the allocator current at creation)
 };
 
 namespace {
@@ -236,26 +238,32 @@ tph_status tph_markers_create(int32_t nx, int32_t ny, double lx, double ly, int3
     h->dy = ly / ny;
     h->capacity = capacity;
     h->st = (hipStream_t)hip_stream;
+    h->mem.a = tph::default_allocator();
     const size_t ncell = (size_t)(nx + 1) * (ny + 1);
-    bool ok = true;
-    for (int k = 0; k < 2 && ok; ++k) {
-        ok = hipMalloc(&h->keys[k], (size_t)capacity * sizeof(uint32_t)) == hipSuccess &&
-             hipMalloc(&h->vals[k], (size_t)capacity * sizeof(int32_t)) == hipSuccess;
+    std::string what;
+    hipError_t e = hipSuccess;
+    auto get = [&](void** p, size_t bytes) {
+        if (e == hipSuccess) e = h->mem.alloc(p, bytes, &what);
+    };
+    for (int k = 0; k < 2; ++k) {
+        get((void**)&h->keys[k], (size_t)capacity * sizeof(uint32_t));
+        get((void**)&h->vals[k], (size_t)capacity * sizeof(int32_t));
     }
-    ok = ok && hipMalloc(&h->cstart, ncell * sizeof(int32_t)) == hipSuccess &&
-         hipMalloc(&h->cend, ncell * sizeof(int32_t)) == hipSuccess &&
-         hipMalloc(&h->partial, ncell * 8 * sizeof(double)) == hipSuccess;
-    if (ok) {
+    get((void**)&h->cstart, ncell * sizeof(int32_t));
+    get((void**)&h->cend, ncell * sizeof(int32_t));
+    get((void**)&h->partial, ncell * 8 * sizeof(double));
+    if (e == hipSuccess) {
         hipcub::DoubleBuffer<uint32_t> kb(h->keys[0], h->keys[1]);
         hipcub::DoubleBuffer<int32_t> vb(h->vals[0], h->vals[1]);
-        ok = hipcub::DeviceRadixSort::SortPairs(nullptr, h->temp_bytes, kb, vb, capacity, 0, 32, h->st) == hipSuccess &&
-             hipMalloc(&h->temp, h->temp_bytes > 0 ? h->temp_bytes : 1) == hipSuccess;
+        e = hipcub::DeviceRadixSort::SortPairs(nullptr, h->temp_bytes, kb, vb, capacity, 0, 32, h->st);
+        if (e != hipSuccess) what = std::string("sort workspace query failed: ") + hipGetErrorString(e);
+        get(&h->temp, h->temp_bytes > 0 ? h->temp_bytes : 1);
     }
-    if (!ok) {
+    if (e != hipSuccess) {
         (void)hipGetLastError();
         tph_markers_destroy(h);
-        tph_internal_set_error_m("out of device memory for the marker workspace");
-        return TPH_ERR_OOM;
+        tph_internal_set_error_m("marker workspace: " + what);
+        return e == hipErrorOutOfMemory ? TPH_ERR_OOM : TPH_ERR_HIP;
     }
     *out = h;
     return TPH_OK;
@@ -264,14 +272,7 @@ tph_status tph_markers_create(int32_t nx, int32_t ny, double lx, double ly, int3
 void tph_markers_destroy(tph_markers* h) {
     if (!h) return;
     if (h->st) (void)hipStreamSynchronize(h->st);
-    for (int k = 0; k < 2; ++k) {
-        if (h->keys[k]) (void)hipFree(h->keys[k]);
-        if (h->vals[k]) (void)hipFree(h->vals[k]);
-    }
-    if (h->cstart) (void)hipFree(h->cstart);
-    if (h->cend) (void)hipFree(h->cend);
-    if (h->partial) (void)hipFree(h->partial);
-    if (h->temp) (void)hipFree(h->temp);
+    h->mem.release_all();
     delete h;
 }
 

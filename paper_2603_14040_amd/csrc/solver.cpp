@@ -24,6 +24,7 @@
 
 #include "../../include/tephra.h"
 #include "common.h"
+#include "devmem.h"
 #include "kernels.h"
 #include "solver_internal.h"
 #include "stencil_dev.h"
@@ -129,8 +130,9 @@ struct tph_solver {
     int kev_used = 0;
     int kdropped = 0;
     double kbytes = 0.0;
-    std::vector<void*> dev_allocs;
+    DeviceArena mem;              // device workspace (through the allocator current at creation)
     int vc_cycle = 0;             // V-cycle index inside the current preconditioner application (RAS shifts)
+    long long vcycles = 0;        // V-cycles run since the current solve started
     // captured preconditioner applications, one per (v, z, w, energy, link) set
     struct PGraph {
         const double* v;
@@ -184,13 +186,12 @@ void ktoc(tph_solver* s, const KTime& k, double words, size_t wbytes) {
 }
 
 tph_status dev_alloc(tph_solver* s, void** p, size_t bytes) {
-    hipError_t e = hipMalloc(p, bytes);
+    std::string what;
+    const hipError_t e = s->mem.alloc(p, bytes, &what);
     if (e != hipSuccess) {
-        *p = nullptr;
-        set_error("device allocation of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+        set_error(what);
         return e == hipErrorOutOfMemory ? TPH_ERR_OOM : TPH_ERR_HIP;
     }
-    s->dev_allocs.push_back(*p);
     TPH_HIP(hipMemsetAsync(*p, 0, bytes, s->st));
     return TPH_OK;
 }
@@ -624,6 +625,7 @@ tph_status precondition_eager(tph_solver* s, double* vraw, double* zraw, bool en
 // Kernel time stamps need per-launch events, so timed solves run eagerly.
 tph_status precondition(tph_solver* s, double* vraw, double* zraw, bool energy, double* wraw = nullptr,
                         bool link = false) {
+    s->vcycles += s->d.uzawa_steps;
     if (!s->d.graph || s->graph_broken || s->ktime || !(wraw || link))
         return precondition_eager(s, vraw, zraw, energy, wraw, link);
     const tph_solver::PGraph* hit = nullptr;
@@ -718,6 +720,24 @@ tph_status energy_residual_vec(tph_solver* s, double* xraw, double* braw, double
     return reduce_to(s, nblk, 1, slot, to_host, to_host);
 }
 
+// Rounding floor of the relative energy residual at iterate x: eps times the
+// energy norm of the row magnitudes |b| + |A| |x|, over the energy norm of b.
+// The FP64 residual b - A x cannot be resolved below roughly this value.
+tph_status rounding_floor(tph_solver* s, double* xraw, double* braw, double bnorm, double* out) {
+    const LevelBuf& L = s->lev[0];
+    int nblk = 0;
+    TPH_HIP(launch_residual_magnitude(L.g, vec3(s, xraw), vec3(s, braw), L.eb64, L.ep64, s->partial, &nblk, s->st));
+    TPH_TRY(reduce_to(s, nblk, 1, kSlotMisc + 4, true, true));
+    TPH_TRY(wait_signal(s));
+    *out = 2.220446049250313e-16 * std::sqrt(s->hscal[kSlotMisc + 4]) / (bnorm > 0.0 ? bnorm : 1.0);
+    return TPH_OK;
+}
+
+// A residual that has not fallen by 10% over three restarts is taken as
+// stagnation only within this factor of the rounding floor; above it the
+// solve keeps going (slow convergence is not a floor).
+constexpr double kFloorMargin = 100.0;
+
 tph_status copy_in(tph_solver* s, const Geom& g, double* base, const double* user) {
     const size_t w = (size_t)(g.nx + 2) * sizeof(double);
     TPH_HIP(hipMemcpy2DAsync(base, (size_t)g.pitch * sizeof(double), user, w, w, g.ny + 2, hipMemcpyDeviceToDevice,
@@ -799,7 +819,12 @@ tph_status fgmres(tph_solver* s, double* braw, tph_info* info) {
         if (bnorm == 0.0 || true_res <= s->d.rtol) { result = TPH_OK; break; }
         if (its >= s->d.max_iters) break;
         if (true_res > 0.9 * best_true) {
-            if (++stalled >= 3) { stagnated = true; break; }
+            if (++stalled >= 3) {
+                double floor_ = 0.0;
+                TPH_TRY(rounding_floor(s, s->x, braw, bnorm, &floor_));
+                if (true_res <= kFloorMargin * floor_) { stagnated = true; break; }
+                stalled = 0;
+            }
         } else {
             stalled = 0;
         }
@@ -878,7 +903,7 @@ tph_status fgmres(tph_solver* s, double* braw, tph_info* info) {
         info->t_solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
     }
     if (result == TPH_NOT_CONVERGED)
-        set_error(std::string(stagnated ? "FGMRES stagnated (rounding floor of the residual)" : "FGMRES reached max_iters") +
+        set_error(std::string(stagnated ? "FGMRES stagnated at the rounding floor of the residual" : "FGMRES reached max_iters") +
                   " with relative energy residual " + std::to_string(true_res));
     return result;
 }
@@ -932,7 +957,12 @@ tph_status gcr(tph_solver* s, double* braw, tph_info* info) {
         if (bnorm == 0.0 || true_res <= s->d.rtol) { result = TPH_OK; break; }
         if (its >= s->d.max_iters) break;
         if (true_res > 0.9 * best_true) {
-            if (++stalled >= 3) { stagnated = true; break; }
+            if (++stalled >= 3) {
+                double floor_ = 0.0;
+                TPH_TRY(rounding_floor(s, s->x, braw, bnorm, &floor_));
+                if (true_res <= kFloorMargin * floor_) { stagnated = true; break; }
+                stalled = 0;
+            }
         } else {
             stalled = 0;
         }
@@ -1034,7 +1064,7 @@ tph_status gcr(tph_solver* s, double* braw, tph_info* info) {
         info->t_solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
     }
     if (result == TPH_NOT_CONVERGED)
-        set_error(std::string(stagnated ? "GCR stagnated (rounding floor of the residual)" : "GCR reached max_iters") +
+        set_error(std::string(stagnated ? "GCR stagnated at the rounding floor of the residual" : "GCR reached max_iters") +
                   " with relative energy residual " + std::to_string(true_res));
     return result;
 }
@@ -1178,8 +1208,13 @@ tph_status anderson(tph_solver* s, double* braw, tph_info* info) {
             best = true_res;
             stalled = 0;
         } else if (++stalled >= stall_limit) {
-            stagnated = true;
-            break;
+            double floor_ = 0.0;
+            TPH_TRY(rounding_floor(s, Xk(k), braw, bnorm, &floor_));
+            if (true_res <= kFloorMargin * floor_) {
+                stagnated = true;
+                break;
+            }
+            stalled = 0;
         }
         // Gram row of f_k, then the window's Gram matrix (oldest first)
         const int sk = (int)(k % ns);
@@ -1236,17 +1271,50 @@ tph_status anderson(tph_solver* s, double* braw, tph_info* info) {
         info->t_solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
     }
     if (result == TPH_NOT_CONVERGED)
-        set_error(std::string(stagnated ? "Anderson acceleration stagnated" : "Anderson acceleration reached max_iters") +
+        set_error(std::string(stagnated ? "Anderson acceleration stagnated at the rounding floor of the residual" : "Anderson acceleration reached max_iters") +
                   " with relative energy residual " + std::to_string(true_res));
     return result;
 }
 
+// plain relative l2 residual ||b - A x||_2 / ||b||_2 over every equation row
+// (no energy weights; Sec. "Residual Norms" reports both): the two squared
+// norms are reduced into the mapped host scalars, read after the stream has
+// drained (plain_residual_read)
+tph_status plain_residual_enqueue(tph_solver* s, double* xraw, double* braw) {
+    const LevelBuf& L = s->lev[0];
+    int nblk = 0;
+    Vec3 b = vec3(s, braw);
+    TPH_HIP(launch_outer_residual(L.g, vec3(s, xraw), &b, L.eb64, L.ep64, vec3(s, s->t1), ResMode::kResidual, false,
+                                  s->partial, &nblk, s->st));
+    TPH_TRY(reduce_to(s, nblk, 1, kSlotMisc + 2, true));
+    TPH_HIP(hipMemsetAsync(s->t2, 0, s->n3 * sizeof(double), s->st));
+    TPH_HIP(launch_outer_residual(L.g, vec3(s, s->t2), &b, L.eb64, L.ep64, vec3(s, s->t1), ResMode::kResidual, false,
+                                  s->partial, &nblk, s->st));
+    return reduce_to(s, nblk, 1, kSlotMisc + 3, true);
+}
+
+double plain_residual_read(const tph_solver* s) {
+    const double rr = std::sqrt(s->hscal[kSlotMisc + 2]), bb = std::sqrt(s->hscal[kSlotMisc + 3]);
+    return bb > 0.0 ? rr / bb : rr;
+}
+
 tph_status accelerate(tph_solver* s, double* braw, tph_info* info) {
+    s->vcycles = 0;
+    tph_status r;
     switch (s->d.accel) {
-        case TPH_ACCEL_GCR: return gcr(s, braw, info);
-        case TPH_ACCEL_ANDERSON: return anderson(s, braw, info);
-        default: return fgmres(s, braw, info);
+        case TPH_ACCEL_GCR: r = gcr(s, braw, info); break;
+        case TPH_ACCEL_ANDERSON: r = anderson(s, braw, info); break;
+        default: r = fgmres(s, braw, info); break;
     }
+    if (r >= 0 && info) {
+        info->vcycles = (int32_t)std::min<long long>(s->vcycles, INT32_MAX);
+        const std::string msg = g_last_error;          // keep a not-converged message
+        TPH_TRY(plain_residual_enqueue(s, s->x, braw));
+        TPH_HIP(hipStreamSynchronize(s->st));
+        info->res_l2 = plain_residual_read(s);
+        g_last_error = msg;
+    }
+    return r;
 }
 
 tph_status require_ready(tph_solver* s) {
@@ -1643,6 +1711,13 @@ tph_status tph_internal_load_solution(tph_solver* s, const double* vx, const dou
     return load_solution(s, s->x, vx, vy, p);
 }
 
+tph_status tph_internal_rounding_floor(tph_solver* s, double bnorm, double* out) {
+    return rounding_floor(s, s->x, s->b, bnorm, out);
+}
+
+tph_status tph_internal_plain_residual_enqueue(tph_solver* s) { return plain_residual_enqueue(s, s->x, s->b); }
+double tph_internal_plain_residual_read(const tph_solver* s) { return plain_residual_read(s); }
+
 tph_status tph_internal_finish_solution(tph_solver* s, double* vx, double* vy, double* p) {
     TPH_TRY(remove_pressure_mean(s, s->x));
     return store_solution(s, s->x, vx, vy, p);
@@ -1692,6 +1767,7 @@ tph_status tph_create(const tph_desc* desc, void* hip_stream, tph_solver** out) 
     int nlev = 0;
     TPH_TRY(validate_desc(desc, &nlev));       // host-only checks before any HIP call
     tph_solver* s = new tph_solver();
+    s->mem.a = default_allocator();
     const tph_status st = create_impl(desc, hip_stream, s);
     if (st != TPH_OK) {
         const std::string msg = g_last_error;
@@ -1792,6 +1868,8 @@ tph_status tph_solve_continuation(tph_solver* s, const double* eta_b, const doub
         s->d.rtol = rtol;
         tot.iters += st.iters;
         tot.restarts += st.restarts;
+        tot.vcycles += st.vcycles;
+        tot.res_l2 = st.res_l2;
         tot.res_energy = st.res_energy;
         tot.res_estimate = st.res_estimate;
         tot.t_setup_ms += s->t_setup_ms;
@@ -2045,8 +2123,9 @@ tph_status tph_kernel_timing_read(tph_solver* s, int32_t* launches, double* tota
 
 void tph_destroy(tph_solver* s) {
     if (!s) return;
-    if (s->st || !s->dev_allocs.empty()) (void)hipStreamSynchronize(s->st);
-    for (void* p : s->dev_allocs) (void)hipFree(p);
+    if (s->st || !s->mem.empty()) (void)hipStreamSynchronize(s->st);
+    if (s->gst) (void)hipStreamSynchronize(s->gst);
+    s->mem.release_all();
     if (s->hscal) (void)hipHostFree(s->hscal);
     if (s->hseq) (void)hipHostFree(s->hseq);
     if (s->ev0) (void)hipEventDestroy(s->ev0);
@@ -2064,6 +2143,21 @@ void tph_destroy(tph_solver* s) {
     if (s->gev0) (void)hipEventDestroy(s->gev0);
     if (s->gev1) (void)hipEventDestroy(s->gev1);
     delete s;
+}
+
+tph_status tph_set_allocator(tph_solver* s, void* (*alloc)(size_t, void*), void (*free_fn)(void*, void*), void* ctx) {
+    g_last_error.clear();
+    if ((alloc == nullptr) != (free_fn == nullptr)) {
+        set_error("alloc and free must both be given or both be NULL");
+        return TPH_ERR_INVALID;
+    }
+    Allocator a;
+    a.alloc = alloc;
+    a.free = free_fn;
+    a.ctx = alloc ? ctx : nullptr;
+    if (s) s->mem.a = a;
+    else set_default_allocator(a);
+    return TPH_OK;
 }
 
 const char* tph_last_error(void) { return g_last_error.c_str(); }

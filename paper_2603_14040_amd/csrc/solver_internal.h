@@ -42,5 +42,12 @@ tph_status tph_internal_load_solution(tph_solver* s, const double* vx, const dou
 tph_status tph_internal_setup_enqueue(tph_solver* s, const double* eta_b, const double* eta_p, const double* rho_b,
                                       double gx, double gy);
 tph_status tph_internal_setup_finish(tph_solver* s);
+// rounding floor of the relative energy residual of the solver's current
+// iterate (waits for its stream)
+tph_status tph_internal_rounding_floor(tph_solver* s, double bnorm, double* out);
+// plain relative l2 residual of the solution held by the solver: enqueue the
+// reductions on its stream, read the value after that stream has drained
+tph_status tph_internal_plain_residual_enqueue(tph_solver* s);
+double tph_internal_plain_residual_read(const tph_solver* s);
 // remove the pressure mean of the solution and copy it out
 tph_status tph_internal_finish_solution(tph_solver* s, double* vx, double* vy, double* p);

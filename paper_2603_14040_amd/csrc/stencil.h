@@ -82,6 +82,32 @@ __device__ __forceinline__ T ly_row_novy(const T* __restrict__ vx, const T* __re
     return (syx_r - syx_l) * idx;
 }
 
+// Magnitudes of the terms of lx_row / ly_row, each flux product taken in
+// absolute value: the scale of the rounding error of a residual row.
+template <typename T>
+__device__ __forceinline__ T lx_row_abs(const T* __restrict__ vx, const T* __restrict__ vy,
+                                        const T* __restrict__ eb, const T* __restrict__ ep,
+                                        int c, int P, T idx, T idy) {
+    const T v = vx[c];
+    const T sxx_r = (T)2 * ep[c + 1] * (fabs(vx[c + 1]) + fabs(v)) * idx;
+    const T sxx_l = (T)2 * ep[c] * (fabs(v) + fabs(vx[c - 1])) * idx;
+    const T sxy_t = eb[c] * ((fabs(vx[c + P]) + fabs(v)) * idy + (fabs(vy[c + 1]) + fabs(vy[c])) * idx);
+    const T sxy_b = eb[c - P] * ((fabs(v) + fabs(vx[c - P])) * idy + (fabs(vy[c - P + 1]) + fabs(vy[c - P])) * idx);
+    return (sxx_r + sxx_l) * idx + (sxy_t + sxy_b) * idy;
+}
+
+template <typename T>
+__device__ __forceinline__ T ly_row_abs(const T* __restrict__ vx, const T* __restrict__ vy,
+                                        const T* __restrict__ eb, const T* __restrict__ ep,
+                                        int c, int P, T idx, T idy) {
+    const T v = vy[c];
+    const T syy_t = (T)2 * ep[c + P] * (fabs(vy[c + P]) + fabs(v)) * idy;
+    const T syy_b = (T)2 * ep[c] * (fabs(v) + fabs(vy[c - P])) * idy;
+    const T syx_r = eb[c] * ((fabs(vx[c + P]) + fabs(vx[c])) * idy + (fabs(vy[c + 1]) + fabs(v)) * idx);
+    const T syx_l = eb[c - 1] * ((fabs(vx[c + P - 1]) + fabs(vx[c - 1])) * idy + (fabs(v) + fabs(vy[c - 1])) * idx);
+    return (syy_t + syy_b) * idy + (syx_r + syx_l) * idx;
+}
+
 // diag(L) at vx(i, j) and vy(i, j).  At a wall-adjacent node the shear term
 // of the boundary basic node enters with weight (1 - mirror): 0 for free
 // slip, 2 for no slip.

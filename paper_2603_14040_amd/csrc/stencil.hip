@@ -35,6 +35,14 @@ __global__ __launch_bounds__(256) void k_outer_residual(Geom g, Vec3 x, Vec3 b, 
     }
 }
 
+__global__ __launch_bounds__(256) void k_residual_magnitude(Geom g, Vec3 x, Vec3 b, const double* __restrict__ eb,
+                                                           const double* __restrict__ ep, double* partial) {
+    const int j = blockIdx.x * BX + threadIdx.x + 1;
+    const int i = blockIdx.y * BY + threadIdx.y + 1;
+    const double s = block_sum(residual_magnitude_cell(g, x, b, eb, ep, i, j));
+    if (threadIdx.x == 0 && threadIdx.y == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = s;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_fill_bc(Geom g, T* vx, T* vy) {
     // grid over [0, ny+1] x [0, nx+1]
@@ -364,6 +372,14 @@ hipError_t launch_outer_residual(const Geom& g, Vec3 x, const Vec3* b, const dou
     Vec3 bb = b ? *b : Vec3{nullptr, 0};
     hipLaunchKernelGGL(k_outer_residual, grid, dim3(BX, BY), 0, st, g, x, bb, b ? 1 : 0, eb, ep, out,
                        mode == ResMode::kApply ? 1 : 0, energy ? 1 : 0, partial, b_scaled ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_magnitude(const Geom& g, Vec3 x, Vec3 b, const double* eb, const double* ep,
+                                    double* partial, int* nblk_out, hipStream_t st) {
+    const dim3 grid = grid_cells(g);
+    *nblk_out = (int)(grid.x * grid.y);
+    hipLaunchKernelGGL(k_residual_magnitude, grid, dim3(BX, BY), 0, st, g, x, b, eb, ep, partial);
     return hipGetLastError();
 }
 

@@ -55,6 +55,40 @@ __device__ __forceinline__ double outer_residual_cell(const Geom& g, const Vec3&
     return acc;
 }
 
+// Energy-weighted magnitude of the residual rows at cell (i, j): |b| plus the
+// absolute terms of A x, scaled as the energy residual; returns the sum of
+// their squares.  eps times its root bounds the size of the rounding error
+// of b - A x (the floor below which the true residual cannot fall).
+__device__ __forceinline__ double residual_magnitude_cell(const Geom& g, const Vec3& x, const Vec3& b,
+                                                          const double* __restrict__ eb,
+                                                          const double* __restrict__ ep, int i, int j) {
+    const LevelC<double> k = level_consts<double>(g);
+    const int P = g.pitch;
+    double acc = 0.0;
+    if (i <= g.ny && j <= g.nx) {
+        const int c = i * P + j;
+        const double* vx = x.vx();
+        const double* vy = x.vy();
+        const double* p = x.p();
+        if (j < g.nx) {
+            const double a = lx_row_abs(vx, vy, eb, ep, c, P, k.idx, k.idy) + (fabs(p[c + 1]) + fabs(p[c])) * k.idx;
+            const double r = (fabs(b.vx()[c]) + a) / sqrt(-lx_diag(eb, ep, c, P, i, g.ny, k));
+            acc += r * r;
+        }
+        if (i < g.ny) {
+            const double a = ly_row_abs(vx, vy, eb, ep, c, P, k.idx, k.idy) + (fabs(p[c + P]) + fabs(p[c])) * k.idy;
+            const double r = (fabs(b.vy()[c]) + a) / sqrt(-ly_diag(eb, ep, c, P, j, g.nx, k));
+            acc += r * r;
+        }
+        {
+            const double a = (fabs(vx[c]) + fabs(vx[c - 1])) * k.idx + (fabs(vy[c]) + fabs(vy[c - P])) * k.idy;
+            const double r = (fabs(b.p()[c]) + a) * sqrt(wp_weight(ep[c], k));
+            acc += r * r;
+        }
+    }
+    return acc;
+}
+
 template <typename T>
 __device__ __forceinline__ void precond_in_cell(const Geom& g, const Vec3& v, const double* __restrict__ eb,
                                                 const double* __restrict__ ep, int energy, T* __restrict__ rx,

@@ -9,6 +9,13 @@ workloads, in the launch configurations the benchmark times.
   rounding (<= 1e-13 relative, random state); the solve reaches the 1e-8
   relative energy residual; the solution has zero walls, mirrored ghosts
   and zero-mean pressure.
+* The benchmark's own tuned plans (the kernel plan and schedule the
+  autotuner picks for the 1024^2 random-viscosity workload: GCR(8), 4 Uzawa
+  steps, 1 + 1 sweeps, multi-sweep levels 1-4, small tiles below the finest
+  level, alpha 1.5 for the mixed solve; GCR(10), 2 Uzawa steps for FP64) on
+  the same recipe at 512^2, solved to a 1e-12 energy residual: element-wise
+  against the oracle's direct (SuperLU) solve, <= 1e-7 (FP64) and <= 1e-6
+  (mixed) relative L2 in v and in zero-mean p.
 * 256 batched sinkers of sizes 64..512 (the benchmark's batch), mixed, the
   benchmark's batched schedule and target: one batched solve brings every
   problem to a 1e-8 energy residual, and the oracle's assembled operator
@@ -18,6 +25,8 @@ workloads, in the launch configurations the benchmark times.
   FP64 rounding in A x puts a floor of 1e-10 to 2e-9 under the relative
   energy residual of the 512^2, 10^4-contrast problems, in both precisions.)
 """
+import functools
+
 import numpy as np
 import pytest
 import torch
@@ -116,3 +125,39 @@ def test_batched_256_sinkers_full_batch():
               flush=True)
         assert res <= 1.3e-8
     bat.close()
+
+
+# the plans the autotuner picks for the 1024^2 random-viscosity benchmark workload
+TUNED_PLANS = {
+    tph.MIXED: dict(nu_pre=1, nu_post=1, nu_growth=1.0, uzawa_steps=4, restart=8, msweep=30, tile_shape=126,
+                    coarse_level=-1, omega=1.0, alpha=1.5, accel="gcr"),
+    tph.FP64: dict(nu_pre=1, nu_post=1, nu_growth=1.0, uzawa_steps=2, restart=10, msweep=30, tile_shape=124,
+                   coarse_level=-1, omega=1.0, alpha=1.5, accel="gcr"),
+}
+
+
+@functools.lru_cache(maxsize=1)
+def _oracle_grf(n):
+    pr = wl.random_viscosity(n)
+    g = st.Grid(n, n)
+    ref = st.solve(g, pr.eta_b, pr.eta_p, pr.rho_b, pr.gx, pr.gy)
+    return pr, g, ref
+
+
+@pytest.mark.parametrize("prec", [tph.MIXED, tph.FP64])
+def test_tuned_benchmark_plan_matches_oracle_512(prec):
+    n = 512
+    print(f"[full] tuned plan prec={prec} {TUNED_PLANS[prec]}: oracle solve at {n}^2", flush=True)
+    pr, g, ref = _oracle_grf(n)
+    print(f"[full] oracle residual {ref.residual_energy:.2e}", flush=True)
+    s = tph.Solver(n, n, precision=prec, device=DEV, rtol=1e-12, max_iters=4000, **TUNED_PLANS[prec])
+    s.set_coefficients(T(pr.eta_b), T(pr.eta_p), T(pr.rho_b), pr.gx, pr.gy)
+    vx, vy, p, info = s.solve()
+    ev, epr = st.parity_errors(g, ref, N(vx), N(vy), N(p))
+    print(f"[full] tuned plan prec={prec}: iters {info.iters} vcycles {info.vcycles} res {info.res_energy:.2e} "
+          f"l2 {info.res_l2:.2e} err v {ev:.2e} p {epr:.2e}", flush=True)
+    tol = 1e-7 if prec == tph.FP64 else 1e-6
+    assert info.status == "TPH_OK"
+    assert info.vcycles == info.iters * TUNED_PLANS[prec]["uzawa_steps"]
+    assert ev < tol and epr < tol
+    s.close()

@@ -371,16 +371,20 @@ def test_invalid_coefficients_rejected():
     assert s.solve()[3].status == "TPH_OK"
 
 
+@pytest.mark.parametrize("n", [32, 64, 128])
 @pytest.mark.parametrize("bc", [(0, 0, 0, 0), (1, 1, 1, 1)])
-def test_adjoint_gradient_matches_oracle(bc):
-    n = 32
+def test_adjoint_gradient_matches_oracle(bc, n):
+    """Misfit gradient with respect to eta_b, eta_p and rho_b from the FP64
+    forward + adjoint solves and the gradient kernel, against the oracle's
+    adjoint (direct solves, term-by-term derivative of the assembled
+    operator): <= 1e-7 relative L2 per field."""
     base = wl.random_viscosity(n, ell=0.15, contrast=100.0)
     base.bc = bc
     g = st.Grid(n, n, 1.0, 1.0, bc)
     rng = np.random.default_rng(9)
     target = 0.01 * rng.standard_normal(n - 1)
     ref = adj.gradient(g, base.eta_b, base.eta_p, base.rho_b, 0.2, -1.0, target)
-    s = solver_for(n, n, bc=bc, precision=tph.FP64, rtol=1e-12, max_iters=2000)
+    s = solver_for(n, n, bc=bc, precision=tph.FP64, rtol=1e-13, max_iters=4000)
     eb = T(base.eta_b).requires_grad_(True)
     ep = T(base.eta_p).requires_grad_(True)
     rho = T(base.rho_b).requires_grad_(True)
@@ -393,7 +397,45 @@ def test_adjoint_gradient_matches_oracle(bc):
                          (ep.grad, "g_eta_p", (slice(1, n + 1), slice(1, n + 1))),
                          (rho.grad, "g_rho_b", (slice(0, n + 1), slice(0, n + 1)))):
         a, b = N(got)[sl], ref[key][sl]
-        assert np.linalg.norm(a - b) / np.linalg.norm(b) < 1e-6, key
+        err = np.linalg.norm(a - b) / np.linalg.norm(b)
+        print(f"[adjoint] n={n} bc={bc} {key} rel err {err:.2e}", flush=True)
+        assert err < 1e-7, key
+
+
+def test_adjoint_uses_the_forward_operator():
+    """Two forwards on one solver, then the backward of the first: the
+    gradient is that of the first problem's operator (the saved forward
+    coefficients are loaded again), equal to a fresh single forward/backward."""
+    n = 32
+    p1 = wl.random_viscosity(n, ell=0.15, contrast=100.0)
+    p2 = wl.random_viscosity(n, ell=0.1, contrast=1000.0, seed_field=77)
+    s = solver_for(n, n, precision=tph.FP64, rtol=1e-13, max_iters=4000)
+
+    def grads(order):
+        outs = {}
+        for k in order:
+            pr = (p1, p2)[k]
+            eb = T(pr.eta_b).requires_grad_(True)
+            vx, vy, p = tph.StokesFunction.apply(eb, T(pr.eta_p), T(pr.rho_b), s, 0.0, -1.0)
+            outs[k] = (eb, torch.sum(vx[n, 1:n] ** 2))
+        return outs
+
+    fresh = grads([0])
+    fresh[0][1].backward()
+    ref = N(fresh[0][0].grad)
+    both = grads([0, 1])
+    both[0][1].backward()                   # first problem's graph, after the second forward
+    got = N(both[0][0].grad)
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-10
+
+
+def test_adjoint_raises_when_the_forward_solve_does_not_converge():
+    n = 32
+    pr = wl.random_viscosity(n, ell=0.15, contrast=100.0)
+    s = solver_for(n, n, precision=tph.FP64, rtol=1e-12, max_iters=2)
+    eb = T(pr.eta_b).requires_grad_(True)
+    with pytest.raises(tph.TephraError, match="did not converge"):
+        tph.StokesFunction.apply(eb, T(pr.eta_p), T(pr.rho_b), s, 0.0, -1.0)
 
 
 @pytest.mark.parametrize("prec", [tph.FP64, tph.MIXED])
@@ -417,8 +459,11 @@ def test_batched_solve_matches_oracle(prec):
         ev, epr = st.parity_errors(g, ref, N(vx[k]), N(vy[k]), N(pp[k]))
         print(f"[batch] problem {k} {pr.nx}x{pr.ny}: iters {infos[k].iters} res {infos[k].res_energy:.2e} "
               f"err v {ev:.2e} p {epr:.2e}", flush=True)
+        tol = 1e-7 if prec == tph.FP64 else 1e-6
         assert infos[k].res_energy < 1e-10
-        assert ev < 1e-6 and epr < 1e-6
+        assert ev < tol and epr < tol
+        assert infos[k].vcycles == infos[k].iters * 2          # uzawa_steps = 2 (default)
+        assert 0.0 <= infos[k].res_l2 < 1e-6
         _check_solution_contract(pr.nx, pr.ny, pr.bc, N(vx[k]), N(vy[k]), N(pp[k]))
     # a second solve on the same batch (graph replay, masks reset) gives the same answer
     vx2, vy2, pp2, infos2 = bat.solve()
