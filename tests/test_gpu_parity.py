@@ -21,6 +21,15 @@ from oracle import stokes as st
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 
+# One FP32 preconditioner application against the FP64 oracle: every output
+# entry depends on a chain of at most S = steps * sum_l (nu_pre,l + nu_post,l
+# + 2) FP32 stages (sweeps, transfers and casts), each adding a relative
+# error of a few u = 2^-24 that the contractive cycle does not amplify.  The
+# longest chain here is S = 68 (2 Uzawa steps, 3 levels, sweeps 2, 4, 8);
+# with 4 u per stage, 68 * 4 * 6e-8 = 1.6e-5 < 2e-5.  The cases measure
+# <= 4.6e-6.
+FP32_PRECOND_TOL = 2e-5
+
 
 def T(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(DEV)
@@ -126,7 +135,7 @@ def test_preconditioner_matches_oracle_vcycle(case, prec, fused):
         ox, oy, op = mg.precondition(levs, prm, rx, ry, rp)
     else:
         ox, oy, op = mg.uzawa_preconditioner(levs, prm, st.assemble(g, eb, ep), rx, ry, rp, steps)
-    tol = 1e-11 if prec == tph.FP64 else 5e-5
+    tol = 1e-11 if prec == tph.FP64 else FP32_PRECOND_TOL
     gx_, gy_, gp_ = N(zx), N(zy), N(zp)
     v_ref = np.concatenate([ox[1:ny + 1, 1:nx].ravel(), oy[1:ny, 1:nx + 1].ravel()])
     v_got = np.concatenate([gx_[1:ny + 1, 1:nx].ravel(), gy_[1:ny, 1:nx + 1].ravel()])
@@ -162,7 +171,7 @@ def test_large_coarsest_system_matches_oracle_vcycle(prec):
     ev = np.linalg.norm(v_got - v_ref) / np.linalg.norm(v_ref)
     epr = np.linalg.norm(zp[1:ny + 1, 1:nx + 1] - op[1:ny + 1, 1:nx + 1]) / np.linalg.norm(op[1:ny + 1, 1:nx + 1])
     print(f"[large coarsest] prec={prec} rel err v {ev:.2e} p {epr:.2e}", flush=True)
-    tol = 1e-11 if prec == tph.FP64 else 5e-5
+    tol = 1e-11 if prec == tph.FP64 else FP32_PRECOND_TOL
     assert ev < tol and epr < tol
 
 
@@ -196,7 +205,7 @@ def test_multisweep_plans_match_oracle_vcycle(case, prec, plan):
         ox, oy, op = mg.precondition(levs, prm, rx, ry, rp)
     else:
         ox, oy, op = mg.uzawa_preconditioner(levs, prm, st.assemble(g, eb, ep), rx, ry, rp, steps)
-    tol = 1e-11 if prec == tph.FP64 else 5e-5
+    tol = 1e-11 if prec == tph.FP64 else FP32_PRECOND_TOL
     gx_, gy_, gp_ = N(zx), N(zy), N(zp)
     v_ref = np.concatenate([ox[1:ny + 1, 1:nx].ravel(), oy[1:ny, 1:nx + 1].ravel()])
     v_got = np.concatenate([gx_[1:ny + 1, 1:nx].ravel(), gy_[1:ny, 1:nx + 1].ravel()])

@@ -2,7 +2,7 @@
 
 One preconditioner application with RAS (every level) and the Mixed
 configuration (Jacobi on the finest level, RAS below) against the oracle's
-V-cycle with the same SplitMix64 tile shifts: <= 1e-11 (FP64) / 5e-5 (FP32)
+V-cycle with the same SplitMix64 tile shifts: <= 1e-11 (FP64) / 2e-5 (FP32)
 relative L2, as for the other smoothers; ragged tiles, every tile side,
 shifts that split the domain edges, seeds across the 64-bit range.  Solves
 with the RAS smoothers reach the direct solution like the others (1e-7 /
@@ -16,6 +16,10 @@ import paper_2603_14040_amd as tph
 import workloads as wl
 from oracle import multigrid as mg
 from oracle import stokes as st
+
+# FP32 preconditioner tolerance: the stage-count bound of test_gpu_parity.py
+# (steps * sum_l (nu_pre,l + nu_post,l + 2) stages of a few u each)
+FP32_PRECOND_TOL = 2e-5
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -72,7 +76,7 @@ def test_ras_preconditioner_matches_oracle(case, prec, fused):
     ev = np.linalg.norm(v_got - v_ref) / np.linalg.norm(v_ref)
     epr = np.linalg.norm(gp_[1:ny + 1, 1:nx + 1] - op[1:ny + 1, 1:nx + 1]) / np.linalg.norm(op[1:ny + 1, 1:nx + 1])
     print(f"[ras] rel err v {ev:.2e} p {epr:.2e}", flush=True)
-    tol = 1e-11 if prec == tph.FP64 else 5e-5
+    tol = 1e-11 if prec == tph.FP64 else FP32_PRECOND_TOL
     assert ev < tol and epr < tol
     assert np.all(gx_[:, 0] == 0) and np.all(gx_[:, nx] == 0)
     assert np.array_equal(gx_[0, 1:nx], (1 if bc[2] == 0 else -1) * gx_[1, 1:nx])
