@@ -306,6 +306,30 @@ tph_status tph_precondition_apply(tph_solver* s, const double* rx, const double*
 tph_status tph_energy_residual(tph_solver* s, const double* vx, const double* vy,
                                const double* p, double* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * residual norms of (vx, vy, p) with no solver handle, no allocation, no
+ * memset and no host synchronisation.
+ *   out[0] = relative energy residual, as tph_energy_residual for a solver
+ *            holding (eta_b, eta_p, rho_b, gx, gy) and no extra force;
+ *   out[1] = plain relative l2 residual ||b - A x||_2 / ||b||_2, as
+ *            tph_info.res_l2.
+ * desc: only nx, ny (each in [2, 32768]; larger grids are rejected with
+ * TPH_ERR_INVALID), lx, ly and bc are read.  All arrays are DEVICE arrays of
+ * the current device in the dense (ny + 2) x (nx + 2) layout of the array
+ * convention above (ghost and wall entries of vx, vy are ignored; viscosity
+ * must be positive and finite, which is not checked here: a bad entry makes
+ * the result NaN).  out: a DEVICE array of 2 doubles, written by a kernel on
+ * hip_stream (a hipStream_t; NULL: the null stream); the call returns once
+ * the two kernels are enqueued.  Reduction partials live in a 64 KiB
+ * library-static device array that each device holds until the process
+ * ends; every call on a device shares it, so calls that overlap on one
+ * device (two streams, two threads) race and must be serialised by the
+ * caller.  Errors: TPH_ERR_INVALID (arguments), TPH_ERR_HIP (launch). */
+tph_status tph_energy_residual_noalloc(const tph_desc* desc, const double* eta_b, const double* eta_p,
+                                       const double* rho_b, double gx, double gy, const double* vx,
+                                       const double* vy, const double* p, double* out, void* hip_stream);
+
 /* Copy the viscosities of multigrid level l (0 = finest) into device arrays
  * of that level's shape ((ny_l + 2) x (nx_l + 2), FP64). */
 tph_status tph_level_viscosity(tph_solver* s, int32_t level, double* eta_b, double* eta_p);

@@ -560,6 +560,27 @@ def solve(eta_b, eta_p, rho_b, gx: float = 0.0, gy: float = -1.0, lx: float = 1.
         return s.solve()
 
 
+def energy_residual_noalloc(eta_b, eta_p, rho_b, vx, vy, p, out, gx: float = 0.0, gy: float = -1.0,
+                            lx: float = 1.0, ly: float = 1.0, bc: Sequence[int] = (FREE_SLIP,) * 4,
+                            stream: Optional[torch.cuda.Stream] = None) -> None:
+    """tph_energy_residual_noalloc: writes (relative energy residual, plain
+    relative l2 residual) of (vx, vy, p) into the 2-element float64 device
+    tensor ``out`` on ``stream`` (default: the current stream); no solver,
+    no allocation, no synchronisation."""
+    lib = _lib.load()
+    ny, nx = eta_b.shape[0] - 2, eta_b.shape[1] - 2
+    d = _desc(lib, nx, ny, lx=lx, ly=ly, bc=bc)
+    shape = (ny + 2, nx + 2)
+    if not (isinstance(out, torch.Tensor) and out.dtype == torch.float64 and out.is_cuda and out.is_contiguous()
+            and out.numel() >= 2):
+        raise ValueError("out must be a contiguous float64 CUDA tensor of at least 2 elements")
+    st = stream if stream is not None else torch.cuda.current_stream(eta_b.device)
+    _lib.check("tph_energy_residual_noalloc", lib.tph_energy_residual_noalloc(
+        ctypes.byref(d), _ptr(eta_b, shape, "eta_b"), _ptr(eta_p, shape, "eta_p"), _ptr(rho_b, shape, "rho_b"),
+        float(gx), float(gy), _ptr(vx, shape, "vx"), _ptr(vy, shape, "vy"), _ptr(p, shape, "p"),
+        ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(st.cuda_stream)))
+
+
 class StokesFunction(torch.autograd.Function):
     """(eta_b, eta_p, rho_b) -> (vx, vy, p) with a hand-written adjoint backward.
 

@@ -94,6 +94,7 @@ def load(path: str = LIB_PATH):
         "tph_precondition": (c_int32, [P, P, P, P, P, P, P]),
         "tph_precondition_apply": (c_int32, [P, P, P, P, P, P, P, P, P, P]),
         "tph_energy_residual": (c_int32, [P, P, P, P, POINTER(c_double)]),
+        "tph_energy_residual_noalloc": (c_int32, [POINTER(Desc), P, P, P, c_double, c_double, P, P, P, P, P]),
         "tph_level_viscosity": (c_int32, [P, c_int32, P, P]),
         "tph_level_shape": (c_int32, [P, c_int32, POINTER(c_int32), POINTER(c_int32)]),
         "tph_level_plan": (c_int32, [P, c_int32, POINTER(c_int32), POINTER(c_int32)]),

@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libtephra.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
 SOURCES = ["stencil.hip", "transfer.hip", "coarse.hip", "krylov.hip", "fused.hip", "msweep_f32.hip", "msweep_f64.hip",
-           "ras.hip", "markers.hip", "batch.hip", "devmem.cpp", "solver.cpp"]
+           "ras.hip", "markers.hip", "batch.hip", "noalloc.hip", "devmem.cpp", "solver.cpp"]
 
 ARCH = "gfx950"
 CFLAGS = [

@@ -91,3 +91,29 @@ def test_null_arguments_rejected(lib):
     assert lib.tph_solve(None, None, None, None, None) == -1
     lib.tph_destroy(None)
     assert lib.tph_version().decode().startswith("tephra")
+
+
+def test_noalloc_residual_validates_on_the_host(lib):
+    """tph_energy_residual_noalloc rejects bad arguments before any HIP call
+    (pointers below are never dereferenced)."""
+    fake = ctypes.c_void_p(256)
+    d = _lib.Desc()
+    lib.tph_desc_default(ctypes.byref(d), 8, 8)
+    args = [fake, fake, fake, 0.0, -1.0, fake, fake, fake, fake, None]
+    assert lib.tph_energy_residual_noalloc(None, *args) == -1
+    for nx, ny in ((40000, 8), (8, 32769), (1, 8), (8, 0)):
+        d.nx, d.ny = nx, ny
+        assert lib.tph_energy_residual_noalloc(ctypes.byref(d), *args) == -1
+        assert "[2, 32768]" in lib.tph_last_error().decode()
+    d.nx, d.ny = 8, 8
+    d.bc[1] = 5
+    assert lib.tph_energy_residual_noalloc(ctypes.byref(d), *args) == -1
+    assert "bc" in lib.tph_last_error().decode()
+    d.bc[1] = 0
+    d.lx = -1.0
+    assert lib.tph_energy_residual_noalloc(ctypes.byref(d), *args) == -1
+    d.lx = 1.0
+    bad = list(args)
+    bad[6] = None                       # vy
+    assert lib.tph_energy_residual_noalloc(ctypes.byref(d), *bad) == -1
+    assert "required" in lib.tph_last_error().decode()
