@@ -6,7 +6,10 @@ Everything here follows Ch. 4 "The Multigrid Method" and "Accelerators":
   fine node inside the physical domain (Sec. "Restriction and Prolongation
   Operators", Alg. "4-Color Parallel Restriction").  The weights are computed
   from node coordinates with the hat function (1 - |r_x|)(1 - |r_y|) of
-  Sec. "Interpolation Between Markers and Grid"; no weight table is typed in.
+  Sec. "Interpolation Between Markers and Grid"; no weight table is typed in,
+  so any coarsening factor works (the paper coarsens by 2.5 in its sinker
+  test; ``coarsen``, ``coarse_cells``); ``bisect_bound`` is the index search
+  of Alg. "Bisect Bound".
   The four-colour ordering of the algorithm only serves race-freedom of a
   parallel scatter; the sums it forms are the ones computed here.
 * prolongation: bilinear interpolation whose weights sum to one, from the
@@ -74,9 +77,34 @@ def hat(t: np.ndarray) -> np.ndarray:
     return np.maximum(0.0, 1.0 - np.abs(t))
 
 
-def coarsen(g: Grid) -> Grid:
-    assert g.nx % 2 == 0 and g.ny % 2 == 0
-    return Grid(g.nx // 2, g.ny // 2, g.lx, g.ly, g.bc)
+def coarse_cells(n: int, factor: float) -> int:
+    """Cells of the next coarser level along one axis: n / factor rounded to
+    the nearest integer (halves up), at least 2.  The paper coarsens its
+    501 x 601-node sinker grid by 2.5 per level (Ch. 4, robustness test);
+    with a factor that does not divide the cell count the coarse nodes fall
+    between fine nodes, which the coordinate-based transfers below handle."""
+    return max(2, int(np.floor(n / factor + 0.5)))
+
+
+def coarsen(g: Grid, factor: float = 2.0) -> Grid:
+    """The next coarser uniform grid on the same domain (factor 2: exact halving)."""
+    if factor == 2.0:
+        assert g.nx % 2 == 0 and g.ny % 2 == 0
+        return Grid(g.nx // 2, g.ny // 2, g.lx, g.ly, g.bc)
+    return Grid(coarse_cells(g.nx, factor), coarse_cells(g.ny, factor), g.lx, g.ly, g.bc)
+
+
+def bisect_bound(x: np.ndarray, xt: float) -> int:
+    """Smallest index i with x[i] >= xt in a non-decreasing array x (the last
+    index when none is), by halving [0, n - 1] (Alg. "Bisect Bound")."""
+    lo, hi = 0, len(x) - 1
+    while lo < hi:
+        mid = (lo + hi) // 2
+        if x[mid] < xt:
+            lo = mid + 1
+        else:
+            hi = mid
+    return lo
 
 
 # ---------------------------------------------------------------------------
@@ -84,15 +112,16 @@ def coarsen(g: Grid) -> Grid:
 # ---------------------------------------------------------------------------
 
 
-def restrict(gf: Grid, kind: str, u: np.ndarray) -> np.ndarray:
-    """Normalised bilinear restriction of a fine array to the coarse grid.
+def restrict(gf: Grid, kind: str, u: np.ndarray, gc: Optional[Grid] = None) -> np.ndarray:
+    """Normalised bilinear restriction of a fine array to the coarse grid
+    ``gc`` (default: the factor-2 coarsening of ``gf``).
 
     Every coarse node of the grid ``kind`` (entries [0, N+1]) receives
     sum w u / sum w over fine nodes inside the domain; coarse nodes with no
     contributing fine node are 0.  Values at fine walls enter with their
     stored value (zero for residuals).
     """
-    gc = coarsen(gf)
+    gc = coarsen(gf) if gc is None else gc
     (xf, inxf), (yf, inyf) = axis_coords(gf, kind)
     (xc, _), (yc, _) = axis_coords(gc, kind)
     wx = hat((xf[None, :] - xc[:, None]) / gc.dx) * inxf[None, :]
@@ -115,18 +144,19 @@ def prolong(gc: Grid, kind: str, uc: np.ndarray, gf: Grid) -> np.ndarray:
 
 
 def coarse_viscosity(gf: Grid, eta_b: np.ndarray, eta_p: np.ndarray,
-                     mean: str = "arithmetic"):
-    """Coarse-level viscosities by normalised bilinear restriction.
+                     mean: str = "arithmetic", gc: Optional[Grid] = None):
+    """Coarse-level viscosities by normalised bilinear restriction to ``gc``
+    (default: the factor-2 coarsening of ``gf``).
 
     ``mean='geometric'`` restricts log(eta) instead.  Unused entries are 1.
     """
-    gc = coarsen(gf)
+    gc = coarsen(gf) if gc is None else gc
     if mean == "geometric":
-        cb = np.exp(restrict(gf, "basic", np.log(eta_b)))
-        cp = np.exp(restrict(gf, "p", np.log(eta_p)))
+        cb = np.exp(restrict(gf, "basic", np.log(eta_b), gc))
+        cp = np.exp(restrict(gf, "p", np.log(eta_p), gc))
     else:
-        cb = restrict(gf, "basic", eta_b)
-        cp = restrict(gf, "p", eta_p)
+        cb = restrict(gf, "basic", eta_b, gc)
+        cp = restrict(gf, "p", eta_p, gc)
     ob = np.ones((gc.ny + 2, gc.nx + 2))
     op = np.ones((gc.ny + 2, gc.nx + 2))
     ob[: gc.ny + 1, : gc.nx + 1] = cb[: gc.ny + 1, : gc.nx + 1]
@@ -217,13 +247,14 @@ class MGParams:
     ras_tile: int = 32              # RAS tile side (T_I = T_J)
     ras_inner: int = 4              # RAS local sweeps per outer iteration
     seed: int = 0                   # RAS shift generator seed
+    coarsen: float = 2.0            # coarsening factor between levels (coarse_cells)
 
 
 def build_hierarchy(g: Grid, eta_b, eta_p, prm: MGParams) -> List[Level]:
     levs = [Level(g, eta_b, eta_p)]
     for _ in range(1, prm.levels):
-        gc = coarsen(levs[-1].g)
-        cb, cp = coarse_viscosity(levs[-1].g, levs[-1].eta_b, levs[-1].eta_p, prm.eta_mean)
+        gc = coarsen(levs[-1].g, prm.coarsen)
+        cb, cp = coarse_viscosity(levs[-1].g, levs[-1].eta_b, levs[-1].eta_p, prm.eta_mean, gc)
         levs.append(Level(gc, cb, cp))
     return levs
 
@@ -261,8 +292,8 @@ def vcycle(levs: List[Level], prm: MGParams, l: int, r: np.ndarray, cycle: int =
     rx[g.ny + 1, :] = 0.0
     ry[:, 0] = 0.0
     ry[:, g.nx + 1] = 0.0
-    rcx = restrict(g, "vx", rx)
-    rcy = restrict(g, "vy", ry)
+    rcx = restrict(g, "vx", rx, gc)
+    rcy = restrict(g, "vy", ry, gc)
     ec = vcycle(levs, prm, l + 1, vel_to_vec(gc, rcx, rcy), cycle)
     ecx, ecy = vec_to_vel(gc, ec)
     fx = prolong(gc, "vx", ecx, g)

@@ -283,3 +283,97 @@ def test_uzawa_steps_converge_to_exact_solution():
     nv = g.n_vx + g.n_vy
     got[nv:] -= got[nv:].mean()
     assert np.allclose(got, x, rtol=1e-8, atol=1e-8 * np.abs(x).max())
+
+
+# ---------------------------------------------------------------------------
+# coarsening by factors other than 2 (the paper's sinker test coarsens by 2.5)
+# ---------------------------------------------------------------------------
+def test_bisect_bound_is_the_smallest_index_not_below_the_target():
+    """Alg. "Bisect Bound" returns the smallest i with x[i] >= x_t; against a
+    linear scan on random sorted arrays with repeats and exact hits."""
+    rng = np.random.default_rng(17)
+    for n in (1, 2, 3, 7, 64, 101):
+        x = np.sort(rng.integers(0, 20, n).astype(np.float64))
+        for xt in list(x) + list(rng.uniform(-1.0, 21.0, 10)):
+            idx = [i for i in range(n) if x[i] >= xt]
+            want = idx[0] if idx else n - 1
+            assert mg.bisect_bound(x, xt) == want
+    assert mg.bisect_bound(np.linspace(0, 1, 11), 0.35) == int(np.searchsorted(np.linspace(0, 1, 11), 0.35))
+
+
+@pytest.mark.parametrize("n,f,want", [(500, 2.5, 200), (200, 2.5, 80), (96, 2.5, 38), (601, 2.5, 240),
+                                      (64, 2.0, 32), (10, 3.0, 3), (3, 2.5, 2)])
+def test_coarse_cell_counts(n, f, want):
+    assert mg.coarse_cells(n, f) == want
+
+
+@pytest.mark.parametrize("kind", ["vx", "vy", "p", "basic"])
+@pytest.mark.parametrize("shape,f", [((10, 15), 2.5), ((12, 9), 3.0), ((9, 7), 1.5), ((25, 20), 2.5)])
+def test_general_ratio_restriction_matches_four_colour_algorithm(kind, shape, f):
+    """Normalised bilinear restriction onto a coarse grid whose nodes fall
+    between fine nodes equals the literal scatter of Alg. "4-Color Parallel
+    Restriction" with bisection bounds."""
+    nx, ny = shape
+    g = st.Grid(nx, ny, 1.0, 1.5)
+    gc = mg.coarsen(g, f)
+    rng = np.random.default_rng(nx * 7 + ny)
+    u = rng.standard_normal((ny + 2, nx + 2))
+    (xf, inx), (yf, iny) = mg.axis_coords(g, kind)
+    (xc, _), (yc, _) = mg.axis_coords(gc, kind)
+    ref = _four_colour_restriction(xf[inx], yf[iny], u[np.ix_(iny, inx)], xc, yc)
+    got = mg.restrict(g, kind, u, gc)
+    (_, cinx), (_, ciny) = mg.axis_coords(gc, kind)
+    sel = np.ix_(ciny, cinx)
+    assert np.allclose(got[sel], ref[sel], rtol=1e-14, atol=1e-14)
+
+
+@pytest.mark.parametrize("kind", ["vx", "vy", "p", "basic"])
+def test_general_ratio_restriction_of_constant_is_constant(kind):
+    g = st.Grid(25, 30, 1.0, 1.2)
+    gc = mg.coarsen(g, 2.5)
+    out = mg.restrict(g, kind, np.full((32, 27), -1.75), gc)
+    (_, cinx), (_, ciny) = mg.axis_coords(gc, kind)
+    assert np.allclose(out[np.ix_(ciny, cinx)], -1.75, rtol=1e-15)
+
+
+@pytest.mark.parametrize("kind", ["vx", "vy", "p", "basic"])
+@pytest.mark.parametrize("f", [2.5, 3.0, 1.5])
+def test_general_ratio_prolongation_exact_for_bilinear_fields(kind, f):
+    gf = st.Grid(15, 12, 2.0, 1.0)
+    gc = mg.coarsen(gf, f)
+    (xc, _), (yc, _) = mg.axis_coords(gc, kind)
+    (xf, inx), (yf, iny) = mg.axis_coords(gf, kind)
+    fn = lambda x, y: 0.5 + 1.3 * x - 0.4 * y + 0.9 * x * y
+    uf = mg.prolong(gc, kind, fn(xc[None, :], yc[:, None]), gf)
+    sx = (xf >= xc[0]) & (xf <= xc[-1]) & inx
+    sy_ = (yf >= yc[0]) & (yf <= yc[-1]) & iny
+    sel = np.ix_(sy_, sx)
+    assert np.allclose(uf[sel], fn(xf[None, :], yf[:, None])[sel], rtol=1e-13, atol=1e-13)
+
+
+def test_vcycle_with_factor_2_5_coarsening_contracts():
+    """The sinker-test hierarchy shape: coarsening by 2.5 per level (50 x 60
+    -> 20 x 24 -> 8 x 10); the V-cycle as a stationary iteration on L
+    contracts, and does so at a rate close to the factor-2 hierarchy's."""
+    nx, ny = 50, 60
+    eb, ep, _ = wl.random_fields(nx, ny, seed=5, eta_decades=1.0)
+    g = st.Grid(nx, ny, 1.0, 1.2)
+    rates = {}
+    for f, levels in ((2.5, 3), (2.0, 2)):
+        prm = mg.MGParams(levels=levels, nu_pre=[2] * levels, nu_post=[2] * levels, omega=1.0, smoother="gs",
+                          coarsen=f)
+        levs = mg.build_hierarchy(g, eb, ep, prm)
+        if f == 2.5:
+            assert [(lv.g.nx, lv.g.ny) for lv in levs] == [(50, 60), (20, 24), (8, 10)]
+        L = levs[0].L
+        rng = np.random.default_rng(3)
+        x_true = rng.standard_normal(L.shape[0])
+        b = L @ x_true
+        x = np.zeros_like(b)
+        errs = []
+        for _ in range(8):
+            x = x + mg.vcycle(levs, prm, 0, b - L @ x)
+            errs.append(np.linalg.norm(x - x_true))
+        rates[f] = (errs[-1] / errs[2]) ** (1 / 5)
+    assert rates[2.5] < 0.5
+    assert rates[2.5] < 1.5 * rates[2.0] + 0.05
