@@ -4,15 +4,15 @@
 //
 // Marker -> grid without atomics: markers are binned by the node-grid cell
 // that contains them (the cell whose four corners are the nodes they weight)
-// with a stable radix sort of (cell, marker) pairs; each cell then sums, in
-// sorted order, the weighted values and weights its markers give to its four
-// corners, and each node adds the partial sums of its (up to) four cells in
-// a fixed order.  Every sum has one writer and a fixed order, so results are
-// bitwise reproducible.  Grid -> marker and RK4 are one thread per marker;
-// all four RK4 stages run in registers, the velocity grids are read through
-// the caches.
+// with a stable least-significant-digit radix sort of (cell, marker) pairs
+// written here (8-bit digits, one pass per digit; see k_digit_count); each
+// cell then sums, in sorted order, the weighted values and weights its
+// markers give to its four corners, and each node adds the partial sums of
+// its (up to) four cells in a fixed order.  Every sum has one writer and a
+// fixed order, so results are bitwise reproducible.  Grid -> marker and RK4
+// are one thread per marker; all four RK4 stages run in registers, the
+// velocity grids are read through the caches.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <cmath>
 #include <cstdint>
@@ -29,8 +29,8 @@ struct tph_markers {
     hipStream_t st = nullptr;
     uint32_t* keys[2] = {nullptr, nullptr};
     int32_t* vals[2] = {nullptr, nullptr};
-    void* temp = nullptr;
-    size_t temp_bytes = 0;
+    int32_t* hist = nullptr;       // radix sort: per-(digit, tile) counts, then their scan
+    int32_t* chunk = nullptr;      // radix sort: scan of the per-chunk totals of hist
     int32_t* cstart = nullptr;     // per cell: first sorted position
     int32_t* cend = nullptr;       // one past the last
     double* partial = nullptr;     // per cell: 4 corners x (sum w phi, sum w)
@@ -87,6 +87,163 @@ __global__ __launch_bounds__(256) void k_bin(NodeGrid q, int nx, int ny, int n, 
     if (m >= n) return;
     keys[m] = cell_key(q, nx, ny, xm[m], ym[m]);
     vals[m] = m;
+}
+
+// ---------------------------------------------------------------------------
+// Stable radix sort of (key, marker) pairs, 8-bit digits, least significant
+// first.  A tile of kTile = 4096 pairs goes to one workgroup of 4 waves; wave
+// w owns pairs [w * 1024, (w + 1) * 1024) of its tile and walks them in 16
+// rounds of 64 consecutive pairs.  In a round, the lanes holding the same
+// digit find each other with 8 ballots (one per digit bit); a lane's rank
+// among them is the number of such lanes below it, added to the wave's
+// running count of that digit (kept in LDS, bumped by the highest lane of
+// each group).  Ranks therefore follow the pair order, which makes the sort
+// stable, and no atomic operation is involved.
+//   k_digit_count:  per tile, the count of each digit -> hist[d * ntiles + t]
+//   k_scan_chunks / k_scan_top: exclusive scan of hist in that (digit-major)
+//                   order, as per-chunk scans plus a scan of the chunk totals
+//   k_digit_scatter: ranks again, then writes each pair to
+//                   scan[d * ntiles + t] + (its rank in the tile)
+// ---------------------------------------------------------------------------
+constexpr int kWaves = 4;
+constexpr int kRounds = 16;
+constexpr int kTile = kWaves * kRounds * 64;     // 4096 pairs per workgroup
+constexpr int kChunk = 4096;                     // scan chunk (entries)
+
+// Counts of the 256 digits over this wave's 1024 pairs of tile t, and (when
+// rank is non-null) each pair's rank among the wave's pairs of its digit.
+__device__ __forceinline__ void wave_rank(const uint32_t* __restrict__ keys, int n, int t, int shift,
+                                          int* __restrict__ wcnt, uint32_t* dig, int* rank) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t below = lane ? ((1ull << lane) - 1ull) : 0ull;
+#pragma unroll
+    for (int k = 0; k < kRounds; ++k) {
+        const long long m = (long long)t * kTile + (long long)w * (kRounds * 64) + k * 64 + lane;
+        const bool valid = m < n;
+        const uint32_t d = valid ? (keys[m] >> shift) & 255u : 0u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t bal = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? bal : ~bal;
+        }
+        // every lane of a group reads the count before its highest lane advances it: the read
+        // precedes the write in program order, and a wave's LDS operations complete in order
+        const int base = valid ? wcnt[d] : 0;
+        if (dig) dig[k] = d;
+        if (rank) rank[k] = base + __popcll(peers & below);
+        if (valid && 63 - __clzll(peers) == lane) wcnt[d] = base + __popcll(peers);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_digit_count(const uint32_t* __restrict__ keys, int n, int ntiles, int shift,
+                                                     int32_t* __restrict__ hist) {
+    __shared__ int cnt[kWaves][256];
+    const int w = threadIdx.x >> 6;
+    for (int d = threadIdx.x; d < kWaves * 256; d += blockDim.x) (&cnt[0][0])[d] = 0;
+    __syncthreads();
+    wave_rank(keys, n, blockIdx.x, shift, cnt[w], nullptr, nullptr);
+    __syncthreads();
+    const int d = threadIdx.x;                       // 256 threads: one digit each
+    int tot = 0;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) tot += cnt[q][d];
+    hist[(size_t)d * ntiles + blockIdx.x] = tot;
+}
+
+// exclusive scan of each chunk of kChunk entries in place; chunk totals to sums
+__global__ __launch_bounds__(256) void k_scan_chunks(int32_t* __restrict__ a, long long len,
+                                                     int32_t* __restrict__ sums) {
+    __shared__ int part[256];
+    const long long base = (long long)blockIdx.x * kChunk + threadIdx.x * (kChunk / 256);
+    int v[kChunk / 256];
+    int s = 0;
+#pragma unroll
+    for (int q = 0; q < kChunk / 256; ++q) {
+        v[q] = base + q < len ? a[base + q] : 0;
+        s += v[q];
+    }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    // inclusive Hillis-Steele scan of the 256 thread totals
+    for (int off = 1; off < 256; off <<= 1) {
+        const int add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += add;
+        __syncthreads();
+    }
+    int run = part[threadIdx.x] - s;                 // exclusive prefix of this thread
+#pragma unroll
+    for (int q = 0; q < kChunk / 256; ++q) {
+        if (base + q < len) a[base + q] = run;
+        run += v[q];
+    }
+    if (threadIdx.x == 255) sums[blockIdx.x] = part[255];
+}
+
+// exclusive scan of the chunk totals (at most kChunk of them), one workgroup
+__global__ __launch_bounds__(256) void k_scan_top(int32_t* __restrict__ sums, int nchunks) {
+    __shared__ int part[256];
+    const int per = kChunk / 256;
+    int v[kChunk / 256];
+    int s = 0;
+#pragma unroll
+    for (int q = 0; q < per; ++q) {
+        const int i = threadIdx.x * per + q;
+        v[q] = i < nchunks ? sums[i] : 0;
+        s += v[q];
+    }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += add;
+        __syncthreads();
+    }
+    int run = part[threadIdx.x] - s;
+#pragma unroll
+    for (int q = 0; q < per; ++q) {
+        const int i = threadIdx.x * per + q;
+        if (i < nchunks) sums[i] = run;
+        run += v[q];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_digit_scatter(const uint32_t* __restrict__ kin,
+                                                       const int32_t* __restrict__ vin, int n, int ntiles, int shift,
+                                                       const int32_t* __restrict__ scan,
+                                                       const int32_t* __restrict__ chunk,
+                                                       uint32_t* __restrict__ kout, int32_t* __restrict__ vout) {
+    __shared__ int cnt[kWaves][256];
+    __shared__ int tile_base[kWaves][256];          // global start of each (wave, digit) run
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int d = threadIdx.x; d < kWaves * 256; d += blockDim.x) (&cnt[0][0])[d] = 0;
+    __syncthreads();
+    uint32_t dig[kRounds];
+    int rank[kRounds];
+    wave_rank(kin, n, blockIdx.x, shift, cnt[w], dig, rank);
+    __syncthreads();
+    {
+        const int d = threadIdx.x;
+        const long long e = (long long)d * ntiles + blockIdx.x;
+        int off = scan[e] + chunk[e / kChunk];
+#pragma unroll
+        for (int q = 0; q < kWaves; ++q) {
+            tile_base[q][d] = off;
+            off += cnt[q][d];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kRounds; ++k) {
+        const long long m = (long long)blockIdx.x * kTile + (long long)w * (kRounds * 64) + k * 64 + lane;
+        if (m < n) {
+            const int pos = tile_base[w][dig[k]] + rank[k];
+            kout[pos] = kin[m];
+            vout[pos] = vin[m];
+        }
+    }
 }
 
 __global__ __launch_bounds__(256) void k_ranges(int n, const uint32_t* __restrict__ keys, int32_t* __restrict__ cstart,
@@ -205,6 +362,8 @@ inline unsigned blocks(long long n) { return (unsigned)((n + 255) / 256); }
         }                                                                                            \
     } while (0)
 
+constexpr int kMaxMarkers = 1 << 28;   // keeps the scan of the digit counts within one top-level workgroup
+
 int key_bits(const tph_markers* h) {
     const uint64_t ncell = (uint64_t)(h->nx + 1) * (uint64_t)(h->ny + 1);
     int b = 1;
@@ -225,8 +384,9 @@ tph_status tph_markers_create(int32_t nx, int32_t ny, double lx, double ly, int3
     }
     *out = nullptr;
     if (nx < 1 || ny < 1 || (int64_t)(nx + 2) * (ny + 2) > (int64_t)1 << 30 || !(lx > 0) || !(ly > 0) ||
-        !std::isfinite(lx) || !std::isfinite(ly) || capacity < 1) {
-        tph_internal_set_error_m("need nx, ny >= 1 (grid at most 2^30 entries), positive finite lx, ly and capacity >= 1");
+        !std::isfinite(lx) || !std::isfinite(ly) || capacity < 1 || capacity > kMaxMarkers) {
+        tph_internal_set_error_m("need nx, ny >= 1 (grid at most 2^30 entries), positive finite lx, ly and capacity "
+                                 "in [1, 2^28]");
         return TPH_ERR_INVALID;
     }
     tph_markers* h = new tph_markers();
@@ -252,13 +412,9 @@ tph_status tph_markers_create(int32_t nx, int32_t ny, double lx, double ly, int3
     get((void**)&h->cstart, ncell * sizeof(int32_t));
     get((void**)&h->cend, ncell * sizeof(int32_t));
     get((void**)&h->partial, ncell * 8 * sizeof(double));
-    if (e == hipSuccess) {
-        hipcub::DoubleBuffer<uint32_t> kb(h->keys[0], h->keys[1]);
-        hipcub::DoubleBuffer<int32_t> vb(h->vals[0], h->vals[1]);
-        e = hipcub::DeviceRadixSort::SortPairs(nullptr, h->temp_bytes, kb, vb, capacity, 0, 32, h->st);
-        if (e != hipSuccess) what = std::string("sort workspace query failed: ") + hipGetErrorString(e);
-        get(&h->temp, h->temp_bytes > 0 ? h->temp_bytes : 1);
-    }
+    const long long ntiles = (capacity + kTile - 1) / kTile;
+    get((void**)&h->hist, (size_t)ntiles * 256 * sizeof(int32_t));
+    get((void**)&h->chunk, (size_t)((ntiles * 256 + kChunk - 1) / kChunk) * sizeof(int32_t));
     if (e != hipSuccess) {
         (void)hipGetLastError();
         tph_markers_destroy(h);
@@ -303,11 +459,20 @@ tph_status tph_markers_bin(tph_markers* h, int32_t kind, int32_t n, const double
     hipLaunchKernelGGL(k_bin, dim3(blocks(n)), dim3(256), 0, h->st, q, h->nx, h->ny, n, xm, ym, h->keys[0],
                        h->vals[0]);
     M_HIP(hipGetLastError());
-    hipcub::DoubleBuffer<uint32_t> kb(h->keys[0], h->keys[1]);
-    hipcub::DoubleBuffer<int32_t> vb(h->vals[0], h->vals[1]);
-    size_t tb = h->temp_bytes;
-    M_HIP(hipcub::DeviceRadixSort::SortPairs(h->temp, tb, kb, vb, n, 0, key_bits(h), h->st));
-    h->sorted = kb.selector;
+    const int ntiles = (n + kTile - 1) / kTile;
+    const long long len = (long long)ntiles * 256;
+    const int nchunks = (int)((len + kChunk - 1) / kChunk);
+    int cur = 0;
+    for (int shift = 0; shift < key_bits(h); shift += 8) {
+        hipLaunchKernelGGL(k_digit_count, dim3(ntiles), dim3(256), 0, h->st, h->keys[cur], n, ntiles, shift, h->hist);
+        hipLaunchKernelGGL(k_scan_chunks, dim3(nchunks), dim3(256), 0, h->st, h->hist, len, h->chunk);
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, h->st, h->chunk, nchunks);
+        hipLaunchKernelGGL(k_digit_scatter, dim3(ntiles), dim3(256), 0, h->st, h->keys[cur], h->vals[cur], n, ntiles,
+                           shift, h->hist, h->chunk, h->keys[1 - cur], h->vals[1 - cur]);
+        M_HIP(hipGetLastError());
+        cur = 1 - cur;
+    }
+    h->sorted = cur;
     hipLaunchKernelGGL(k_ranges, dim3(blocks(n)), dim3(256), 0, h->st, n, h->keys[h->sorted], h->cstart, h->cend);
     M_HIP(hipGetLastError());
     return TPH_OK;
