@@ -600,6 +600,18 @@ tph_status batch_create_impl(tph_batch* b, int count, const tph_desc* descs) {
         P.prow = std::max(P.nchunk, P.ncell);
         prow_off[p] = prow_total;
         prow_total += (size_t)P.prow * (tph::kMaxRestart + 2);
+    }
+    // work lists in longest-processing-time order: problems by decreasing cell
+    // count (ties by index), so every launch starts the items of the largest
+    // problems first and the small ones fill in behind them
+    std::vector<int> lpt(count);
+    for (int p = 0; p < count; ++p) lpt[p] = p;
+    std::stable_sort(lpt.begin(), lpt.end(), [&](int a, int c) {
+        return (long long)pr[a].g.nx * pr[a].g.ny > (long long)pr[c].g.nx * pr[c].g.ny;
+    });
+    for (const int p : lpt) {
+        const TphSolverView v = tph_internal_view(b->s[p]);
+        const BProb& P = pr[p];
         for (int d = 0; d < v.lc; ++d) {
             const Geom& g = v.g[d];
             const int th = b->mixed() ? tile_h<float>() : tile_h<double>();
