@@ -113,11 +113,13 @@ enum { TPH_MEAN_ARITHMETIC = 0, TPH_MEAN_GEOMETRIC = 1 };
 enum { TPH_ACCEL_FGMRES = 0, TPH_ACCEL_GCR = 1, TPH_ACCEL_ANDERSON = 2 };
 
 typedef struct tph_desc {
-    int32_t nx, ny;        /* cells; each must be divisible by 2^(levels-1)  */
+    int32_t nx, ny;        /* cells; each must be divisible by 2^(levels-1)
+                              when coarsen = 2                                 */
     double lx, ly;         /* domain size, dx = lx / nx, dy = ly / ny        */
     int32_t bc[4];         /* TPH_FREE_SLIP / TPH_NO_SLIP per wall           */
     int32_t precision;     /* TPH_FP64 or TPH_MIXED                          */
-    int32_t levels;        /* multigrid levels; 0 = automatic (coarsest side in [8, 16)) */
+    int32_t levels;        /* multigrid levels; 0 = automatic (coarsest side in [8, 16)
+                              for coarsen = 2) */
     int32_t smoother;      /* TPH_SMOOTH_*                                    */
     int32_t nu_pre;        /* pre-smoothing sweeps on the finest level       */
     int32_t nu_post;       /* post-smoothing sweeps on the finest level      */
@@ -130,7 +132,7 @@ typedef struct tph_desc {
                               (1..64), Anderson depth (0..64)                 */
     int32_t max_iters;     /* total iterations (applications of the Uzawa
                               preconditioner)                                 */
-    int32_t uzawa_steps;   /* Uzawa sweeps per preconditioner application (1..8):
+    int32_t uzawa_steps;   /* Uzawa sweeps per preconditioner application (1..16):
                               z <- z + M^{-1}(r - A z), the fixed-point map of the
                               splitting A = M - N applied this many times         */
     int32_t fused;         /* 1: LDS-tiled fused smoother / residual-restriction
@@ -167,6 +169,16 @@ typedef struct tph_desc {
                               into a library stream joined by events) ran the
                               benchmark solve no faster than direct launches */
     int32_t pad_;          /* must be zero                                    */
+    double coarsen;        /* coarsening factor between levels: 2 (exact halving;
+                              sides divisible by 2^(levels-1)), or any value in
+                              [1.25, 4] with fused = 0: level l+1 has
+                              round(n_l / coarsen) cells per side (halves up, at
+                              least 2), its nodes fall between fine nodes, and the
+                              transfers use the normalised bilinear weights of
+                              node coordinates with the fine index bounds of
+                              Alg. "Bisect Bound" (the paper's sinker test
+                              coarsens by 2.5); levels = 0 then coarsens while
+                              both sides stay >= 8                             */
 } tph_desc;
 
 typedef struct tph_info {
@@ -375,8 +387,12 @@ enum {
                                 normalise the new direction w against i = restart / 2 earlier
                                 ones and update r (FP64, every entry of the vectors; x is
                                 updated once per cycle) */
-    TPH_KERNEL_AA_MIX = 6    /* Anderson mixing x = sum_i alpha_i (x_i + beta f_i) over
+    TPH_KERNEL_AA_MIX = 6,   /* Anderson mixing x = sum_i alpha_i (x_i + beta f_i) over
                                 restart + 1 stored pairs (FP64, every entry of the vectors) */
+    TPH_KERNEL_LINK = 7      /* one Uzawa link pass (Sec. "Uzawa Iteration as a Fixed Point
+                                Method"): z += e with the pressure update, then the next step's
+                                FP64 residual or the Krylov apply; live timing only
+                                (tph_kernel_timing_target), not tph_time_kernel */
 };
 
 /* Measurement hook: run `reps` back-to-back launches of one hot-path kernel
@@ -405,6 +421,15 @@ tph_status tph_time_kernel(tph_solver* s, int32_t kind, int32_t reps, double* ms
  * quarter of two fields; plus 0.5 when the pass also restricts its residual),
  * then resets the counters. */
 tph_status tph_kernel_timing(tph_solver* s, int32_t enable);
+/* Kernel class that tph_kernel_timing times: TPH_KERNEL_SMOOTH (default; the
+ * finest-level smoothing launches, bytes as above) or TPH_KERNEL_LINK (every
+ * Uzawa link pass on the finest level; bytes per cell: e 2 words of the
+ * V-cycle type, eta_b, eta_p and the pressure source 3 FP64 words, z_old 3
+ * FP64 words after the first step, z written 3 FP64 words, plus r read 3
+ * FP64 words and the next right-hand side written 2 V-cycle words + 1 FP64
+ * word for a link into the next step, or w written 3 FP64 words for the
+ * link into the Krylov apply).  Resets the sampling counter. */
+tph_status tph_kernel_timing_target(tph_solver* s, int32_t kind);
 tph_status tph_kernel_timing_read(tph_solver* s, int32_t* launches, double* total_ms, double* total_bytes,
                                   int32_t* dropped);
 

@@ -128,7 +128,7 @@ class Solver:
                  max_iters: int = 500, uzawa_steps: int = 2, fused: bool = True,
                  msweep: int = -1, tile_shape: int = -1, coarse_level: int = -1,
                  accel="fgmres", beta: float = 1.0, ras_tile: int = 32, ras_inner: int = 4, seed: int = 0,
-                 graph: bool = False,
+                 graph: bool = False, coarsen: float = 2.0,
                  device: Optional[torch.device] = None,
                  stream: Optional[torch.cuda.Stream] = None):
         lib = _lib.load()
@@ -137,7 +137,8 @@ class Solver:
                   nu_pre=nu_pre, nu_post=nu_post, nu_growth=nu_growth, omega=omega, alpha=alpha,
                   eta_mean=eta_mean, rtol=rtol, restart=restart, max_iters=max_iters, uzawa_steps=uzawa_steps,
                   fused=fused, msweep=msweep, tile_shape=tile_shape, coarse_level=coarse_level,
-                  accel=accel, beta=beta, ras_tile=ras_tile, ras_inner=ras_inner, seed=seed, graph=graph)
+                  accel=accel, beta=beta, ras_tile=ras_tile, ras_inner=ras_inner, seed=seed, graph=graph,
+                  coarsen=coarsen)
         self.desc = d
         self.nx, self.ny = nx, ny
         self.shape = (ny + 2, nx + 2)
@@ -335,8 +336,12 @@ class Solver:
                                                                 ctypes.byref(by)))
         return ms.value, by.value
 
-    def kernel_timing(self, stride: int = 1):
-        """Time every stride-th finest-level smoothing launch of later solves (0: off)."""
+    def kernel_timing(self, stride: int = 1, target: Optional[int] = None):
+        """Time every stride-th launch of the target kernel class of later
+        solves (0: off): the finest-level smoother (default) or, with
+        target=_lib.KERNEL_LINK, the Uzawa link passes."""
+        if target is not None:
+            _lib.check("tph_kernel_timing_target", self._lib.tph_kernel_timing_target(self._h, int(target)))
         _lib.check("tph_kernel_timing", self._lib.tph_kernel_timing(self._h, int(stride)))
 
     def kernel_timing_read(self):
@@ -359,7 +364,7 @@ class Solver:
 def _desc(lib, nx, ny, lx=1.0, ly=1.0, bc=(FREE_SLIP,) * 4, precision=MIXED, levels=0, smoother=SMOOTH_GS,
           nu_pre=2, nu_post=2, nu_growth=1.0, omega=1.0, alpha=1.0, eta_mean=MEAN_ARITHMETIC, rtol=1e-8,
           restart=20, max_iters=500, uzawa_steps=2, fused=True, msweep=-1, tile_shape=-1, coarse_level=-1,
-          accel="fgmres", beta=1.0, ras_tile=32, ras_inner=4, seed=0, graph=False):
+          accel="fgmres", beta=1.0, ras_tile=32, ras_inner=4, seed=0, graph=False, coarsen=2.0):
     d = _lib.Desc()
     lib.tph_desc_default(ctypes.byref(d), nx, ny)
     d.lx, d.ly = float(lx), float(ly)
@@ -374,6 +379,7 @@ def _desc(lib, nx, ny, lx=1.0, ly=1.0, bc=(FREE_SLIP,) * 4, precision=MIXED, lev
     d.beta = float(beta)
     d.ras_tile, d.ras_inner, d.seed = int(ras_tile), int(ras_inner), int(seed)
     d.graph = int(bool(graph))
+    d.coarsen = float(coarsen)
     return d
 
 

@@ -26,7 +26,7 @@ NODES_BASIC, NODES_CELL, NODES_VX, NODES_VY = 0, 1, 2, 3
 NODE_KINDS = {"basic": NODES_BASIC, "cell": NODES_CELL, "vx": NODES_VX, "vy": NODES_VY}
 ACCEL_NAMES = {"fgmres": ACCEL_FGMRES, "gcr": ACCEL_GCR, "anderson": ACCEL_ANDERSON}
 KERNEL_SMOOTH, KERNEL_APPLY, KERNEL_RESIDUAL, KERNEL_RESTRICT, KERNEL_PROLONG = 0, 1, 2, 3, 4
-KERNEL_GCR_STEP, KERNEL_AA_MIX = 5, 6
+KERNEL_GCR_STEP, KERNEL_AA_MIX, KERNEL_LINK = 5, 6, 7
 
 
 class Desc(ctypes.Structure):
@@ -38,7 +38,7 @@ class Desc(ctypes.Structure):
                 ("max_iters", c_int32), ("uzawa_steps", c_int32), ("fused", c_int32),
                 ("msweep", c_int32), ("tile_shape", c_int32), ("coarse_level", c_int32),
                 ("accel", c_int32), ("beta", c_double), ("ras_tile", c_int32), ("ras_inner", c_int32),
-                ("seed", c_uint64), ("graph", c_int32), ("pad_", c_int32)]
+                ("seed", c_uint64), ("graph", c_int32), ("pad_", c_int32), ("coarsen", c_double)]
 
 
 class Info(ctypes.Structure):
@@ -102,6 +102,7 @@ def load(path: str = LIB_PATH):
         "tph_coeff_gradient": (c_int32, [P, P, P, P, P, P, P, P, P, P]),
         "tph_time_kernel": (c_int32, [P, c_int32, c_int32, POINTER(c_double), POINTER(c_double)]),
         "tph_kernel_timing": (c_int32, [P, c_int32]),
+        "tph_kernel_timing_target": (c_int32, [P, c_int32]),
         "tph_kernel_timing_read": (c_int32, [P, POINTER(c_int32), POINTER(c_double), POINTER(c_double),
                                              POINTER(c_int32)]),
         "tph_destroy": (None, [P]),

@@ -48,7 +48,7 @@ struct LinkArgs;
 // uzawa_link_cell
 template <typename T>
 hipError_t launch_uzawa_link(const Geom& g, const LinkArgs<T>& a, int mode, const double* eb, const double* ep,
-                             hipStream_t st);
+                             hipStream_t st, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 template <typename T>
 hipError_t launch_precond_out(const Geom& g, const T* ex, const T* ey, Vec3 v, const double* ep,
                               bool energy, double alpha, Vec3 z, hipStream_t st, bool accumulate = false);

@@ -122,8 +122,10 @@ struct tph_solver {
     double t_setup_ms = 0;
     long long reorth_count = 0;  // second Gram-Schmidt passes taken (diagnostic)
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    // optional event timing of the finest-level smoother inside solves
+    // optional event timing of one kernel class inside solves (the finest-level
+    // smoother or the Uzawa link, tph_kernel_timing_target)
     bool ktime = false;
+    int ktarget = TPH_KERNEL_SMOOTH;
     int kstride = 1;              // time every kstride-th launch
     long long kcount = 0;
     std::vector<hipEvent_t> kev;  // 2 per recorded launch
@@ -166,9 +168,9 @@ struct KTime {
     hipEvent_t t0 = nullptr, t1 = nullptr;
 };
 
-KTime ktic(tph_solver* s, int l) {
+KTime ktic(tph_solver* s, int l, int kind = TPH_KERNEL_SMOOTH) {
     KTime k;
-    if (!s->ktime || l != 0) return k;
+    if (!s->ktime || l != 0 || kind != s->ktarget) return k;
     if (s->kcount++ % s->kstride != 0) return k;    // every kstride-th finest-level launch
     if (s->kev_used + 2 > (int)s->kev.size()) {
         ++s->kdropped;
@@ -183,6 +185,18 @@ void ktoc(tph_solver* s, const KTime& k, double words, size_t wbytes) {
     if (!k.t0) return;
     s->kev_used += 2;
     s->kbytes += words * (double)s->lev[0].g.nx * (double)s->lev[0].g.ny * (double)wbytes;
+}
+
+// Algorithmic bytes per cell of one Uzawa link pass (uzawa_link_cell): the
+// correction e (2 words of the V-cycle type), the pressure source, eta_b and
+// eta_p, z_old (3 FP64 words) after the first step; writes z (3 FP64); then
+// kLinkNext reads r (3 FP64) and writes the next right-hand side (2 words of
+// the V-cycle type) and its pressure part, kLinkApply writes w (3 FP64).
+double link_bytes_per_cell(int mode, bool acc, size_t tbytes) {
+    double b = 2.0 * tbytes + 8.0 * (1 + 2) + (acc ? 24.0 : 0.0) + 24.0;
+    if (mode == kLinkNext) b += 24.0 + 2.0 * tbytes + 8.0;
+    else if (mode == kLinkApply) b += 24.0;
+    return b;
 }
 
 tph_status dev_alloc(tph_solver* s, void** p, size_t bytes) {
@@ -207,6 +221,13 @@ tph_status alloc_field(tph_solver* s, const Geom& g, size_t bytes_per, void** ba
 int level_sweeps(int nu, double growth, int l) {
     const double v = std::ceil(nu * std::pow(growth, l) - 1e-9);
     return (int)std::min(v, 256.0);
+}
+
+// cells of the next coarser level along one axis for coarsening factor f: n / f
+// rounded to the nearest integer (halves up), at least 2
+int coarse_cells(int n, double f) {
+    const int c = (int)std::floor(n / f + 0.5);
+    return c < 2 ? 2 : c;
 }
 
 tph_status validate_desc(const tph_desc* d, int* nlev_out) {
@@ -247,25 +268,51 @@ tph_status validate_desc(const tph_desc* d, int* nlev_out) {
         return TPH_ERR_INVALID;
     }
     if (d->max_iters < 1) { set_error("max_iters must be >= 1"); return TPH_ERR_INVALID; }
-    if (d->uzawa_steps < 1 || d->uzawa_steps > 8) { set_error("uzawa_steps must be in [1, 8]"); return TPH_ERR_INVALID; }
+    if (d->uzawa_steps < 1 || d->uzawa_steps > 16) { set_error("uzawa_steps must be in [1, 16]"); return TPH_ERR_INVALID; }
     if (d->fused != 0 && d->fused != 1) { set_error("fused must be 0 or 1"); return TPH_ERR_INVALID; }
     if (d->msweep < -1 || d->tile_shape < -1) { set_error("msweep and tile_shape must be -1 or a level mask"); return TPH_ERR_INVALID; }
     if (d->graph != 0 && d->graph != 1) { set_error("graph must be 0 or 1"); return TPH_ERR_INVALID; }
     if (d->coarse_level < -2) { set_error("coarse_level must be -2, -1 or a level index"); return TPH_ERR_INVALID; }
+    if (!(d->coarsen == 2.0 || (d->coarsen >= 1.25 && d->coarsen <= 4.0))) {
+        set_error("coarsen must be 2 or in [1.25, 4]");
+        return TPH_ERR_INVALID;
+    }
+    const bool general = d->coarsen != 2.0;
+    if (general && d->fused) {
+        set_error("coarsening factors other than 2 run with fused = 0 (the LDS-tiled kernels assume halving)");
+        return TPH_ERR_INVALID;
+    }
     int nlev = d->levels;
     if (nlev == 0) {
         nlev = 1;
         int nx = d->nx, ny = d->ny;
-        while (nx % 2 == 0 && ny % 2 == 0 && nx / 2 >= 8 && ny / 2 >= 8 && nlev < kMaxLevels) {
-            nx /= 2;
-            ny /= 2;
-            ++nlev;
+        if (general) {
+            while (coarse_cells(nx, d->coarsen) >= 8 && coarse_cells(ny, d->coarsen) >= 8 && nlev < kMaxLevels) {
+                nx = coarse_cells(nx, d->coarsen);
+                ny = coarse_cells(ny, d->coarsen);
+                ++nlev;
+            }
+        } else {
+            while (nx % 2 == 0 && ny % 2 == 0 && nx / 2 >= 8 && ny / 2 >= 8 && nlev < kMaxLevels) {
+                nx /= 2;
+                ny /= 2;
+                ++nlev;
+            }
         }
     }
     if (nlev < 1 || nlev > kMaxLevels) { set_error("levels must be in [1, 16]"); return TPH_ERR_INVALID; }
-    const int f = 1 << (nlev - 1);
-    if (d->nx % f || d->ny % f) { set_error("nx and ny must be divisible by 2^(levels-1)"); return TPH_ERR_INVALID; }
-    const int cx = d->nx / f, cy = d->ny / f;
+    int cx = d->nx, cy = d->ny;
+    if (general) {
+        for (int l = 1; l < nlev; ++l) {
+            cx = coarse_cells(cx, d->coarsen);
+            cy = coarse_cells(cy, d->coarsen);
+        }
+    } else {
+        const int f = 1 << (nlev - 1);
+        if (d->nx % f || d->ny % f) { set_error("nx and ny must be divisible by 2^(levels-1)"); return TPH_ERR_INVALID; }
+        cx = d->nx / f;
+        cy = d->ny / f;
+    }
     if (cx < 2 || cy < 2) { set_error("coarsest level must have at least 2 x 2 cells"); return TPH_ERR_INVALID; }
     const int nc = cy * (cx - 1) + (cy - 1) * cx;
     if (nc > 4096) { set_error("coarsest level too large for the dense FP64 solve (max 4096 unknowns)"); return TPH_ERR_INVALID; }
@@ -585,7 +632,9 @@ tph_status precondition_t(tph_solver* s, double* vraw, double* zraw, bool energy
             a.wout = wraw ? vec3(s, wraw) : Vec3{nullptr, 0};
             a.w_scaled = energy ? 1 : 0;
             const int mode = q < S - 1 ? kLinkNext : (wraw ? kLinkApply : kLinkStore);
-            TPH_HIP(launch_uzawa_link<T>(L.g, a, mode, L.eb64, L.ep64, s->st));
+            const KTime tk = ktic(s, 0, TPH_KERNEL_LINK);
+            TPH_HIP(launch_uzawa_link<T>(L.g, a, mode, L.eb64, L.ep64, s->st, tk.t0, tk.t1));
+            ktoc(s, tk, link_bytes_per_cell(mode, a.acc != 0, sizeof(T)), 1);
         }
         return TPH_OK;
     }
@@ -917,14 +966,20 @@ tph_status fgmres(tph_solver* s, double* braw, tph_info* info) {
 // h_j C e_j) / nu_i), so x += sum_i alpha_i z'_i is applied once per cycle as
 // x += Z (C alpha): the same iterate, without rewriting z and x every step.  The Gram-Schmidt projection against the earlier w's is one classical
 // pass whose coefficients come from one multi-dot, with the norm of the
-// projected vector from Pythagoras; when that cancels (|w_perp|^2 < |w|^2 / 2)
-// the projection is carried out explicitly and repeated once, as for the
-// FGMRES basis.  Normalising the pair, x += alpha z and r -= alpha w are one
+// projected vector from Pythagoras.  Pythagoras' |w_perp|^2 = |w|^2 - |h|^2
+// is off by about eps |w|^2, and one classical pass leaves w_perp out of
+// orthogonality by about eps |w| / |w_perp|: both stay near 1e-13 relative
+// while |w_perp|^2 >= kCgsTrust |w|^2, ample for an FP64 solve to 1e-8.
+// Below that the projection is carried out explicitly and repeated once if
+// it still cancels (|w_perp|^2 < |w|^2 / 2 after it), as for the FGMRES
+// basis.  Normalising the pair, x += alpha z and r -= alpha w are one
 // kernel.  alpha = <r, w_i> is taken from the same multi-dot, before the
 // projection: r is orthogonal to the earlier w's, so both agree up to
 // rounding.  |r|^2 then drops by alpha^2, which gives the convergence
 // estimate without another reduction; each restart recomputes the true
 // residual.
+constexpr double kCgsTrust = 1e-6;
+
 tph_status gcr(tph_solver* s, double* braw, tph_info* info) {
     const int m = s->d.restart;
     const size_t n3 = s->n3;
@@ -989,7 +1044,7 @@ tph_status gcr(tph_solver* s, double* braw, tph_info* info) {
             }
             double nu2 = w2 - h2;
             a.orth_w = 1;
-            if (i > 0 && !(nu2 >= 0.5 * w2)) {
+            if (i > 0 && !(nu2 >= kCgsTrust * w2)) {
                 TPH_HIP(launch_axpy_dot(w, Vk(1), n3, i, s->dscal + kSlotH1 + 1, n3, false, 0, s->partial, nblk,
                                         s->st));
                 TPH_TRY(reduce_to(s, nblk, 1, kSlotNrm, true, true));
@@ -1351,8 +1406,13 @@ tph_status create_impl(const tph_desc* desc, void* stream, tph_solver* s) {
     s->nlev = nlev;
     for (int l = 0; l < nlev; ++l) {
         Geom& g = s->lev[l].g;
-        g.nx = desc->nx >> l;
-        g.ny = desc->ny >> l;
+        if (desc->coarsen != 2.0) {
+            g.nx = l == 0 ? desc->nx : coarse_cells(s->lev[l - 1].g.nx, desc->coarsen);
+            g.ny = l == 0 ? desc->ny : coarse_cells(s->lev[l - 1].g.ny, desc->coarsen);
+        } else {
+            g.nx = desc->nx >> l;
+            g.ny = desc->ny >> l;
+        }
         g.pitch = pitch_for(g.nx);
         g.dx = desc->lx / g.nx;
         g.dy = desc->ly / g.ny;
@@ -1752,6 +1812,7 @@ void tph_desc_default(tph_desc* d, int32_t nx, int32_t ny) {
     d->seed = 0;
     d->graph = 0;
     d->pad_ = 0;
+    d->coarsen = 2.0;
     d->max_iters = 500;
     d->uzawa_steps = 2;
     d->fused = 1;
@@ -2094,6 +2155,18 @@ tph_status tph_kernel_timing(tph_solver* s, int32_t enable) {
     }
     s->ktime = enable > 0;
     s->kstride = enable > 0 ? enable : 1;
+    s->kcount = 0;
+    return TPH_OK;
+}
+
+tph_status tph_kernel_timing_target(tph_solver* s, int32_t kind) {
+    g_last_error.clear();
+    if (!s) { set_error("null handle"); return TPH_ERR_INVALID; }
+    if (kind != TPH_KERNEL_SMOOTH && kind != TPH_KERNEL_LINK) {
+        set_error("the timing target must be TPH_KERNEL_SMOOTH or TPH_KERNEL_LINK");
+        return TPH_ERR_INVALID;
+    }
+    s->ktarget = kind;
     s->kcount = 0;
     return TPH_OK;
 }

@@ -9,6 +9,8 @@
 // vy(i, j) (i < ny) and p(i, j) and writes the ghost entry mirrored from an
 // owned wall-adjacent value, so solution-type arrays stay ghost-consistent
 // without a separate boundary pass.
+#include <hip/hip_ext.h>
+
 #include "kernels.h"
 #include "reduce.h"
 #include "stencil.h"
@@ -435,15 +437,24 @@ hipError_t launch_precond_out(const Geom& g, const T* ex, const T* ey, Vec3 v, c
     return hipGetLastError();
 }
 
+template <typename T, int MODE>
+void launch_link_mode(const Geom& g, const LinkArgs<T>& a, const double* eb, const double* ep, hipStream_t st,
+                      hipEvent_t t0, hipEvent_t t1) {
+    if (t0)
+        hipExtLaunchKernelGGL((k_uzawa_link<T, MODE>), grid_cells(g), dim3(BX, BY), 0, st, t0, t1, 0, g, a, eb, ep);
+    else
+        hipLaunchKernelGGL((k_uzawa_link<T, MODE>), grid_cells(g), dim3(BX, BY), 0, st, g, a, eb, ep);
+}
+
 template <typename T>
 hipError_t launch_uzawa_link(const Geom& g, const LinkArgs<T>& a, int mode, const double* eb, const double* ep,
-                             hipStream_t st) {
+                             hipStream_t st, hipEvent_t t0, hipEvent_t t1) {
     if (mode == kLinkApply)
-        hipLaunchKernelGGL((k_uzawa_link<T, kLinkApply>), grid_cells(g), dim3(BX, BY), 0, st, g, a, eb, ep);
+        launch_link_mode<T, kLinkApply>(g, a, eb, ep, st, t0, t1);
     else if (mode == kLinkStore)
-        hipLaunchKernelGGL((k_uzawa_link<T, kLinkStore>), grid_cells(g), dim3(BX, BY), 0, st, g, a, eb, ep);
+        launch_link_mode<T, kLinkStore>(g, a, eb, ep, st, t0, t1);
     else if (mode == kLinkNext)
-        hipLaunchKernelGGL((k_uzawa_link<T, kLinkNext>), grid_cells(g), dim3(BX, BY), 0, st, g, a, eb, ep);
+        launch_link_mode<T, kLinkNext>(g, a, eb, ep, st, t0, t1);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -518,7 +529,7 @@ hipError_t launch_cast_f64_f32(const double* src, float* dst, size_t n, hipStrea
     template hipError_t launch_precond_out<T>(const Geom&, const T*, const T*, Vec3, const double*, bool,    \
                                               double, Vec3, hipStream_t, bool);                              \
     template hipError_t launch_uzawa_link<T>(const Geom&, const LinkArgs<T>&, int, const double*,           \
-                                             const double*, hipStream_t);
+                                             const double*, hipStream_t, hipEvent_t, hipEvent_t);
 TPH_INST(float)
 TPH_INST(double)
 #undef TPH_INST

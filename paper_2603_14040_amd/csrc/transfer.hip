@@ -1,5 +1,5 @@
-// Inter-level transfers for factor-2 coarsening (Ch. 4 "Restriction and
-// Prolongation Operators").
+// Inter-level transfers (Ch. 4 "Restriction and Prolongation Operators"):
+// dedicated factor-2 kernels, and coordinate-based ones for any other factor.
 //
 // Restriction is the normalised bilinear weighting sum w r / sum w of
 // Alg. "4-Color Parallel Restriction" written as a gather: each coarse node
@@ -155,12 +155,173 @@ __global__ __launch_bounds__(256) void k_prolong_add(Geom gf, Geom gc, const T* 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Any coarsening factor (the coarse nodes fall between fine nodes).  The
+// same normalised bilinear weighting, computed from node coordinates: along
+// one axis the nodes of a kind sit at x(j) = (j + off) h with off = 0 on
+// basic-node lines and -1/2 on cell-centre lines, and the nodes inside the
+// physical domain are j in [lo, hi] (basic lines [0, n], cell lines
+// [1, n]).  A coarse node X gathers the fine nodes with |x - X| < H, found
+// with the index search of Alg. "Bisect Bound" over the implicit fine
+// coordinates, weighted by the hat 1 - |x - X| / H; prolongation weights the
+// two coarse nodes that bracket a fine node by the same hat.
+// ---------------------------------------------------------------------------
+struct Axis {
+    double h, off;     // spacing and node offset in spacings
+    int lo, hi;        // nodes inside the domain
+};
+
+__device__ __forceinline__ Axis axis_of(int n, double h, bool cell_line) {
+    return cell_line ? Axis{h, -0.5, 1, n} : Axis{h, 0.0, 0, n};
+}
+
+__device__ __forceinline__ double coord(const Axis& a, int j) { return (j + a.off) * a.h; }
+
+// smallest j in [a.lo, a.hi] with coord(j) >= t (a.hi when there is none)
+__device__ __forceinline__ int bisect_bound(const Axis& a, double t) {
+    int l = a.lo, r = a.hi;
+    while (l < r) {
+        const int m = (l + r) >> 1;
+        if (coord(a, m) < t) l = m + 1;
+        else r = m;
+    }
+    return l;
+}
+
+__device__ __forceinline__ double hat(double t) { return fmax(0.0, 1.0 - fabs(t)); }
+
+// sum of w * u and of w over the fine nodes around coarse node (I, J);
+// value(i, j) gives the fine entry (zero where the field has no equation)
+template <typename F>
+__device__ __forceinline__ double gather(const Axis& fy, const Axis& fx, const Axis& cy, const Axis& cx, int I, int J,
+                                         F value) {
+    const double Y = coord(cy, I), X = coord(cx, J);
+    const int i0 = bisect_bound(fy, Y - cy.h), i1 = bisect_bound(fy, Y + cy.h);
+    const int j0 = bisect_bound(fx, X - cx.h), j1 = bisect_bound(fx, X + cx.h);
+    double num = 0.0, wys = 0.0, wxs = 0.0;
+    for (int j = j0; j <= j1; ++j) wxs += hat((coord(fx, j) - X) / cx.h);
+    for (int i = i0; i <= i1; ++i) {
+        const double wy = hat((coord(fy, i) - Y) / cy.h);
+        if (wy == 0.0) continue;
+        wys += wy;
+        double row = 0.0;
+        for (int j = j0; j <= j1; ++j) row += hat((coord(fx, j) - X) / cx.h) * value(i, j);
+        num += wy * row;
+    }
+    const double den = wys * wxs;
+    return den > 0.0 ? num / den : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_restrict_eta_gen(Geom gf, Geom gc, const double* __restrict__ ebf,
+                                                         const double* __restrict__ epf, double* __restrict__ ebc,
+                                                         double* __restrict__ epc, int geometric) {
+    const int J = blockIdx.x * BX + threadIdx.x;
+    const int I = blockIdx.y * BY + threadIdx.y;
+    if (I > gc.ny || J > gc.nx) return;
+    const int Pf = gf.pitch;
+    {   // basic grid: nodes [0, n] in both directions
+        const Axis fy = axis_of(gf.ny, gf.dy, false), fx = axis_of(gf.nx, gf.dx, false);
+        const Axis cy = axis_of(gc.ny, gc.dy, false), cx = axis_of(gc.nx, gc.dx, false);
+        const double m = gather(fy, fx, cy, cx, I, J, [&](int i, int j) {
+            const double v = ebf[i * Pf + j];
+            return geometric ? log(v) : v;
+        });
+        ebc[I * gc.pitch + J] = geometric ? exp(m) : m;
+    }
+    if (I >= 1 && J >= 1) {   // cell centres: [1, n] in both directions
+        const Axis fy = axis_of(gf.ny, gf.dy, true), fx = axis_of(gf.nx, gf.dx, true);
+        const Axis cy = axis_of(gc.ny, gc.dy, true), cx = axis_of(gc.nx, gc.dx, true);
+        const double m = gather(fy, fx, cy, cx, I, J, [&](int i, int j) {
+            const double v = epf[i * Pf + j];
+            return geometric ? log(v) : v;
+        });
+        epc[I * gc.pitch + J] = geometric ? exp(m) : m;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict_res_gen(Geom gf, Geom gc, const T* __restrict__ tx,
+                                                         const T* __restrict__ ty, T* __restrict__ rx,
+                                                         T* __restrict__ ry) {
+    const int J = blockIdx.x * BX + threadIdx.x + 1;
+    const int I = blockIdx.y * BY + threadIdx.y + 1;
+    if (I > gc.ny || J > gc.nx) return;
+    const int Pf = gf.pitch;
+    const int C = I * gc.pitch + J;
+    if (J < gc.nx) {
+        // vx: basic lines in x (walls inside, holding zero), cell lines in y
+        const Axis fy = axis_of(gf.ny, gf.dy, true), fx = axis_of(gf.nx, gf.dx, false);
+        const Axis cy = axis_of(gc.ny, gc.dy, true), cx = axis_of(gc.nx, gc.dx, false);
+        rx[C] = (T)gather(fy, fx, cy, cx, I, J, [&](int i, int j) {
+            return (j >= 1 && j < gf.nx) ? (double)tx[i * Pf + j] : 0.0;
+        });
+    }
+    if (I < gc.ny) {
+        // vy: cell lines in x, basic lines in y (walls inside, holding zero)
+        const Axis fy = axis_of(gf.ny, gf.dy, false), fx = axis_of(gf.nx, gf.dx, true);
+        const Axis cy = axis_of(gc.ny, gc.dy, false), cx = axis_of(gc.nx, gc.dx, true);
+        ry[C] = (T)gather(fy, fx, cy, cx, I, J, [&](int i, int j) {
+            return (i >= 1 && i < gf.ny) ? (double)ty[i * Pf + j] : 0.0;
+        });
+    }
+}
+
+// bilinear value at fine coordinate (y, x) from the coarse nodes that bracket
+// it; coarse entries [0, n + 1] (ghosts hold the mirrored values)
+template <typename T>
+__device__ __forceinline__ double interp_coarse(const T* __restrict__ ec, int Pc, const Axis& cy, const Axis& cx,
+                                                int ny1, int nx1, double y, double x) {
+    int I = (int)floor(y / cy.h - cy.off), J = (int)floor(x / cx.h - cx.off);
+    I = I < 0 ? 0 : (I > ny1 - 1 ? ny1 - 1 : I);
+    J = J < 0 ? 0 : (J > nx1 - 1 ? nx1 - 1 : J);
+    double v = 0.0;
+    for (int a = 0; a < 2; ++a) {
+        const double wy = hat((y - coord(cy, I + a)) / cy.h);
+        for (int b = 0; b < 2; ++b) v += wy * hat((x - coord(cx, J + b)) / cx.h) * (double)ec[(I + a) * Pc + J + b];
+    }
+    return v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong_add_gen(Geom gf, Geom gc, const T* __restrict__ ecx,
+                                                        const T* __restrict__ ecy, T* __restrict__ ex,
+                                                        T* __restrict__ ey) {
+    const int j = blockIdx.x * BX + threadIdx.x + 1;
+    const int i = blockIdx.y * BY + threadIdx.y + 1;
+    if (i > gf.ny || j > gf.nx) return;
+    const int P = gf.pitch;
+    const int c = i * P + j;
+    if (j < gf.nx) {
+        const Axis cy = axis_of(gc.ny, gc.dy, true), cx = axis_of(gc.nx, gc.dx, false);
+        const double v = interp_coarse(ecx, gc.pitch, cy, cx, gc.ny + 1, gc.nx + 1, (i - 0.5) * gf.dy, j * gf.dx);
+        const T e = ex[c] + (T)v;
+        ex[c] = e;
+        if (i == 1) ex[c - P] = (T)gf.mir[2] * e;
+        if (i == gf.ny) ex[c + P] = (T)gf.mir[3] * e;
+    }
+    if (i < gf.ny) {
+        const Axis cy = axis_of(gc.ny, gc.dy, false), cx = axis_of(gc.nx, gc.dx, true);
+        const double v = interp_coarse(ecy, gc.pitch, cy, cx, gc.ny + 1, gc.nx + 1, i * gf.dy, (j - 0.5) * gf.dx);
+        const T e = ey[c] + (T)v;
+        ey[c] = e;
+        if (j == 1) ey[c - 1] = (T)gf.mir[0] * e;
+        if (j == gf.nx) ey[c + 1] = (T)gf.mir[1] * e;
+    }
+}
+
 }  // namespace
+
+// factor 2 when each fine side is twice the coarse one, else the general form
+inline bool halving(const Geom& gf, const Geom& gc) { return gf.nx == 2 * gc.nx && gf.ny == 2 * gc.ny; }
 
 hipError_t launch_restrict_eta(const Geom& gf, const Geom& gc, const double* ebf, const double* epf,
                                double* ebc, double* epc, bool geometric, hipStream_t st) {
     const dim3 grid((gc.nx + 1 + BX - 1) / BX, (gc.ny + 1 + BY - 1) / BY);
-    hipLaunchKernelGGL(k_restrict_eta, grid, dim3(BX, BY), 0, st, gf, gc, ebf, epf, ebc, epc, geometric ? 1 : 0);
+    if (halving(gf, gc))
+        hipLaunchKernelGGL(k_restrict_eta, grid, dim3(BX, BY), 0, st, gf, gc, ebf, epf, ebc, epc, geometric ? 1 : 0);
+    else
+        hipLaunchKernelGGL(k_restrict_eta_gen, grid, dim3(BX, BY), 0, st, gf, gc, ebf, epf, ebc, epc,
+                           geometric ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -168,7 +329,10 @@ template <typename T>
 hipError_t launch_restrict_res(const Geom& gf, const Geom& gc, const T* tx, const T* ty, T* rx, T* ry,
                                hipStream_t st) {
     const dim3 grid((gc.nx + BX - 1) / BX, (gc.ny + BY - 1) / BY);
-    hipLaunchKernelGGL(k_restrict_res<T>, grid, dim3(BX, BY), 0, st, gf, gc, tx, ty, rx, ry);
+    if (halving(gf, gc))
+        hipLaunchKernelGGL(k_restrict_res<T>, grid, dim3(BX, BY), 0, st, gf, gc, tx, ty, rx, ry);
+    else
+        hipLaunchKernelGGL(k_restrict_res_gen<T>, grid, dim3(BX, BY), 0, st, gf, gc, tx, ty, rx, ry);
     return hipGetLastError();
 }
 
@@ -176,7 +340,10 @@ template <typename T>
 hipError_t launch_prolong_add(const Geom& gf, const Geom& gc, const T* ecx, const T* ecy, T* ex, T* ey,
                               hipStream_t st) {
     const dim3 grid((gf.nx + BX - 1) / BX, (gf.ny + BY - 1) / BY);
-    hipLaunchKernelGGL(k_prolong_add<T>, grid, dim3(BX, BY), 0, st, gf, gc, ecx, ecy, ex, ey);
+    if (halving(gf, gc))
+        hipLaunchKernelGGL(k_prolong_add<T>, grid, dim3(BX, BY), 0, st, gf, gc, ecx, ecy, ex, ey);
+    else
+        hipLaunchKernelGGL(k_prolong_add_gen<T>, grid, dim3(BX, BY), 0, st, gf, gc, ecx, ecy, ex, ey);
     return hipGetLastError();
 }
 

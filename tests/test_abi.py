@@ -26,7 +26,6 @@ def test_struct_layout_matches_header(lib):
     # tph_desc: offsets follow the C layout (doubles 8-aligned)
     assert _lib.Desc.lx.offset == 8 and _lib.Desc.bc.offset == 24
     assert _lib.Desc.nu_growth.offset == 64 and _lib.Desc.rtol.offset == 96
-    assert ctypes.sizeof(_lib.Desc) == 168
     d = _lib.Desc()
     lib.tph_desc_default(ctypes.byref(d), 64, 32)
     assert (d.nx, d.ny, d.lx, d.precision, d.restart) == (64, 32, 1.0, _lib.MIXED, 20)
@@ -37,6 +36,7 @@ def test_struct_layout_matches_header(lib):
     assert _lib.Desc.ras_tile.offset == 144 and _lib.Desc.ras_inner.offset == 148 and _lib.Desc.seed.offset == 152
     assert (d.ras_tile, d.ras_inner, d.seed) == (32, 4, 0)
     assert _lib.Desc.graph.offset == 160 and d.graph == 0
+    assert _lib.Desc.coarsen.offset == 168 and ctypes.sizeof(_lib.Desc) == 176 and d.coarsen == 2.0
 
 
 def _create(lib, **kw):
@@ -54,6 +54,9 @@ def _create(lib, **kw):
     (dict(precision=7), "precision"),
     (dict(levels=6, nx=48, ny=48), "divisible"),
     (dict(levels=1, nx=128, ny=128), "coarsest level too large"),
+    (dict(coarsen=2.5), "fused = 0"),
+    (dict(coarsen=1.1, fused=0), "coarsen"),
+    (dict(coarsen=5.0, fused=0), "coarsen"),
     (dict(restart=0), "restart"),
     (dict(restart=65), "restart"),
     (dict(omega=0.0), "omega"),
