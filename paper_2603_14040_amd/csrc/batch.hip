@@ -33,6 +33,14 @@ using namespace dev;
 
 constexpr int kChunk = 8192;      // flat elements per Krylov work item
 
+// slots of a problem's device scalar block (same layout as the single solver's)
+constexpr int kSlotH1 = 0;
+constexpr int kSlotH2 = kSlotH1 + tph::kMaxRestart + 1;
+constexpr int kSlotNrm = kSlotH2 + tph::kMaxRestart + 1;
+constexpr int kSlotY = kSlotNrm + 1;
+constexpr int kSlotMisc = kSlotY + tph::kMaxRestart;
+constexpr int kScal = kSlotMisc + 8;
+
 template <typename T>
 struct BLevel {
     Geom g;
@@ -186,23 +194,35 @@ __device__ __forceinline__ void chunk_range(const BProb& P, int c, size_t& lo, s
     hi = lo + kChunk < P.n3 ? lo + kChunk : P.n3;
 }
 
-// partial rows: v < j+1 dots of V_v with w = V_{j+1}; row j+1: w.w when want_norm
+// Classical Gram-Schmidt of w = V_{j+1} against V_0..V_j, with a second pass
+// only for the problems where the first one cancels badly: after the
+// explicit first projection the norm |w_perp| is exact and the projected
+// vector is off orthogonality by about eps |w| / |w_perp|, which stays near
+// 1e-13 while |w_perp|^2 >= kCgsTrust |w|^2 (kb_decide sets the per-problem
+// flag the second-pass kernels read).
+constexpr double kCgsTrust = 1e-6;
+
+// partial rows: v < j+1 dots of V_v with w = V_{j+1}; row j+1: w.w.  With a
+// gate, only the problems whose gate flag is set take part.
 __global__ __launch_bounds__(256) void kb_multidot(const BProb* __restrict__ prob, const int2* __restrict__ items,
-                                                  const int* __restrict__ active, const int* __restrict__ dj) {
+                                                  const int* __restrict__ active, const int* __restrict__ dj,
+                                                  const int* __restrict__ gate) {
     const int2 it = items[item_index()];
     const int p = it.x;
-    if (!active[p]) return;
+    if (!active[p] || (gate && !gate[p])) return;
     const BProb& P = prob[p];
     const int nv = *dj + 1;
     size_t lo, hi;
     chunk_range(P, it.y, lo, hi);
     const double* w = P.V + (size_t)nv * P.n3;
+    double ww = 0.0;
     for (int v0 = 0; v0 < nv; v0 += 8) {
         double acc[8];
 #pragma unroll
         for (int v = 0; v < 8; ++v) acc[v] = 0.0;
         for (size_t t = lo + threadIdx.x; t < hi; t += 256) {
             const double wv = w[t];
+            if (v0 == 0) ww += wv * wv;
 #pragma unroll
             for (int v = 0; v < 8; ++v)
                 if (v0 + v < nv) acc[v] += P.V[(size_t)(v0 + v) * P.n3 + t] * wv;
@@ -215,41 +235,55 @@ __global__ __launch_bounds__(256) void kb_multidot(const BProb* __restrict__ pro
             }
         }
     }
+    const double s = block_sum(ww);
+    if (threadIdx.x == 0) P.part[(size_t)nv * P.prow + it.y] = s;
 }
 
-// w -= sum_v h[v] V_v; then partial dots of V_v with the new w (want_dots) or its norm (row 0)
+// w -= sum_v h[v] V_v and the partial norms of the new w (row 0); gated like kb_multidot
 __global__ __launch_bounds__(256) void kb_axpy(const BProb* __restrict__ prob, const int2* __restrict__ items,
                                               const int* __restrict__ active, const int* __restrict__ dj, int hslot,
-                                              int want_dots) {
+                                              const int* __restrict__ gate) {
     const int2 it = items[item_index()];
     const int p = it.x;
-    if (!active[p]) return;
+    if (!active[p] || (gate && !gate[p])) return;
     const BProb& P = prob[p];
     const int nv = *dj + 1;
     size_t lo, hi;
     chunk_range(P, it.y, lo, hi);
     double* w = P.V + (size_t)nv * P.n3;
     const double* h = P.scal + hslot;
+    double acc = 0.0;
     for (size_t t = lo + threadIdx.x; t < hi; t += 256) {
         double x = w[t];
         for (int v = 0; v < nv; ++v) x -= h[v] * P.V[(size_t)v * P.n3 + t];
         w[t] = x;
+        acc += x * x;
     }
-    if (!want_dots) {
-        double acc = 0.0;
-        for (size_t t = lo + threadIdx.x; t < hi; t += 256) acc += w[t] * w[t];
-        const double s = block_sum(acc);
-        if (threadIdx.x == 0) P.part[it.y] = s;
-    }
-    // (the dots of the second pass are formed by kb_multidot on the updated w)
+    const double s = block_sum(acc);
+    if (threadIdx.x == 0) P.part[it.y] = s;
+}
+
+// per problem: second Gram-Schmidt pass wanted when |w_perp|^2 < kCgsTrust |w|^2;
+// otherwise the second-pass coefficients are zero
+__global__ __launch_bounds__(64) void kb_decide(const BProb* __restrict__ prob, const int* __restrict__ active,
+                                               const int* __restrict__ dj, int* __restrict__ reorth) {
+    const int p = blockIdx.x;
+    if (!active[p]) return;
+    const BProb& P = prob[p];
+    const int nv = *dj + 1;
+    const double w2 = P.scal[kSlotH1 + nv], n2 = P.scal[kSlotNrm];
+    const int r = !(n2 >= kCgsTrust * w2);
+    if (threadIdx.x == 0) reorth[p] = r;
+    if (!r)
+        for (int v = threadIdx.x; v < nv; v += 64) P.scal[kSlotH2 + v] = 0.0;
 }
 
 // out[slot + r] = sum over the problem's partial row r
 __global__ __launch_bounds__(256) void kb_reduce(const BProb* __restrict__ prob, const int* __restrict__ active,
                                                 const int* __restrict__ dj, int rows_plus, int fixed_rows, int ncols_kind,
-                                                int slot) {
+                                                int slot, const int* __restrict__ gate) {
     const int p = blockIdx.x;
-    if (!active[p]) return;
+    if (!active[p] || (gate && !gate[p])) return;
     const BProb& P = prob[p];
     const int rows = fixed_rows > 0 ? fixed_rows : *dj + rows_plus;
     const int r = blockIdx.y;
@@ -316,6 +350,7 @@ struct tph_batch {
     void* d_cargs = nullptr;                       // CoarseArgs<T>[count]
     size_t coarse_lds = 0;
     int* d_active = nullptr;                       // iteration mask
+    int* d_reorth = nullptr;                       // per problem: second Gram-Schmidt pass this iteration
     int* d_unfinished = nullptr;                   // restart / update mask
     int* d_j = nullptr;
     int* d_k = nullptr;                            // per problem, basis vectors in this cycle
@@ -344,12 +379,6 @@ struct tph_batch {
 
 namespace {
 
-constexpr int kSlotH1 = 0;
-constexpr int kSlotH2 = kSlotH1 + tph::kMaxRestart + 1;
-constexpr int kSlotNrm = kSlotH2 + tph::kMaxRestart + 1;
-constexpr int kSlotY = kSlotNrm + 1;
-constexpr int kSlotMisc = kSlotY + tph::kMaxRestart;
-constexpr int kScal = kSlotMisc + 8;
 
 tph_status b_alloc(tph_batch* b, void** p, size_t bytes) {
     std::string what;
@@ -488,14 +517,19 @@ tph_status enqueue_iteration_t(tph_batch* b) {
     hipLaunchKernelGGL(kb_outer, cells, dim3(64, 4), 0, st, b->d_prob, b->d_cells, act, b->d_j, (int)kResApply);
     const dim3 chunks(b->n_chunks);
     const dim3 rgrid(b->count, tph::kMaxRestart + 2);
-    // classical Gram-Schmidt, twice, then the norm
-    hipLaunchKernelGGL(kb_multidot, chunks, dim3(256), 0, st, b->d_prob, b->d_chunks, act, b->d_j);
-    hipLaunchKernelGGL(kb_reduce, rgrid, dim3(256), 0, st, b->d_prob, act, b->d_j, 1, 0, 0, kSlotH1);
-    hipLaunchKernelGGL(kb_axpy, chunks, dim3(256), 0, st, b->d_prob, b->d_chunks, act, b->d_j, kSlotH1, 1);
-    hipLaunchKernelGGL(kb_multidot, chunks, dim3(256), 0, st, b->d_prob, b->d_chunks, act, b->d_j);
-    hipLaunchKernelGGL(kb_reduce, rgrid, dim3(256), 0, st, b->d_prob, act, b->d_j, 1, 0, 0, kSlotH2);
-    hipLaunchKernelGGL(kb_axpy, chunks, dim3(256), 0, st, b->d_prob, b->d_chunks, act, b->d_j, kSlotH2, 0);
-    hipLaunchKernelGGL(kb_reduce, dim3(b->count, 1), dim3(256), 0, st, b->d_prob, act, b->d_j, 0, 1, 0, kSlotNrm);
+    // classical Gram-Schmidt (dots and |w|^2, projection with the exact new
+    // norm), then a second pass only where the first cancelled (kb_decide)
+    const dim3 ngrid(b->count, 1);
+    const int* ro = b->d_reorth;
+    hipLaunchKernelGGL(kb_multidot, chunks, dim3(256), 0, st, b->d_prob, b->d_chunks, act, b->d_j, nullptr);
+    hipLaunchKernelGGL(kb_reduce, rgrid, dim3(256), 0, st, b->d_prob, act, b->d_j, 2, 0, 0, kSlotH1, nullptr);
+    hipLaunchKernelGGL(kb_axpy, chunks, dim3(256), 0, st, b->d_prob, b->d_chunks, act, b->d_j, kSlotH1, nullptr);
+    hipLaunchKernelGGL(kb_reduce, ngrid, dim3(256), 0, st, b->d_prob, act, b->d_j, 0, 1, 0, kSlotNrm, nullptr);
+    hipLaunchKernelGGL(kb_decide, dim3(b->count), dim3(64), 0, st, b->d_prob, act, b->d_j, b->d_reorth);
+    hipLaunchKernelGGL(kb_multidot, chunks, dim3(256), 0, st, b->d_prob, b->d_chunks, act, b->d_j, ro);
+    hipLaunchKernelGGL(kb_reduce, rgrid, dim3(256), 0, st, b->d_prob, act, b->d_j, 1, 0, 0, kSlotH2, ro);
+    hipLaunchKernelGGL(kb_axpy, chunks, dim3(256), 0, st, b->d_prob, b->d_chunks, act, b->d_j, kSlotH2, ro);
+    hipLaunchKernelGGL(kb_reduce, ngrid, dim3(256), 0, st, b->d_prob, act, b->d_j, 0, 1, 0, kSlotNrm, ro);
     hipLaunchKernelGGL(kb_scale, chunks, dim3(256), 0, st, b->d_prob, b->d_chunks, act, b->d_j, 0, kSlotNrm);
     B_HIP(hipMemcpyAsync(b->h_scal, b->d_scal, (size_t)b->count * kScal * sizeof(double), hipMemcpyDeviceToHost, st));
     return TPH_OK;
@@ -658,6 +692,7 @@ tph_status batch_create_impl(tph_batch* b, int count, const tph_desc* descs) {
     b->n_cells = (int)cells.size();
     b->n_chunks = (int)chunks.size();
     B_TRY(b_alloc(b, (void**)&b->d_active, count * sizeof(int)));
+    B_TRY(b_alloc(b, (void**)&b->d_reorth, count * sizeof(int)));
     B_TRY(b_alloc(b, (void**)&b->d_unfinished, count * sizeof(int)));
     B_TRY(b_alloc(b, (void**)&b->d_k, count * sizeof(int)));
     B_TRY(b_alloc(b, (void**)&b->d_j, sizeof(int)));
@@ -704,7 +739,7 @@ tph_status batch_solve_impl(tph_batch* b, tph_info* infos) {
     hipLaunchKernelGGL(kb_outer, cells, dim3(64, 4), 0, st, b->d_prob, b->d_cells, b->d_unfinished, b->d_j,
                        (int)kResBnorm);
     hipLaunchKernelGGL(kb_reduce, dim3(P, 1), dim3(256), 0, st, b->d_prob, b->d_unfinished, b->d_j, 0, 1, 1,
-                       kSlotMisc);
+                       kSlotMisc, nullptr);
     B_HIP(hipMemcpyAsync(b->h_scal, b->d_scal, (size_t)P * kScal * sizeof(double), hipMemcpyDeviceToHost, st));
     B_HIP(hipStreamSynchronize(st));
     for (int p = 0; p < P; ++p) bnorm[p] = std::sqrt(b->h_scal[(size_t)p * kScal + kSlotMisc]);
@@ -714,7 +749,7 @@ tph_status batch_solve_impl(tph_batch* b, tph_info* infos) {
         hipLaunchKernelGGL(kb_outer, cells, dim3(64, 4), 0, st, b->d_prob, b->d_cells, b->d_unfinished, b->d_j,
                            (int)kResRestart);
         hipLaunchKernelGGL(kb_reduce, dim3(P, 1), dim3(256), 0, st, b->d_prob, b->d_unfinished, b->d_j, 0, 1, 1,
-                           kSlotMisc);
+                           kSlotMisc, nullptr);
         B_HIP(hipMemcpyAsync(b->h_scal, b->d_scal, (size_t)P * kScal * sizeof(double), hipMemcpyDeviceToHost, st));
         B_HIP(hipStreamSynchronize(st));
         bool any = false;
