@@ -41,4 +41,19 @@ struct Vec3 {
     __host__ __device__ double* p() const { return base + 2 * stride; }
 };
 
+// Workgroups are dispatched to the 8 XCDs round-robin by flat id.  Map the
+// flat id so that XCD x gets a contiguous run of tiles (a band of tile rows):
+// halo re-reads and the next kernel's reads of this band then hit that
+// XCD's own L2.  Bijective for any tile count.
+__device__ __forceinline__ void xcd_tile(int& bx, int& by) {
+    const int nbx = gridDim.x;
+    const int n = nbx * gridDim.y;
+    const int b = blockIdx.y * nbx + blockIdx.x;
+    const int x = b & 7, k = b >> 3;
+    const int q = n >> 3, r = n & 7;
+    const int t = x * q + (x < r ? x : r) + k;
+    by = t / nbx;
+    bx = t - by * nbx;
+}
+
 }  // namespace tph

@@ -53,21 +53,6 @@ __device__ __forceinline__ T prolong_vy(const T* __restrict__ ec, int Pc, int i,
     return (T)0.375 * (ec[I * Pc + J0] + ec[(I + 1) * Pc + J0]) + (T)0.125 * (ec[I * Pc + J1] + ec[(I + 1) * Pc + J1]);
 }
 
-// Workgroups are dispatched to the 8 XCDs round-robin by flat id.  Map the
-// flat id so that XCD x gets a contiguous run of tiles (a band of tile rows):
-// halo re-reads and the next kernel's reads of this band then hit that
-// XCD's own L2.  Bijective for any tile count.
-__device__ __forceinline__ void xcd_tile(int& bx, int& by) {
-    const int nbx = gridDim.x;
-    const int n = nbx * gridDim.y;
-    const int b = blockIdx.y * nbx + blockIdx.x;
-    const int x = b & 7, k = b >> 3;
-    const int q = n >> 3, r = n & 7;
-    const int t = x * q + (x < r ? x : r) + k;
-    by = t / nbx;
-    bx = t - by * nbx;
-}
-
 __device__ __forceinline__ bool is_vx(const Geom& g, int i, int j) { return i >= 1 && i <= g.ny && j >= 1 && j < g.nx; }
 __device__ __forceinline__ bool is_vy(const Geom& g, int i, int j) { return i >= 1 && i < g.ny && j >= 1 && j <= g.nx; }
 

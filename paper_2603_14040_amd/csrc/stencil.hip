@@ -195,8 +195,12 @@ __global__ __launch_bounds__(256) void k_precond_out(Geom g, const T* __restrict
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void k_uzawa_link(Geom g, LinkArgs<T> a, const double* __restrict__ eb,
                                                    const double* __restrict__ ep) {
-    const int j = blockIdx.x * BX + threadIdx.x + 1;
-    const int i = blockIdx.y * BY + threadIdx.y + 1;
+    // XCD-aware block order: each XCD takes a band of block rows, so the halo
+    // rows of the 3 x 3 patches are shared through that XCD's L2
+    int bx, by;
+    xcd_tile(bx, by);
+    const int j = bx * BX + threadIdx.x + 1;
+    const int i = by * BY + threadIdx.y + 1;
     uzawa_link_cell<T, MODE>(g, a, eb, ep, i, j);
 }
 
@@ -440,10 +444,11 @@ hipError_t launch_precond_out(const Geom& g, const T* ex, const T* ey, Vec3 v, c
 template <typename T, int MODE>
 void launch_link_mode(const Geom& g, const LinkArgs<T>& a, const double* eb, const double* ep, hipStream_t st,
                       hipEvent_t t0, hipEvent_t t1) {
+    const dim3 grid = grid_cells(g);
     if (t0)
-        hipExtLaunchKernelGGL((k_uzawa_link<T, MODE>), grid_cells(g), dim3(BX, BY), 0, st, t0, t1, 0, g, a, eb, ep);
+        hipExtLaunchKernelGGL((k_uzawa_link<T, MODE>), grid, dim3(BX, BY), 0, st, t0, t1, 0, g, a, eb, ep);
     else
-        hipLaunchKernelGGL((k_uzawa_link<T, MODE>), grid_cells(g), dim3(BX, BY), 0, st, g, a, eb, ep);
+        hipLaunchKernelGGL((k_uzawa_link<T, MODE>), grid, dim3(BX, BY), 0, st, g, a, eb, ep);
 }
 
 template <typename T>
