@@ -15,7 +15,7 @@ Knobs (all of them descriptor fields of tph_create):
   * the first level of the single-workgroup coarse tail (``coarse_level``);
   * pre- and post-smoothing sweeps and their growth per level (the paper's
     level-dependent schedule, nu_l = ceil(nu * growth^l));
-  * Uzawa sweeps per preconditioner application (``uzawa_steps``, 1..8) and the
+  * Uzawa sweeps per preconditioner application (``uzawa_steps``, 1..16) and the
     Uzawa pressure relaxation ``alpha``; the smoother damping ``omega``;
   * the Krylov accelerator (flexible GMRES or GCR) and its restart length;
     for Anderson acceleration (tuned from an explicit knob list) the depth
@@ -150,20 +150,30 @@ def plan_to_masks(plan: Sequence[Tuple[int, int]], levels: Sequence[int]) -> Tup
 
 
 def solver_kwargs(p: Params, tile_levels: Sequence[int]) -> dict:
-    """Solver keyword arguments of a parameter set."""
+    """Solver keyword arguments of a parameter set (a joint ``krylov`` =
+    (accelerator, restart) entry overrides ``accel`` and ``restart``)."""
     plan = [tuple(p[f"L{l}"]) for l in tile_levels]
     msw, shp = plan_to_masks(plan, tile_levels)
+    accel, restart = (p["krylov"] if "krylov" in p else (p.get("accel", "fgmres"), p["restart"]))
     return dict(nu_pre=int(p["nu_pre"]), nu_post=int(p["nu_post"]), nu_growth=float(p.get("nu_growth", 1.0)),
-                uzawa_steps=int(p["uzawa_steps"]), restart=int(p["restart"]), msweep=msw, tile_shape=shp,
+                uzawa_steps=int(p["uzawa_steps"]), restart=int(restart), msweep=msw, tile_shape=shp,
                 coarse_level=int(p.get("coarse_level", -1)), omega=float(p.get("omega", 1.0)),
-                alpha=float(p.get("alpha", 1.0)), accel=str(p.get("accel", "fgmres")),
+                alpha=float(p.get("alpha", 1.0)), accel=str(accel),
                 beta=float(p.get("beta", 1.0)), smoother=int(p.get("smoother", 1)),
                 ras_tile=int(p.get("ras_tile", 32)), ras_inner=int(p.get("ras_inner", 4)))
 
 
+# A second starting point of the search besides the library defaults: a
+# short-restart GCR around a deeper Uzawa preconditioner with one sweep per
+# leg.  Coordinate descent moves one knob at a time, and from the defaults
+# (FGMRES(20), two Uzawa steps) it can settle where a better restart /
+# accelerator / Uzawa-depth combination needs several knobs to move at once.
+ALT_START: Params = {"krylov": ("gcr", 8), "uzawa_steps": 4, "alpha": 1.5, "nu_pre": 1, "nu_post": 1}
+
+
 def knobs_for(tile_levels: Sequence[int], coarse_levels: Sequence[int] = (), nus=(1, 2, 3),
-              growths=(1.0, 1.5, 2.0), uzawa=(1, 2, 3, 4, 6, 8), restarts=(5, 8, 10, 15, 20, 30, 50, 64),
-              alphas=(1.0, 1.5, 2.0, 3.0), omegas=(0.8, 1.0, 1.2),
+              growths=(1.0, 1.5, 2.0), uzawa=(1, 2, 3, 4, 6, 8, 12, 16), restarts=(5, 8, 10, 15, 20, 30, 50, 64),
+              alphas=(1.0, 1.5, 1.75, 2.0, 3.0), omegas=(0.8, 1.0, 1.2),
               accels=("fgmres", "gcr")) -> List[Knob]:
     """Schedule knobs first (they move the iteration count), then the kernel plan.
 
@@ -171,9 +181,7 @@ def knobs_for(tile_levels: Sequence[int], coarse_levels: Sequence[int] = (), nus
     over the preconditioned directions) is a knob beside its restart length."""
     ks = [Knob("alpha", list(alphas)), Knob("uzawa_steps", list(uzawa)), Knob("nu_pre", list(nus)),
           Knob("nu_post", list(nus)), Knob("omega", list(omegas)), Knob("nu_growth", list(growths)),
-          Knob("restart", list(restarts))]
-    if len(accels) > 1:
-        ks.append(Knob("accel", list(accels)))
+          Knob("krylov", [(a, r) for a in accels for r in restarts])]
     if coarse_levels:
         ks.append(Knob("coarse_level", [-1] + list(coarse_levels)))
     ks += [Knob(f"L{l}", [(0, 0), (0, 1), (1, 0), (1, 1)]) for l in tile_levels]
@@ -185,8 +193,9 @@ def knobs_for(tile_levels: Sequence[int], coarse_levels: Sequence[int] = (), nus
 # ---------------------------------------------------------------------------
 def schedule_knobs() -> List[Knob]:
     """Knobs that carry over between grid sizes of one recipe (no per-level plan)."""
-    return [Knob("restart", [8, 16, 30, 50, 64]), Knob("accel", ["fgmres", "gcr"]), Knob("alpha", [1.0, 1.5, 2.0, 3.0]),
-            Knob("uzawa_steps", [1, 2, 3, 4, 6, 8]), Knob("nu_pre", [1, 2, 3]), Knob("nu_post", [1, 2, 3]),
+    return [Knob("krylov", [(a, r) for a in ("fgmres", "gcr") for r in (8, 16, 30, 40, 48, 64)]),
+            Knob("alpha", [1.0, 1.5, 1.75, 2.0, 3.0]),
+            Knob("uzawa_steps", [1, 2, 3, 4, 6, 8, 12, 16]), Knob("nu_pre", [1, 2, 3]), Knob("nu_post", [1, 2, 3]),
             Knob("omega", [0.8, 1.0, 1.2])]
 
 
@@ -194,14 +203,16 @@ def tune(eta_b, eta_p, rho_b, gx: float = 0.0, gy: float = -1.0, *, precision: O
          lx: float = 1.0, ly: float = 1.0, bc=(0, 0, 0, 0), rtol: float = 1e-8, reps: int = 3, rounds: int = 2,
          rel_gain: float = 0.02, db: Optional[TuningDB] = None, tag: str = "", device=None,
          knobs: Optional[Sequence[Knob]] = None, log: Optional[Callable[[str], None]] = None,
-         max_iters: int = 2000, start: Optional[dict] = None) -> dict:
+         max_iters: int = 2000, start: Optional[dict] = None, starts: Optional[Sequence[dict]] = None) -> dict:
     """Tune the solve of one problem (device FP64 arrays of shape (ny+2, nx+2)).
 
     Returns the database entry: ``params`` (Solver keyword arguments),
     ``ms`` (median solve time), ``iters``, ``trials`` and ``seconds``
     spent.  With ``db`` the entry is stored under the problem's key.
     ``start`` overrides entries of the starting point (schedule keys of
-    ``solver_kwargs``, ``accel``, ``beta``).
+    ``solver_kwargs``, ``accel``, ``restart``, ``beta``, ``krylov``);
+    ``starts`` lists further overrides, each the start of another descent
+    (measured candidates are shared), and the fastest result wins.
     """
     import torch
     from . import MIXED, Solver, _lib
@@ -226,9 +237,12 @@ def tune(eta_b, eta_p, rho_b, gx: float = 0.0, gy: float = -1.0, *, precision: O
     for l in tile_levels:
         k, s = plan0[l]
         init[f"L{l}"] = (1 if k == "multisweep" else 0, int(s))
+    init["krylov"] = (init["accel"], init["restart"])
     for key, v in (start or {}).items():
         if key in init and not key.startswith("L"):
             init[key] = v
+    if start and ("accel" in start or "restart" in start) and "krylov" not in start:
+        init["krylov"] = (start.get("accel", init["krylov"][0]), start.get("restart", init["krylov"][1]))
     if start and ("msweep" in start or "tile_shape" in start):
         # a per-level plan given as descriptor masks (-1: that level's default)
         for l in tile_levels:
@@ -281,8 +295,21 @@ def tune(eta_b, eta_p, rho_b, gx: float = 0.0, gy: float = -1.0, *, precision: O
         finally:
             s.close()
 
-    res = coordinate_search(measure, knobs if knobs is not None else knobs_for(tile_levels, coarse_levels), init,
-                            rounds=rounds, rel_gain=rel_gain)
+    ks = knobs if knobs is not None else knobs_for(tile_levels, coarse_levels)
+    if not any(k.name == "krylov" for k in ks):
+        init.pop("krylov", None)          # separate accel / restart knobs (or neither) drive those two
+    res = coordinate_search(measure, ks, init, rounds=rounds, rel_gain=rel_gain)
+    for extra in starts or ():
+        p0 = dict(init)
+        for key, v in extra.items():
+            if key in p0 and not key.startswith("L"):
+                p0[key] = tuple(v) if isinstance(v, list) else v
+            elif key == "krylov" and "krylov" not in p0:
+                p0["accel"], p0["restart"] = v
+        r2 = coordinate_search(measure, ks, p0, rounds=rounds, rel_gain=rel_gain)
+        trials = res.trials + r2.trials
+        res = r2 if r2.cost < res.cost else res
+        res = SearchResult(res.params, res.cost, trials)
     best_kw = solver_kwargs(res.params, tile_levels)
     entry = {"params": best_kw, "ms": res.cost, "iters": iters.get(eff_of.get(json.dumps(res.params, sort_keys=True))),
              "default_ms": res.trials[0][1], "trials": len(res.trials),

@@ -95,6 +95,15 @@ SMOOTHER_SOURCES = ("common.h", "stencil.h", "reduce.h", "fused_dev.h", "msweep.
                     "msweep_f64.hip", "fused.hip")
 
 
+# the files that hold the code of the Uzawa link pass (kernel, cell body,
+# stencils) and of its launcher
+LINK_SOURCES = ("common.h", "stencil.h", "stencil_dev.h", "stencil.hip")
+
+# sources whose hash a committed counter summary carries, by the kernel class
+# bench.py reports in its roofline entry
+KERNEL_SOURCES = {"smooth": SMOOTHER_SOURCES, "link": LINK_SOURCES}
+
+
 def sources_hash(files=SMOOTHER_SOURCES) -> str:
     """SHA-256 over the sources of the profiled kernel (which code the counters belong to)."""
     import hashlib
@@ -107,7 +116,8 @@ def sources_hash(files=SMOOTHER_SOURCES) -> str:
     return h.hexdigest()
 
 
-def traffic(fetch_dir: str, write_dir: str, kernel: str, copy_bytes: float, grid: int = 0) -> dict:
+def traffic(fetch_dir: str, write_dir: str, kernel: str, copy_bytes: float, grid: int = 0,
+            sources=SMOOTHER_SOURCES) -> dict:
     rx = re.compile(kernel)
     res = {}
     for tag, d, cname in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
@@ -121,7 +131,8 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str, copy_bytes: float, grid
     res["bytes_per_launch"] = res["fetch"]["bytes"] + res["write"]["bytes"]
     res["kernel"] = kernel
     res["grid"] = grid
-    res["sources_sha256"] = sources_hash()
+    res["sources_sha256"] = sources_hash(sources)
+    res["sources"] = list(sources)
     return res
 
 
@@ -138,6 +149,8 @@ def main(argv=None) -> int:
     s2.add_argument("--copy-bytes", type=float, required=True)
     s2.add_argument("--grid", type=int, default=0, help="only dispatches of this grid size (work items)")
     s2.add_argument("--json", default=None)
+    s2.add_argument("--sources", choices=sorted(KERNEL_SOURCES), default="smooth",
+                    help="kernel class whose source files the summary's hash covers")
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         rows = kernel_stats(a.dir)
@@ -147,7 +160,7 @@ def main(argv=None) -> int:
             print(f"| `{k}` | {c} | {s:.2f} | {m:.2f} | {100 * s / tot:.1f} |")
         print(f"\nall kernels: {tot:.2f} ms")
         return 0
-    r = traffic(a.fetch_dir, a.write_dir, a.kernel, a.copy_bytes, a.grid)
+    r = traffic(a.fetch_dir, a.write_dir, a.kernel, a.copy_bytes, a.grid, KERNEL_SOURCES[a.sources])
     print(f"kernel /{a.kernel}/: {r['fetch']['launches']} launches; FETCH {r['fetch']['raw_bytes'] / 1e6:.2f} MB raw x "
           f"{r['fetch']['calibration']:.3f} = {r['fetch']['bytes'] / 1e6:.2f} MB; WRITE "
           f"{r['write']['raw_bytes'] / 1e6:.2f} MB raw x {r['write']['calibration']:.3f} = "

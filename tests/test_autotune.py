@@ -51,10 +51,17 @@ def test_masks_and_solver_kwargs():
     assert kw["accel"] == "anderson" and kw["beta"] == 0.7
     ks = at.knobs_for([0, 1, 2], [5])
     names = [k.name for k in ks]
-    assert names[:8] == ["alpha", "uzawa_steps", "nu_pre", "nu_post", "omega", "nu_growth", "restart", "accel"]
-    assert list(ks[7].candidates) == ["fgmres", "gcr"]
+    assert names[:7] == ["alpha", "uzawa_steps", "nu_pre", "nu_post", "omega", "nu_growth", "krylov"]
+    # accelerator and restart move together: every (accelerator, restart) pair is one candidate
+    kry = list(ks[6].candidates)
+    assert ("fgmres", 20) in kry and ("gcr", 8) in kry and len(kry) == 2 * len(set(r for _, r in kry))
     assert "coarse_level" in names and names[-3:] == ["L0", "L1", "L2"]
-    assert "accel" not in [k.name for k in at.knobs_for([0], accels=("fgmres",))]
+    assert {a for a, _ in at.knobs_for([0], accels=("fgmres",))[6].candidates} == {"fgmres"}
+    # a joint krylov entry overrides accel and restart
+    kw = at.solver_kwargs(dict(p, krylov=("gcr", 8)), [0, 1])
+    assert kw["accel"] == "gcr" and kw["restart"] == 8
+    # the second starting point names a joint entry
+    assert at.ALT_START["krylov"] == ("gcr", 8)
 
 
 def test_database_round_trip(tmp_path):

@@ -1,6 +1,7 @@
 """Host-side contract of bench.py that needs no GPU: more than one GPU is
-refused with one JSON line and exit status 2, and the options that skip the
-side workloads exist (the profiling commands in profiles/ use them)."""
+refused with one JSON line and exit status 2, the options that pick and size
+the sections exist (the profiling commands in profiles/ use them), and an
+unknown section is rejected."""
 import json
 import os
 import subprocess
@@ -21,6 +22,14 @@ def test_side_workload_switches_exist():
     res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"], capture_output=True, text=True,
                          cwd=ROOT, timeout=120)
     assert res.returncode == 0
-    for opt in ("--steps", "--warmup", "--fp64-steps", "--batch", "--large", "--accel-steps", "--ras-steps",
+    for opt in ("--steps", "--warmup", "--only", "--fp64-steps", "--batch", "--large", "--large-reps",
+                "--tune-large", "--roofline-kernel", "--skip-continuation", "--tune-batch", "--batch-reps", "--cpu-sizes", "--accel-steps", "--ras-steps",
                 "--mic-steps", "--robust-iters", "--no-cpu-baseline", "--tuning-db", "--reuse-tuning"):
         assert opt in res.stdout, opt
+
+
+def test_unknown_section_is_rejected():
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--only", "headline,nosuch"],
+                         capture_output=True, text=True, cwd=ROOT, timeout=120)
+    assert res.returncode == 2
+    assert "nosuch" in res.stderr
