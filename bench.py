@@ -101,6 +101,7 @@ def main():
                     help="tune the batch schedule on its held-out instance instead of BATCH_PARAMS")
     ap.add_argument("--batch", type=int, default=256, help="problems in the batched workload")
     ap.add_argument("--batch-reps", type=int, default=5, help="timed batched solves per precision (median)")
+    ap.add_argument("--batch-precisions", default="mixed,fp64", help="precisions of the batched runs")
     ap.add_argument("--adjoint-reps", type=int, default=5)
     ap.add_argument("--config1-steps", type=int, default=20)
     ap.add_argument("--accel-steps", type=int, default=5)
@@ -170,7 +171,7 @@ def main():
         torch.cuda.empty_cache()
         return gbs
 
-    if "headline" in only or "large" in only:
+    if "headline" in only or "large" in only or "batch" in only:
         out["copy_GBps"] = round(copy_probe(), 1)
         log(f"[bench] device copy {out['copy_GBps']:.0f} GB/s")
 
@@ -424,9 +425,12 @@ def main():
         batch = {"workload": f"{len(probs)} centred sinkers, sizes 64..512 (seed 4), radius U(0.05,0.2), contrast "
                              f"10^U(1,4), free slip", "cells": bcells, "tuned": btuned}
         for prec, tag in ((tph.MIXED, "mixed"), (tph.FP64, "fp64")):
+            if tag not in args.batch_precisions.split(","):
+                continue
             t0 = time.perf_counter()
             bat = tph.Batch(shapes, device=dev, precision=prec, **btuned["params"])
             t_create = time.perf_counter() - t0
+            log(f"[bench] batch {tag}: created in {t_create:.1f} s")
             outs = bat.zeros(), bat.zeros(), bat.zeros()
 
             def bstep():
@@ -437,6 +441,7 @@ def main():
                 return bat.solve(*outs)[3]
 
             bstep()
+            log(f"[bench] batch {tag}: warm-up solve done")
             ts, binf = [], None
             for _ in range(args.batch_reps):
                 sync()

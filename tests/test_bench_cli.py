@@ -23,7 +23,7 @@ def test_side_workload_switches_exist():
                          cwd=ROOT, timeout=120)
     assert res.returncode == 0
     for opt in ("--steps", "--warmup", "--only", "--fp64-steps", "--batch", "--large", "--large-reps",
-                "--tune-large", "--roofline-kernel", "--skip-continuation", "--tune-batch", "--batch-reps", "--cpu-sizes", "--accel-steps", "--ras-steps",
+                "--tune-large", "--roofline-kernel", "--skip-continuation", "--tune-batch", "--batch-precisions", "--batch-reps", "--cpu-sizes", "--accel-steps", "--ras-steps",
                 "--mic-steps", "--robust-iters", "--no-cpu-baseline", "--tuning-db", "--reuse-tuning"):
         assert opt in res.stdout, opt
 
