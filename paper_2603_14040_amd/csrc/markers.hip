@@ -14,6 +14,7 @@
 // velocity grids are read through the caches.
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cmath>
 #include <cstdint>
 #include <string>
@@ -255,32 +256,89 @@ __global__ __launch_bounds__(256) void k_ranges(int n, const uint32_t* __restric
     if (p == n - 1 || keys[p + 1] != k) cend[k] = p + 1;
 }
 
-// per cell, in sorted (stable: marker index) order: sums of w phi and w for its four corners
+// Per cell, in sorted (stable: marker index) order: sums of w phi and w for
+// its four corners.  A workgroup owns 256 consecutive cells, whose markers
+// occupy one contiguous run of the sorted order.  The run goes through LDS
+// in chunks of kStage markers: the workgroup reads the sorted marker indices
+// and gathers x, y and phi with neighbouring lanes on neighbouring entries;
+// then every thread walks its own cell's part of the chunk from LDS.  The
+// products and sums per cell are those of a direct loop over the cell's
+// markers, in the same order.  Slots are padded by one per 16 entries: the
+// cells of neighbouring lanes start about 16 markers apart, which would
+// otherwise put their reads on the same LDS banks.
+constexpr int kStage = 1024;
+constexpr int kStageSlots = kStage + kStage / 16;
+__device__ __forceinline__ int stage_slot(int t) { return t + (t >> 4); }
+
 __global__ __launch_bounds__(256) void k_cell_partials(NodeGrid q, int nx, int ny, const int32_t* __restrict__ cstart,
                                                        const int32_t* __restrict__ cend,
                                                        const int32_t* __restrict__ order,
                                                        const double* __restrict__ xm, const double* __restrict__ ym,
                                                        const double* __restrict__ phi, double* __restrict__ partial) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double sx[kStageSlots], sy[kStageSlots], sf[kStageSlots];
+    __shared__ int run_lo[4], run_hi[4];
     const int ncell = (nx + 1) * (ny + 1);
-    if (c >= ncell) return;
-    const int i = c / (nx + 1), j = c - i * (nx + 1);
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = c < ncell;
+    const int b = live ? cstart[c] : 0, e = live ? cend[c] : 0;     // empty cells: b == e
+    // run of the workgroup: first start and last end over its non-empty cells
+    int lo = b < e ? b : INT_MAX, hi = b < e ? e : 0;
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = min(lo, __shfl_xor(lo, o));
+        hi = max(hi, __shfl_xor(hi, o));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        run_lo[threadIdx.x >> 6] = lo;
+        run_hi[threadIdx.x >> 6] = hi;
+    }
+    __syncthreads();
+    const int P0 = min(min(run_lo[0], run_lo[1]), min(run_lo[2], run_lo[3]));
+    const int P1 = max(max(run_hi[0], run_hi[1]), max(run_hi[2], run_hi[3]));
+    const int i = live ? c / (nx + 1) : 0, j = c - i * (nx + 1);
     const double xj = q.x0 + j * q.dx, yi = q.y0 + i * q.dy;
     double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int p = cstart[c]; p < cend[c]; ++p) {
-        const int m = order[p];
-        const double rx = (xm[m] - xj) / q.dx, ry = (ym[m] - yi) / q.dy;
-        const double f = phi[m];
-        const double w00 = (1.0 - rx) * (1.0 - ry), w01 = rx * (1.0 - ry), w10 = (1.0 - rx) * ry, w11 = rx * ry;
-        s[0] += w00 * f;
-        s[1] += w00;
-        s[2] += w01 * f;
-        s[3] += w01;
-        s[4] += w10 * f;
-        s[5] += w10;
-        s[6] += w11 * f;
-        s[7] += w11;
+    constexpr int KS = kStage / 256;
+    for (int base = P0; base < P1; base += kStage) {
+        const int cnt = min(kStage, P1 - base);
+        int m[KS];
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            const int t = threadIdx.x + k * 256;
+            m[k] = t < cnt ? order[base + t] : -1;
+        }
+        double vx[KS], vy[KS], vf[KS];
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            vx[k] = m[k] >= 0 ? xm[m[k]] : 0.0;
+            vy[k] = m[k] >= 0 ? ym[m[k]] : 0.0;
+            vf[k] = m[k] >= 0 ? phi[m[k]] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            const int t = stage_slot(threadIdx.x + k * 256);
+            sx[t] = vx[k];
+            sy[t] = vy[k];
+            sf[t] = vf[k];
+        }
+        __syncthreads();
+        const int pe = min(e, base + cnt);
+        for (int p = max(b, base); p < pe; ++p) {
+            const int t = stage_slot(p - base);
+            const double rx = (sx[t] - xj) / q.dx, ry = (sy[t] - yi) / q.dy;
+            const double f = sf[t];
+            const double w00 = (1.0 - rx) * (1.0 - ry), w01 = rx * (1.0 - ry), w10 = (1.0 - rx) * ry, w11 = rx * ry;
+            s[0] += w00 * f;
+            s[1] += w00;
+            s[2] += w01 * f;
+            s[3] += w01;
+            s[4] += w10 * f;
+            s[5] += w10;
+            s[6] += w11 * f;
+            s[7] += w11;
+        }
+        __syncthreads();
     }
+    if (!live) return;
     double* out = partial + (size_t)c * 8;
 #pragma unroll
     for (int k = 0; k < 8; ++k) out[k] = s[k];

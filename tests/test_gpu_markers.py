@@ -6,6 +6,7 @@
   markers on walls and corners, every marker in one cell, ragged grids;
 * grid -> marker for the four node kinds: <= 1e-13;
 * RK4 on a solver velocity field: positions after several steps <= 1e-12;
+* cells with more markers than one staging chunk of the cell-sum kernel;
 * the benchmark size (1024^2 cells, 4 markers per cell): marker -> grid
   against the oracle on every node.
 """
@@ -93,6 +94,29 @@ def test_markers_edge_cases():
     with pytest.raises(tph.TephraError):
         big = torch.zeros(101, dtype=torch.float64, device=DEV)
         m.to_grid("basic", big, big, [big])
+    m.close()
+
+
+def test_markers_crowded_cells():
+    """Cells holding more markers than the kernel stages at once (a run of
+    several thousand sorted markers in one cell and a few hundred in its
+    neighbours), beside sparse ones, in random marker order."""
+    g = st.Grid(40, 30)
+    rng = np.random.default_rng(17)
+    n1, n2, n3 = 5000, 700, 2000
+    xm = np.concatenate([0.500 + 0.02 * rng.random(n1), 0.525 + 0.02 * rng.random(n2), rng.uniform(0, 1, n3)])
+    ym = np.concatenate([0.400 + 0.03 * rng.random(n1), 0.410 + 0.02 * rng.random(n2), rng.uniform(0, 1, n3)])
+    perm = rng.permutation(xm.size)
+    xm, ym = xm[perm], ym[perm]
+    f = 10.0 ** rng.uniform(-3, 3, xm.size)
+    m = tph.Markers(40, 30, capacity=xm.size, device=DEV)
+    print(f"[case] crowded cells, {xm.size} markers", flush=True)
+    for kind in ("basic", "cell"):
+        got = _range(g, kind, N(m.to_grid(kind, T(xm), T(ym), [T(f)], fill=-1.0)[0]))
+        ref = _range(g, kind, mk.markers_to_grid(g, kind, xm, ym, f, fill=-1.0))
+        empty = ref == -1.0
+        assert np.array_equal(got[empty], ref[empty])
+        assert _rel(got[~empty], ref[~empty]) < 1e-12
     m.close()
 
 
