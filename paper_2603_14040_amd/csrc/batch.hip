@@ -7,10 +7,12 @@
 // at one depth of its V-cycle; the coarse tails run as one workgroup per
 // problem.  Converged problems are masked by a device flag.  The FGMRES
 // iteration index is read from device memory, so the device work of one
-// iteration (Uzawa/V-cycle preconditioner, operator apply, classical
-// Gram-Schmidt twice, normalisation, read-back of the Hessenberg columns) is
-// captured once as a hipGraph and replayed for every iteration; the host
-// only runs the Givens updates of each problem between replays.
+// iteration (Uzawa/V-cycle preconditioner, each step closed by one link pass
+// that also forms the next step's right-hand side or, after the last step,
+// the operator apply; classical Gram-Schmidt, normalisation, read-back of
+// the Hessenberg columns) is captured once as a hipGraph and replayed for
+// every iteration; the host only runs the Givens updates of each problem
+// between replays.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -60,6 +62,8 @@ struct BProb {
     double* b;
     double* V;
     double* Z;
+    double* t1;                    // second z of the Uzawa link
+    double* t2;                    // pressure residuals of the Uzawa link (t2, t3)
     double* t3;
     size_t F, n3;
     int nchunk;                    // Krylov work items per vector
@@ -120,71 +124,82 @@ __global__ __launch_bounds__(coarse_threads<T>()) void kb_coarse(const CoarseArg
 }
 
 // ---------------------------------------------------- finest-level cell kernels
-enum { kPinKrylov = 0, kPinInner = 1 };
-
+// Entry of the preconditioner: the level-0 right-hand side from the Krylov
+// basis vector V_j (energy-scaled).
 template <typename T>
 __global__ __launch_bounds__(256) void kb_precond_in(const BLevel<T>* __restrict__ lev, const BProb* __restrict__ prob,
                                                     const int2* __restrict__ items, const int* __restrict__ active,
-                                                    const int* __restrict__ dj, int src) {
+                                                    const int* __restrict__ dj) {
     const int2 it = items[item_index()];
     const int p = it.x;
     if (!active[p]) return;
     const BProb& P = prob[p];
-    const int jj = *dj;
-    const Vec3 v = src == kPinKrylov ? bvec(P, P.V + (size_t)jj * P.n3) : bvec(P, P.t3);
+    const Vec3 v = bvec(P, P.V + (size_t)(*dj) * P.n3);
     const int j = (it.y & 0xffff) * 64 + threadIdx.x + 1;
     const int i = (it.y >> 16) * 4 + threadIdx.y + 1;
-    precond_in_cell<T>(P.g, v, P.eb64, P.ep64, src == kPinKrylov, lev[p * kMaxLevels].rx, lev[p * kMaxLevels].ry, i, j);
+    precond_in_cell<T>(P.g, v, P.eb64, P.ep64, 1, lev[p * kMaxLevels].rx, lev[p * kMaxLevels].ry, i, j);
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void kb_precond_out(const BLevel<T>* __restrict__ lev, const BProb* __restrict__ prob,
-                                                     const int2* __restrict__ items, const int* __restrict__ active,
-                                                     const int* __restrict__ dj, int src, int cur) {
+// Exit of Uzawa step q of S (the single solver's link pass, uzawa_link_cell):
+// z = z_old + e with the pressure update, then the next step's right-hand
+// side (kLinkNext) or, after the last step, the Krylov apply
+// V_{j+1} = W^(1/2) A Z_j (kLinkApply).  z alternates between t1 and Z_j so
+// that the last step writes Z_j; the pressure residual between t3 and t2.
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void kb_uzawa_link(const BLevel<T>* __restrict__ lev,
+                                                    const BProb* __restrict__ prob, const int2* __restrict__ items,
+                                                    const int* __restrict__ active, const int* __restrict__ dj,
+                                                    int q, int S, int cur) {
     const int2 it = items[item_index()];
     const int p = it.x;
     if (!active[p]) return;
     const BProb& P = prob[p];
     const int jj = *dj;
-    const Vec3 v = src == kPinKrylov ? bvec(P, P.V + (size_t)jj * P.n3) : bvec(P, P.t3);
-    const Vec3 z = bvec(P, P.Z + (size_t)jj * P.n3);
-    const int j = (it.y & 0xffff) * 64 + threadIdx.x + 1;
-    const int i = (it.y >> 16) * 4 + threadIdx.y + 1;
+    const BLevel<T>& L = lev[p * kMaxLevels];
     // the coarse-tail kernel leaves the correction in buffer 0 when it owns the finest level
     const int c = P.lc == 0 ? 0 : cur;
-    const BLevel<T>& L = lev[p * kMaxLevels];
-    precond_out_cell<T>(P.g, L.ex[c], L.ey[c], v, P.ep64, src == kPinKrylov, P.alpha, z, src == kPinInner, i, j);
+    const Vec3 v = bvec(P, P.V + (size_t)jj * P.n3);
+    const Vec3 zj = bvec(P, P.Z + (size_t)jj * P.n3), z1 = bvec(P, P.t1);
+    double* const tp0 = bvec(P, P.t3).p();
+    double* const tp1 = bvec(P, P.t2).p();
+    LinkArgs<T> a{};
+    a.ex = L.ex[c];
+    a.ey = L.ey[c];
+    a.zold = ((S - q) & 1) ? z1 : zj;
+    a.acc = q > 0 ? 1 : 0;
+    a.srcp = q == 0 ? v.p() : (((q - 1) & 1) ? tp1 : tp0);
+    a.src_scaled = q == 0 ? 1 : 0;
+    a.alpha = P.alpha;
+    a.zout = ((S - 1 - q) & 1) ? z1 : zj;
+    a.r = v;
+    a.r_scaled = 1;
+    a.rx = L.rx;
+    a.ry = L.ry;
+    a.tp = (q & 1) ? tp1 : tp0;
+    a.wout = bvec(P, P.V + (size_t)(jj + 1) * P.n3);
+    a.w_scaled = 1;
+    const int j = (it.y & 0xffff) * 64 + threadIdx.x + 1;
+    const int i = (it.y >> 16) * 4 + threadIdx.y + 1;
+    uzawa_link_cell<T, MODE>(P.g, a, P.eb64, P.ep64, i, j);
 }
 
-enum { kResApply = 0, kResInner = 1, kResRestart = 2, kResBnorm = 3 };
+enum { kResRestart = 0, kResBnorm = 1 };
 
+// FP64 residual at a restart: V_0 = W^(1/2) (b - A x), or of x = 0 (the
+// zeroed scratch vector t3) for |W^(1/2) b|; block sums of squares to part
 __global__ __launch_bounds__(256) void kb_outer(const BProb* __restrict__ prob, const int2* __restrict__ items,
-                                               const int* __restrict__ active, const int* __restrict__ dj, int mode) {
+                                               const int* __restrict__ active, int mode) {
     const int2 it = items[item_index()];
     const int p = it.x;
     if (!active[p]) return;
     const BProb& P = prob[p];
-    const int jj = *dj;
     const int bx = it.y & 0xffff, by = it.y >> 16;
     const int j = bx * 64 + threadIdx.x + 1;
     const int i = by * 4 + threadIdx.y + 1;
-    double acc;
-    if (mode == kResApply) {
-        acc = outer_residual_cell(P.g, bvec(P, P.Z + (size_t)jj * P.n3), Vec3{nullptr, 0}, 0, P.eb64, P.ep64,
-                                  bvec(P, P.V + (size_t)(jj + 1) * P.n3), 1, 1, 0, i, j);
-    } else if (mode == kResInner) {
-        acc = outer_residual_cell(P.g, bvec(P, P.Z + (size_t)jj * P.n3), bvec(P, P.V + (size_t)jj * P.n3), 1, P.eb64,
-                                  P.ep64, bvec(P, P.t3), 0, 0, 1, i, j);
-    } else if (mode == kResRestart) {
-        acc = outer_residual_cell(P.g, bvec(P, P.x), bvec(P, P.b), 1, P.eb64, P.ep64, bvec(P, P.V), 0, 1, 0, i, j);
-    } else {
-        // |W^(1/2) b|: residual of x = 0 (the zeroed scratch vector), written to V_0
-        acc = outer_residual_cell(P.g, bvec(P, P.t3), bvec(P, P.b), 1, P.eb64, P.ep64, bvec(P, P.V), 0, 1, 0, i, j);
-    }
-    if (mode == kResRestart || mode == kResBnorm) {
-        const double s = block_sum(acc);
-        if (threadIdx.x == 0 && threadIdx.y == 0) P.part[by * P.nbx + bx] = s;
-    }
+    const Vec3 x = mode == kResRestart ? bvec(P, P.x) : bvec(P, P.t3);
+    const double acc = outer_residual_cell(P.g, x, bvec(P, P.b), 1, P.eb64, P.ep64, bvec(P, P.V), 0, 1, 0, i, j);
+    const double s = block_sum(acc);
+    if (threadIdx.x == 0 && threadIdx.y == 0) P.part[by * P.nbx + bx] = s;
 }
 
 // ---------------------------------------------------------------- Krylov
@@ -483,11 +498,9 @@ tph_status enqueue_iteration_t(tph_batch* b) {
     const int cur_pre = (nu_pre - 1) & 1;
     const int cur_post = (cur_pre + nu_post) & 1;
     const dim3 cells(b->n_cells);
-    for (int step = 0; step < b->d.uzawa_steps; ++step) {
-        const int src = step == 0 ? kPinKrylov : kPinInner;
-        if (step > 0)
-            hipLaunchKernelGGL(kb_outer, cells, dim3(64, 4), 0, st, b->d_prob, b->d_cells, act, b->d_j, (int)kResInner);
-        hipLaunchKernelGGL(kb_precond_in<T>, cells, dim3(64, 4), 0, st, lev, b->d_prob, b->d_cells, act, b->d_j, src);
+    const int S = b->d.uzawa_steps;
+    hipLaunchKernelGGL(kb_precond_in<T>, cells, dim3(64, 4), 0, st, lev, b->d_prob, b->d_cells, act, b->d_j);
+    for (int step = 0; step < S; ++step) {
         for (int d = 0; d < b->maxdepth; ++d) {
             if (b->n_tiles[d] == 0) continue;
             tile_launch(d, kModeZero, 0, 0, 0);
@@ -511,10 +524,13 @@ tph_status enqueue_iteration_t(tph_batch* b) {
                 cur = 1 - cur;
             }
         }
-        hipLaunchKernelGGL(kb_precond_out<T>, cells, dim3(64, 4), 0, st, lev, b->d_prob, b->d_cells, act, b->d_j, src,
-                           cur_post);
+        if (step < S - 1)
+            hipLaunchKernelGGL((kb_uzawa_link<T, kLinkNext>), cells, dim3(64, 4), 0, st, lev, b->d_prob, b->d_cells,
+                               act, b->d_j, step, S, cur_post);
+        else
+            hipLaunchKernelGGL((kb_uzawa_link<T, kLinkApply>), cells, dim3(64, 4), 0, st, lev, b->d_prob, b->d_cells,
+                               act, b->d_j, step, S, cur_post);
     }
-    hipLaunchKernelGGL(kb_outer, cells, dim3(64, 4), 0, st, b->d_prob, b->d_cells, act, b->d_j, (int)kResApply);
     const dim3 chunks(b->n_chunks);
     const dim3 rgrid(b->count, tph::kMaxRestart + 2);
     // classical Gram-Schmidt (dots and |w|^2, projection with the exact new
@@ -623,6 +639,8 @@ tph_status batch_create_impl(tph_batch* b, int count, const tph_desc* descs) {
         P.b = v.b;
         P.V = v.V;
         P.Z = v.Z;
+        P.t1 = v.t1;
+        P.t2 = v.t2;
         P.t3 = v.t3;
         P.F = v.F;
         P.n3 = v.n3;
@@ -736,8 +754,7 @@ tph_status batch_solve_impl(tph_batch* b, tph_info* infos) {
         const TphSolverView v = tph_internal_view(b->s[p]);
         B_HIP(hipMemsetAsync(v.t3, 0, v.n3 * sizeof(double), st));
     }
-    hipLaunchKernelGGL(kb_outer, cells, dim3(64, 4), 0, st, b->d_prob, b->d_cells, b->d_unfinished, b->d_j,
-                       (int)kResBnorm);
+    hipLaunchKernelGGL(kb_outer, cells, dim3(64, 4), 0, st, b->d_prob, b->d_cells, b->d_unfinished, (int)kResBnorm);
     hipLaunchKernelGGL(kb_reduce, dim3(P, 1), dim3(256), 0, st, b->d_prob, b->d_unfinished, b->d_j, 0, 1, 1,
                        kSlotMisc, nullptr);
     B_HIP(hipMemcpyAsync(b->h_scal, b->d_scal, (size_t)P * kScal * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -746,7 +763,7 @@ tph_status batch_solve_impl(tph_batch* b, tph_info* infos) {
     while (true) {
         // true residual of every unfinished problem into V_0
         B_TRY(set_mask(b->d_unfinished, h_unf));
-        hipLaunchKernelGGL(kb_outer, cells, dim3(64, 4), 0, st, b->d_prob, b->d_cells, b->d_unfinished, b->d_j,
+        hipLaunchKernelGGL(kb_outer, cells, dim3(64, 4), 0, st, b->d_prob, b->d_cells, b->d_unfinished,
                            (int)kResRestart);
         hipLaunchKernelGGL(kb_reduce, dim3(P, 1), dim3(256), 0, st, b->d_prob, b->d_unfinished, b->d_j, 0, 1, 1,
                            kSlotMisc, nullptr);

@@ -1759,6 +1759,8 @@ TphSolverView tph_internal_view(const tph_solver* s) {
     v.b = s->b;
     v.V = s->V;
     v.Z = s->Z;
+    v.t1 = s->t1;
+    v.t2 = s->t2;
     v.t3 = s->t3;
     v.F = s->F;
     v.n3 = s->n3;

@@ -28,6 +28,8 @@ struct TphSolverView {
     double* b;
     double* V;                    // restart + 1 basis vectors, stride n3
     double* Z;
+    double* t1;                   // scratch vectors (the Uzawa link's second z and pressure residual)
+    double* t2;
     double* t3;
     size_t F, n3;
 };

@@ -447,9 +447,12 @@ def test_adjoint_raises_when_the_forward_solve_does_not_converge():
         tph.StokesFunction.apply(eb, T(pr.eta_p), T(pr.rho_b), s, 0.0, -1.0)
 
 
+@pytest.mark.parametrize("steps", [1, 2, 3])
 @pytest.mark.parametrize("prec", [tph.FP64, tph.MIXED])
-def test_batched_solve_matches_oracle(prec):
-    """Uneven problems in one batch: each result matches its own oracle solve."""
+def test_batched_solve_matches_oracle(prec, steps):
+    """Uneven problems in one batch: each result matches its own oracle solve
+    (1, 2 and 3 Uzawa steps: the link passes alternate z between two buffers,
+    so odd and even step counts end differently)."""
     probs = [wl.sinker(64, radius=0.12, eta_in=30.0),
              wl.sinker(32, radius=0.2, eta_in=10.0),
              wl.random_viscosity(64, ell=0.15, contrast=100.0),
@@ -457,8 +460,8 @@ def test_batched_solve_matches_oracle(prec):
              wl.sinker(48, ny=32, lx=1.5, ly=1.0, center=(0.6, 0.5), eta_in=5.0),
              wl.sinker(64, radius=0.15, eta_in=200.0, bc=(1, 1, 0, 1))]
     shapes = [(p.nx, p.ny, p.lx, p.ly, p.bc) for p in probs]
-    print(f"[batch] prec={prec} shapes={shapes}", flush=True)
-    bat = tph.Batch(shapes, device=DEV, precision=prec, rtol=1e-11, max_iters=2000, restart=16)
+    print(f"[batch] prec={prec} steps={steps} shapes={shapes}", flush=True)
+    bat = tph.Batch(shapes, device=DEV, precision=prec, rtol=1e-11, max_iters=2000, restart=16, uzawa_steps=steps)
     bat.set_coefficients([T(p.eta_b) for p in probs], [T(p.eta_p) for p in probs],
                          [T(p.rho_b) for p in probs], [(p.gx, p.gy) for p in probs])
     vx, vy, pp, infos = bat.solve()
@@ -471,7 +474,7 @@ def test_batched_solve_matches_oracle(prec):
         tol = 1e-7 if prec == tph.FP64 else 1e-6
         assert infos[k].res_energy < 1e-10
         assert ev < tol and epr < tol
-        assert infos[k].vcycles == infos[k].iters * 2          # uzawa_steps = 2 (default)
+        assert infos[k].vcycles == infos[k].iters * steps
         assert 0.0 <= infos[k].res_l2 < 1e-6
         _check_solution_contract(pr.nx, pr.ny, pr.bc, N(vx[k]), N(vy[k]), N(pp[k]))
     # a second solve on the same batch (graph replay, masks reset) gives the same answer
