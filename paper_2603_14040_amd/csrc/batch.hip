@@ -356,6 +356,11 @@ struct tph_batch {
     hipStream_t st = nullptr;                      // own stream (graph capture needs a non-null stream)
     hipStream_t user_st = nullptr;                 // caller's stream
     hipEvent_t ev = nullptr;
+    // per-problem work (set-ups, copies in and out, residual checks: a few
+    // small launches per problem) runs on streams of its own, problem p on
+    // ps[p % size], forked from and joined back to st by events
+    std::vector<hipStream_t> ps;
+    std::vector<hipEvent_t> pev;
     tph_desc d{};                                  // shared settings (first problem's)
     std::vector<tph_solver*> s;
     int maxdepth = 0;                              // fine depths driven by tile kernels
@@ -418,6 +423,26 @@ tph_status b_alloc(tph_batch* b, void** p, size_t bytes) {
         tph_status s_ = (expr);        \
         if (s_ != TPH_OK) return s_;   \
     } while (0)
+
+constexpr int kProblemStreams = 4;
+
+hipStream_t problem_stream(const tph_batch* b, int p) { return b->ps[(size_t)p % b->ps.size()]; }
+
+// the per-problem streams wait for the work enqueued so far on the batch stream
+tph_status fork_problems(tph_batch* b) {
+    B_HIP(hipEventRecord(b->ev, b->st));
+    for (hipStream_t q : b->ps) B_HIP(hipStreamWaitEvent(q, b->ev, 0));
+    return TPH_OK;
+}
+
+// the batch stream waits for the work enqueued so far on the per-problem streams
+tph_status join_problems(tph_batch* b) {
+    for (size_t k = 0; k < b->ps.size(); ++k) {
+        B_HIP(hipEventRecord(b->pev[k], b->ps[k]));
+        B_HIP(hipStreamWaitEvent(b->st, b->pev[k], 0));
+    }
+    return TPH_OK;
+}
 
 template <typename T>
 tph_status build_tables_t(tph_batch* b) {
@@ -596,7 +621,7 @@ tph_status batch_create_impl(tph_batch* b, int count, const tph_desc* descs) {
     }
     b->s.assign(count, nullptr);
     for (int p = 0; p < count; ++p) {
-        B_TRY(tph_create(&descs[p], b->st, &b->s[p]));
+        B_TRY(tph_create(&descs[p], problem_stream(b, p), &b->s[p]));
         const TphSolverView v = tph_internal_view(b->s[p]);
         if (v.lc < 0) {
             tph_internal_set_error("problem " + std::to_string(p) + " has no single-workgroup coarse tail");
@@ -750,10 +775,12 @@ tph_status batch_solve_impl(tph_batch* b, tph_info* infos) {
     };
     // |W^(1/2) b| per problem
     B_TRY(set_mask(b->d_unfinished, h_unf));
+    B_TRY(fork_problems(b));
     for (int p = 0; p < P; ++p) {
         const TphSolverView v = tph_internal_view(b->s[p]);
-        B_HIP(hipMemsetAsync(v.t3, 0, v.n3 * sizeof(double), st));
+        B_HIP(hipMemsetAsync(v.t3, 0, v.n3 * sizeof(double), problem_stream(b, p)));
     }
+    B_TRY(join_problems(b));
     hipLaunchKernelGGL(kb_outer, cells, dim3(64, 4), 0, st, b->d_prob, b->d_cells, b->d_unfinished, (int)kResBnorm);
     hipLaunchKernelGGL(kb_reduce, dim3(P, 1), dim3(256), 0, st, b->d_prob, b->d_unfinished, b->d_j, 0, 1, 1,
                        kSlotMisc, nullptr);
@@ -867,7 +894,9 @@ tph_status batch_solve_impl(tph_batch* b, tph_info* infos) {
     }
     const auto t1 = std::chrono::steady_clock::now();
     if (infos) {
+        B_TRY(fork_problems(b));
         for (int p = 0; p < P; ++p) B_TRY(tph_internal_plain_residual_enqueue(b->s[p]));
+        B_TRY(join_problems(b));
         B_HIP(hipStreamSynchronize(st));
     }
     tph_status worst = TPH_OK;
@@ -908,6 +937,22 @@ tph_status tph_batch_create(int32_t count, const tph_desc* descs, void* hip_stre
         tph_internal_set_error("could not create the batch stream");
         s = TPH_ERR_HIP;
     }
+    for (int k = 0; s == TPH_OK && k < std::min<int>(kProblemStreams, count); ++k) {
+        hipStream_t q = nullptr;
+        hipEvent_t e = nullptr;
+        if (hipStreamCreateWithFlags(&q, hipStreamNonBlocking) != hipSuccess) {
+            tph_internal_set_error("could not create the per-problem streams");
+            s = TPH_ERR_HIP;
+            break;
+        }
+        b->ps.push_back(q);
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            tph_internal_set_error("could not create the per-problem stream events");
+            s = TPH_ERR_HIP;
+            break;
+        }
+        b->pev.push_back(e);
+    }
     if (s == TPH_OK) s = batch_create_impl(b, count, descs);
     if (s != TPH_OK) {
         const std::string msg = tph_last_error();
@@ -932,9 +977,10 @@ tph_status tph_batch_set_coefficients(tph_batch* b, const double* const* eta_b, 
         tph_internal_set_error("could not order the batch stream after the caller's stream");
         return TPH_ERR_HIP;
     }
+    B_TRY(fork_problems(b));
     if (b->d_gj_mats) {
-        // every problem's setup enqueued on the batch stream, one launch factors all
-        // coarsest operators, one wait covers everything
+        // every problem's setup enqueued on its stream, one launch on the batch
+        // stream factors all coarsest operators
         for (int p = 0; p < b->count; ++p) {
             const tph_status s = tph_internal_setup_enqueue(b->s[p], eta_b[p], eta_p[p], rho_b[p], gxy[2 * p],
                                                             gxy[2 * p + 1]);
@@ -943,6 +989,7 @@ tph_status tph_batch_set_coefficients(tph_batch* b, const double* const* eta_b, 
                 return s;
             }
         }
+        B_TRY(join_problems(b));
         B_HIP(launch_gauss_jordan_batched(b->d_gj_mats, b->d_gj_n, b->count, b->gj_nmax, b->st));
         for (int p = 0; p < b->count; ++p) {
             const tph_status s = tph_internal_setup_finish(b->s[p]);
@@ -960,6 +1007,7 @@ tph_status tph_batch_set_coefficients(tph_batch* b, const double* const* eta_b, 
                 return s;
             }
         }
+        B_TRY(join_problems(b));
     }
     b->ready = true;
     return TPH_OK;
@@ -979,16 +1027,20 @@ tph_status tph_batch_solve(tph_batch* b, double* const* vx, double* const* vy, d
         tph_internal_set_error("could not order the batch stream after the caller's stream");
         return TPH_ERR_HIP;
     }
+    B_TRY(fork_problems(b));
     for (int q = 0; q < b->count; ++q) {
         const tph_status s = tph_internal_load_solution(b->s[q], vx[q], vy[q], p[q]);
         if (s != TPH_OK) return s;
     }
+    B_TRY(join_problems(b));
     const tph_status r = batch_solve_impl(b, infos);
     if (r < 0) return r;
+    B_TRY(fork_problems(b));
     for (int q = 0; q < b->count; ++q) {
         const tph_status s = tph_internal_finish_solution(b->s[q], vx[q], vy[q], p[q]);
         if (s != TPH_OK) return s;
     }
+    B_TRY(join_problems(b));
     const hipError_t e = hipStreamSynchronize(b->st);
     if (e != hipSuccess) {
         tph_internal_set_error(std::string("HIP error: ") + hipGetErrorString(e));
@@ -1000,6 +1052,7 @@ tph_status tph_batch_solve(tph_batch* b, double* const* vx, double* const* vy, d
 void tph_batch_destroy(tph_batch* b) {
     if (!b) return;
     if (b->st) (void)hipStreamSynchronize(b->st);
+    for (hipStream_t q : b->ps) (void)hipStreamSynchronize(q);
     if (b->iter_exec) (void)hipGraphExecDestroy(b->iter_exec);
     if (b->iter_graph) (void)hipGraphDestroy(b->iter_graph);
     for (tph_solver* s : b->s) tph_destroy(s);
@@ -1007,6 +1060,8 @@ void tph_batch_destroy(tph_batch* b) {
     if (b->h_scal) (void)hipHostFree(b->h_scal);
     if (b->h_j) (void)hipHostFree(b->h_j);
     if (b->h_int) (void)hipHostFree(b->h_int);
+    for (hipEvent_t e : b->pev) (void)hipEventDestroy(e);
+    for (hipStream_t q : b->ps) (void)hipStreamDestroy(q);
     if (b->ev) (void)hipEventDestroy(b->ev);
     if (b->st) (void)hipStreamDestroy(b->st);
     delete b;

@@ -71,8 +71,14 @@ hipError_t launch_coeff_gradient(const Geom& g, Vec3 x, Vec3 lam, double gx, dou
                                  double* g_eb, double* g_ep, double* g_rho, hipStream_t st);
 // adjoint right-hand side: fold gradients of ghost entries onto their interior owners
 hipError_t launch_fold_ghost_grad(const Geom& g, Vec3 v, hipStream_t st);
-// cast a field of the level (whole array)
-hipError_t launch_cast_f64_f32(const double* src, float* dst, size_t n, hipStream_t st);
+// FP64 -> FP32 casts of whole arrays in one launch (the viscosities of every level)
+struct CastList {
+    const double* src[2 * kMaxLevels];
+    float* dst[2 * kMaxLevels];
+    size_t n[2 * kMaxLevels];
+    int count;
+};
+hipError_t launch_cast_list(const CastList& c, hipStream_t st);
 
 // --------------------------------------------------------------- transfer.hip
 // coarse viscosities from fine ones (normalised bilinear gather; geometric = log-mean)

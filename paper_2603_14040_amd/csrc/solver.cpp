@@ -1683,11 +1683,17 @@ tph_status setup_enqueue(tph_solver* s, const double* eta_b, const double* eta_p
         TPH_HIP(launch_restrict_eta(s->lev[l - 1].g, s->lev[l].g, s->lev[l - 1].eb64, s->lev[l - 1].ep64,
                                     s->lev[l].eb64, s->lev[l].ep64, s->d.eta_mean == TPH_MEAN_GEOMETRIC, s->st));
     if (s->mixed()) {
+        CastList cl{};
         for (int l = 0; l < s->nlev; ++l) {
             const size_t n = field_alloc(s->lev[l].g);
-            TPH_HIP(launch_cast_f64_f32(s->lev[l].eb64 - (kAlign - 1), (float*)s->lev[l].eb - (kAlign - 1), n, s->st));
-            TPH_HIP(launch_cast_f64_f32(s->lev[l].ep64 - (kAlign - 1), (float*)s->lev[l].ep - (kAlign - 1), n, s->st));
+            cl.src[cl.count] = s->lev[l].eb64 - (kAlign - 1);
+            cl.dst[cl.count] = (float*)s->lev[l].eb - (kAlign - 1);
+            cl.n[cl.count++] = n;
+            cl.src[cl.count] = s->lev[l].ep64 - (kAlign - 1);
+            cl.dst[cl.count] = (float*)s->lev[l].ep - (kAlign - 1);
+            cl.n[cl.count++] = n;
         }
+        TPH_HIP(launch_cast_list(cl, s->st));
     }
     const LevelBuf& C = s->lev[s->nlev - 1];
     TPH_HIP(launch_coarse_assemble(C.g, C.eb64, C.ep64, s->Minv, s->st));

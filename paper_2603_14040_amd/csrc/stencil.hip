@@ -363,7 +363,11 @@ __global__ __launch_bounds__(256) void k_zero_vel(Geom g, T* __restrict__ ex, T*
     ey[i * g.pitch + j] = (T)0;
 }
 
-__global__ void k_cast_f64_f32(const double* __restrict__ s, float* __restrict__ d, size_t n) {
+// FP64 -> FP32 copies of whole arrays, one array of the list per blockIdx.y
+__global__ void k_cast_list(CastList c) {
+    const double* __restrict__ s = c.src[blockIdx.y];
+    float* __restrict__ d = c.dst[blockIdx.y];
+    const size_t n = c.n[blockIdx.y];
     for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
         d[t] = (float)s[t];
 }
@@ -514,9 +518,12 @@ hipError_t launch_fold_ghost_grad(const Geom& g, Vec3 v, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_cast_f64_f32(const double* src, float* dst, size_t n, hipStream_t st) {
-    const int nb = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
-    hipLaunchKernelGGL(k_cast_f64_f32, dim3(nb > 0 ? nb : 1), dim3(256), 0, st, src, dst, n);
+hipError_t launch_cast_list(const CastList& c, hipStream_t st) {
+    if (c.count < 1 || c.count > 2 * kMaxLevels) return hipErrorInvalidValue;
+    size_t nmax = 0;
+    for (int k = 0; k < c.count; ++k) nmax = c.n[k] > nmax ? c.n[k] : nmax;
+    const int nb = (int)((nmax + 255) / 256 < 4096 ? (nmax + 255) / 256 : 4096);
+    hipLaunchKernelGGL(k_cast_list, dim3(nb > 0 ? nb : 1, c.count), dim3(256), 0, st, c);
     return hipGetLastError();
 }
 
