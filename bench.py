@@ -270,7 +270,8 @@ def main():
         })
         out["configs"] = out.get("configs", {})
         out["configs"]["2_random_viscosity_1024"] = {
-            "mixed": {"value": cells / (ms_mix * 1e-3), "ms": ms_mix, **solve_stats(inf_mix)},
+            "mixed": {"value": cells / (ms_mix * 1e-3), "ms": ms_mix, **solve_stats(inf_mix),
+                      "vcycle_cells_per_s": cells * inf_mix[-1].vcycles / (ms_mix * 1e-3)},
             "fp64": ({"value": cells / (ms_64 * 1e-3), "ms": ms_64, **solve_stats(inf_64)} if inf_64 else None),
             "mixed_speedup_vs_fp64": (ms_64 / ms_mix) if ms_64 else None}
         s_mix.close()
@@ -451,8 +452,14 @@ def main():
                 ts.append(time.perf_counter() - t0)
             bdt = median(ts)
             its = [i.iters for i in binf]
+            # lockstep fill: useful problem-iterations (weighted by cells) over what a
+            # lockstep run to the slowest problem would cost with every problem active
+            cell_its = sum(p.cells * i.iters for p, i in zip(probs, binf))
+            vc_cells = sum(p.cells * i.vcycles for p, i in zip(probs, binf))
             batch[tag] = {"value": bcells / bdt, "ms": 1e3 * bdt, "ms_all": [round(1e3 * t, 1) for t in ts],
                           "iters_max": max(its), "iters_mean": sum(its) / len(its),
+                          "lockstep_fill": cell_its / (bcells * max(its)),
+                          "vcycle_cells_per_s": vc_cells / bdt,
                           "converged": sum(1 for i in binf if i.status == "TPH_OK"), "create_s": round(t_create, 2)}
             log(f"[bench] batch {tag}: median {1e3 * bdt:.1f} ms, {bcells / bdt:.3e} cells/s, iterations max "
                 f"{max(its)} mean {sum(its) / len(its):.1f}")
