@@ -75,6 +75,89 @@ def median(xs):
     return statistics.median(xs) if xs else None
 
 
+def eta_from_logvisc(m, n):
+    """eta_p = 10**m at cell centres, eta_b = 10**(mean of m over the touching
+    cells) at basic nodes, from a (n, n) torch tensor (differentiable)."""
+    import torch
+    ep = torch.ones((n + 2, n + 2), dtype=torch.float64, device=m.device)
+    ep = ep.index_put((torch.arange(1, n + 1, device=m.device)[:, None],
+                       torch.arange(1, n + 1, device=m.device)[None, :]), 10.0 ** m)
+    mp = torch.nn.functional.pad(m, (1, 1, 1, 1))
+    one = torch.nn.functional.pad(torch.ones_like(m), (1, 1, 1, 1))
+    s = mp[:-1, :-1] + mp[1:, :-1] + mp[:-1, 1:] + mp[1:, 1:]
+    c = one[:-1, :-1] + one[1:, :-1] + one[:-1, 1:] + one[1:, 1:]
+    eb = torch.nn.functional.pad(10.0 ** (s / c), (0, 1, 0, 1), value=1.0)
+    return eb, ep
+
+
+def fd_check(n, base, m, cells, m_true, dev, log):
+    """The adjoint workload's finite-difference check: dJ/dm (m = log10 eta_p
+    per cell) from the adjoint path (StokesFunction) against central
+    differences with h = 1e-3 on the given cells, two perturbed solves per
+    cell (mixed, 1e-11).  Each perturbed solution is v0 + d with
+    A(m +- h) d = b - A(m +- h) v0, so the solver error is relative to the
+    small correction.  Returns the wall time of the perturbed solves and the
+    largest relative error."""
+    import numpy as np
+    import torch
+    import paper_2603_14040_amd as tph
+    import workloads as wl
+    s = tph.Solver(n, n, precision=tph.MIXED, rtol=1e-11, max_iters=3000, device=dev)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+    rho = T(base.rho_b)
+    gx, gy = base.gx, base.gy
+    eb_t, ep_t = wl.logvisc_to_eta(m_true, n, n)
+    s.set_coefficients(T(eb_t), T(ep_t), rho, gx, gy)
+    target = s.solve()[0][n, 1:n].clone()
+
+    def J_of_v(vx):
+        return 0.5 * (1.0 / n) * torch.sum((vx[n, 1:n] - target) ** 2)
+
+    mt = T(m).requires_grad_(True)
+    eb, ep = eta_from_logvisc(mt, n)
+    vx, _, _ = tph.StokesFunction.apply(eb, ep, rho, s, gx, gy)
+    J_of_v(vx).backward()
+    grad = mt.grad.detach().cpu().numpy()
+    gmax = float(np.abs(grad).max())
+    with torch.no_grad():
+        eb0, ep0 = eta_from_logvisc(T(m), n)
+        s.set_coefficients(eb0, ep0, rho, gx, gy)
+        vx0, vy0, p0, _ = s.solve()
+        bx, by = torch.zeros_like(rho), torch.zeros_like(rho)
+        bx[1:n + 1, 1:n] = -gx * 0.5 * (rho[0:n, 1:n] + rho[1:n + 1, 1:n])
+        by[1:n, 1:n + 1] = -gy * 0.5 * (rho[1:n, 0:n] + rho[1:n, 1:n + 1])
+
+        def J_pert(mm):
+            ebp, epp = eta_from_logvisc(mm, n)
+            s.set_coefficients(ebp, epp, rho, gx, gy)
+            ax, ay, ap = s.apply(vx0, vy0, p0)
+            dvx, _, _, info = s.solve_rhs(bx - ax, by - ay, -ap)
+            if info.res_energy > 1e-9:
+                raise RuntimeError(f"finite-difference solve stopped at {info.res_energy:.2e}")
+            return float(J_of_v(vx0 + dvx))
+
+        h = 1e-3
+        errs = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for (ci, cj) in cells:
+            i, j = int(ci) - 1, int(cj) - 1
+            mp_, mm_ = T(m), T(m)
+            mp_[i, j] += h
+            mm_[i, j] -= h
+            fd = (J_pert(mp_) - J_pert(mm_)) / (2 * h)
+            errs.append(abs(grad[i, j] - fd) / max(abs(fd), 1e-3 * gmax))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    s.close()
+    res = {"cells": len(cells), "solves": 2 * len(cells), "seconds": round(dt, 3),
+           "ms_per_solve": 1e3 * dt / (2 * len(cells)), "max_rel_err": float(max(errs)),
+           "median_rel_err": float(np.median(errs)), "passed": bool(max(errs) <= 1e-4)}
+    log(f"[bench] adjoint finite-difference check: {2 * len(cells)} solves in {dt:.2f} s, max rel err "
+        f"{res['max_rel_err']:.2e}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +186,8 @@ def main():
     ap.add_argument("--batch-reps", type=int, default=5, help="timed batched solves per precision (median)")
     ap.add_argument("--batch-precisions", default="mixed,fp64", help="precisions of the batched runs")
     ap.add_argument("--adjoint-reps", type=int, default=5)
+    ap.add_argument("--fd-cells", type=int, default=64,
+                    help="cells of the adjoint finite-difference check (two perturbed solves each; 0: skip)")
     ap.add_argument("--config1-steps", type=int, default=20)
     ap.add_argument("--accel-steps", type=int, default=5)
     ap.add_argument("--ras-steps", type=int, default=5)
@@ -522,6 +607,8 @@ def main():
             log(f"[bench] adjoint {tag}: forward {fwd:.1f} ms, adjoint {adm:.1f} ms, gradient {grd:.2f} ms, "
                 f"autograd step {adj[tag]['autograd_step_ms']:.1f} ms")
             sa.close()
+        if args.fd_cells > 0:
+            adj["fd_check"] = fd_check(n, base, m, cells_[:args.fd_cells], m_true, dev, log)
         out.setdefault("configs", {})["5_adjoint_1024"] = adj
 
     # ---------------------------------------------------------------- accelerators (next row N2)
