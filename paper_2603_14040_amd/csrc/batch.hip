@@ -87,7 +87,7 @@ __device__ __forceinline__ int item_index() {
 
 // ------------------------------------------------------------------ V-cycle
 template <typename T, int SM, int MODE>
-__global__ __launch_bounds__(256) void kb_smooth_tile(const BLevel<T>* __restrict__ lev,
+__global__ __launch_bounds__(kTileThreads) void kb_smooth_tile(const BLevel<T>* __restrict__ lev,
                                                      const BProb* __restrict__ prob, const int2* __restrict__ items,
                                                      const int* __restrict__ active, int depth, int src, int dst,
                                                      int ccur_post, T omega) {
@@ -506,8 +506,8 @@ tph_status enqueue_iteration_t(tph_batch* b) {
     auto tile_launch = [&](int d, int mode, int src, int dst, int ccur) {
         const dim3 grid(b->n_tiles[d]);
 #define KB(SM_, MODE_)                                                                                          \
-    hipLaunchKernelGGL((kb_smooth_tile<T, SM_, MODE_>), grid, dim3(256), 0, st, lev, b->d_prob, b->d_tiles[d], act, \
-                       d, src, dst, ccur, om)
+    hipLaunchKernelGGL((kb_smooth_tile<T, SM_, MODE_>), grid, dim3(kTileThreads), 0, st, lev, b->d_prob,            \
+                       b->d_tiles[d], act, d, src, dst, ccur, om)
         if (sm == TPH_SMOOTH_GS) {
             if (mode == kModeZero) KB(kSmGS, kModeZero);
             else if (mode == kModeProlong) KB(kSmGS, kModeProlong);

@@ -11,7 +11,7 @@ namespace {
 using namespace dev;
 
 template <typename T, int TW, int TH, int SM, int MODE>
-__global__ __launch_bounds__(256) void k_smooth_tile(Geom g, Geom gc, const T* __restrict__ exi,
+__global__ __launch_bounds__(kTileThreads) void k_smooth_tile(Geom g, Geom gc, const T* __restrict__ exi,
                                                     const T* __restrict__ eyi, T* __restrict__ exo,
                                                     T* __restrict__ eyo, const T* __restrict__ rx,
                                                     const T* __restrict__ ry, const T* __restrict__ eb,
@@ -61,11 +61,11 @@ hipError_t launch_smooth_tile(const Geom& g, const Geom* gc, int smoother, int m
 #define TPH_SMT(SM, MODE)                                                                                        \
     do {                                                                                                          \
         if (t0)                                                                                                   \
-            hipExtLaunchKernelGGL((k_smooth_tile<T, TW, TH, SM, MODE>), grid, dim3(256), 0, st, t0, t1, 0, g, gcc, \
-                                  exi, eyi, exo, eyo, rx, ry, eb, ep, ecx, ecy, omega);                         \
+            hipExtLaunchKernelGGL((k_smooth_tile<T, TW, TH, SM, MODE>), grid, dim3(kTileThreads), 0, st, t0, t1, \
+                                  0, g, gcc, exi, eyi, exo, eyo, rx, ry, eb, ep, ecx, ecy, omega);              \
         else                                                                                                      \
-            hipLaunchKernelGGL((k_smooth_tile<T, TW, TH, SM, MODE>), grid, dim3(256), 0, st, g, gcc, exi, eyi,    \
-                               exo, eyo, rx, ry, eb, ep, ecx, ecy, omega);                                        \
+            hipLaunchKernelGGL((k_smooth_tile<T, TW, TH, SM, MODE>), grid, dim3(kTileThreads), 0, st, g, gcc, exi, \
+                               eyi, exo, eyo, rx, ry, eb, ep, ecx, ecy, omega);                                   \
     } while (0)
     if (smoother == kSmGS) {
         if (mode == kModeZero) TPH_SMT(kSmGS, kModeZero);

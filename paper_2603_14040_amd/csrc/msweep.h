@@ -2,7 +2,7 @@
 // fused_dev.h) and their launcher, instantiated per arithmetic type in
 // msweep_f32.hip / msweep_f64.hip.
 //
-// Tile shapes (fine nodes, TW x TH; 256 threads per tile):
+// Tile shapes (fine nodes, TW x TH; kTileThreads threads per tile):
 //   shape 0, FP32: 64 x 16 for one or two sweeps per pass
 //   shape 0, FP64: 64 x 8 for one sweep, 32 x 8 for two (64 KB of LDS)
 //   shape 1: 32 x 8 (FP32) / 32 x 4 (FP64): four times the tiles, for
@@ -24,12 +24,13 @@ struct TileShape {
 };
 
 template <typename T, int TW, int TH, int NS, int MODE, int RR>
-__global__ __launch_bounds__(256) void k_gs_tile(Geom g, Geom gc, const T* __restrict__ exi, const T* __restrict__ eyi,
-                                                T* __restrict__ exo, T* __restrict__ eyo, const T* __restrict__ rx,
-                                                const T* __restrict__ ry, const T* __restrict__ eb,
-                                                const T* __restrict__ ep, const T* __restrict__ ecx,
-                                                const T* __restrict__ ecy, T* __restrict__ rcx, T* __restrict__ rcy,
-                                                T omega) {
+__global__ __launch_bounds__(kTileThreads) void k_gs_tile(Geom g, Geom gc, const T* __restrict__ exi,
+                                                         const T* __restrict__ eyi, T* __restrict__ exo,
+                                                         T* __restrict__ eyo, const T* __restrict__ rx,
+                                                         const T* __restrict__ ry, const T* __restrict__ eb,
+                                                         const T* __restrict__ ep, const T* __restrict__ ecx,
+                                                         const T* __restrict__ ecy, T* __restrict__ rcx,
+                                                         T* __restrict__ rcy, T omega) {
     int tbx, tby;
     xcd_tile(tbx, tby);
     gs_tile_body<T, TW, TH, NS, MODE, RR>(g, gc, exi, eyi, exo, eyo, rx, ry, eb, ep, ecx, ecy, rcx, rcy, omega, tbx,
@@ -43,11 +44,11 @@ hipError_t launch_one(const Geom& g, const Geom& gc, const T* exi, const T* eyi,
     constexpr int TW = TileShape<T, NS, SHAPE>::TW, TH = TileShape<T, NS, SHAPE>::TH;
     const dim3 grid((g.nx + TW - 1) / TW, (g.ny + TH - 1) / TH);
     if (t0)
-        hipExtLaunchKernelGGL((k_gs_tile<T, TW, TH, NS, MODE, RR>), grid, dim3(256), 0, st, t0, t1, 0, g, gc, exi, eyi,
-                              exo, eyo, rx, ry, eb, ep, ecx, ecy, rcx, rcy, omega);
+        hipExtLaunchKernelGGL((k_gs_tile<T, TW, TH, NS, MODE, RR>), grid, dim3(kTileThreads), 0, st, t0, t1, 0, g,
+                              gc, exi, eyi, exo, eyo, rx, ry, eb, ep, ecx, ecy, rcx, rcy, omega);
     else
-        hipLaunchKernelGGL((k_gs_tile<T, TW, TH, NS, MODE, RR>), grid, dim3(256), 0, st, g, gc, exi, eyi, exo, eyo, rx,
-                           ry, eb, ep, ecx, ecy, rcx, rcy, omega);
+        hipLaunchKernelGGL((k_gs_tile<T, TW, TH, NS, MODE, RR>), grid, dim3(kTileThreads), 0, st, g, gc, exi, eyi,
+                           exo, eyo, rx, ry, eb, ep, ecx, ecy, rcx, rcy, omega);
     return hipGetLastError();
 }
 
