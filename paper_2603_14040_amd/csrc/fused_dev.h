@@ -1017,8 +1017,11 @@ __device__ __forceinline__ void coarse_cycle_body(const CoarseArgs<T>& A) {
 
 template <typename T>
 constexpr int tile_h() { return sizeof(T) == 4 ? 16 : 8; }
+// coarse cells per fused residual + restriction tile: kRRTileW x rr_tile_h
+// (one thread each; 32 x 8 for either type: taller FP32 tiles gained nothing,
+// 32 x 4 FP64 tiles were 2 % slower per solve)
 template <typename T>
-constexpr int rr_tile_h() { return sizeof(T) == 4 ? 8 : 4; }
+constexpr int rr_tile_h() { return 8; }
 constexpr int kTileW = 64;
 constexpr int kRRTileW = 32;
 
