@@ -131,7 +131,7 @@ def test_batched_256_sinkers_full_batch():
 TUNED_PLANS = {
     tph.MIXED: dict(nu_pre=1, nu_post=1, nu_growth=1.0, uzawa_steps=4, restart=8, msweep=30, tile_shape=126,
                     coarse_level=-1, omega=1.0, alpha=1.5, accel="gcr"),
-    tph.FP64: dict(nu_pre=1, nu_post=1, nu_growth=1.0, uzawa_steps=2, restart=10, msweep=30, tile_shape=124,
+    tph.FP64: dict(nu_pre=1, nu_post=1, nu_growth=1.0, uzawa_steps=2, restart=8, msweep=30, tile_shape=124,
                    coarse_level=-1, omega=1.0, alpha=1.5, accel="gcr"),
 }
 
