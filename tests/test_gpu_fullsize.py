@@ -12,7 +12,7 @@ workloads, in the launch configurations the benchmark times.
 * The benchmark's own tuned plans (the kernel plan and schedule the
   autotuner picks for the 1024^2 random-viscosity workload: GCR(8), 4 Uzawa
   steps, 1 + 1 sweeps, multi-sweep levels 1-4, small tiles below the finest
-  level, alpha 1.5 for the mixed solve; GCR(10), 2 Uzawa steps for FP64) on
+  level, alpha 1.5 for the mixed solve; GCR(8), 2 Uzawa steps for FP64) on
   the same recipe at 512^2, solved to a 1e-12 energy residual: element-wise
   against the oracle's direct (SuperLU) solve, <= 1e-7 (FP64) and <= 1e-6
   (mixed) relative L2 in v and in zero-mean p.
@@ -67,8 +67,9 @@ def test_multi_inclusion_4096_operator_windows_and_solve():
     n, m = 4096, 12
     pr = wl.multi_inclusion(n)
     print(f"[full] multi-inclusion {n}^2 built", flush=True)
-    s = tph.Solver(n, n, precision=tph.MIXED, device=DEV, accel="gcr", restart=64, uzawa_steps=8, nu_pre=1,
-                   nu_post=2, alpha=1.5, max_iters=1000)
+    # the benchmark's schedule for this workload (GCR(40), 16 Uzawa steps, 1 + 2 sweeps, alpha 1.75)
+    s = tph.Solver(n, n, precision=tph.MIXED, device=DEV, accel="gcr", restart=40, uzawa_steps=16, nu_pre=1,
+                   nu_post=2, alpha=1.75, max_iters=1000)
     s.set_coefficients(T(pr.eta_b), T(pr.eta_p), T(pr.rho_b), pr.gx, pr.gy)
     # operator at full size against the oracle on windows
     vx, vy, p = wl.random_state(n, n, seed=21)
