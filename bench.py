@@ -62,7 +62,7 @@ LARGE_PARAMS = {
 LARGE_TUNE_SEED = 13
 # Schedule of the 256-problem batch: autotune.tune_batch on a held-out batch
 # of the recipe (seed 14); `--tune-batch` repeats that search.
-BATCH_PARAMS = {"alpha": 1.5, "uzawa_steps": 4, "nu_pre": 2, "nu_post": 2, "restart": 16}
+BATCH_PARAMS = {"alpha": 1.5, "uzawa_steps": 8, "nu_pre": 2, "nu_post": 2, "restart": 16}
 BATCH_TUNE_SEED = 14
 HEADLINE_TUNE_SEEDS = (12, 32)        # GRF and noise seeds of the held-out tuning instance
 

@@ -336,9 +336,9 @@ def tune_batch(shapes, eta_b, eta_p, rho_b, gxy, *, precision: Optional[int] = N
     precision = MIXED if precision is None else precision
     t_start = time.perf_counter()
     start: Params = {"alpha": 1.0, "uzawa_steps": 2, "nu_pre": 2, "nu_post": 2, "restart": 16}
-    ks = knobs if knobs is not None else [Knob("alpha", [1.0, 1.5, 2.0]), Knob("uzawa_steps", [2, 3, 4]),
-                                          Knob("nu_pre", [1, 2]), Knob("nu_post", [1, 2]),
-                                          Knob("restart", [8, 16])]
+    ks = knobs if knobs is not None else [Knob("uzawa_steps", [2, 3, 4, 6, 8, 12]), Knob("restart", [6, 8, 12, 16, 24]),
+                                          Knob("alpha", [1.0, 1.5, 1.75, 2.0]), Knob("nu_pre", [1, 2, 3]),
+                                          Knob("nu_post", [1, 2, 3])]
 
     def measure(p: Params) -> float:
         b = Batch(shapes, device=device, precision=precision, rtol=rtol, **p)

@@ -105,7 +105,7 @@ def test_batched_256_sinkers_full_batch():
     shapes = [(p.nx, p.ny) for p in probs]
     print(f"[full] batch of {len(probs)}, {sum(p.cells for p in probs)} cells", flush=True)
     bat = tph.Batch(shapes, device=DEV, precision=tph.MIXED, rtol=1e-8, max_iters=3000, restart=16, alpha=1.5,
-                    uzawa_steps=4, nu_pre=2, nu_post=2)
+                    uzawa_steps=8, nu_pre=2, nu_post=2)
     bat.set_coefficients([T(p.eta_b) for p in probs], [T(p.eta_p) for p in probs], [T(p.rho_b) for p in probs],
                          [(p.gx, p.gy) for p in probs])
     vx, vy, pp, infos = bat.solve()
