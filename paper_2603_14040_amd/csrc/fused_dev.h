@@ -623,9 +623,8 @@ struct LGeo {            // a level inside LDS: tight pitch nx + 2
 // 64), so every lane of a wave has work on small levels and node indices come
 // from shifts instead of divisions by a runtime width.
 __device__ __forceinline__ int lanes_log2(int width) {
-    int s = 0;
-    while ((1 << s) < width && s < 6) ++s;
-    return s;
+    const int s = width <= 1 ? 0 : 32 - __clz(width - 1);
+    return s < 6 ? s : 6;
 }
 
 // one Gauss-Seidel colour half-sweep of component comp, in place
@@ -832,16 +831,20 @@ __device__ __forceinline__ void coarse_cycle_body(const CoarseArgs<T>& A) {
     }
     __syncthreads();
 
+    // The level tables are read from LDS once per level and phase group into
+    // registers (the colour phases then start without an LDS round trip).
     auto smooth = [&](int l, int nu) {
         T *ex = F(l, 0), *ey = F(l, 1), *rx = F(l, 2), *ry = F(l, 3), *eb = F(l, 4), *ep = F(l, 5);
+        const LGeo<T> Lg = L[l];
+        const LevelC<T> Kg = K[l];
         for (int s = 0; s < nu; ++s) {
             if (A.smoother == kSmGS) {
                 for (int h = 0; h < 4; ++h) {
-                    cc_gs_half(L[l], K[l], h >> 1, h & 1, ex, ey, rx, ry, eb, ep, A.omega);
+                    cc_gs_half(Lg, Kg, h >> 1, h & 1, ex, ey, rx, ry, eb, ep, A.omega);
                     __syncthreads();
                 }
             } else {
-                cc_jacobi(L[l], K[l], ex, ey, rx, ry, eb, ep, A.omega);
+                cc_jacobi(Lg, Kg, ex, ey, rx, ry, eb, ep, A.omega);
             }
         }
     };
@@ -849,7 +852,8 @@ __device__ __forceinline__ void coarse_cycle_body(const CoarseArgs<T>& A) {
     // ---- down: smooth, residual, restrict
     for (int l = 0; l < nl - 1; ++l) {
         smooth(l, A.nu_pre[l]);
-        const LGeo<T>& G = L[l];
+        const LGeo<T> G = L[l];
+        const LevelC<T> Kl = K[l];
         T *ex = F(l, 0), *ey = F(l, 1), *rx = F(l, 2), *ry = F(l, 3), *eb = F(l, 4), *ep = F(l, 5);
         int rt, rs_, ct, cs_;
         rowmap(G.P, rt, rs_, ct, cs_);
@@ -858,12 +862,12 @@ __device__ __forceinline__ void coarse_cycle_body(const CoarseArgs<T>& A) {
                 const int q = i * G.P + j;
                 const bool vx = i >= 1 && i <= G.ny && j >= 1 && j < G.nx;
                 const bool vy = i >= 1 && i < G.ny && j >= 1 && j <= G.nx;
-                tx[q] = vx ? rx[q] - lx_row(ex, ey, eb, ep, q, G.P, K[l].idx, K[l].idy) : (T)0;
-                ty[q] = vy ? ry[q] - ly_row(ex, ey, eb, ep, q, G.P, K[l].idx, K[l].idy) : (T)0;
+                tx[q] = vx ? rx[q] - lx_row(ex, ey, eb, ep, q, G.P, Kl.idx, Kl.idy) : (T)0;
+                ty[q] = vy ? ry[q] - ly_row(ex, ey, eb, ep, q, G.P, Kl.idx, Kl.idy) : (T)0;
             }
         }
         __syncthreads();
-        const LGeo<T>& C = L[l + 1];
+        const LGeo<T> C = L[l + 1];
         T *rcx = F(l + 1, 2), *rcy = F(l + 1, 3);
         rowmap(C.nx, rt, rs_, ct, cs_);
         for (int I = 1 + rt; I <= C.ny; I += rs_) {
@@ -971,8 +975,9 @@ __device__ __forceinline__ void coarse_cycle_body(const CoarseArgs<T>& A) {
 
     // ---- up: prolong + correct, post-smooth
     for (int l = nl - 2; l >= 0; --l) {
-        const LGeo<T>& G = L[l];
-        const LGeo<T>& C = L[l + 1];
+        const LGeo<T> G = L[l];
+        const LGeo<T> C = L[l + 1];
+        const LevelC<T> Kl = K[l];
         T *ex = F(l, 0), *ey = F(l, 1);
         const T *ecx = F(l + 1, 0), *ecy = F(l + 1, 1);
         int rt, rs_, ct, cs_;
@@ -983,14 +988,14 @@ __device__ __forceinline__ void coarse_cycle_body(const CoarseArgs<T>& A) {
                 if (j < G.nx) {
                     const T e = ex[c] + prolong_vx(ecx, C.P, i, j);
                     ex[c] = e;
-                    if (i == 1) ex[c - G.P] = K[l].mirS * e;
-                    if (i == G.ny) ex[c + G.P] = K[l].mirN * e;
+                    if (i == 1) ex[c - G.P] = Kl.mirS * e;
+                    if (i == G.ny) ex[c + G.P] = Kl.mirN * e;
                 }
                 if (i < G.ny) {
                     const T e = ey[c] + prolong_vy(ecy, C.P, i, j);
                     ey[c] = e;
-                    if (j == 1) ey[c - 1] = K[l].mirW * e;
-                    if (j == G.nx) ey[c + 1] = K[l].mirE * e;
+                    if (j == 1) ey[c - 1] = Kl.mirW * e;
+                    if (j == G.nx) ey[c + 1] = Kl.mirE * e;
                 }
             }
         }
