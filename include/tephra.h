@@ -443,10 +443,15 @@ void tph_destroy(tph_solver* s);
  * device work of one FGMRES iteration is captured once as a hipGraph and
  * replayed; converged problems are masked on the device.  All problems must
  * share precision, smoother, sweep counts (>= 1, nu_growth 1), omega, alpha,
- * eta_mean, restart, max_iters, uzawa_steps and rtol, use fused kernels, and
- * be large enough to have a coarse tail of at least one level (any grid whose
- * automatic hierarchy has >= 2 levels).  Pointer-array arguments are HOST
- * arrays of `count` DEVICE pointers with the single-problem conventions. */
+ * eta_mean, restart, max_iters, uzawa_steps, rtol and msweep, use fused
+ * kernels, and be large enough to have a coarse tail of at least one level
+ * (any grid whose automatic hierarchy has >= 2 levels).  With Gauss-Seidel,
+ * msweep selects the depths (bit d = level d of every problem; -1 = none,
+ * unlike a single solve) smoothed in multi-sweep passes (FP32: up to two
+ * sweeps per pass; FP64: one), the last pre-smoothing pass restricting the
+ * residual and the first post-smoothing pass applying the prolongation;
+ * tile_shape is not used.  Pointer-array arguments are HOST arrays of `count` DEVICE pointers
+ * with the single-problem conventions. */
 typedef struct tph_batch tph_batch;
 
 tph_status tph_batch_create(int32_t count, const tph_desc* descs, void* hip_stream, tph_batch** out);

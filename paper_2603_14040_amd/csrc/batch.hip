@@ -102,6 +102,33 @@ __global__ __launch_bounds__(kTileThreads) void kb_smooth_tile(const BLevel<T>* 
         L.ey[dst], L.rx, L.ry, L.eb, L.ep, C.ex[cc], C.ey[cc], omega, it.y & 0xffff, it.y >> 16);
 }
 
+// Multi-sweep pass over the tiles of one depth (the single solver's
+// gs_tile_body on the batch tables): NS Gauss-Seidel sweeps from zero, from
+// the iterate in buffer src, or from it plus the prolongated correction of
+// the next depth (buffer ccur there, 0 where that depth is the coarse
+// tail); with RR the pass ends with the residual restricted to the next
+// depth's right-hand side.  The tiles are the depth's one-sweep tiles
+// (kTileW x tile_h), which are the multi-sweep tiles for FP32 passes of one
+// or two sweeps and FP64 passes of one.
+template <typename T, int NS, int MODE, int RR>
+__global__ __launch_bounds__(kTileThreads) void kb_gs_tile(const BLevel<T>* __restrict__ lev,
+                                                          const BProb* __restrict__ prob,
+                                                          const int2* __restrict__ items,
+                                                          const int* __restrict__ active, int depth, int src, int dst,
+                                                          int ccur, T omega) {
+    const int2 it = items[item_index()];
+    const int p = it.x;
+    if (!active[p]) return;
+    const BLevel<T>& L = lev[p * kMaxLevels + depth];
+    const BLevel<T>& C = lev[p * kMaxLevels + depth + 1];
+    const int cc = (MODE == kModeProlong && depth + 1 != prob[p].lc) ? ccur : 0;
+    gs_tile_body<T, kTileW, tile_h<T>(), NS, MODE, RR>(
+        L.g, C.g, MODE == kModeZero ? nullptr : L.ex[src], MODE == kModeZero ? nullptr : L.ey[src], L.ex[dst],
+        L.ey[dst], L.rx, L.ry, L.eb, L.ep, MODE == kModeProlong ? C.ex[cc] : nullptr,
+        MODE == kModeProlong ? C.ey[cc] : nullptr, RR ? C.rx : nullptr, RR ? C.ry : nullptr, omega, it.y & 0xffff,
+        it.y >> 16);
+}
+
 template <typename T>
 __global__ __launch_bounds__(kRRTileW * rr_tile_h<T>()) void kb_res_restrict(const BLevel<T>* __restrict__ lev,
                                                                              const int2* __restrict__ items,
@@ -364,6 +391,7 @@ struct tph_batch {
     tph_desc d{};                                  // shared settings (first problem's)
     std::vector<tph_solver*> s;
     int maxdepth = 0;                              // fine depths driven by tile kernels
+    unsigned msw_mask = 0;                         // depths smoothed in multi-sweep passes (bit d)
     // device tables
     void* d_lev = nullptr;                         // BLevel<T>[count * kMaxLevels]
     BProb* d_prob = nullptr;
@@ -519,15 +547,63 @@ tph_status enqueue_iteration_t(tph_batch* b) {
         }
 #undef KB
     };
-    // ping-pong index after pre- and post-smoothing (the same for every problem)
-    const int cur_pre = (nu_pre - 1) & 1;
-    const int cur_post = (cur_pre + nu_post) & 1;
+    // Multi-sweep passes of a depth: passes of up to two sweeps (FP32) or of
+    // one (FP64), the last pre-smoothing pass with the residual restriction,
+    // the first post-smoothing pass with the prolongation.
+    auto msw_launch = [&](int d, int ns, int mode, int rr, int src, int dst, int ccur) {
+        const dim3 grid(b->n_tiles[d]);
+#define KG(NS_, MODE_, RR_)                                                                                    \
+    hipLaunchKernelGGL((kb_gs_tile<T, NS_, MODE_, RR_>), grid, dim3(kTileThreads), 0, st, lev, b->d_prob,       \
+                       b->d_tiles[d], act, d, src, dst, ccur, om)
+#define KG_NS(NS_)                                                                                             \
+    do {                                                                                                       \
+        if (mode == kModeProlong) KG(NS_, kModeProlong, 0);                                                    \
+        else if (mode == kModeZero) { if (rr) KG(NS_, kModeZero, 1); else KG(NS_, kModeZero, 0); }           \
+        else { if (rr) KG(NS_, kModePlain, 1); else KG(NS_, kModePlain, 0); }                                 \
+    } while (0)
+        if constexpr (sizeof(T) == 4) {
+            if (ns == 2) KG_NS(2);
+            else KG_NS(1);
+        } else {
+            KG_NS(1);
+        }
+#undef KG_NS
+#undef KG
+    };
+    const int max_ns = sizeof(T) == 4 ? 2 : 1;
+    auto msw = [&](int d) { return ((b->msw_mask >> d) & 1u) != 0; };
+    // buffer of the iterate after pre-smoothing and after post-smoothing, per
+    // depth (the same for every problem at that depth)
+    std::vector<int> cur_pre(b->maxdepth + 1, 0), fin(b->maxdepth + 1, 0);
+    for (int d = 0; d < b->maxdepth; ++d) {
+        if (msw(d)) {
+            const int np = (nu_pre + max_ns - 1) / max_ns, nq = (nu_post + max_ns - 1) / max_ns;
+            cur_pre[d] = (np - 1) & 1;
+            fin[d] = (cur_pre[d] + nq) & 1;
+        } else {
+            cur_pre[d] = (nu_pre - 1) & 1;
+            fin[d] = (cur_pre[d] + nu_post) & 1;
+        }
+    }
     const dim3 cells(b->n_cells);
     const int S = b->d.uzawa_steps;
     hipLaunchKernelGGL(kb_precond_in<T>, cells, dim3(64, 4), 0, st, lev, b->d_prob, b->d_cells, act, b->d_j);
     for (int step = 0; step < S; ++step) {
         for (int d = 0; d < b->maxdepth; ++d) {
             if (b->n_tiles[d] == 0) continue;
+            if (msw(d)) {
+                int cur = 0;
+                bool zero = true;
+                for (int left = nu_pre; left > 0;) {
+                    const int ns = left >= max_ns ? max_ns : 1;
+                    const int dst = zero ? 0 : 1 - cur;
+                    msw_launch(d, ns, zero ? kModeZero : kModePlain, left == ns ? 1 : 0, cur, dst, 0);
+                    cur = dst;
+                    zero = false;
+                    left -= ns;
+                }
+                continue;
+            }
             tile_launch(d, kModeZero, 0, 0, 0);
             int cur = 0;
             for (int k = 1; k < nu_pre; ++k) {
@@ -541,8 +617,19 @@ tph_status enqueue_iteration_t(tph_batch* b) {
                            (const CoarseArgs<T>*)b->d_cargs, act);
         for (int d = b->maxdepth - 1; d >= 0; --d) {
             if (b->n_tiles[d] == 0) continue;
-            int cur = cur_pre;
-            tile_launch(d, kModeProlong, cur, 1 - cur, cur_post);
+            int cur = cur_pre[d];
+            if (msw(d)) {
+                bool pro = true;
+                for (int left = nu_post; left > 0;) {
+                    const int ns = left >= max_ns ? max_ns : 1;
+                    msw_launch(d, ns, pro ? kModeProlong : kModePlain, 0, cur, 1 - cur, fin[d + 1]);
+                    cur = 1 - cur;
+                    pro = false;
+                    left -= ns;
+                }
+                continue;
+            }
+            tile_launch(d, kModeProlong, cur, 1 - cur, fin[d + 1]);
             cur = 1 - cur;
             for (int k = 1; k < nu_post; ++k) {
                 tile_launch(d, kModePlain, cur, 1 - cur, 0);
@@ -551,10 +638,10 @@ tph_status enqueue_iteration_t(tph_batch* b) {
         }
         if (step < S - 1)
             hipLaunchKernelGGL((kb_uzawa_link<T, kLinkNext>), cells, dim3(64, 4), 0, st, lev, b->d_prob, b->d_cells,
-                               act, b->d_j, step, S, cur_post);
+                               act, b->d_j, step, S, fin[0]);
         else
             hipLaunchKernelGGL((kb_uzawa_link<T, kLinkApply>), cells, dim3(64, 4), 0, st, lev, b->d_prob, b->d_cells,
-                               act, b->d_j, step, S, cur_post);
+                               act, b->d_j, step, S, fin[0]);
     }
     const dim3 chunks(b->n_chunks);
     const dim3 rgrid(b->count, tph::kMaxRestart + 2);
@@ -601,9 +688,10 @@ tph_status batch_create_impl(tph_batch* b, int count, const tph_desc* descs) {
         if (q.precision != r.precision || q.smoother != r.smoother || q.nu_pre != r.nu_pre || q.nu_post != r.nu_post ||
             q.nu_growth != r.nu_growth || q.omega != r.omega || q.alpha != r.alpha || q.restart != r.restart ||
             q.max_iters != r.max_iters || q.uzawa_steps != r.uzawa_steps || q.rtol != r.rtol || q.fused != 1 ||
-            q.nu_pre < 1 || q.nu_post < 1 || q.nu_growth != 1.0) {
+            q.nu_pre < 1 || q.nu_post < 1 || q.nu_growth != 1.0 || q.msweep != r.msweep) {
             tph_internal_set_error("batched problems must share precision, smoother, sweeps (>= 1, no growth), "
-                                   "omega, alpha, restart, max_iters, uzawa_steps and rtol, with fused kernels");
+                                   "omega, alpha, restart, max_iters, uzawa_steps, rtol and msweep, with fused "
+                                   "kernels");
             return TPH_ERR_INVALID;
         }
         if (q.smoother != TPH_SMOOTH_JACOBI && q.smoother != TPH_SMOOTH_GS) {
@@ -628,6 +716,14 @@ tph_status batch_create_impl(tph_batch* b, int count, const tph_desc* descs) {
             return TPH_ERR_UNSUPPORTED;
         }
         b->maxdepth = std::max(b->maxdepth, v.lc);
+    }
+    // depths smoothed in multi-sweep passes (desc.msweep: bit d = depth d;
+    // -1, the default, = none: with many problems in flight the one-sweep
+    // launches are wide enough that the halo recomputation of the passes
+    // costs more than the launches they save; Gauss-Seidel only)
+    if (b->d.smoother == TPH_SMOOTH_GS && b->maxdepth > 0 && b->d.msweep > 0) {
+        const unsigned all = b->maxdepth >= 32 ? ~0u : ((1u << b->maxdepth) - 1u);
+        b->msw_mask = (unsigned)b->d.msweep & all;
     }
     {
         std::vector<double*> mats(count);

@@ -447,12 +447,16 @@ def test_adjoint_raises_when_the_forward_solve_does_not_converge():
         tph.StokesFunction.apply(eb, T(pr.eta_p), T(pr.rho_b), s, 0.0, -1.0)
 
 
-@pytest.mark.parametrize("steps", [1, 2, 3])
+@pytest.mark.parametrize("steps,nu,msweep", [(1, 2, -1), (2, 2, 0b10), (3, 2, -1), (2, 1, 0b10), (2, 3, 0b10),
+                                             (2, 2, 0), (2, 3, 0b101), (3, 1, 0b111)])
 @pytest.mark.parametrize("prec", [tph.FP64, tph.MIXED])
-def test_batched_solve_matches_oracle(prec, steps):
+def test_batched_solve_matches_oracle(prec, steps, nu, msweep):
     """Uneven problems in one batch: each result matches its own oracle solve
     (1, 2 and 3 Uzawa steps: the link passes alternate z between two buffers,
-    so odd and even step counts end differently)."""
+    so odd and even step counts end differently; 1-3 sweeps with multi-sweep
+    passes on no depth (the batch default), on every depth but the finest,
+    on chosen depths and on every depth, which changes the buffers each depth
+    ends in)."""
     probs = [wl.sinker(64, radius=0.12, eta_in=30.0),
              wl.sinker(32, radius=0.2, eta_in=10.0),
              wl.random_viscosity(64, ell=0.15, contrast=100.0),
@@ -460,8 +464,9 @@ def test_batched_solve_matches_oracle(prec, steps):
              wl.sinker(48, ny=32, lx=1.5, ly=1.0, center=(0.6, 0.5), eta_in=5.0),
              wl.sinker(64, radius=0.15, eta_in=200.0, bc=(1, 1, 0, 1))]
     shapes = [(p.nx, p.ny, p.lx, p.ly, p.bc) for p in probs]
-    print(f"[batch] prec={prec} steps={steps} shapes={shapes}", flush=True)
-    bat = tph.Batch(shapes, device=DEV, precision=prec, rtol=1e-11, max_iters=2000, restart=16, uzawa_steps=steps)
+    print(f"[batch] prec={prec} steps={steps} nu={nu} msweep={msweep} shapes={shapes}", flush=True)
+    bat = tph.Batch(shapes, device=DEV, precision=prec, rtol=1e-11, max_iters=2000, restart=16, uzawa_steps=steps,
+                    nu_pre=nu, nu_post=nu, msweep=msweep)
     bat.set_coefficients([T(p.eta_b) for p in probs], [T(p.eta_p) for p in probs],
                          [T(p.rho_b) for p in probs], [(p.gx, p.gy) for p in probs])
     vx, vy, pp, infos = bat.solve()
