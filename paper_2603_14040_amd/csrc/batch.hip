@@ -67,7 +67,7 @@ struct BProb {
     double* t3;
     size_t F, n3;
     int nchunk;                    // Krylov work items per vector
-    int ncell;                     // 64 x 4 cell blocks of the finest level
+    int ncell;                     // kCellBX x kCellBY cell blocks of the finest level
     int nbx;                       // cell blocks per row
     int lc;                        // level of the coarse-tail kernel
     double alpha;
@@ -154,16 +154,18 @@ __global__ __launch_bounds__(coarse_threads<T>()) void kb_coarse(const CoarseArg
 // Entry of the preconditioner: the level-0 right-hand side from the Krylov
 // basis vector V_j (energy-scaled).
 template <typename T>
-__global__ __launch_bounds__(256) void kb_precond_in(const BLevel<T>* __restrict__ lev, const BProb* __restrict__ prob,
-                                                    const int2* __restrict__ items, const int* __restrict__ active,
-                                                    const int* __restrict__ dj) {
+__global__ __launch_bounds__(kCellBX * kCellBY) void kb_precond_in(const BLevel<T>* __restrict__ lev,
+                                                                   const BProb* __restrict__ prob,
+                                                                   const int2* __restrict__ items,
+                                                                   const int* __restrict__ active,
+                                                                   const int* __restrict__ dj) {
     const int2 it = items[item_index()];
     const int p = it.x;
     if (!active[p]) return;
     const BProb& P = prob[p];
     const Vec3 v = bvec(P, P.V + (size_t)(*dj) * P.n3);
-    const int j = (it.y & 0xffff) * 64 + threadIdx.x + 1;
-    const int i = (it.y >> 16) * 4 + threadIdx.y + 1;
+    const int j = (it.y & 0xffff) * kCellBX + threadIdx.x + 1;
+    const int i = (it.y >> 16) * kCellBY + threadIdx.y + 1;
     precond_in_cell<T>(P.g, v, P.eb64, P.ep64, 1, lev[p * kMaxLevels].rx, lev[p * kMaxLevels].ry, i, j);
 }
 
@@ -173,10 +175,11 @@ __global__ __launch_bounds__(256) void kb_precond_in(const BLevel<T>* __restrict
 // V_{j+1} = W^(1/2) A Z_j (kLinkApply).  z alternates between t1 and Z_j so
 // that the last step writes Z_j; the pressure residual between t3 and t2.
 template <typename T, int MODE>
-__global__ __launch_bounds__(256) void kb_uzawa_link(const BLevel<T>* __restrict__ lev,
-                                                    const BProb* __restrict__ prob, const int2* __restrict__ items,
-                                                    const int* __restrict__ active, const int* __restrict__ dj,
-                                                    int q, int S, int cur) {
+__global__ __launch_bounds__(kCellBX * kCellBY) void kb_uzawa_link(const BLevel<T>* __restrict__ lev,
+                                                                   const BProb* __restrict__ prob,
+                                                                   const int2* __restrict__ items,
+                                                                   const int* __restrict__ active,
+                                                                   const int* __restrict__ dj, int q, int S, int cur) {
     const int2 it = items[item_index()];
     const int p = it.x;
     if (!active[p]) return;
@@ -205,8 +208,8 @@ __global__ __launch_bounds__(256) void kb_uzawa_link(const BLevel<T>* __restrict
     a.tp = (q & 1) ? tp1 : tp0;
     a.wout = bvec(P, P.V + (size_t)(jj + 1) * P.n3);
     a.w_scaled = 1;
-    const int j = (it.y & 0xffff) * 64 + threadIdx.x + 1;
-    const int i = (it.y >> 16) * 4 + threadIdx.y + 1;
+    const int j = (it.y & 0xffff) * kCellBX + threadIdx.x + 1;
+    const int i = (it.y >> 16) * kCellBY + threadIdx.y + 1;
     uzawa_link_cell<T, MODE>(P.g, a, P.eb64, P.ep64, i, j);
 }
 
@@ -214,15 +217,16 @@ enum { kResRestart = 0, kResBnorm = 1 };
 
 // FP64 residual at a restart: V_0 = W^(1/2) (b - A x), or of x = 0 (the
 // zeroed scratch vector t3) for |W^(1/2) b|; block sums of squares to part
-__global__ __launch_bounds__(256) void kb_outer(const BProb* __restrict__ prob, const int2* __restrict__ items,
-                                               const int* __restrict__ active, int mode) {
+__global__ __launch_bounds__(kCellBX * kCellBY) void kb_outer(const BProb* __restrict__ prob,
+                                                              const int2* __restrict__ items,
+                                                              const int* __restrict__ active, int mode) {
     const int2 it = items[item_index()];
     const int p = it.x;
     if (!active[p]) return;
     const BProb& P = prob[p];
     const int bx = it.y & 0xffff, by = it.y >> 16;
-    const int j = bx * 64 + threadIdx.x + 1;
-    const int i = by * 4 + threadIdx.y + 1;
+    const int j = bx * kCellBX + threadIdx.x + 1;
+    const int i = by * kCellBY + threadIdx.y + 1;
     const Vec3 x = mode == kResRestart ? bvec(P, P.x) : bvec(P, P.t3);
     const double acc = outer_residual_cell(P.g, x, bvec(P, P.b), 1, P.eb64, P.ep64, bvec(P, P.V), 0, 1, 0, i, j);
     const double s = block_sum(acc);
@@ -587,7 +591,7 @@ tph_status enqueue_iteration_t(tph_batch* b) {
     }
     const dim3 cells(b->n_cells);
     const int S = b->d.uzawa_steps;
-    hipLaunchKernelGGL(kb_precond_in<T>, cells, dim3(64, 4), 0, st, lev, b->d_prob, b->d_cells, act, b->d_j);
+    hipLaunchKernelGGL(kb_precond_in<T>, cells, dim3(kCellBX, kCellBY), 0, st, lev, b->d_prob, b->d_cells, act, b->d_j);
     for (int step = 0; step < S; ++step) {
         for (int d = 0; d < b->maxdepth; ++d) {
             if (b->n_tiles[d] == 0) continue;
@@ -637,10 +641,10 @@ tph_status enqueue_iteration_t(tph_batch* b) {
             }
         }
         if (step < S - 1)
-            hipLaunchKernelGGL((kb_uzawa_link<T, kLinkNext>), cells, dim3(64, 4), 0, st, lev, b->d_prob, b->d_cells,
+            hipLaunchKernelGGL((kb_uzawa_link<T, kLinkNext>), cells, dim3(kCellBX, kCellBY), 0, st, lev, b->d_prob, b->d_cells,
                                act, b->d_j, step, S, fin[0]);
         else
-            hipLaunchKernelGGL((kb_uzawa_link<T, kLinkApply>), cells, dim3(64, 4), 0, st, lev, b->d_prob, b->d_cells,
+            hipLaunchKernelGGL((kb_uzawa_link<T, kLinkApply>), cells, dim3(kCellBX, kCellBY), 0, st, lev, b->d_prob, b->d_cells,
                                act, b->d_j, step, S, fin[0]);
     }
     const dim3 chunks(b->n_chunks);
@@ -766,8 +770,8 @@ tph_status batch_create_impl(tph_batch* b, int count, const tph_desc* descs) {
         P.F = v.F;
         P.n3 = v.n3;
         P.nchunk = (int)((v.n3 + kChunk - 1) / kChunk);
-        P.nbx = (P.g.nx + 63) / 64;
-        P.ncell = P.nbx * ((P.g.ny + 3) / 4);
+        P.nbx = (P.g.nx + kCellBX - 1) / kCellBX;
+        P.ncell = P.nbx * ((P.g.ny + kCellBY - 1) / kCellBY);
         P.lc = v.lc;
         P.alpha = descs[p].alpha;
         P.prow = std::max(P.nchunk, P.ncell);
@@ -797,7 +801,7 @@ tph_status batch_create_impl(tph_batch* b, int count, const tph_desc* descs) {
             for (int y = 0; y < cby; ++y)
                 for (int x = 0; x < cbx; ++x) rr[d].push_back(make_int2(p, x | (y << 16)));
         }
-        for (int y = 0; y < (P.g.ny + 3) / 4; ++y)
+        for (int y = 0; y < (P.g.ny + kCellBY - 1) / kCellBY; ++y)
             for (int x = 0; x < P.nbx; ++x) cells.push_back(make_int2(p, x | (y << 16)));
         for (int c = 0; c < P.nchunk; ++c) chunks.push_back(make_int2(p, c));
     }
@@ -877,7 +881,7 @@ tph_status batch_solve_impl(tph_batch* b, tph_info* infos) {
         B_HIP(hipMemsetAsync(v.t3, 0, v.n3 * sizeof(double), problem_stream(b, p)));
     }
     B_TRY(join_problems(b));
-    hipLaunchKernelGGL(kb_outer, cells, dim3(64, 4), 0, st, b->d_prob, b->d_cells, b->d_unfinished, (int)kResBnorm);
+    hipLaunchKernelGGL(kb_outer, cells, dim3(kCellBX, kCellBY), 0, st, b->d_prob, b->d_cells, b->d_unfinished, (int)kResBnorm);
     hipLaunchKernelGGL(kb_reduce, dim3(P, 1), dim3(256), 0, st, b->d_prob, b->d_unfinished, b->d_j, 0, 1, 1,
                        kSlotMisc, nullptr);
     B_HIP(hipMemcpyAsync(b->h_scal, b->d_scal, (size_t)P * kScal * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -886,7 +890,7 @@ tph_status batch_solve_impl(tph_batch* b, tph_info* infos) {
     while (true) {
         // true residual of every unfinished problem into V_0
         B_TRY(set_mask(b->d_unfinished, h_unf));
-        hipLaunchKernelGGL(kb_outer, cells, dim3(64, 4), 0, st, b->d_prob, b->d_cells, b->d_unfinished,
+        hipLaunchKernelGGL(kb_outer, cells, dim3(kCellBX, kCellBY), 0, st, b->d_prob, b->d_cells, b->d_unfinished,
                            (int)kResRestart);
         hipLaunchKernelGGL(kb_reduce, dim3(P, 1), dim3(256), 0, st, b->d_prob, b->d_unfinished, b->d_j, 0, 1, 1,
                            kSlotMisc, nullptr);

@@ -71,6 +71,13 @@ hipError_t launch_coeff_gradient(const Geom& g, Vec3 x, Vec3 lam, double gx, dou
                                  double* g_eb, double* g_ep, double* g_rho, hipStream_t st);
 // adjoint right-hand side: fold gradients of ghost entries onto their interior owners
 hipError_t launch_fold_ghost_grad(const Geom& g, Vec3 v, hipStream_t st);
+// Cell block of the one-thread-per-cell kernels (operator apply, residuals,
+// Uzawa entry, exit and link passes, coefficient checks, and the batch's cell
+// work items): kCellBX x kCellBY cells, one thread each.  The per-block
+// reduction partials are sized from it.
+constexpr int kCellBX = 64;
+constexpr int kCellBY = 4;
+
 // FP64 -> FP32 casts of whole arrays in one launch (the viscosities of every level)
 struct CastList {
     const double* src[2 * kMaxLevels];

@@ -1444,7 +1444,7 @@ tph_status create_impl(const tph_desc* desc, void* stream, tph_solver* s) {
     TPH_TRY(alloc_field(s, g0, sizeof(double), &p)); s->fxe = (double*)p;
     TPH_TRY(alloc_field(s, g0, sizeof(double), &p)); s->fye = (double*)p;
     for (int k = 0; k < 3; ++k) { TPH_TRY(alloc_field(s, g0, sizeof(double), &p)); s->gtmp[k] = (double*)p; }
-    const int nb_cells = (int)(((g0.nx + 2 + 63) / 64) * ((g0.ny + 2 + 3) / 4));
+    const int nb_cells = (int)(((g0.nx + 2 + kCellBX - 1) / kCellBX) * ((g0.ny + 2 + kCellBY - 1) / kCellBY));
     s->partial_len = (size_t)std::max(nb_cells * 2, (kMaxRestart + 2) * 2048);
     TPH_TRY(dev_alloc(s, (void**)&s->partial, s->partial_len * sizeof(double)));
     TPH_TRY(dev_alloc(s, (void**)&s->dscal, kScalars * sizeof(double)));

@@ -19,8 +19,9 @@
 namespace tph {
 namespace {
 
-constexpr int BX = 64;
-constexpr int BY = 4;
+constexpr int BX = kCellBX;
+constexpr int BY = kCellBY;
+static_assert(BX * BY <= 256, "the cell kernels are compiled for blocks of at most 256 threads");
 
 inline dim3 grid_cells(const Geom& g) { return dim3((g.nx + BX - 1) / BX, (g.ny + BY - 1) / BY); }
 
