@@ -64,7 +64,10 @@ LARGE_TUNE_SEED = 13
 # of the recipe (seed 14); `--tune-batch` repeats that search.
 BATCH_PARAMS = {"alpha": 1.5, "uzawa_steps": 8, "nu_pre": 2, "nu_post": 2, "restart": 16}
 BATCH_TUNE_SEED = 14
-HEADLINE_TUNE_SEEDS = (12, 32)        # GRF and noise seeds of the held-out tuning instance
+# GRF and noise seeds of the held-out tuning instances: a candidate's cost is
+# its mean solve time over all of them, so that the schedule is not picked for the
+# iteration count of one instance
+HEADLINE_TUNE_SEEDS = ((12, 32), (13, 33), (14, 34))
 
 
 def log(msg):
@@ -268,10 +271,12 @@ def main():
         log(f"[bench] building the random-viscosity workload {n}x{n}")
         pr = wl.random_viscosity(n)
         eb, ep, rho = to(pr.eta_b), to(pr.eta_p), to(pr.rho_b)
-        # schedule and kernel plan tuned on a held-out instance of the recipe (untimed; the answer does not
+        # schedule and kernel plan tuned on held-out instances of the recipe (untimed; the answer does not
         # depend on them)
-        ph = wl.random_viscosity(n, seed_field=HEADLINE_TUNE_SEEDS[0], seed_noise=HEADLINE_TUNE_SEEDS[1])
+        held = [wl.random_viscosity(n, seed_field=a, seed_noise=b) for a, b in HEADLINE_TUNE_SEEDS]
+        ph = held[0]
         ebh, eph, rhoh = to(ph.eta_b), to(ph.eta_p), to(ph.rho_b)
+        also = [(to(q.eta_b), to(q.eta_p), to(q.rho_b), q.gx, q.gy) for q in held[1:]]
         for prec, tag in ((tph.MIXED, "mixed"), (tph.FP64, "fp64")):
             if args.no_tune or (prec == tph.FP64 and args.fp64_steps == 0):
                 tuned[tag] = {"params": {}, "ms": None, "default_ms": None, "trials": 0, "seconds": 0.0}
@@ -283,13 +288,13 @@ def main():
                 tuned[tag] = db.get(key)
                 log(f"[bench] {tag}: parameters from {args.tuning_db}")
                 continue
-            log(f"[bench] autotuning the {tag} solve on the held-out instance")
+            log(f"[bench] autotuning the {tag} solve on the held-out instances")
             tuned[tag] = autotune.tune(ebh, eph, rhoh, ph.gx, ph.gy, precision=prec, reps=args.tune_reps, device=dev,
-                                       db=db, tag="grf-heldout", starts=[autotune.ALT_START])
-            log(f"[bench] {tag}: tuned {tuned[tag]['params']} {tuned[tag]['ms']:.2f} ms on the held-out instance "
-                f"(defaults {tuned[tag]['default_ms']:.2f} ms, {tuned[tag]['trials']} trials, "
+                                       db=db, tag="grf-heldout", starts=[autotune.ALT_START], also=also)
+            log(f"[bench] {tag}: tuned {tuned[tag]['params']} {tuned[tag]['ms']:.2f} ms on the first held-out "
+                f"instance (defaults {tuned[tag]['default_ms']:.2f} ms, {tuned[tag]['trials']} trials, "
                 f"{tuned[tag]['seconds']:.1f} s)")
-        del ebh, eph, rhoh
+        del ebh, eph, rhoh, also
 
     # ---------------------------------------------------------------- headline
     if "headline" in only:
@@ -343,8 +348,9 @@ def main():
                                    f"{s_mix.levels}-level V-cycle, relative energy residual 1e-8",
                        "cells": cells, "levels": s_mix.levels, "precision": "mixed", "global_batch": 1},
             "setup_ms": inf_mix[-1].t_setup_ms, "solve_ms": inf_mix[-1].t_solve_ms,
-            "tuned": {"instance": f"held-out random-viscosity instance (seeds {HEADLINE_TUNE_SEEDS[0]}/"
-                                  f"{HEADLINE_TUNE_SEEDS[1]})", **tuned},
+            "tuned": {"instance": "held-out random-viscosity instances (seeds " +
+                                  ", ".join(f"{a}/{b}" for a, b in HEADLINE_TUNE_SEEDS) +
+                                  "; cost = mean solve time over them; ms = the first)", **tuned},
             # the 1024^2 FP32 working set (~30 MB) sits in the 256 MB Infinity Cache: effective bandwidth, no
             # HBM fraction
             "cache_effective": {"kernel": f"finest-level Gauss-Seidel sweep ({plan0[0]}, tile shape {plan0[1]}), "

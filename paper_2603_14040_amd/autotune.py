@@ -203,7 +203,8 @@ def tune(eta_b, eta_p, rho_b, gx: float = 0.0, gy: float = -1.0, *, precision: O
          lx: float = 1.0, ly: float = 1.0, bc=(0, 0, 0, 0), rtol: float = 1e-8, reps: int = 3, rounds: int = 2,
          rel_gain: float = 0.02, db: Optional[TuningDB] = None, tag: str = "", device=None,
          knobs: Optional[Sequence[Knob]] = None, log: Optional[Callable[[str], None]] = None,
-         max_iters: int = 2000, start: Optional[dict] = None, starts: Optional[Sequence[dict]] = None) -> dict:
+         max_iters: int = 2000, start: Optional[dict] = None, starts: Optional[Sequence[dict]] = None,
+         also: Optional[Sequence[tuple]] = None) -> dict:
     """Tune the solve of one problem (device FP64 arrays of shape (ny+2, nx+2)).
 
     Returns the database entry: ``params`` (Solver keyword arguments),
@@ -213,6 +214,11 @@ def tune(eta_b, eta_p, rho_b, gx: float = 0.0, gy: float = -1.0, *, precision: O
     ``solver_kwargs``, ``accel``, ``restart``, ``beta``, ``krylov``);
     ``starts`` lists further overrides, each the start of another descent
     (measured candidates are shared), and the fastest result wins.
+    ``also`` lists further problems on the same grid, as (eta_b, eta_p,
+    rho_b, gx, gy): a candidate's cost is then the mean of its median solve
+    times over all the problems, so that a schedule is not picked for the
+    iteration count of one instance (``ms`` and ``iters`` stay those of the
+    first problem).
     """
     import torch
     from . import MIXED, Solver, _lib
@@ -252,8 +258,9 @@ def tune(eta_b, eta_p, rho_b, gx: float = 0.0, gy: float = -1.0, *, precision: O
     base.close()
     del base
 
-    iters: Dict[str, int] = {}       # effective plan -> iterations
+    iters: Dict[str, int] = {}       # effective plan -> iterations (first problem)
     seen: Dict[str, float] = {}       # effective plan -> cost
+    first_ms: Dict[str, float] = {}   # effective plan -> median solve time of the first problem
     eff_of: Dict[str, str] = {}       # parameter set -> effective plan
 
     def measure(p: Params) -> float:
@@ -272,25 +279,30 @@ def tune(eta_b, eta_p, rho_b, gx: float = 0.0, gy: float = -1.0, *, precision: O
             eff_of[json.dumps(p, sort_keys=True)] = eff
             if eff in seen:
                 return seen[eff]
-            s.set_coefficients(eta_b, eta_p, rho_b, gx, gy)
             vx, vy, pp = s.zeros(), s.zeros(), s.zeros()
-            ts = []
-            for r in range(reps + 1):
-                vx.zero_(); vy.zero_(); pp.zero_()
-                torch.cuda.synchronize(device)
-                t0 = time.perf_counter()
-                info = s.solve(vx, vy, pp)[3]
-                torch.cuda.synchronize(device)
-                if info.status != "TPH_OK":
-                    seen[eff] = math.inf
-                    return math.inf
-                if r > 0:
-                    ts.append(time.perf_counter() - t0)
-            c = statistics.median(ts) * 1e3
+            costs, first_iters = [], None
+            for prob in [(eta_b, eta_p, rho_b, gx, gy)] + list(also or ()):
+                s.set_coefficients(*prob)
+                ts = []
+                for r in range(reps + 1):
+                    vx.zero_(); vy.zero_(); pp.zero_()
+                    torch.cuda.synchronize(device)
+                    t0 = time.perf_counter()
+                    info = s.solve(vx, vy, pp)[3]
+                    torch.cuda.synchronize(device)
+                    if info.status != "TPH_OK":
+                        seen[eff] = math.inf
+                        return math.inf
+                    if r > 0:
+                        ts.append(time.perf_counter() - t0)
+                costs.append(statistics.median(ts) * 1e3)
+                first_iters = info.iters if first_iters is None else first_iters
+            c = statistics.mean(costs)
             seen[eff] = c
-            iters[eff] = info.iters
+            first_ms[eff] = costs[0]
+            iters[eff] = first_iters
             if log:
-                log(f"[tune] {p} -> {c:.2f} ms, {info.iters} iterations")
+                log(f"[tune] {p} -> {c:.2f} ms, {first_iters} iterations")
             return c
         finally:
             s.close()
@@ -311,8 +323,11 @@ def tune(eta_b, eta_p, rho_b, gx: float = 0.0, gy: float = -1.0, *, precision: O
         res = r2 if r2.cost < res.cost else res
         res = SearchResult(res.params, res.cost, trials)
     best_kw = solver_kwargs(res.params, tile_levels)
-    entry = {"params": best_kw, "ms": res.cost, "iters": iters.get(eff_of.get(json.dumps(res.params, sort_keys=True))),
-             "default_ms": res.trials[0][1], "trials": len(res.trials),
+    best_eff = eff_of.get(json.dumps(res.params, sort_keys=True))
+    default_eff = eff_of.get(json.dumps(res.trials[0][0], sort_keys=True)) if res.trials else None
+    entry = {"params": best_kw, "ms": first_ms.get(best_eff, res.cost), "iters": iters.get(best_eff),
+             "cost": res.cost, "problems": 1 + len(also or ()),
+             "default_ms": first_ms.get(default_eff, res.trials[0][1]), "trials": len(res.trials),
              "seconds": round(time.perf_counter() - t_start, 2),
              "search": {k: (list(v) if isinstance(v, tuple) else v) for k, v in res.params.items()}}
     if db is not None:

@@ -769,6 +769,11 @@ tph_status energy_residual_vec(tph_solver* s, double* xraw, double* braw, double
     return reduce_to(s, nblk, 1, slot, to_host, to_host);
 }
 
+// GCR's residual recurrence |r_new|^2 = |r|^2 - alpha^2 is replaced by the
+// norm of the updated residual once it falls below this fraction of the
+// cycle's starting |r|^2 (it holds about 1e4 times its rounding error there).
+constexpr double kPythFloor = 1e-10;
+
 // Rounding floor of the relative energy residual at iterate x: eps times the
 // energy norm of the row magnitudes |b| + |A| |x|, over the energy norm of b.
 // The FP64 residual b - A x cannot be resolved below roughly this value.
@@ -1090,6 +1095,17 @@ tph_status gcr(tph_solver* s, double* braw, tph_info* info) {
             alph[i] = a.alpha;
             done = i + 1;
             rho2 = std::max(rho2 - a.alpha * a.alpha, 0.0);
+            // rho2 carries a rounding error of a few eps times the cycle's
+            // starting beta^2 (each step subtracts a term of nearly its own
+            // size), so it cannot resolve |r| / beta below about sqrt(eps);
+            // once it falls to kPythFloor beta^2, the norm of the updated
+            // residual r itself replaces it
+            if (rho2 <= kPythFloor * beta * beta) {
+                TPH_HIP(launch_multidot(Vk(0), n3, 1, Vk(0), n3, s->partial, nblk, s->st));
+                TPH_TRY(reduce_to(s, nblk, 1, kSlotMisc + 5, true, true));
+                TPH_TRY(wait_signal(s));
+                rho2 = s->hscal[kSlotMisc + 5];
+            }
             est = std::sqrt(rho2) / bnorm;
             if (info && info->history && its < info->history_len) info->history[its] = est;
             ++its;

@@ -146,6 +146,30 @@ def test_full_size_random_viscosity_residual_property(accel, m, beta):
     assert info.res_energy == pytest.approx(res, rel=1e-4)
 
 
+@pytest.mark.parametrize("prec", [tph.FP64, tph.MIXED])
+def test_gcr_stops_at_the_target_within_a_long_cycle(prec):
+    """GCR's in-cycle residual estimate must resolve the target even when
+    the cycle starts from |r| = |b|: the recurrence |r|^2 - alpha^2 alone
+    bottoms out near sqrt(eps) ~ 1.5e-8 relative to the cycle's start, above
+    a 1e-8 target.  With a restart longer than the solve needs, the solve
+    stops in its first cycle just below the target (it does not run out the
+    cycle to a far smaller residual), and the oracle confirms the residual."""
+    n = 256
+    pr = wl.random_viscosity(n)
+    s = solver_for(pr, precision=prec, accel="gcr", restart=64, uzawa_steps=4, alpha=1.5, rtol=1e-8)
+    s.set_coefficients(T(pr.eta_b), T(pr.eta_p), T(pr.rho_b), pr.gx, pr.gy)
+    vx, vy, p, info = s.solve()
+    print(f"[gcr long cycle] prec={prec} iters={info.iters} restarts={info.restarts} res={info.res_energy:.3e}",
+          flush=True)
+    assert info.status == "TPH_OK" and info.restarts == 1 and info.iters < 64
+    assert 1e-10 < info.res_energy <= 1e-8
+    g = st.Grid(n, n)
+    A = st.assemble(g, pr.eta_b, pr.eta_p)
+    b = st.rhs(g, pr.rho_b, pr.gx, pr.gy)
+    res = st.energy_residual(g, A, st.to_vector(g, N(vx), N(vy), N(p)), b, pr.eta_p)
+    assert res == pytest.approx(info.res_energy, rel=1e-3)
+
+
 def test_accelerator_solves_are_deterministic():
     pr = wl.random_viscosity(64)
     for accel in ("gcr", "anderson"):
