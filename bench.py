@@ -266,6 +266,7 @@ def main():
     n = args.n
     cells = n * n
     pr = eb = ep = rho = None
+    heldout = None  # (eta_b, eta_p, rho, gx, gy, also): the first held-out instance and the others
     tuned = {"mixed": {"params": {}}, "fp64": {"params": {}}}
     if any(s in only for s in ("headline", "adjoint", "accel", "ras", "mic")):
         log(f"[bench] building the random-viscosity workload {n}x{n}")
@@ -294,6 +295,7 @@ def main():
             log(f"[bench] {tag}: tuned {tuned[tag]['params']} {tuned[tag]['ms']:.2f} ms on the first held-out "
                 f"instance (defaults {tuned[tag]['default_ms']:.2f} ms, {tuned[tag]['trials']} trials, "
                 f"{tuned[tag]['seconds']:.1f} s)")
+        heldout = (ebh, eph, rhoh, ph.gx, ph.gy, also)
         del ebh, eph, rhoh, also
 
     # ---------------------------------------------------------------- headline
@@ -629,8 +631,9 @@ def main():
             params = dict(base, accel=name, **first[name])
             at_ = None
             if not args.no_tune:
-                at_ = autotune.tune(eb, ep, rho, pr.gx, pr.gy, precision=tph.MIXED, reps=1, rounds=1, device=dev,
-                                    knobs=space[name], start=params)
+                hb, hp, hr, hgx, hgy, hal = heldout
+                at_ = autotune.tune(hb, hp, hr, hgx, hgy, precision=tph.MIXED, reps=1, rounds=1, device=dev,
+                                    knobs=space[name], start=params, also=hal)
                 params = at_["params"]
             sa_ = tph.Solver(n, n, precision=tph.MIXED, device=dev, **params)
             ax_, ay_, ap_ = sa_.zeros(), sa_.zeros(), sa_.zeros()
@@ -654,6 +657,7 @@ def main():
                             "iters": ainf[-1].iters, "res_energy": ainf[-1].res_energy,
                             "restart": params["restart"], "beta": params["beta"] if name == "anderson" else None,
                             "tuning_trials": at_["trials"] if at_ else 0,
+                            "tuned_on": "held-out instances" if at_ else None,
                             "kernel": {"name": "k_gcr_step" if name == "gcr" else "k_mix",
                                        "what": ("GCR step update with restart/2 earlier directions" if name == "gcr"
                                                 else "Anderson mixing over restart + 1 stored pairs"),
@@ -670,7 +674,8 @@ def main():
         params = dict(base, smoother=tph.SMOOTH_RAS, ras_tile=16, ras_inner=4, nu_pre=4, nu_post=4, omega=0.6)
         rt_ = None
         if not args.no_tune:
-            rt_ = autotune.tune(eb, ep, rho, pr.gx, pr.gy, precision=tph.MIXED, reps=1, rounds=2, device=dev,
+            hb, hp, hr, hgx, hgy, hal = heldout
+            rt_ = autotune.tune(hb, hp, hr, hgx, hgy, precision=tph.MIXED, reps=1, rounds=2, device=dev, also=hal,
                                 knobs=[Knob("smoother", [tph.SMOOTH_RAS, tph.SMOOTH_RAS_MIXED]),
                                        Knob("ras_tile", [8, 16, 32]), Knob("ras_inner", [1, 2, 4, 8]),
                                        Knob("nu_pre", [2, 4, 8]), Knob("nu_post", [2, 4, 8]),
@@ -703,6 +708,7 @@ def main():
                       "params": {k: params[k] for k in ("smoother", "ras_tile", "ras_inner", "nu_pre", "nu_post",
                                                         "omega", "accel", "restart", "uzawa_steps", "alpha")},
                       "tuning_trials": rt_["trials"] if rt_ else 0,
+                      "tuned_on": "held-out instances" if rt_ else None,
                       "kernel": {"name": "k_ras_tile",
                                  "what": (f"one outer iteration ({params['ras_inner']} Jacobi sweeps) on "
                                           f"{params['ras_tile']}^2 tiles, finest level"),
