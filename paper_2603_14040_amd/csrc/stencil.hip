@@ -193,7 +193,7 @@ __global__ __launch_bounds__(256) void k_precond_out(Geom g, const T* __restrict
     precond_out_cell<T>(g, ex, ey, v, ep, energy, alpha, z, acc, i, j);
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, bool NT>
 __global__ __launch_bounds__(256) void k_uzawa_link(Geom g, LinkArgs<T> a, const double* __restrict__ eb,
                                                    const double* __restrict__ ep) {
     // XCD-aware block order: each XCD takes a band of block rows, so the halo
@@ -202,7 +202,7 @@ __global__ __launch_bounds__(256) void k_uzawa_link(Geom g, LinkArgs<T> a, const
     xcd_tile(bx, by);
     const int j = bx * BX + threadIdx.x + 1;
     const int i = by * BY + threadIdx.y + 1;
-    uzawa_link_cell<T, MODE>(g, a, eb, ep, i, j);
+    uzawa_link_cell<T, MODE, NT>(g, a, eb, ep, i, j);
 }
 
 // Lithostatic pressure, one thread per column marching up the rows: the
@@ -446,14 +446,29 @@ hipError_t launch_precond_out(const Geom& g, const T* ex, const T* ey, Vec3 v, c
     return hipGetLastError();
 }
 
+template <typename T, int MODE, bool NT>
+void launch_link_nt(const Geom& g, const LinkArgs<T>& a, const double* eb, const double* ep, hipStream_t st,
+                    hipEvent_t t0, hipEvent_t t1) {
+    const dim3 grid = grid_cells(g);
+    if (t0)
+        hipExtLaunchKernelGGL((k_uzawa_link<T, MODE, NT>), grid, dim3(BX, BY), 0, st, t0, t1, 0, g, a, eb, ep);
+    else
+        hipLaunchKernelGGL((k_uzawa_link<T, MODE, NT>), grid, dim3(BX, BY), 0, st, g, a, eb, ep);
+}
+
+// Streaming per-cell accesses once one FP64 vector of the grid (three
+// fields) outgrows the 256 MB last-level cache (4096^2: 2.5 % faster links);
+// below that the next kernel reads the link's outputs from that cache, and
+// streaming them costs 3 % of a 1024^2 solve.
+constexpr double kLinkStreamBytes = 256.0 * 1024 * 1024;
+
 template <typename T, int MODE>
 void launch_link_mode(const Geom& g, const LinkArgs<T>& a, const double* eb, const double* ep, hipStream_t st,
                       hipEvent_t t0, hipEvent_t t1) {
-    const dim3 grid = grid_cells(g);
-    if (t0)
-        hipExtLaunchKernelGGL((k_uzawa_link<T, MODE>), grid, dim3(BX, BY), 0, st, t0, t1, 0, g, a, eb, ep);
+    if (3.0 * sizeof(double) * (double)g.elems() > kLinkStreamBytes)
+        launch_link_nt<T, MODE, true>(g, a, eb, ep, st, t0, t1);
     else
-        hipLaunchKernelGGL((k_uzawa_link<T, MODE>), grid, dim3(BX, BY), 0, st, g, a, eb, ep);
+        launch_link_nt<T, MODE, false>(g, a, eb, ep, st, t0, t1);
 }
 
 template <typename T>

@@ -192,7 +192,22 @@ __device__ __forceinline__ double link_zp(const LinkArgs<T>& a, const double* __
     return (a.acc ? a.zold.p()[c] : 0.0) + a.alpha * ep[c] * (sp - div);
 }
 
-template <typename T, int MODE>
+// Per-cell loads and stores of the link that no neighbour shares: streaming
+// (nontemporal) when NT, so that on grids far larger than the last-level
+// cache they do not evict the shared 3 x 3 patch rows; ordinary otherwise,
+// where the next kernel finds them in that cache.
+template <bool NT, typename V>
+__device__ __forceinline__ void link_st(V* p, V v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+template <bool NT>
+__device__ __forceinline__ double link_ld(const double* p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+template <typename T, int MODE, bool NT = false>
 __device__ __forceinline__ void uzawa_link_cell(const Geom& g, const LinkArgs<T>& a, const double* __restrict__ eb,
                                                 const double* __restrict__ ep, int i, int j) {
     if (i > g.ny || j > g.nx) return;
@@ -215,16 +230,16 @@ __device__ __forceinline__ void uzawa_link_cell(const Geom& g, const LinkArgs<T>
     const double zpc = link_zp(a, ep, c, P, k);
     // this cell's z_new (with ghost mirrors of wall-adjacent values)
     if (j < g.nx) {
-        a.zout.vx()[c] = zx[4];
+        link_st<NT>(a.zout.vx() + c, zx[4]);
         if (i == 1) a.zout.vx()[c - P] = (double)g.mir[2] * zx[4];
         if (i == g.ny) a.zout.vx()[c + P] = (double)g.mir[3] * zx[4];
     }
     if (i < g.ny) {
-        a.zout.vy()[c] = zy[4];
+        link_st<NT>(a.zout.vy() + c, zy[4]);
         if (j == 1) a.zout.vy()[c - 1] = (double)g.mir[0] * zy[4];
         if (j == g.nx) a.zout.vy()[c + 1] = (double)g.mir[1] * zy[4];
     }
-    a.zout.p()[c] = zpc;
+    link_st<NT>(a.zout.p() + c, zpc);
     if (MODE == kLinkStore) return;
     const double* X = zx + 4;
     const double* Y = zy + 4;
@@ -234,33 +249,33 @@ __device__ __forceinline__ void uzawa_link_cell(const Geom& g, const LinkArgs<T>
         const double av = lx_row(X, Y, B, E, 0, 3, k.idx, k.idy) - (link_zp(a, ep, c + 1, P, k) - zpc) * k.idx;
         const double sq = sqrt(-lx_diag(B, E, 0, 3, i, g.ny, k));
         if (MODE == kLinkNext) {
-            double rv = a.r.vx()[c];
+            double rv = link_ld<NT>(a.r.vx() + c);
             if (a.r_scaled) rv *= sq;
-            a.rx[c] = (T)(rv - av);
+            link_st<NT>(a.rx + c, (T)(rv - av));
         } else {
-            a.wout.vx()[c] = a.w_scaled ? av / sq : av;
+            link_st<NT>(a.wout.vx() + c, a.w_scaled ? av / sq : av);
         }
     }
     if (i < g.ny) {
         const double av = ly_row(X, Y, B, E, 0, 3, k.idx, k.idy) - (link_zp(a, ep, c + P, P, k) - zpc) * k.idy;
         const double sq = sqrt(-ly_diag(B, E, 0, 3, j, g.nx, k));
         if (MODE == kLinkNext) {
-            double rv = a.r.vy()[c];
+            double rv = link_ld<NT>(a.r.vy() + c);
             if (a.r_scaled) rv *= sq;
-            a.ry[c] = (T)(rv - av);
+            link_st<NT>(a.ry + c, (T)(rv - av));
         } else {
-            a.wout.vy()[c] = a.w_scaled ? av / sq : av;
+            link_st<NT>(a.wout.vy() + c, a.w_scaled ? av / sq : av);
         }
     }
     {
         const double av = (zx[4] - zx[3]) * k.idx + (zy[4] - zy[1]) * k.idy;
         const double sw = sqrt(wp_weight(ep[c], k));
         if (MODE == kLinkNext) {
-            double rv = a.r.p()[c];
+            double rv = link_ld<NT>(a.r.p() + c);
             if (a.r_scaled) rv /= sw;
-            a.tp[c] = rv - av;
+            link_st<NT>(a.tp + c, rv - av);
         } else {
-            a.wout.p()[c] = a.w_scaled ? av * sw : av;
+            link_st<NT>(a.wout.p() + c, a.w_scaled ? av * sw : av);
         }
     }
 }
