@@ -771,7 +771,8 @@ tph_status energy_residual_vec(tph_solver* s, double* xraw, double* braw, double
 
 // GCR's residual recurrence |r_new|^2 = |r|^2 - alpha^2 is replaced by the
 // norm of the updated residual once it falls below this fraction of the
-// cycle's starting |r|^2 (it holds about 1e4 times its rounding error there).
+// |r|^2 it started from, the cycle's or that of the last such replacement
+// (it holds about 1e4 times its rounding error there).
 constexpr double kPythFloor = 1e-10;
 
 // Rounding floor of the relative energy residual at iterate x: eps times the
@@ -1029,6 +1030,7 @@ tph_status gcr(tph_solver* s, double* braw, tph_info* info) {
         best_true = std::min(best_true, true_res);
         ++restarts;
         double rho2 = beta * beta;
+        double ref2 = rho2;            // |r|^2 of the last exact evaluation
         int done = 0;
         for (int i = 0; i < m; ++i) {
             double* w = Vk(i + 1);
@@ -1095,16 +1097,18 @@ tph_status gcr(tph_solver* s, double* braw, tph_info* info) {
             alph[i] = a.alpha;
             done = i + 1;
             rho2 = std::max(rho2 - a.alpha * a.alpha, 0.0);
-            // rho2 carries a rounding error of a few eps times the cycle's
-            // starting beta^2 (each step subtracts a term of nearly its own
-            // size), so it cannot resolve |r| / beta below about sqrt(eps);
-            // once it falls to kPythFloor beta^2, the norm of the updated
-            // residual r itself replaces it
-            if (rho2 <= kPythFloor * beta * beta) {
+            // rho2 carries a rounding error of a few eps times the |r|^2 it
+            // started from (each step subtracts a term of nearly its own
+            // size), so it cannot resolve |r| below about sqrt(eps) of that
+            // start; once it falls to kPythFloor times it, the norm of the
+            // updated residual r itself replaces it and becomes the new start
+            // (the later steps subtract terms of the new, smaller size)
+            if (rho2 <= kPythFloor * ref2) {
                 TPH_HIP(launch_multidot(Vk(0), n3, 1, Vk(0), n3, s->partial, nblk, s->st));
                 TPH_TRY(reduce_to(s, nblk, 1, kSlotMisc + 5, true, true));
                 TPH_TRY(wait_signal(s));
                 rho2 = s->hscal[kSlotMisc + 5];
+                ref2 = rho2;
             }
             est = std::sqrt(rho2) / bnorm;
             if (info && info->history && its < info->history_len) info->history[its] = est;
