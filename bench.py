@@ -189,6 +189,7 @@ def main():
     ap.add_argument("--batch-reps", type=int, default=5, help="timed batched solves per precision (median)")
     ap.add_argument("--batch-precisions", default="mixed,fp64", help="precisions of the batched runs")
     ap.add_argument("--adjoint-reps", type=int, default=5)
+    ap.add_argument("--adjoint-precisions", default="mixed,fp64", help="precisions of the adjoint runs")
     ap.add_argument("--fd-cells", type=int, default=64,
                     help="cells of the adjoint finite-difference check (two perturbed solves each; 0: skip)")
     ap.add_argument("--config1-steps", type=int, default=20)
@@ -572,6 +573,8 @@ def main():
                            f"target from the perturbed field (seed 5); forward solve, adjoint solve and gradient "
                            f"kernel each timed (median), plus the autograd step (StokesFunction)"}
         for prec, tag in ((tph.MIXED, "mixed"), (tph.FP64, "fp64")):
+            if tag not in args.adjoint_precisions.split(","):
+                continue
             sa = tph.Solver(n, n, precision=prec, device=dev, **tuned[tag]["params"])
             sa.set_coefficients(to(eb_t), to(ep_t), rho, pr.gx, pr.gy)
             target = sa.solve()[0][n, 1:n].clone()

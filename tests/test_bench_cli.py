@@ -24,7 +24,8 @@ def test_side_workload_switches_exist():
     assert res.returncode == 0
     for opt in ("--steps", "--warmup", "--only", "--fp64-steps", "--batch", "--large", "--large-reps",
                 "--tune-large", "--roofline-kernel", "--skip-continuation", "--tune-batch", "--batch-precisions", "--batch-reps", "--cpu-sizes", "--accel-steps", "--ras-steps",
-                "--mic-steps", "--robust-iters", "--no-cpu-baseline", "--tuning-db", "--reuse-tuning"):
+                "--mic-steps", "--robust-iters", "--no-cpu-baseline", "--tuning-db", "--reuse-tuning",
+                "--adjoint-precisions", "--adjoint-reps", "--fd-cells", "--large-fp64-reps"):
         assert opt in res.stdout, opt
 
 
