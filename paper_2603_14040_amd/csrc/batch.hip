@@ -11,8 +11,10 @@
 // that also forms the next step's right-hand side or, after the last step,
 // the operator apply; classical Gram-Schmidt, normalisation, read-back of
 // the Hessenberg columns) is captured once as a hipGraph and replayed for
-// every iteration; the host only runs the Givens updates of each problem
-// between replays.
+// every iteration while every problem iterates; once some have converged the
+// iteration is launched directly over work lists compacted to the others,
+// so the launches no longer dispatch the converged problems' items.  The
+// host only runs the Givens updates of each problem between iterations.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -418,6 +420,19 @@ struct tph_batch {
     int n_cells = 0;
     int2* d_chunks = nullptr;
     int n_chunks = 0;
+    // Work lists of the lockstep iterations: the full lists above, or only the
+    // items of the problems still iterating (same order).  The captured graph
+    // holds the full counts, so it runs only while the lists are full; with
+    // compacted lists the iteration is launched directly.
+    std::vector<std::vector<int2>> h_tiles, h_rr;  // full lists (host)
+    std::vector<int2> h_cells, h_chunks;
+    std::vector<int2*> it_tiles, it_rr;            // device, capacity of the full lists
+    int2* it_cells = nullptr;
+    int2* it_chunks = nullptr;
+    std::vector<int> itn_tiles, itn_rr;
+    int itn_cells = 0, itn_chunks = 0;
+    int2* h_stage = nullptr;                       // pinned staging of list uploads
+    bool it_full = true;
     hipGraphExec_t iter_exec = nullptr;
     hipGraph_t iter_graph = nullptr;
     // batched coarsest factorisation: one workgroup per problem (null: some problem too large)
@@ -536,10 +551,10 @@ tph_status enqueue_iteration_t(tph_batch* b) {
     const int nu_pre = b->d.nu_pre, nu_post = b->d.nu_post;
     const int* act = b->d_active;
     auto tile_launch = [&](int d, int mode, int src, int dst, int ccur) {
-        const dim3 grid(b->n_tiles[d]);
+        const dim3 grid(b->itn_tiles[d]);
 #define KB(SM_, MODE_)                                                                                          \
     hipLaunchKernelGGL((kb_smooth_tile<T, SM_, MODE_>), grid, dim3(kTileThreads), 0, st, lev, b->d_prob,            \
-                       b->d_tiles[d], act, d, src, dst, ccur, om)
+                       b->it_tiles[d], act, d, src, dst, ccur, om)
         if (sm == TPH_SMOOTH_GS) {
             if (mode == kModeZero) KB(kSmGS, kModeZero);
             else if (mode == kModeProlong) KB(kSmGS, kModeProlong);
@@ -555,10 +570,10 @@ tph_status enqueue_iteration_t(tph_batch* b) {
     // one (FP64), the last pre-smoothing pass with the residual restriction,
     // the first post-smoothing pass with the prolongation.
     auto msw_launch = [&](int d, int ns, int mode, int rr, int src, int dst, int ccur) {
-        const dim3 grid(b->n_tiles[d]);
+        const dim3 grid(b->itn_tiles[d]);
 #define KG(NS_, MODE_, RR_)                                                                                    \
     hipLaunchKernelGGL((kb_gs_tile<T, NS_, MODE_, RR_>), grid, dim3(kTileThreads), 0, st, lev, b->d_prob,       \
-                       b->d_tiles[d], act, d, src, dst, ccur, om)
+                       b->it_tiles[d], act, d, src, dst, ccur, om)
 #define KG_NS(NS_)                                                                                             \
     do {                                                                                                       \
         if (mode == kModeProlong) KG(NS_, kModeProlong, 0);                                                    \
@@ -589,12 +604,12 @@ tph_status enqueue_iteration_t(tph_batch* b) {
             fin[d] = (cur_pre[d] + nu_post) & 1;
         }
     }
-    const dim3 cells(b->n_cells);
+    const dim3 cells(b->itn_cells);
     const int S = b->d.uzawa_steps;
-    hipLaunchKernelGGL(kb_precond_in<T>, cells, dim3(kCellBX, kCellBY), 0, st, lev, b->d_prob, b->d_cells, act, b->d_j);
+    hipLaunchKernelGGL(kb_precond_in<T>, cells, dim3(kCellBX, kCellBY), 0, st, lev, b->d_prob, b->it_cells, act, b->d_j);
     for (int step = 0; step < S; ++step) {
         for (int d = 0; d < b->maxdepth; ++d) {
-            if (b->n_tiles[d] == 0) continue;
+            if (b->itn_tiles[d] == 0) continue;
             if (msw(d)) {
                 int cur = 0;
                 bool zero = true;
@@ -614,13 +629,13 @@ tph_status enqueue_iteration_t(tph_batch* b) {
                 tile_launch(d, kModePlain, cur, 1 - cur, 0);
                 cur = 1 - cur;
             }
-            hipLaunchKernelGGL(kb_res_restrict<T>, dim3(b->n_rr[d]), dim3(kRRTileW * rr_tile_h<T>()), 0, st, lev,
-                               b->d_rr[d], act, d, cur);
+            hipLaunchKernelGGL(kb_res_restrict<T>, dim3(b->itn_rr[d]), dim3(kRRTileW * rr_tile_h<T>()), 0, st, lev,
+                               b->it_rr[d], act, d, cur);
         }
         hipLaunchKernelGGL(kb_coarse<T>, dim3(b->count), dim3(coarse_threads<T>()), b->coarse_lds, st,
                            (const CoarseArgs<T>*)b->d_cargs, act);
         for (int d = b->maxdepth - 1; d >= 0; --d) {
-            if (b->n_tiles[d] == 0) continue;
+            if (b->itn_tiles[d] == 0) continue;
             int cur = cur_pre[d];
             if (msw(d)) {
                 bool pro = true;
@@ -641,28 +656,29 @@ tph_status enqueue_iteration_t(tph_batch* b) {
             }
         }
         if (step < S - 1)
-            hipLaunchKernelGGL((kb_uzawa_link<T, kLinkNext>), cells, dim3(kCellBX, kCellBY), 0, st, lev, b->d_prob, b->d_cells,
+            hipLaunchKernelGGL((kb_uzawa_link<T, kLinkNext>), cells, dim3(kCellBX, kCellBY), 0, st, lev, b->d_prob, b->it_cells,
                                act, b->d_j, step, S, fin[0]);
         else
-            hipLaunchKernelGGL((kb_uzawa_link<T, kLinkApply>), cells, dim3(kCellBX, kCellBY), 0, st, lev, b->d_prob, b->d_cells,
+            hipLaunchKernelGGL((kb_uzawa_link<T, kLinkApply>), cells, dim3(kCellBX, kCellBY), 0, st, lev, b->d_prob, b->it_cells,
                                act, b->d_j, step, S, fin[0]);
     }
-    const dim3 chunks(b->n_chunks);
+    const dim3 chunks(b->itn_chunks);
+    const int2* ck = b->it_chunks;
     const dim3 rgrid(b->count, tph::kMaxRestart + 2);
     // classical Gram-Schmidt (dots and |w|^2, projection with the exact new
     // norm), then a second pass only where the first cancelled (kb_decide)
     const dim3 ngrid(b->count, 1);
     const int* ro = b->d_reorth;
-    hipLaunchKernelGGL(kb_multidot, chunks, dim3(256), 0, st, b->d_prob, b->d_chunks, act, b->d_j, nullptr);
+    hipLaunchKernelGGL(kb_multidot, chunks, dim3(256), 0, st, b->d_prob, ck, act, b->d_j, nullptr);
     hipLaunchKernelGGL(kb_reduce, rgrid, dim3(256), 0, st, b->d_prob, act, b->d_j, 2, 0, 0, kSlotH1, nullptr);
-    hipLaunchKernelGGL(kb_axpy, chunks, dim3(256), 0, st, b->d_prob, b->d_chunks, act, b->d_j, kSlotH1, nullptr);
+    hipLaunchKernelGGL(kb_axpy, chunks, dim3(256), 0, st, b->d_prob, ck, act, b->d_j, kSlotH1, nullptr);
     hipLaunchKernelGGL(kb_reduce, ngrid, dim3(256), 0, st, b->d_prob, act, b->d_j, 0, 1, 0, kSlotNrm, nullptr);
     hipLaunchKernelGGL(kb_decide, dim3(b->count), dim3(64), 0, st, b->d_prob, act, b->d_j, b->d_reorth);
-    hipLaunchKernelGGL(kb_multidot, chunks, dim3(256), 0, st, b->d_prob, b->d_chunks, act, b->d_j, ro);
+    hipLaunchKernelGGL(kb_multidot, chunks, dim3(256), 0, st, b->d_prob, ck, act, b->d_j, ro);
     hipLaunchKernelGGL(kb_reduce, rgrid, dim3(256), 0, st, b->d_prob, act, b->d_j, 1, 0, 0, kSlotH2, ro);
-    hipLaunchKernelGGL(kb_axpy, chunks, dim3(256), 0, st, b->d_prob, b->d_chunks, act, b->d_j, kSlotH2, ro);
+    hipLaunchKernelGGL(kb_axpy, chunks, dim3(256), 0, st, b->d_prob, ck, act, b->d_j, kSlotH2, ro);
     hipLaunchKernelGGL(kb_reduce, ngrid, dim3(256), 0, st, b->d_prob, act, b->d_j, 0, 1, 0, kSlotNrm, ro);
-    hipLaunchKernelGGL(kb_scale, chunks, dim3(256), 0, st, b->d_prob, b->d_chunks, act, b->d_j, 0, kSlotNrm);
+    hipLaunchKernelGGL(kb_scale, chunks, dim3(256), 0, st, b->d_prob, ck, act, b->d_j, 0, kSlotNrm);
     B_HIP(hipMemcpyAsync(b->h_scal, b->d_scal, (size_t)b->count * kScal * sizeof(double), hipMemcpyDeviceToHost, st));
     return TPH_OK;
 }
@@ -834,6 +850,27 @@ tph_status batch_create_impl(tph_batch* b, int count, const tph_desc* descs) {
     B_TRY(upload(chunks, &b->d_chunks));
     b->n_cells = (int)cells.size();
     b->n_chunks = (int)chunks.size();
+    // the iteration lists start full; the host keeps the full lists to compact from
+    b->it_tiles.assign(b->maxdepth, nullptr);
+    b->it_rr.assign(b->maxdepth, nullptr);
+    size_t stage = cells.size() + chunks.size();
+    for (int d = 0; d < b->maxdepth; ++d) {
+        B_TRY(upload(tiles[d], &b->it_tiles[d]));
+        B_TRY(upload(rr[d], &b->it_rr[d]));
+        stage += tiles[d].size() + rr[d].size();
+    }
+    B_TRY(upload(cells, &b->it_cells));
+    B_TRY(upload(chunks, &b->it_chunks));
+    b->itn_tiles = b->n_tiles;
+    b->itn_rr = b->n_rr;
+    b->itn_cells = b->n_cells;
+    b->itn_chunks = b->n_chunks;
+    b->h_tiles = std::move(tiles);
+    b->h_rr = std::move(rr);
+    b->h_cells = std::move(cells);
+    b->h_chunks = std::move(chunks);
+    b->it_full = true;
+    B_HIP(hipHostMalloc((void**)&b->h_stage, std::max<size_t>(stage, 1) * sizeof(int2), hipHostMallocDefault));
     B_TRY(b_alloc(b, (void**)&b->d_active, count * sizeof(int)));
     B_TRY(b_alloc(b, (void**)&b->d_reorth, count * sizeof(int)));
     B_TRY(b_alloc(b, (void**)&b->d_unfinished, count * sizeof(int)));
@@ -847,6 +884,35 @@ tph_status batch_create_impl(tph_batch* b, int count, const tph_desc* descs) {
     else B_TRY(build_tables_t<double>(b));
     B_HIP(hipDeviceSynchronize());
     B_TRY(build_graph(b));
+    return TPH_OK;
+}
+
+// Iteration work lists of the problems with mask[p] set (all set: the full
+// lists, which the captured graph expects).  The stream is idle on entry (the
+// solve loop has just synchronised it), so the staging buffer is free.
+tph_status set_iteration_lists(tph_batch* b, const std::vector<int>& mask) {
+    bool all = true;
+    for (int p = 0; p < b->count; ++p) all = all && mask[p] != 0;
+    if (all && b->it_full) return TPH_OK;
+    B_HIP(hipStreamSynchronize(b->st));
+    size_t off = 0;
+    auto put = [&](const std::vector<int2>& full, int2* dst, int* n) -> tph_status {
+        int2* out = b->h_stage + off;
+        int k = 0;
+        for (const int2& it : full)
+            if (all || mask[it.x]) out[k++] = it;
+        *n = k;
+        if (k > 0) B_HIP(hipMemcpyAsync(dst, out, (size_t)k * sizeof(int2), hipMemcpyHostToDevice, b->st));
+        off += (size_t)k;
+        return TPH_OK;
+    };
+    for (int d = 0; d < b->maxdepth; ++d) {
+        B_TRY(put(b->h_tiles[d], b->it_tiles[d], &b->itn_tiles[d]));
+        B_TRY(put(b->h_rr[d], b->it_rr[d], &b->itn_rr[d]));
+    }
+    B_TRY(put(b->h_cells, b->it_cells, &b->itn_cells));
+    B_TRY(put(b->h_chunks, b->it_chunks, &b->itn_chunks));
+    b->it_full = all;
     return TPH_OK;
 }
 
@@ -929,13 +995,15 @@ tph_status batch_solve_impl(tph_batch* b, tph_info* infos) {
         h_act = h_unf;
         B_TRY(set_mask(b->d_unfinished, h_unf));
         B_TRY(set_mask(b->d_active, h_act));
+        B_TRY(set_iteration_lists(b, h_act));
         hipLaunchKernelGGL(kb_scale, chunks, dim3(256), 0, st, b->d_prob, b->d_chunks, b->d_active, b->d_j, 1,
                            kSlotMisc);
         std::fill(jdone.begin(), jdone.end(), 0);
         for (int j = 0; j < m; ++j) {
             b->h_j[0] = j;
             B_HIP(hipMemcpyAsync(b->d_j, b->h_j, sizeof(int), hipMemcpyHostToDevice, st));
-            B_HIP(hipGraphLaunch(b->iter_exec, st));
+            if (b->it_full) B_HIP(hipGraphLaunch(b->iter_exec, st));
+            else B_TRY(enqueue_iteration(b));
             B_HIP(hipStreamSynchronize(st));
             bool changed = false, left = false;
             for (int p = 0; p < P; ++p) {
@@ -972,7 +1040,10 @@ tph_status batch_solve_impl(tph_batch* b, tph_info* infos) {
                 }
             }
             if (!left) break;
-            if (changed) B_TRY(set_mask(b->d_active, h_act));
+            if (changed) {
+                B_TRY(set_mask(b->d_active, h_act));
+                B_TRY(set_iteration_lists(b, h_act));
+            }
         }
         // y_p = R^{-1} g, x_p += Z y_p
         for (int p = 0; p < P; ++p) {
@@ -1160,6 +1231,7 @@ void tph_batch_destroy(tph_batch* b) {
     if (b->h_scal) (void)hipHostFree(b->h_scal);
     if (b->h_j) (void)hipHostFree(b->h_j);
     if (b->h_int) (void)hipHostFree(b->h_int);
+    if (b->h_stage) (void)hipHostFree(b->h_stage);
     for (hipEvent_t e : b->pev) (void)hipEventDestroy(e);
     for (hipStream_t q : b->ps) (void)hipStreamDestroy(q);
     if (b->ev) (void)hipEventDestroy(b->ev);
