@@ -441,7 +441,10 @@ void tph_destroy(tph_solver* s);
  * V-cycle phase is one launch for the whole batch (work lists of (problem,
  * tile) items), the coarse tails run one workgroup per problem, and the
  * device work of one FGMRES iteration is captured once as a hipGraph and
- * replayed; converged problems are masked on the device.  All problems must
+ * replayed while every problem iterates; once some have converged, the
+ * iteration is launched directly over work lists holding only the items of
+ * the problems still iterating (converged problems are also masked on the
+ * device).  All problems must
  * share precision, smoother, sweep counts (>= 1, nu_growth 1), omega, alpha,
  * eta_mean, restart, max_iters, uzawa_steps, rtol and msweep, use fused
  * kernels, and be large enough to have a coarse tail of at least one level
