@@ -456,7 +456,9 @@ def test_batched_solve_matches_oracle(prec, steps, nu, msweep):
     so odd and even step counts end differently; 1-3 sweeps with multi-sweep
     passes on no depth (the batch default), on every depth but the finest,
     on chosen depths and on every depth, which changes the buffers each depth
-    ends in)."""
+    ends in).  The problems need different iteration counts, so the later
+    iterations run over work lists compacted to the problems still
+    iterating, and the second solve starts again from the full lists."""
     probs = [wl.sinker(64, radius=0.12, eta_in=30.0),
              wl.sinker(32, radius=0.2, eta_in=10.0),
              wl.random_viscosity(64, ell=0.15, contrast=100.0),
@@ -482,7 +484,9 @@ def test_batched_solve_matches_oracle(prec, steps, nu, msweep):
         assert infos[k].vcycles == infos[k].iters * steps
         assert 0.0 <= infos[k].res_l2 < 1e-6
         _check_solution_contract(pr.nx, pr.ny, pr.bc, N(vx[k]), N(vy[k]), N(pp[k]))
-    # a second solve on the same batch (graph replay, masks reset) gives the same answer
+    # the problems stop at different iterations: the compacted work lists were used
+    assert len({i.iters for i in infos}) > 1
+    # a second solve on the same batch (graph replay, masks and full lists reset) gives the same answer
     vx2, vy2, pp2, infos2 = bat.solve()
     for k in range(len(probs)):
         assert np.array_equal(N(vx[k]), N(vx2[k])) and np.array_equal(N(pp[k]), N(pp2[k]))
