@@ -895,6 +895,7 @@ tph_status set_iteration_lists(tph_batch* b, const std::vector<int>& mask) {
     for (int p = 0; p < b->count; ++p) all = all && mask[p] != 0;
     if (all && b->it_full) return TPH_OK;
     B_HIP(hipStreamSynchronize(b->st));
+    b->it_full = false;    // until every list is written (a failed upload leaves them to be rewritten)
     size_t off = 0;
     auto put = [&](const std::vector<int2>& full, int2* dst, int* n) -> tph_status {
         int2* out = b->h_stage + off;
